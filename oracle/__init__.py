@@ -1,0 +1,123 @@
+"""CPU oracle for the direct dedispersion transform (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the GPU library; see
+``dedisp_oracle.c`` for the definitions it implements and the readings of the
+paper it fixes.  Functions take and return numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_f64p = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.oracle_partial_delay.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, _f64p]
+    lib.oracle_delay_table.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, _f64p, ctypes.c_int, _i32p, _i32p]
+    lib.oracle_dedisperse.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                      _i32p, ctypes.c_int, ctypes.c_int32, _u32p,
+                                      ctypes.c_int64, ctypes.c_int]
+    lib.oracle_dedisperse_points.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                             _i32p, ctypes.c_int, ctypes.c_int32, _i64p, _i64p,
+                                             ctypes.c_int64, _u32p, ctypes.c_int]
+    for f in ("oracle_partial_delay", "oracle_delay_table", "oracle_dedisperse",
+              "oracle_dedisperse_points", "oracle_max_threads"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(f"{what} failed with code {rc}")
+
+
+def max_threads() -> int:
+    return int(_load().oracle_max_threads())
+
+
+def partial_delay(nchans, dt, f_top, df) -> np.ndarray:
+    """Delta T(nu) in samples per unit DM, float64 [nchans]."""
+    out = np.zeros(nchans, dtype=np.float64)
+    _check(_load().oracle_partial_delay(nchans, dt, f_top, df, _ptr(out, _f64p)), "partial_delay")
+    return out
+
+
+def delay_table(nchans, dt, f_top, df, dms):
+    """(int32 [ndm][nchans] delay table, max_delay)."""
+    dms = np.ascontiguousarray(dms, dtype=np.float64)
+    ndm = int(dms.shape[0])
+    table = np.zeros((max(ndm, 1), nchans), dtype=np.int32)
+    mx = ctypes.c_int32(0)
+    _check(_load().oracle_delay_table(nchans, dt, f_top, df, _ptr(dms, _f64p), ndm,
+                                      _ptr(table, _i32p), ctypes.byref(mx)), "delay_table")
+    return table, int(mx.value)
+
+
+def dedisperse(packed, nsamps, nchans, nbits, table, max_delay=None, nthreads=0):
+    """Full transform: uint32 [ndm][nsamps - max_delay]."""
+    packed = np.ascontiguousarray(packed, dtype=np.uint8).reshape(-1)
+    table = np.ascontiguousarray(table, dtype=np.int32)
+    ndm = int(table.shape[0])
+    if max_delay is None:
+        max_delay = int(table.max())
+    nout = int(nsamps) - int(max_delay)
+    if nout <= 0:
+        raise OracleError("too few samples")
+    if packed.size < int(nsamps) * nchans * nbits // 8:
+        raise OracleError("input too short")
+    out = np.zeros((ndm, nout), dtype=np.uint32)
+    _check(_load().oracle_dedisperse(_ptr(packed, _u8p), int(nsamps), nchans, nbits,
+                                     _ptr(table, _i32p), ndm, int(max_delay),
+                                     _ptr(out, _u32p), nout, int(nthreads)), "dedisperse")
+    return out
+
+
+def dedisperse_points(packed, nsamps, nchans, nbits, table, d_idx, t_idx, max_delay=None,
+                      nthreads=0):
+    """The transform at the listed (d, t) points only: uint32 [npts]."""
+    packed = np.ascontiguousarray(packed, dtype=np.uint8).reshape(-1)
+    table = np.ascontiguousarray(table, dtype=np.int32)
+    d_idx = np.ascontiguousarray(d_idx, dtype=np.int64)
+    t_idx = np.ascontiguousarray(t_idx, dtype=np.int64)
+    if max_delay is None:
+        max_delay = int(table.max())
+    if packed.size < int(nsamps) * nchans * nbits // 8:
+        raise OracleError("input too short")
+    out = np.zeros(d_idx.shape[0], dtype=np.uint32)
+    _check(_load().oracle_dedisperse_points(_ptr(packed, _u8p), int(nsamps), nchans, nbits,
+                                            _ptr(table, _i32p), int(table.shape[0]),
+                                            int(max_delay), _ptr(d_idx, _i64p),
+                                            _ptr(t_idx, _i64p), int(d_idx.shape[0]),
+                                            _ptr(out, _u32p), int(nthreads)),
+           "dedisperse_points")
+    return out

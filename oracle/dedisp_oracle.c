@@ -1,0 +1,193 @@
+/*
+ * CPU oracle for the direct incoherent dedispersion transform.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link or
+ * call this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * with the GPU library: every number below is derived here from the paper
+ * (Barsdell, Bailes, Barnes & Fluke 2012, "Accelerating incoherent
+ * dedispersion", MNRAS 422, 379).
+ *
+ * It is deliberately plain and slow: each output is the sum of the definition
+ * written out, one channel at a time, decoding every sample from the packed
+ * input at the moment it is used.  Parallelism over DM rows (OpenMP) changes
+ * no arithmetic: every output is an independent integer sum.
+ *
+ * Readings of the paper that this file fixes (listed in the design notes):
+ *   - channel c is at frequency f_top + c*df (f_top = start of the band),
+ *   - "rounded to the nearest integer" is round-half-away-from-zero,
+ *   - the delay is evaluated in IEEE binary64 in the order written below,
+ *   - outputs exist for 0 <= t < nsamps - max_delay only,
+ *   - samples are raw unsigned codes; 2-bit samples are packed four per byte,
+ *     channel c at bits [2*(c%4), 2*(c%4)+1] of byte c/4 of its time row.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math -shared -fPIC.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Dispersion constant k_DM in MHz^2 pc^-1 cm^3 s (Section 1, the dispersion
+ * delay equation).  The paper notes the common 1/2.41e-4 approximation and
+ * gives this value as the constant itself. */
+static const double ORACLE_K_DM = 4.148808e3;
+
+enum {
+    ORACLE_OK = 0,
+    ORACLE_BAD_ARG = -1,
+    ORACLE_TOO_FEW_SAMPLES = -2
+};
+
+/* Same acceptance rules as the library's public interface: the transform is
+ * only defined here for a band that descends from f_top (df < 0) and stays
+ * at positive frequency, 2- or 8-bit codes, whole bytes per time row. */
+static int oracle_check_params(int nchans, double dt, double f_top, double df, int nbits)
+{
+    if (nchans <= 0) return ORACLE_BAD_ARG;
+    if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
+    if (((long long)nchans * nbits) % 8 != 0) return ORACLE_BAD_ARG;
+    if (!(dt > 0.0) || !isfinite(dt)) return ORACLE_BAD_ARG;
+    if (!(f_top > 0.0) || !isfinite(f_top)) return ORACLE_BAD_ARG;
+    if (!(df < 0.0) || !isfinite(df)) return ORACLE_BAD_ARG;
+    if (!(f_top + (double)(nchans - 1) * df > 0.0)) return ORACLE_BAD_ARG;
+    return ORACLE_OK;
+}
+
+/* Delta T(nu) of the "partial_delay" equation of Section 2.1: the delay in
+ * samples per unit DM of channel nu relative to the start of the band,
+ *   (k_DM / dtau) * ( 1/(nu0 + nu*dnu)^2 - 1/nu0^2 ). */
+int oracle_partial_delay(int nchans, double dt, double f_top, double df, double* dT)
+{
+    if (!dT) return ORACLE_BAD_ARG;
+    if (oracle_check_params(nchans, dt, f_top, df, 8) != ORACLE_OK) return ORACLE_BAD_ARG;
+    const double inv_top2 = 1.0 / (f_top * f_top);
+    const double scale = ORACLE_K_DM / dt;
+    for (int nu = 0; nu < nchans; ++nu) {
+        const double f = f_top + (double)nu * df;
+        dT[nu] = scale * (1.0 / (f * f) - inv_top2);
+    }
+    return ORACLE_OK;
+}
+
+/* Delta t(d, nu) of the "delay" equation of Section 2.1:
+ * round(DM(d) * Delta T(nu)), for every trial DM (rows) and channel
+ * (columns).  Also returns the largest delay, which fixes how many outputs
+ * exist. */
+int oracle_delay_table(int nchans, double dt, double f_top, double df,
+                       const double* dms, int ndm, int32_t* table, int32_t* max_delay)
+{
+    if (!dms || !table || !max_delay || ndm <= 0) return ORACLE_BAD_ARG;
+    if (oracle_check_params(nchans, dt, f_top, df, 8) != ORACLE_OK) return ORACLE_BAD_ARG;
+    for (int d = 0; d < ndm; ++d)
+        if (!(dms[d] >= 0.0) || !isfinite(dms[d])) return ORACLE_BAD_ARG;
+
+    const double inv_top2 = 1.0 / (f_top * f_top);
+    const double scale = ORACLE_K_DM / dt;
+    int32_t mx = 0;
+    for (int d = 0; d < ndm; ++d) {
+        for (int nu = 0; nu < nchans; ++nu) {
+            const double f = f_top + (double)nu * df;
+            const double dTnu = scale * (1.0 / (f * f) - inv_top2);
+            const double v = round(dms[d] * dTnu);      /* half away from zero */
+            if (!(v < 2147483647.0)) return ORACLE_BAD_ARG;
+            const int32_t di = (int32_t)v;
+            table[(size_t)d * nchans + nu] = di;
+            if (di > mx) mx = di;
+        }
+    }
+    *max_delay = mx;
+    return ORACLE_OK;
+}
+
+/* A[nu][t]: the unsigned code of channel nu at time sample t, read straight
+ * from the packed time-major input. */
+static inline uint32_t oracle_sample(const uint8_t* in, int nchans, int nbits,
+                                     int64_t t, int nu)
+{
+    if (nbits == 8)
+        return in[(size_t)t * (size_t)nchans + (size_t)nu];
+    const size_t row_bytes = (size_t)nchans / 4;
+    const uint8_t byte = in[(size_t)t * row_bytes + (size_t)(nu / 4)];
+    return (uint32_t)((byte >> (2 * (nu % 4))) & 3u);
+}
+
+/* The direct dedispersion transform, the "direct" equation of Section 2.1:
+ *   D[d][t] = sum over nu = 0..N_nu-1 of A[nu][t + Delta t(d, nu)]
+ * for 0 <= d < ndm and 0 <= t < nsamps - max_delay, written to
+ * out[d * out_stride + t]. */
+int oracle_dedisperse(const uint8_t* in, int64_t nsamps, int nchans, int nbits,
+                      const int32_t* table, int ndm, int32_t max_delay,
+                      uint32_t* out, int64_t out_stride, int nthreads)
+{
+    if (!in || !table || !out || ndm <= 0 || nchans <= 0) return ORACLE_BAD_ARG;
+    if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
+    if (nbits == 2 && nchans % 4) return ORACLE_BAD_ARG;
+    if (nsamps <= (int64_t)max_delay) return ORACLE_TOO_FEW_SAMPLES;
+    const int64_t nout = nsamps - (int64_t)max_delay;
+    if (out_stride < nout) return ORACLE_BAD_ARG;
+    for (size_t i = 0; i < (size_t)ndm * (size_t)nchans; ++i)
+        if (table[i] < 0 || table[i] > max_delay) return ORACLE_BAD_ARG;
+
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int d = 0; d < ndm; ++d) {
+        const int32_t* delay = table + (size_t)d * nchans;
+        uint32_t* row = out + (size_t)d * (size_t)out_stride;
+        for (int64_t t = 0; t < nout; ++t) {
+            uint32_t sum = 0;
+            for (int nu = 0; nu < nchans; ++nu)
+                sum += oracle_sample(in, nchans, nbits, t + delay[nu], nu);
+            row[t] = sum;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* The same definition evaluated only at the listed (d, t) points, for
+ * checking sampled outputs of inputs too large to transform whole on a CPU. */
+int oracle_dedisperse_points(const uint8_t* in, int64_t nsamps, int nchans, int nbits,
+                             const int32_t* table, int ndm, int32_t max_delay,
+                             const int64_t* d_idx, const int64_t* t_idx, int64_t npts,
+                             uint32_t* out, int nthreads)
+{
+    if (!in || !table || !out || !d_idx || !t_idx || npts < 0) return ORACLE_BAD_ARG;
+    if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
+    if (nbits == 2 && nchans % 4) return ORACLE_BAD_ARG;
+    if (nsamps <= (int64_t)max_delay) return ORACLE_TOO_FEW_SAMPLES;
+    const int64_t nout = nsamps - (int64_t)max_delay;
+    for (int64_t i = 0; i < npts; ++i)
+        if (d_idx[i] < 0 || d_idx[i] >= ndm || t_idx[i] < 0 || t_idx[i] >= nout)
+            return ORACLE_BAD_ARG;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < npts; ++i) {
+        const int32_t* delay = table + (size_t)d_idx[i] * nchans;
+        const int64_t t = t_idx[i];
+        uint32_t sum = 0;
+        for (int nu = 0; nu < nchans; ++nu)
+            sum += oracle_sample(in, nchans, nbits, t + delay[nu], nu);
+        out[i] = sum;
+    }
+    return ORACLE_OK;
+}
+
+int oracle_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,334 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+The oracle is the yardstick for every GPU parity test, so here it is checked
+against things other than itself:
+
+* the delay table against exact rational arithmetic of the delay equations
+  (Section 2.1, eqs. partial_delay and delay), rounded half away from zero,
+  and against the channel-frequency convention implied by the centre
+  frequency the paper prints for its HTRU workload (Fig. 3 caption vs
+  Section 5.2);
+* the transform (Section 2.1, eq. direct) against a push-style brute force
+  that scatters every input sample into the outputs it reaches, impulse
+  responses, linearity, time-shift equivariance, textbook reductions (the DM 0
+  row is a plain channel sum, one channel is a copy, constant input), 2-bit
+  decoding against numpy's own bit packer, and recovery of injected pulses at
+  the trial and time they were injected (the analogue of Fig. 1).
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1201_5380_amd import synth
+
+# ---------------------------------------------------------------------------
+# delay table
+# ---------------------------------------------------------------------------
+
+# (nchans, dt, f_top, df) as decimal strings so the exact arithmetic sees the
+# numbers as written, plus the DM list parameters.
+CASES = {
+    "tiny": ("64", "64e-6", "1500", "-1", 32, 100.0),
+    "survey": ("1024", "64e-6", "1581.8", "-0.390625", 1024, 1000.0),
+    "large": ("4096", "54.6e-6", "1500", "-0.09765625", 2048, 2000.0),
+}
+
+
+def _exact_delays(nchans, dt, f_top, df, dms, dm_rows, k_dm="4148.808"):
+    """Exact-rational round(DM * Delta T(nu)); None where within 1e-9 of a tie."""
+    K, dt, f0, dfr = Fraction(k_dm), Fraction(dt), Fraction(f_top), Fraction(df)
+    inv0 = 1 / (f0 * f0)
+    dT = []
+    for c in range(nchans):
+        f = f0 + c * dfr
+        dT.append(K / dt * (1 / (f * f) - inv0))
+    out = {}
+    half = Fraction(1, 2)
+    for d in dm_rows:
+        dm = Fraction(float(dms[d]))
+        row = []
+        for c in range(nchans):
+            v = dm * dT[c]
+            fl = v.numerator // v.denominator
+            frac = v - fl
+            if abs(frac - half) < Fraction(1, 10**9):
+                row.append(None)
+            else:
+                row.append(fl + (1 if frac > half else 0))
+        out[d] = row
+    return out
+
+
+@pytest.mark.parametrize("case", ["tiny", "survey", "large"])
+def test_delay_table_matches_exact_rational(case):
+    nch, dt, f0, df, ndm, dm_max = CASES[case]
+    nchans = int(nch)
+    dms = synth.dm_list_linear(ndm, dm_max)
+    table, mx = oracle.delay_table(nchans, float(dt), float(f0), float(df), dms)
+    if case == "tiny":
+        rows = list(range(ndm))
+    else:
+        rows = sorted(set(list(range(0, ndm, ndm // 12)) + [1, ndm - 1]))
+    exact = _exact_delays(nchans, dt, f0, df, dms, rows)
+    ties = 0
+    for d in rows:
+        for c in range(nchans):
+            e = exact[d][c]
+            if e is None:
+                ties += 1
+                continue
+            assert table[d, c] == e, (case, d, c, table[d, c], e)
+    assert ties <= 2
+    # the largest delay sits at the largest DM and the lowest channel
+    assert mx == exact[ndm - 1][nchans - 1]
+    assert mx == int(table.max())
+
+
+def test_max_delay_values():
+    """Largest delays of the three single-beam workloads (exact arithmetic above)."""
+    want = {"tiny": 250, "survey": 20456, "large": 58003}
+    for case, expect in want.items():
+        nch, dt, f0, df, ndm, dm_max = CASES[case]
+        dms = synth.dm_list_linear(ndm, dm_max)
+        _, mx = oracle.delay_table(int(nch), float(dt), float(f0), float(df), dms)
+        assert mx == expect, case
+
+
+def test_tiny_trail_endpoints():
+    """DM 50 on the 64-channel band: no delay at the top, 129 samples at the bottom."""
+    table, _ = oracle.delay_table(64, 64e-6, 1500.0, -1.0, np.array([50.0]))
+    assert table[0, 0] == 0 and table[0, 63] == 129
+
+
+def test_k_dm_and_channel_frequency_convention(golden_paper):
+    """Channel N/2 of the HTRU band sits at the printed centre frequency.
+
+    Section 5.2 gives nu0 = 1581.8 MHz, dnu = -0.39062 MHz, N = 1024; the
+    Fig. 3 caption gives nu_c = 1381.8 MHz and BW = 400 MHz for the same data,
+    with nu_c = nu0 + BW/2 (Section 2.1).  So channel nu = 512 is at exactly
+    nu_c when channel nu is at nu0 + nu*dnu, and Delta T(512) must equal the
+    dispersion delay between nu0 and nu_c in samples per unit DM, with the
+    constant k_DM the paper gives (not its common 1/2.41e-4 approximation).
+    """
+    k = float(golden_paper["k_dm"])
+    nu0 = float(golden_paper["htru_nu0_mhz"])
+    nuc = float(golden_paper["htru_nuc_mhz"])
+    bw = float(golden_paper["htru_bw_mhz"])
+    n = int(golden_paper["htru_nchans"])
+    dtau = float(golden_paper["htru_dtau_s"])
+    dnu_printed = float(golden_paper["htru_dnu_mhz"])
+    dnu = -bw / n
+    assert abs(dnu - dnu_printed) < 1e-5          # the printed value is rounded
+    dT = oracle.partial_delay(n, dtau, nu0, dnu)
+    assert dT[0] == 0.0
+    want = k / dtau * (nuc ** -2 - nu0 ** -2)
+    assert abs(dT[n // 2] / want - 1) < 1e-12
+    approx = 1 / float(golden_paper["k_dm_approx_inverse"]) / dtau * (nuc ** -2 - nu0 ** -2)
+    assert abs(dT[n // 2] / approx - 1) > 1e-4     # the approximation is a different constant
+    # a half-channel offset in the convention would move channel 512 off nu_c
+    half_off = k / dtau * ((nuc - dnu / 2) ** -2 - nu0 ** -2)
+    assert abs(dT[n // 2] / half_off - 1) > 1e-4
+
+
+def test_delay_table_invariants():
+    nchans, ndm = 256, 64
+    dms = synth.dm_list_linear(ndm, 800.0)
+    table, mx = oracle.delay_table(nchans, 64e-6, 1400.0, -0.5, dms)
+    assert np.all(table[:, 0] == 0)               # no delay at the top of the band
+    assert np.all(table[0] == 0)                  # DM 0 has no delay
+    assert np.all(np.diff(table, axis=1) >= 0)    # lower channels are delayed more
+    assert np.all(np.diff(table, axis=0) >= 0)    # larger DMs are delayed more
+    assert mx == table.max()
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nchans=0), dict(df=0.0), dict(df=0.5), dict(dt=0.0), dict(f_top=-1.0),
+    dict(nchans=64, f_top=10.0, df=-1.0),          # band reaches zero frequency
+    dict(dms=[1.0, -2.0]), dict(dms=[float("nan")]), dict(dms=[])])
+def test_delay_table_rejects_bad_arguments(bad):
+    kw = dict(nchans=16, dt=64e-6, f_top=1500.0, df=-1.0, dms=[0.0, 10.0])
+    kw.update(bad)
+    with pytest.raises(oracle.OracleError):
+        oracle.delay_table(kw["nchans"], kw["dt"], kw["f_top"], kw["df"],
+                           np.asarray(kw["dms"], dtype=np.float64))
+
+
+# ---------------------------------------------------------------------------
+# the transform
+# ---------------------------------------------------------------------------
+
+def _random_case(rng, nsamps, nchans, nbits, ndm, max_delay):
+    max_code = 255 if nbits == 8 else 3
+    codes = rng.integers(0, max_code + 1, size=(nsamps, nchans), dtype=np.uint8)
+    table = rng.integers(0, max_delay + 1, size=(ndm, nchans)).astype(np.int32)
+    table[:, 0] = 0
+    table[0, -1] = max_delay                      # make the stated maximum real
+    return codes, table
+
+
+def _push_brute_force(codes, table):
+    """Scatter every input sample into each output it reaches.
+
+    Sample (t', c) contributes its code to out[d][t' - delay[d][c]] whenever
+    that index is a valid output.  This enumerates inputs, not outputs, so it
+    shares no loop structure with the oracle.
+    """
+    nsamps, nchans = codes.shape
+    ndm = table.shape[0]
+    mx = int(table.max())
+    nout = nsamps - mx
+    out = np.zeros((ndm, nout), dtype=np.int64)
+    tprime = np.arange(nsamps)
+    for d in range(ndm):
+        for c in range(nchans):
+            t = tprime - int(table[d, c])
+            ok = (t >= 0) & (t < nout)
+            np.add.at(out[d], t[ok], codes[ok, c].astype(np.int64))
+    return out
+
+
+@pytest.mark.parametrize("nbits,nchans,ndm,nsamps,maxd", [
+    (8, 1, 3, 50, 0), (8, 5, 4, 64, 9), (2, 4, 6, 80, 17), (2, 8, 16, 200, 31),
+    (8, 64, 16, 512, 100), (2, 64, 8, 300, 45)])
+def test_transform_matches_push_brute_force(nbits, nchans, ndm, nsamps, maxd):
+    rng = np.random.default_rng(nbits * 1000 + nchans)
+    codes, table = _random_case(rng, nsamps, nchans, nbits, ndm, maxd)
+    got = oracle.dedisperse(synth.pack(codes, nbits), nsamps, nchans, nbits, table)
+    want = _push_brute_force(codes, table)
+    assert got.shape == want.shape
+    assert np.array_equal(got.astype(np.int64), want)
+
+
+@pytest.mark.parametrize("nbits", [2, 8])
+def test_impulse_response_recovers_every_delay(nbits):
+    """x = 1 at (t*, c*) only: out[d][t] = 1 exactly where t + delay[d][c*] = t*."""
+    nchans, ndm, nsamps = 8, 12, 160
+    rng = np.random.default_rng(7 + nbits)
+    _, table = _random_case(rng, nsamps, nchans, nbits, ndm, 40)
+    nout = nsamps - int(table.max())
+    for c in range(nchans):
+        for ts in (40, 77, 159):
+            codes = np.zeros((nsamps, nchans), dtype=np.uint8)
+            codes[ts, c] = 1
+            out = oracle.dedisperse(synth.pack(codes, nbits), nsamps, nchans, nbits, table)
+            want = np.zeros_like(out)
+            for d in range(ndm):
+                t = ts - table[d, c]
+                if 0 <= t < nout:
+                    want[d, t] = 1
+            assert np.array_equal(out, want), (c, ts)
+
+
+def test_linearity():
+    nsamps, nchans, ndm, nbits = 300, 16, 8, 8
+    rng = np.random.default_rng(3)
+    x = rng.integers(0, 128, size=(nsamps, nchans), dtype=np.uint8)
+    y = rng.integers(0, 128, size=(nsamps, nchans), dtype=np.uint8)
+    _, table = _random_case(rng, nsamps, nchans, nbits, ndm, 60)
+    f = lambda a: oracle.dedisperse(synth.pack(a, nbits), nsamps, nchans, nbits, table).astype(np.int64)
+    assert np.array_equal(f(x + y), f(x) + f(y))
+
+
+def test_time_shift_equivariance():
+    nsamps, nchans, ndm, nbits, s = 400, 32, 8, 2, 37
+    rng = np.random.default_rng(4)
+    codes, table = _random_case(rng, nsamps, nchans, nbits, ndm, 90)
+    full = oracle.dedisperse(synth.pack(codes, nbits), nsamps, nchans, nbits, table)
+    shifted = oracle.dedisperse(synth.pack(codes[s:], nbits), nsamps - s, nchans, nbits, table)
+    assert np.array_equal(shifted, full[:, s:])
+
+
+@pytest.mark.parametrize("nbits,nchans", [(2, 64), (8, 48)])
+def test_dm_zero_row_is_channel_sum(nbits, nchans):
+    b_rng = np.random.default_rng(5)
+    nsamps = 700
+    codes = b_rng.integers(0, 256 if nbits == 8 else 4, size=(nsamps, nchans), dtype=np.uint8)
+    dms = synth.dm_list_linear(8, 300.0)
+    table, mx = oracle.delay_table(nchans, 64e-6, 1500.0, -1.0, dms)
+    out = oracle.dedisperse(synth.pack(codes, nbits), nsamps, nchans, nbits, table)
+    assert np.array_equal(out[0], codes.sum(axis=1, dtype=np.uint32)[: nsamps - mx])
+
+
+def test_single_channel_is_copy():
+    nsamps = 100
+    codes = np.random.default_rng(6).integers(0, 256, size=(nsamps, 1), dtype=np.uint8)
+    table, _ = oracle.delay_table(1, 64e-6, 1500.0, -1.0, np.array([0.0, 5.0, 500.0]))
+    out = oracle.dedisperse(codes, nsamps, 1, 8, table)
+    for d in range(3):
+        assert np.array_equal(out[d], codes[:, 0])
+
+
+@pytest.mark.parametrize("nbits,k,nchans", [(8, 255, 4096), (8, 7, 100), (2, 3, 1024)])
+def test_constant_input(nbits, k, nchans):
+    nsamps = 64
+    codes = np.full((nsamps, nchans), k, dtype=np.uint8)
+    rng = np.random.default_rng(8)
+    table = rng.integers(0, 20, size=(4, nchans)).astype(np.int32)
+    out = oracle.dedisperse(synth.pack(codes, nbits), nsamps, nchans, nbits, table)
+    assert np.all(out == k * nchans)
+
+
+def test_two_bit_decoding_against_numpy_packbits():
+    """Channel c of a 2-bit row sits at bits [2(c%4), 2(c%4)+1] of byte c/4."""
+    nsamps, nchans = 40, 16
+    rng = np.random.default_rng(9)
+    zero = np.zeros((1, nchans), dtype=np.int32)
+    for c in range(nchans):
+        codes = np.zeros((nsamps, nchans), dtype=np.uint8)
+        codes[:, c] = rng.integers(0, 4, size=nsamps)
+        # bit k of the row bit-string is bit (k % 2) of channel k // 2's code
+        bits = np.stack([(codes >> 0) & 1, (codes >> 1) & 1], axis=2).reshape(nsamps, 2 * nchans)
+        packed = np.packbits(bits.astype(np.uint8), axis=1, bitorder="little")
+        assert np.array_equal(packed, synth.pack(codes, 2))
+        out = oracle.dedisperse(packed, nsamps, nchans, 2, zero)
+        assert np.array_equal(out[0], codes[:, c]), c
+
+
+def test_points_agree_with_full_transform():
+    nsamps, nchans, ndm, nbits = 600, 64, 16, 2
+    rng = np.random.default_rng(10)
+    codes, table = _random_case(rng, nsamps, nchans, nbits, ndm, 120)
+    packed = synth.pack(codes, nbits)
+    full = oracle.dedisperse(packed, nsamps, nchans, nbits, table)
+    d = rng.integers(0, ndm, size=200)
+    t = rng.integers(0, nsamps - 120, size=200)
+    pts = oracle.dedisperse_points(packed, nsamps, nchans, nbits, table, d, t)
+    assert np.array_equal(pts, full[d, t])
+
+
+def test_too_few_samples_rejected():
+    codes = np.zeros((10, 4), dtype=np.uint8)
+    table = np.array([[0, 3, 6, 10]], dtype=np.int32)
+    with pytest.raises(oracle.OracleError):
+        oracle.dedisperse(codes, 10, 4, 8, table)
+
+
+def test_tiny_pulse_lands_at_injected_trial_and_time():
+    """A pulse at DM 50 (trial 16), t0 = 1000 peaks at exactly (16, 1000)."""
+    b = synth.tiny_beam()
+    table, mx = oracle.delay_table(b.nchans, b.dt, b.f_top, b.df, b.dms)
+    assert mx == 250
+    b.inject(lambda i: table[i])
+    out = oracle.dedisperse(b.packed(), b.nsamps, b.nchans, b.nbits, table)
+    assert out.shape == (32, 4096 - 250)
+    assert np.unravel_index(int(out.argmax()), out.shape) == (16, 1000)
+
+
+def test_two_bit_pulses_land_at_injected_trials_and_times():
+    b = synth.survey_beam(seed=21, nsamps=1 << 14, nchans=256, ndm=32, npulses=3,
+                          max_delay_hint=6000)
+    b.dms = synth.dm_list_linear(32, 400.0)
+    table, mx = oracle.delay_table(b.nchans, b.dt, b.f_top, b.df, b.dms)
+    for p in b.pulses:
+        p.t0 = min(p.t0, b.nsamps - mx - 1)
+    b.inject(lambda i: table[i])
+    out = oracle.dedisperse(b.packed(), b.nsamps, b.nchans, b.nbits, table).astype(np.int64)
+    for p in b.pulses:
+        # each pulse is the maximum of its own neighbourhood in (DM, t)
+        d0, t0 = p.dm_index, p.t0
+        lo, hi = max(0, t0 - 64), min(out.shape[1], t0 + 65)
+        win = out[:, lo:hi]
+        dd, tt = np.unravel_index(int(win.argmax()), win.shape)
+        assert (dd, tt + lo) == (d0, t0), (p, dd, tt + lo)
