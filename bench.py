@@ -1,0 +1,199 @@
+"""Benchmark: direct incoherent dedispersion of one survey-shaped beam on one GPU.
+
+Workload (one "step" = one whole transform of one beam, the full hot path):
+2-bit packed time-major filterbank, 1024 channels, 2^19 samples of 64 us
+(33.6 s), f_top 1581.8 MHz, df -0.390625 MHz, 1024 trial DMs in [0, 1000)
+pc cm^-3, uint32 output [1024][2^19 - 20456].  Seeded synthetic levels with
+8 injected pulses.  The input is resident in HBM before timing starts.
+
+Prints one JSON line.  `value` is dedispersed outputs (DM x sample) per second
+over the timed steps; the dominant kernel's duration is measured per launch
+with HIP events on the stream it runs on.  The CPU oracle is timed on a
+bounded DM subset of the same beam (`cpu_baseline`).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X peaks used for the roofline: 256 CUs x 64 int32 lane-adds/clock x
+# 2.4 GHz (one VALU add per lane per clock) and 8 TB/s HBM3E.
+INT_ADD_PEAK_TADDS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nsamps", type=int, default=1 << 19)
+    ap.add_argument("--no-tune", action="store_true", help="use the default tile shape")
+    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate CPU time budget for the oracle baseline")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="HBM bytes per launch measured by rocprofv3 counters, if present")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def cpu_baseline(packed, nsamps, nchans, nbits, table, budget_s):
+    """Time the oracle on the first k DM rows of the beam (whole time range)."""
+    import oracle
+    ndm = table.shape[0]
+    nout = nsamps - int(table.max())
+    mx = int(table.max())
+    # calibrate on one DM row, then size the sample to the budget
+    t0 = time.perf_counter()
+    oracle.dedisperse(packed, nsamps, nchans, nbits, table[:1], max_delay=mx)
+    one = time.perf_counter() - t0
+    threads = oracle.max_threads()
+    k = int(max(threads, min(ndm, budget_s / max(one, 1e-6))))
+    k = max(1, min(ndm, (k // threads) * threads or threads))
+    t0 = time.perf_counter()
+    oracle.dedisperse(packed, nsamps, nchans, nbits, table[:k], max_delay=mx)
+    dt = time.perf_counter() - t0
+    return {"value": k * nout / dt, "unit": "outputs/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {k} of {ndm} DM rows x all {nout} output samples "
+                      f"({k * nout * nchans:.3g} channel-adds) in {dt:.2f} s",
+            "adds_per_s": k * nout * nchans / dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(beams or time ranges would be sharded across GPUs with no exchange "
+              "beyond a max_delay halo).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1201_5380_amd import Plan, synth
+
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = 1 << 30
+        a = torch.empty(n, dtype=torch.uint8, device=dev)
+        b = torch.empty(n, dtype=torch.uint8, device=dev)
+        a.fill_(1)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "launches": 5}))
+        return
+
+    beam = synth.survey_beam(nsamps=args.nsamps)
+    plan = Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(beam.dms)
+    table = plan.delay_table()
+    beam.inject(lambda i: table[i])
+    packed = beam.packed()
+    nsamps, nchans, ndm = beam.nsamps, beam.nchans, len(beam.dms)
+    mx = plan.max_delay
+    nout = nsamps - mx
+
+    inp = torch.from_numpy(packed.reshape(-1)).to(dev)
+    out = torch.empty((ndm, nout), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    tune_ms = None
+    if not args.no_tune:
+        tune_ms = plan.tune(inp, out, nsamps, cache_path=args.tune_cache)
+    cfg = plan.tile_config()
+
+    for _ in range(args.warmup):
+        plan.execute(inp, nsamps, out=out)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        plan.execute(inp, nsamps, out=out, stream=stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    kern_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+
+    # sanity: every injected pulse peaks at its trial and time
+    got = out.cpu().numpy().view(np.uint32)
+    pulses_ok = True
+    for p in beam.pulses:
+        lo, hi = max(0, p.t0 - 100), min(nout, p.t0 + 101)
+        win = got[:, lo:hi]
+        dd, tt = np.unravel_index(int(win.argmax()), win.shape)
+        pulses_ok &= (int(dd), int(tt) + lo) == (p.dm_index, p.t0)
+
+    outputs = ndm * nout
+    adds = outputs * nchans
+    mean_ms = float(kern_ms.mean())
+    ms_per_step = wall * 1e3 / args.steps
+    achieved_tadds = adds / (mean_ms * 1e-3) / 1e12
+    alg_bytes = nsamps * nchans * beam.nbits // 8 + 4 * outputs + 4 * ndm * nchans
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            if tj.get("workload") == beam.name and tj.get("tile") == cfg:
+                traffic = tj.get("hbm_bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    result = {
+        "metric": "dedispersed outputs/s (DM x sample)",
+        "value": outputs / (ms_per_step * 1e-3),
+        "unit": "outputs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"survey beam: 2-bit, {nchans} ch, {nsamps} samples x 64 us, "
+                        f"{ndm} DMs in [0, 1000), f_top 1581.8 MHz, df -0.390625 MHz",
+            "nsamps": nsamps, "nchans": nchans, "nbits": beam.nbits, "ndm": ndm,
+            "max_delay": mx, "nout": nout, "tile": cfg,
+        },
+        "kernel_ms": {"mean": mean_ms, "median": float(np.median(kern_ms)),
+                      "p5": float(np.percentile(kern_ms, 5)),
+                      "p95": float(np.percentile(kern_ms, 95))},
+        "channel_adds_per_s": adds / (mean_ms * 1e-3),
+        "realtime_factor": nsamps * beam.dt / (mean_ms * 1e-3),
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved_tadds,
+            "peak": INT_ADD_PEAK_TADDS,
+            "unit": "Tadd/s",
+            "frac": achieved_tadds / INT_ADD_PEAK_TADDS,
+            "traffic": traffic,
+        },
+        "hbm_algorithmic_GBs": alg_bytes / (mean_ms * 1e-3) / 1e9,
+        "pulses_recovered": bool(pulses_ok),
+        "tune_best_ms": tune_ms,
+        "device": torch.cuda.get_device_name(0),
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(packed, nsamps, nchans, beam.nbits, table,
+                                              args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,240 @@
+/*
+ * dedisp.h -- C ABI of the MI355X (gfx950) direct incoherent dedispersion
+ * library.
+ *
+ * The transform (Barsdell, Bailes, Barnes & Fluke 2012, "Accelerating
+ * incoherent dedispersion", Section 2.1, eq. direct):
+ *
+ *     out[d][t] = sum_{c=0}^{nchans-1} in[t + delay[d][c]][c]
+ *
+ * with the per-channel delay of the Section 2.1 delay equations,
+ *
+ *     DeltaT[c]   = (k_DM / dt) * (1/(f_top + c*df)^2 - 1/f_top^2)
+ *     delay[d][c] = round(DM[d] * DeltaT[c])        (half away from zero)
+ *
+ * k_DM = 4.148808e3 MHz^2 pc^-1 cm^3 s (Section 1), dt in seconds,
+ * frequencies in MHz, DM in pc cm^-3.  Delays are computed once on the host
+ * in IEEE binary64 in exactly that order and uploaded as an int32 table; the
+ * GPU never recomputes them.  Sums are exact 32-bit unsigned integers.
+ *
+ * Conventions shared by every entry point:
+ *   - Input ("filterbank"): nsamps rows, one per time sample, each
+ *     nchans*nbits/8 bytes, channel fastest (time-major).  nbits is 2 or 8.
+ *     2-bit: channel c is bits [2*(c%4), 2*(c%4)+1] of byte c/4 of its row.
+ *     Samples are raw unsigned codes (0..3 or 0..255), summed as they are.
+ *   - Channel 0 is the top of the band (frequency f_top, zero delay);
+ *     df < 0 so delays grow with channel index.
+ *   - Output: ndm rows of uint32, row d at out + d*out_row_stride elements
+ *     (out_row_stride = 0 means nsamps - max_delay).  Only fully covered
+ *     outputs exist: t in [0, nsamps - max_delay).
+ *   - Device pointers are HIP device addresses owned by the caller; they must
+ *     stay valid until the work enqueued on `stream` has finished.  Host
+ *     pointers are only read during the call.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     Every compute call is asynchronous on that stream and returns as soon
+ *     as the work is enqueued.
+ *   - Every argument is validated on the host before any HIP call; an
+ *     invalid call changes nothing and returns an error code.  No C++
+ *     exception crosses this interface.
+ *   - A plan, stream or batch is used by one host thread at a time.
+ */
+#ifndef DEDISP_H
+#define DEDISP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dedisp_plan_s*   dedisp_plan;    /* observing set-up + DM list + device tables */
+typedef struct dedisp_stream_s* dedisp_stream;  /* one unbounded input stream (owns its history) */
+typedef struct dedisp_batch_s*  dedisp_batch;   /* a fixed set of beams run as one launch */
+typedef int dedisp_status;
+
+enum {
+    DEDISP_OK                  = 0,
+    DEDISP_ERR_INVALID_ARG     = -1,  /* a null pointer, size or parameter out of range */
+    DEDISP_ERR_NO_DM_LIST      = -2,  /* compute requested before dedisp_set_dm_list */
+    DEDISP_ERR_TOO_FEW_SAMPLES = -3,  /* nsamps <= max_delay: no output is fully covered */
+    DEDISP_ERR_OOM             = -4,  /* a device or host allocation failed */
+    DEDISP_ERR_HIP             = -5,  /* a HIP runtime call failed; see dedisp_last_error */
+    DEDISP_ERR_UNSUPPORTED     = -6   /* valid request this build cannot serve */
+};
+
+/* Human-readable name of a status code (static storage). */
+const char* dedisp_status_string(dedisp_status status);
+
+/* Text of the most recent error on the calling host thread (static,
+ * thread-local storage; "" if none).  Holds the HIP error string after
+ * DEDISP_ERR_HIP. */
+const char* dedisp_last_error(void);
+
+/* ---------------------------------------------------------------- plans */
+
+/* Create a plan for `nchans` channels of `nbits`-bit samples taken every
+ * `dt_s` seconds, channel 0 at `f_top_mhz`, channel spacing `df_mhz`
+ * (Section 2.1: the band start nu_0 and channel spacing Delta nu).
+ * Host-only: no HIP call is made.
+ * Errors: INVALID_ARG if out == NULL, nchans <= 0, nbits not in {2, 8},
+ * nchans*nbits not a multiple of 8, dt_s <= 0, f_top_mhz <= 0, df_mhz >= 0,
+ * f_top_mhz + (nchans-1)*df_mhz <= 0, or any value not finite.
+ * The caller owns *out and releases it with dedisp_plan_destroy. */
+dedisp_status dedisp_plan_create(dedisp_plan* out, int nchans, double dt_s,
+                                 double f_top_mhz, double df_mhz, int nbits);
+
+/* Release a plan and its device tables (NULL is ignored).  Work already
+ * enqueued that uses the plan must have finished. */
+void dedisp_plan_destroy(dedisp_plan plan);
+
+/* Set the trial DMs (the DM(d) array of Section 2.1), `ndm` values in
+ * pc cm^-3, any order, copied from host memory.  Computes the delay table on
+ * the host; the device copy is made by the next compute call.
+ * Errors: INVALID_ARG if dms == NULL, ndm <= 0, a DM is negative or not
+ * finite, or a delay does not fit in int32. */
+dedisp_status dedisp_set_dm_list(dedisp_plan plan, const double* dms, int ndm);
+
+/* Plan queries (host-only).  NO_DM_LIST before dedisp_set_dm_list for the
+ * DM-dependent ones. */
+dedisp_status dedisp_get_nchans(dedisp_plan plan, int* nchans);
+dedisp_status dedisp_get_nbits(dedisp_plan plan, int* nbits);
+dedisp_status dedisp_get_dm_count(dedisp_plan plan, int* ndm);
+dedisp_status dedisp_get_max_delay(dedisp_plan plan, int* max_delay);
+
+/* Copy the delay table, row-major int32 [ndm][nchans] (row = DM), to host
+ * memory `host_out` of at least ndm*nchans elements. */
+dedisp_status dedisp_get_delay_table(dedisp_plan plan, int32_t* host_out);
+
+/* The transform over one resident block of input.
+ * d_in: device, nsamps rows of the input layout above.
+ * d_out: device, ndm rows of out_row_stride (0 = nsamps - max_delay)
+ * uint32 elements; only t < nsamps - max_delay is written.
+ * Errors: INVALID_ARG (null pointer, stride too small), NO_DM_LIST,
+ * TOO_FEW_SAMPLES (nsamps <= max_delay), OOM, HIP. */
+dedisp_status dedisp_execute(dedisp_plan plan, const void* d_in, size_t nsamps,
+                             uint32_t* d_out, size_t out_row_stride, void* stream);
+
+/* ----------------------------------------------------- kernel selection */
+
+/* Shape of the LDS-tiled kernel: `waves` wavefronts per workgroup share one
+ * staged time tile; each wave sums `dms_per_wave` neighbouring trial DMs;
+ * each lane owns 4*`words_per_lane` consecutive output samples (so a tile is
+ * 256*words_per_lane samples long); `chunk_chans` channels are staged in LDS
+ * at a time.  kind = 0 is the LDS-tiled kernel, kind = 1 the untiled
+ * fallback (no LDS; used automatically when a tile would not fit). */
+typedef struct {
+    int kind;
+    int waves;
+    int dms_per_wave;
+    int words_per_lane;
+    int chunk_chans;
+} dedisp_tile_config;
+
+/* Number of tile shapes compiled into this library, and the i-th one. */
+int dedisp_tile_config_count(void);
+dedisp_status dedisp_tile_config_get(int index, dedisp_tile_config* cfg);
+
+/* Choose the tile shape used by later compute calls on this plan
+ * (must be one of the compiled shapes; chunk_chans a multiple of 4 in
+ * [4, 256]).  Host-only.  INVALID_ARG for an unknown shape. */
+dedisp_status dedisp_set_tile_config(dedisp_plan plan, const dedisp_tile_config* cfg);
+
+/* The tile shape the next compute call on `nsamps` samples will use
+ * (after falling back if the chosen one does not fit in LDS). */
+dedisp_status dedisp_get_tile_config(dedisp_plan plan, dedisp_tile_config* cfg);
+
+/* Autotune: time every compiled shape on the given input/output buffers
+ * (the output is overwritten with a valid result), keep the fastest on the
+ * plan, and if `cache_path` is not NULL read/update a JSON cache keyed by
+ * (nbits, nchans, ndm, max_delay, nsamps bucket).  Synchronises `stream`.
+ * `best_ms` (nullable) receives the best time of one call. */
+dedisp_status dedisp_tune(dedisp_plan plan, const void* d_in, size_t nsamps,
+                          uint32_t* d_out, size_t out_row_stride, void* stream,
+                          const char* cache_path, float* best_ms);
+
+/* ------------------------------------------------------------- streams */
+
+/* An unbounded input stream: each push appends a chunk of input rows and
+ * produces every output that the data seen so far fully covers, so that the
+ * concatenated outputs of all pushes equal dedisp_execute on the
+ * concatenated input (overlap-save over the time axis).  The stream keeps the
+ * last max_delay input rows on the device as its history.
+ * The plan must have a DM list and must outlive the stream.
+ * Allocates device memory for the history.  Errors: INVALID_ARG,
+ * NO_DM_LIST, OOM, HIP. */
+dedisp_status dedisp_stream_create(dedisp_plan plan, dedisp_stream* out);
+void dedisp_stream_destroy(dedisp_stream s);
+
+/* Push `nsamps` rows at device address d_chunk.  *n_out receives the number
+ * of new output samples per DM written to d_out (rows of out_row_stride
+ * elements; 0 = n_out): while the stream has seen at most max_delay rows it
+ * is 0 and the rows are only kept; after that it is nsamps (the first push
+ * past max_delay yields total - max_delay).  d_out may be NULL only when
+ * *n_out will be 0.  The caller must not reuse d_chunk before the stream's
+ * work on `stream` has finished.  Errors: INVALID_ARG, OOM, HIP. */
+dedisp_status dedisp_stream_push(dedisp_stream s, const void* d_chunk, size_t nsamps,
+                                 uint32_t* d_out, size_t out_row_stride, size_t* n_out,
+                                 void* stream);
+
+/* Several streams' pushes as one launch (the continuous-batching step of a
+ * serving loop).  Arrays of length n; streams must be distinct and share
+ * nothing but, possibly, their plans.  Same per-stream semantics as
+ * dedisp_stream_push. */
+dedisp_status dedisp_stream_push_many(dedisp_stream* streams, const void* const* d_chunks,
+                                      const size_t* nsamps, uint32_t* const* d_outs,
+                                      const size_t* out_row_strides, size_t* n_outs, int n,
+                                      void* stream);
+
+/* Rows currently held as history, and total rows pushed since creation or
+ * the last reset / set_history. */
+dedisp_status dedisp_stream_get_state(dedisp_stream s, size_t* history_rows,
+                                      uint64_t* total_rows);
+
+/* Checkpoint / restore of the history (synchronous host copies).
+ * get: host_buf of at least history_rows * row_bytes bytes; *nsamps receives
+ * history_rows.  set: replaces the history with nsamps <= max_delay rows
+ * (the stream then behaves as if exactly those rows had been pushed, with
+ * total = nsamps ... unless nsamps == max_delay, which marks it as primed). */
+dedisp_status dedisp_stream_get_history(dedisp_stream s, void* host_buf, size_t* nsamps);
+dedisp_status dedisp_stream_set_history(dedisp_stream s, const void* host_buf, size_t nsamps,
+                                        uint64_t total_rows);
+dedisp_status dedisp_stream_reset(dedisp_stream s);
+
+/* ------------------------------------------------------------- batches */
+
+/* One beam of a batch: its plan (observing set-up and DM list), resident
+ * input and output.  Beams borrow plans and buffers, which must outlive the
+ * batch; different beams may differ in nchans, nbits, nsamps and DM list. */
+typedef struct {
+    dedisp_plan plan;
+    const void* d_in;
+    size_t      nsamps;
+    uint32_t*   d_out;
+    size_t      out_row_stride;   /* elements; 0 = nsamps - max_delay */
+} dedisp_beam;
+
+/* Build a batch: pick a tile shape per beam (from `tune_cache_path` when it
+ * holds the beam's key, else by timing the candidates on the beam's own
+ * buffers and recording the result there), upload a device descriptor table
+ * and a flat work list, and capture one persistent launch into a HIP graph.
+ * Uses `stream` for tuning and capture and synchronises it.
+ * Errors: INVALID_ARG, NO_DM_LIST, TOO_FEW_SAMPLES, OOM, HIP. */
+dedisp_status dedisp_batch_create(const dedisp_beam* beams, int nbeams,
+                                  const char* tune_cache_path, void* stream,
+                                  dedisp_batch* out);
+
+/* Run every beam of the batch: one graph launch on `stream`. */
+dedisp_status dedisp_batch_execute(dedisp_batch b, void* stream);
+
+/* Run every beam with one persistent launch but without the graph (for
+ * comparison and for callers that re-point buffers between runs). */
+dedisp_status dedisp_batch_execute_direct(dedisp_batch b, void* stream);
+
+void dedisp_batch_destroy(dedisp_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEDISP_H */

@@ -1,0 +1,244 @@
+"""Python binding of the C ABI in include/dedisp.h.
+
+Thin wrappers that marshal torch tensors (device memory) and streams into the
+library's plain-pointer entry points; every step of the transform runs in the
+HIP kernels.  Output buffers are torch.int32 tensors holding the library's
+uint32 sums (every sum is below 2^31: at most 255 * nchans).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import numpy as np
+
+from . import _native
+from ._native import TileConfig, check, lib
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(int(t.data_ptr()))
+
+
+def tile_configs():
+    """Every tile shape compiled into the library."""
+    out = []
+    for i in range(lib().dedisp_tile_config_count()):
+        c = TileConfig()
+        check(lib().dedisp_tile_config_get(i, ctypes.byref(c)), "dedisp_tile_config_get")
+        out.append(c.as_dict())
+    return out
+
+
+class Plan:
+    """Observing set-up, DM list and device delay tables (``dedisp_plan``)."""
+
+    def __init__(self, nchans: int, dt: float, f_top: float, df: float, nbits: int):
+        self._h = ctypes.c_void_p()
+        check(lib().dedisp_plan_create(ctypes.byref(self._h), int(nchans), float(dt),
+                                       float(f_top), float(df), int(nbits)),
+              "dedisp_plan_create")
+        self.nchans, self.nbits = int(nchans), int(nbits)
+        self.dt, self.f_top, self.df = float(dt), float(f_top), float(df)
+        self.ndm = 0
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().dedisp_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def row_bytes(self) -> int:
+        return self.nchans * self.nbits // 8
+
+    def set_dm_list(self, dms: Sequence[float]):
+        arr = np.ascontiguousarray(dms, dtype=np.float64)
+        check(lib().dedisp_set_dm_list(self._h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       int(arr.shape[0])), "dedisp_set_dm_list")
+        self.ndm = int(arr.shape[0])
+        return self
+
+    @property
+    def max_delay(self) -> int:
+        v = ctypes.c_int()
+        check(lib().dedisp_get_max_delay(self._h, ctypes.byref(v)), "dedisp_get_max_delay")
+        return int(v.value)
+
+    def delay_table(self) -> np.ndarray:
+        out = np.zeros((self.ndm, self.nchans), dtype=np.int32)
+        check(lib().dedisp_get_delay_table(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+              "dedisp_get_delay_table")
+        return out
+
+    def set_tile_config(self, cfg: dict):
+        c = TileConfig(**cfg)
+        check(lib().dedisp_set_tile_config(self._h, ctypes.byref(c)), "dedisp_set_tile_config")
+
+    def tile_config(self) -> dict:
+        c = TileConfig()
+        check(lib().dedisp_get_tile_config(self._h, ctypes.byref(c)), "dedisp_get_tile_config")
+        return c.as_dict()
+
+    def nout(self, nsamps: int) -> int:
+        return int(nsamps) - self.max_delay
+
+    def alloc_output(self, nsamps: int, device="cuda"):
+        import torch
+        return torch.empty((self.ndm, self.nout(nsamps)), dtype=torch.int32, device=device)
+
+    def _check_input(self, inp, nsamps):
+        if nsamps is None:
+            nsamps = inp.numel() // self.row_bytes
+        if inp.numel() < nsamps * self.row_bytes:
+            raise ValueError("input holds fewer than nsamps rows")
+        if not inp.is_contiguous():
+            raise ValueError("input must be contiguous")
+        return int(nsamps)
+
+    def execute(self, inp, nsamps: int | None = None, out=None, out_row_stride: int = 0,
+                stream=None):
+        """Dedisperse ``nsamps`` rows of device tensor ``inp``; returns the output tensor."""
+        nsamps = self._check_input(inp, nsamps)
+        if out is None:
+            out = self.alloc_output(nsamps, inp.device)
+            out_row_stride = 0
+        check(lib().dedisp_execute(self._h, _ptr(inp), nsamps, _ptr(out), int(out_row_stride),
+                                   _stream_handle(stream)), "dedisp_execute")
+        return out
+
+    def tune(self, inp, out, nsamps: int | None = None, out_row_stride: int = 0,
+             cache_path: str | None = None, stream=None) -> float:
+        nsamps = self._check_input(inp, nsamps)
+        ms = ctypes.c_float()
+        check(lib().dedisp_tune(self._h, _ptr(inp), nsamps, _ptr(out), int(out_row_stride),
+                                _stream_handle(stream),
+                                cache_path.encode() if cache_path else None, ctypes.byref(ms)),
+              "dedisp_tune")
+        return float(ms.value)
+
+
+class Stream:
+    """An unbounded input stream with device-resident history (``dedisp_stream``)."""
+
+    def __init__(self, plan: Plan):
+        self.plan = plan
+        self._h = ctypes.c_void_p()
+        check(lib().dedisp_stream_create(plan.handle, ctypes.byref(self._h)), "dedisp_stream_create")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().dedisp_stream_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, chunk, out=None, out_row_stride: int = 0, nsamps: int | None = None,
+             stream=None):
+        """Push a device chunk; returns (n_out, out) where out[:, :n_out] is new output."""
+        if nsamps is None:
+            nsamps = chunk.numel() // self.plan.row_bytes
+        n_out = ctypes.c_size_t()
+        outp = _ptr(out) if out is not None else ctypes.c_void_p()
+        check(lib().dedisp_stream_push(self._h, _ptr(chunk), int(nsamps), outp,
+                                       int(out_row_stride), ctypes.byref(n_out),
+                                       _stream_handle(stream)), "dedisp_stream_push")
+        return int(n_out.value), out
+
+    def state(self):
+        h = ctypes.c_size_t()
+        t = ctypes.c_uint64()
+        check(lib().dedisp_stream_get_state(self._h, ctypes.byref(h), ctypes.byref(t)),
+              "dedisp_stream_get_state")
+        return int(h.value), int(t.value)
+
+    def get_history(self) -> np.ndarray:
+        rows, _ = self.state()
+        buf = np.zeros(max(1, rows * self.plan.row_bytes), dtype=np.uint8)
+        n = ctypes.c_size_t()
+        check(lib().dedisp_stream_get_history(self._h, buf.ctypes.data_as(ctypes.c_void_p),
+                                              ctypes.byref(n)), "dedisp_stream_get_history")
+        return buf[: int(n.value) * self.plan.row_bytes].reshape(int(n.value), self.plan.row_bytes)
+
+    def set_history(self, rows: np.ndarray, total_rows: int):
+        rows = np.ascontiguousarray(rows, dtype=np.uint8)
+        n = rows.shape[0] if rows.ndim == 2 else rows.size // self.plan.row_bytes
+        check(lib().dedisp_stream_set_history(self._h, rows.ctypes.data_as(ctypes.c_void_p), int(n),
+                                              int(total_rows)), "dedisp_stream_set_history")
+
+    def reset(self):
+        check(lib().dedisp_stream_reset(self._h), "dedisp_stream_reset")
+
+
+def push_many(streams: Sequence[Stream], chunks, outs, out_row_strides=None, stream=None):
+    """Push one chunk into each of several streams with a single launch; returns n_outs."""
+    n = len(streams)
+    hs = (ctypes.c_void_p * n)(*[s.handle.value for s in streams])
+    cs = (ctypes.c_void_p * n)(*[int(c.data_ptr()) for c in chunks])
+    ns = (ctypes.c_size_t * n)(*[c.numel() // s.plan.row_bytes for c, s in zip(chunks, streams)])
+    os_ = (ctypes.c_void_p * n)(*[int(o.data_ptr()) if o is not None else 0 for o in outs])
+    st = (ctypes.c_size_t * n)(*(out_row_strides or [0] * n))
+    nouts = (ctypes.c_size_t * n)()
+    check(lib().dedisp_stream_push_many(hs, cs, ns, os_, st, nouts, n, _stream_handle(stream)),
+          "dedisp_stream_push_many")
+    return [int(v) for v in nouts]
+
+
+class Batch:
+    """A fixed set of beams run as one persistent, graph-captured launch (``dedisp_batch``)."""
+
+    def __init__(self, beams, tune_cache_path: str | None = None, stream=None):
+        """``beams``: sequence of (plan, input tensor, nsamps, output tensor, out_row_stride)."""
+        n = len(beams)
+        arr = (_native.BeamStruct * n)()
+        self._keep = []
+        for i, (plan, inp, nsamps, out, stride) in enumerate(beams):
+            arr[i].plan = plan.handle.value
+            arr[i].d_in = int(inp.data_ptr())
+            arr[i].nsamps = int(nsamps)
+            arr[i].d_out = int(out.data_ptr())
+            arr[i].out_row_stride = int(stride)
+            self._keep.append((plan, inp, out))
+        self._h = ctypes.c_void_p()
+        check(lib().dedisp_batch_create(arr, n, tune_cache_path.encode() if tune_cache_path else None,
+                                        _stream_handle(stream), ctypes.byref(self._h)),
+              "dedisp_batch_create")
+
+    def execute(self, stream=None, graph: bool = True):
+        fn = lib().dedisp_batch_execute if graph else lib().dedisp_batch_execute_direct
+        check(fn(self._h, _stream_handle(stream)), "dedisp_batch_execute")
+
+    def close(self):
+        if self._h:
+            lib().dedisp_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

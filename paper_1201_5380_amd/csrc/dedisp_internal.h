@@ -1,0 +1,68 @@
+// Internal interface between the host library (dedisp_api.cpp) and the
+// gfx950 kernels (dedisp_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace dedisp {
+
+// One beam (or one stream push) as the kernels see it.  The input is a
+// virtual concatenation of two row segments so that a stream's resident
+// history and a new chunk can be summed without copying them together:
+// rows [0, n0) are at in0, rows [n0, nsamps) at in1.
+struct BeamDesc {
+    const uint8_t* in0;
+    const uint8_t* in1;
+    long long n0;
+    long long nsamps;
+    long long nout;           // nsamps - max_delay
+    uint32_t* out;
+    long long out_stride;     // elements between DM rows
+    const int32_t* rel;       // [nblocks*DB][nchans] delay minus window start
+    const int32_t* base;      // [nblocks][nchans/4] window start per 4-channel group
+    const int32_t* table;     // [ndm][nchans] full delay table (untiled kernel)
+    int nchans;
+    int row_bytes;
+    int ndm;
+    int nblocks;              // ceil(ndm / DB)
+    int ntiles;               // ceil(nout / tile length)
+    int rw;                   // LDS row length in 32-bit words
+    int flush_every;          // chunks between packed-lane flushes
+    int shape;                // index into the compiled shape list
+    int pad_;
+    long long work_begin;     // first global work item of this beam
+};
+
+// A compiled kernel shape.
+struct Shape {
+    int kind;       // 0 = LDS-tiled, 1 = untiled
+    int nbits;
+    int waves;
+    int dpw;        // DMs per wave
+    int m;          // 32-bit words per lane (4 samples each)
+    int cc;         // channels staged per chunk
+    int pi;         // staging slabs: window length <= pi*waves*64 words
+};
+
+// Shapes compiled into the library (index = shape id).
+int shape_count();
+const Shape& shape_at(int i);
+
+// Largest dynamic LDS a workgroup may use on this device (bytes).
+constexpr int kMaxLdsBytes = 160 * 1024;
+
+// Enqueue the transform of one beam with the given shape.
+hipError_t launch_tiled(const BeamDesc& d, const Shape& s, int lds_bytes, hipStream_t st);
+hipError_t launch_untiled(const BeamDesc& d, int nbits, hipStream_t st);
+
+// Persistent launch over a device array of beam descriptors; every shape
+// used must have waves == kPersistentWaves.  counters: two device uint32
+// zeroed once at allocation; the kernel leaves them zero when it ends.
+constexpr int kPersistentWaves = 4;
+hipError_t launch_persistent(const BeamDesc* d_descs, int nbeams, long long total_work,
+                             unsigned int* d_counters, int lds_bytes, int grid,
+                             hipStream_t st);
+int persistent_max_grid(int lds_bytes);
+
+}  // namespace dedisp

@@ -28,3 +28,21 @@ def read_golden(name):
 @pytest.fixture(scope="session")
 def golden_paper():
     return read_golden("paper_values.txt")
+
+
+@pytest.fixture(scope="session")
+def native():
+    """The built library (built here only if nothing is built yet)."""
+    from paper_1201_5380_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_1201_5380_amd import build
+        build.build()
+    return _native.lib()
+
+
+@pytest.fixture(scope="session")
+def cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")

@@ -1,0 +1,230 @@
+"""GPU parity: the HIP kernels against the CPU oracle, bit for bit.
+
+Every test dedisperses seeded synthetic input on the GPU through the C ABI and
+compares with the oracle on the same bytes: whole outputs at sizes the
+oracle finishes in seconds (several time tiles, several DM blocks, ragged
+tails), and sampled outputs plus size-independent properties at the full
+survey-beam size the benchmark times.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1201_5380_amd import Plan, synth, tile_configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _to_gpu(arr, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(arr)).to(dev)
+
+
+def _out_np(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _run(plan, packed, nsamps, dev, cfg=None, stride=0):
+    import torch
+    if cfg is not None:
+        plan.set_tile_config(cfg)
+    inp = _to_gpu(packed.reshape(-1), dev)
+    nout = nsamps - plan.max_delay
+    if stride:
+        out = torch.full((plan.ndm, stride), -1, dtype=torch.int32, device=dev)
+        plan.execute(inp, nsamps, out=out, out_row_stride=stride)
+    else:
+        out = plan.execute(inp, nsamps)
+    torch.cuda.synchronize()
+    o = _out_np(out)
+    if stride:
+        assert np.all(o[:, nout:] == 0xFFFFFFFF), "wrote past nout"
+        o = o[:, :nout]
+    return o
+
+
+def _plan_for(beam):
+    return Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(beam.dms)
+
+
+def _configs_for(plan):
+    """Every compiled shape usable for this plan's bit depth (tiled ones that fit + untiled)."""
+    out, seen_untiled = [], False
+    for c in tile_configs():
+        if c["kind"] == 1:
+            if seen_untiled:
+                continue
+            seen_untiled = True
+        try:
+            plan.set_tile_config(c)
+        except Exception:
+            continue
+        got = plan.tile_config()
+        if c["kind"] == 1 or (got["kind"] == 0 and got["waves"] == c["waves"]
+                              and got["dms_per_wave"] == c["dms_per_wave"]
+                              and got["words_per_lane"] == c["words_per_lane"]
+                              and got["chunk_chans"] == c["chunk_chans"]):
+            out.append(c)
+    return out
+
+
+def test_tiny_every_shape_bit_exact(native, cuda):
+    b = synth.tiny_beam()
+    table, mx = oracle.delay_table(b.nchans, b.dt, b.f_top, b.df, b.dms)
+    b.inject(lambda i: table[i])
+    want = oracle.dedisperse(b.packed(), b.nsamps, b.nchans, b.nbits, table)
+    plan = _plan_for(b)
+    cfgs = _configs_for(plan)
+    assert len(cfgs) >= 3
+    for cfg in cfgs:
+        got = _run(plan, b.packed(), b.nsamps, cuda, cfg)
+        assert np.array_equal(got, want), cfg
+    assert np.unravel_index(int(got.argmax()), got.shape) == (16, 1000)
+
+
+@pytest.mark.parametrize("nbits,nchans,ndm,nsamps", [
+    (2, 1024, 64, 24576),      # survey band, 64 DMs over [0, 1000): 4 DM blocks, ragged tail
+    (2, 256, 40, 9000),        # ndm not a multiple of any DM block
+    (8, 512, 48, 12000),
+    (8, 1024, 33, 7000)])
+def test_survey_like_every_shape_bit_exact(native, cuda, nbits, nchans, ndm, nsamps):
+    rng = np.random.default_rng(nbits * 7 + nchans + ndm)
+    if nbits == 2:
+        codes = synth.two_bit_codes(rng, nsamps, nchans)
+    else:
+        codes = synth.eight_bit_noise(rng, nsamps, nchans, 128.0, 20.0)
+    df = -400.0 / nchans
+    dms = synth.dm_list_linear(ndm, 1000.0 * ndm / 64 if nsamps > 20000 else 300.0)
+    table, mx = oracle.delay_table(nchans, 64e-6, 1581.8, df, dms)
+    assert nsamps > mx
+    packed = synth.pack(codes, nbits)
+    want = oracle.dedisperse(packed, nsamps, nchans, nbits, table)
+    plan = Plan(nchans, 64e-6, 1581.8, df, nbits).set_dm_list(dms)
+    assert np.array_equal(plan.delay_table(), table)
+    cfgs = _configs_for(plan)
+    for cfg in cfgs:
+        if cfg["kind"] == 1 and nchans * ndm * nsamps > 5e8:
+            continue
+        got = _run(plan, packed, nsamps, cuda, cfg)
+        assert np.array_equal(got, want), cfg
+
+
+@pytest.mark.parametrize("nbits", [2, 8])
+def test_ragged_edges_and_strides(native, cuda, nbits):
+    nchans, ndm = 64, 7
+    rng = np.random.default_rng(11 + nbits)
+    dms = synth.dm_list_linear(ndm, 200.0)
+    plan = Plan(nchans, 64e-6, 1500.0, -1.0, nbits).set_dm_list(dms)
+    mx = plan.max_delay
+    table = plan.delay_table()
+    for nsamps in (mx + 1, mx + 3, mx + 4, mx + 1279, mx + 1281, mx + 5000):
+        maxc = 255 if nbits == 8 else 3
+        codes = rng.integers(0, maxc + 1, size=(nsamps, nchans), dtype=np.uint8)
+        packed = synth.pack(codes, nbits)
+        want = oracle.dedisperse(packed, nsamps, nchans, nbits, table)
+        for stride in (0, nsamps - mx + 3, nsamps - mx + 8):
+            got = _run(plan, packed, nsamps, cuda, None, stride)
+            assert np.array_equal(got, want), (nsamps, stride)
+
+
+def test_unsorted_and_repeated_dms(native, cuda):
+    nchans, nsamps = 256, 6000
+    rng = np.random.default_rng(12)
+    dms = rng.permutation(np.concatenate([synth.dm_list_linear(30, 150.0), [75.0, 75.0, 0.0]]))
+    plan = Plan(nchans, 64e-6, 1500.0, -0.5, 2).set_dm_list(dms)
+    table = plan.delay_table()
+    codes = synth.two_bit_codes(rng, nsamps, nchans)
+    packed = synth.pack(codes, 2)
+    want = oracle.dedisperse(packed, nsamps, nchans, 2, table)
+    assert plan.tile_config()["kind"] == 0
+    assert np.array_equal(_run(plan, packed, nsamps, cuda), want)
+
+
+def test_huge_dm_gap_uses_untiled_kernel(native, cuda):
+    nchans, nsamps = 64, 40000
+    dms = np.array([0.0, 5000.0, 10.0, 4000.0])
+    plan = Plan(nchans, 64e-6, 1500.0, -1.0, 8).set_dm_list(dms)
+    assert plan.tile_config()["kind"] == 1
+    table = plan.delay_table()
+    codes = np.random.default_rng(13).integers(0, 256, size=(nsamps, nchans), dtype=np.uint8)
+    want = oracle.dedisperse(codes, nsamps, nchans, 8, table)
+    assert np.array_equal(_run(plan, codes, nsamps, cuda), want)
+
+
+@pytest.mark.parametrize("nbits", [2, 8])
+def test_impulse_probe_recovers_delay_table(native, cuda, nbits):
+    """x = 1 at (t*, c*) only: out[d][t] = 1 exactly at t = t* - delay[d][c*]."""
+    nchans, ndm = 128, 20
+    dms = synth.dm_list_linear(ndm, 400.0)
+    plan = Plan(nchans, 64e-6, 1500.0, -1.0, nbits).set_dm_list(dms)
+    table = plan.delay_table()
+    mx = plan.max_delay
+    nsamps = mx + 3000
+    for cstar in (0, 5, 63, 64, 127):
+        tstar = mx + 1000
+        codes = np.zeros((nsamps, nchans), dtype=np.uint8)
+        codes[tstar, cstar] = 1
+        got = _run(plan, synth.pack(codes, nbits), nsamps, cuda)
+        want = np.zeros_like(got)
+        for d in range(ndm):
+            want[d, tstar - table[d, cstar]] = 1
+        assert np.array_equal(got, want), cstar
+
+
+def test_extreme_codes_do_not_overflow_packed_lanes(native, cuda):
+    """All-maximum input: every output equals max_code * nchans exactly."""
+    for nbits, nchans in ((2, 1024), (8, 4096)):
+        maxc = 3 if nbits == 2 else 255
+        dms = synth.dm_list_linear(16, 100.0)
+        plan = Plan(nchans, 64e-6, 1500.0, -0.09765625 * 4096 / nchans, nbits).set_dm_list(dms)
+        nsamps = plan.max_delay + 2000
+        codes = np.full((nsamps, nchans), maxc, dtype=np.uint8)
+        for cfg in _configs_for(plan):
+            got = _run(plan, synth.pack(codes, nbits), nsamps, cuda, cfg)
+            assert np.all(got == maxc * nchans), cfg
+
+
+def test_determinism(native, cuda):
+    b = synth.survey_beam(seed=3, nsamps=40000, nchans=512, ndm=64, npulses=0)
+    plan = _plan_for(b)
+    packed = b.packed()
+    a = _run(plan, packed, b.nsamps, cuda)
+    c = _run(plan, packed, b.nsamps, cuda)
+    assert np.array_equal(a, c)
+
+
+def test_survey_beam_full_size_sampled(native, cuda):
+    """The 2-bit, 1024-channel, 1024-DM, 2^19-sample beam, in the benchmark's launch.
+
+    Sampled outputs against the oracle point by point; the DM 0 row against
+    numpy's channel sum over the whole output; every injected pulse at its
+    trial and time.
+    """
+    import torch
+    b = synth.survey_beam()
+    plan = _plan_for(b)
+    table = plan.delay_table()
+    otab, omx = oracle.delay_table(b.nchans, b.dt, b.f_top, b.df, b.dms)
+    assert np.array_equal(table, otab) and omx == 20456
+    b.inject(lambda i: otab[i])
+    packed = b.packed()
+    inp = _to_gpu(packed.reshape(-1), cuda)
+    out = plan.execute(inp, b.nsamps)
+    torch.cuda.synchronize()
+    got = _out_np(out)
+    nout = b.nsamps - omx
+    assert got.shape == (1024, nout)
+    rng = np.random.default_rng(99)
+    d = rng.integers(0, 1024, size=20000)
+    t = rng.integers(0, nout, size=20000)
+    # always include the corners and the last tile
+    d = np.concatenate([d, [0, 1023, 0, 1023, 511]])
+    t = np.concatenate([t, [0, 0, nout - 1, nout - 1, nout - 2]])
+    want = oracle.dedisperse_points(packed, b.nsamps, b.nchans, b.nbits, otab, d, t)
+    assert np.array_equal(got[d, t], want)
+    assert np.array_equal(got[0], b.codes.sum(axis=1, dtype=np.uint32)[:nout])
+    for p in b.pulses:
+        lo, hi = max(0, p.t0 - 100), min(nout, p.t0 + 101)
+        win = got[:, lo:hi].astype(np.int64)
+        dd, tt = np.unravel_index(int(win.argmax()), win.shape)
+        assert (dd, tt + lo) == (p.dm_index, p.t0), p
