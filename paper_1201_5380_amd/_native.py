@@ -103,6 +103,12 @@ def lib():
         raise RuntimeError(
             f"{LIB_PATH} is missing: build it with `python -m paper_1201_5380_amd.build` "
             "(there is no fallback implementation)")
+    # The library must share torch's HIP runtime (torch's device allocations
+    # and streams are what it is handed).  torch bundles its own
+    # libamdhip64.so (soname libamdhip64.so.7); loading torch first makes the
+    # dynamic linker bind our NEEDED libamdhip64.so.7 to that same copy
+    # instead of a second runtime from /opt/rocm.
+    import torch  # noqa: F401
     handle = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(handle, name)

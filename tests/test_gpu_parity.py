@@ -159,16 +159,19 @@ def test_impulse_probe_recovers_delay_table(native, cuda, nbits):
     plan = Plan(nchans, 64e-6, 1500.0, -1.0, nbits).set_dm_list(dms)
     table = plan.delay_table()
     mx = plan.max_delay
-    nsamps = mx + 3000
+    nsamps = 2 * mx + 3000
+    nout = nsamps - mx
     for cstar in (0, 5, 63, 64, 127):
-        tstar = mx + 1000
-        codes = np.zeros((nsamps, nchans), dtype=np.uint8)
-        codes[tstar, cstar] = 1
-        got = _run(plan, synth.pack(codes, nbits), nsamps, cuda)
-        want = np.zeros_like(got)
-        for d in range(ndm):
-            want[d, tstar - table[d, cstar]] = 1
-        assert np.array_equal(got, want), cstar
+        for tstar in (mx + 1000, 7, nsamps - 1):
+            codes = np.zeros((nsamps, nchans), dtype=np.uint8)
+            codes[tstar, cstar] = 1
+            got = _run(plan, synth.pack(codes, nbits), nsamps, cuda)
+            want = np.zeros_like(got)
+            for d in range(ndm):
+                t = tstar - table[d, cstar]
+                if 0 <= t < nout:
+                    want[d, t] = 1
+            assert np.array_equal(got, want), (cstar, tstar)
 
 
 def test_extreme_codes_do_not_overflow_packed_lanes(native, cuda):
