@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nsamps", type=int, default=1 << 19)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile shape")
+    ap.add_argument("--tile", default=None,
+                    help="waves,dms_per_wave,words_per_lane,chunk_chans: use this shape, no tuning")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -108,7 +110,11 @@ def main():
     stream = torch.cuda.current_stream()
 
     tune_ms = None
-    if not args.no_tune:
+    if args.tile:
+        w, dpw, m, cc = (int(x) for x in args.tile.split(","))
+        plan.set_tile_config(dict(kind=0, waves=w, dms_per_wave=dpw, words_per_lane=m,
+                                  chunk_chans=cc))
+    elif not args.no_tune:
         tune_ms = plan.tune(inp, out, nsamps, cache_path=args.tune_cache)
     cfg = plan.tile_config()
 

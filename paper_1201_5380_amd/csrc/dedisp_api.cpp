@@ -58,7 +58,7 @@ struct BlockTables {
     int nblocks = 0;
     int relmax = 0;
     std::vector<int32_t> rel;    // [nblocks*db][nchans]
-    std::vector<int32_t> base;   // [nblocks][nchans/4]
+    std::vector<int32_t> base;   // [nblocks][nchans]
     int32_t* d_rel = nullptr;
     int32_t* d_base = nullptr;
 };
@@ -78,6 +78,8 @@ struct dedisp_plan_s {
     int device = -1;
     int32_t* d_table = nullptr;
     std::map<int, BlockTables> blocks;  // keyed by DM-block size
+    uint8_t* d_xc = nullptr;            // channel-major scratch for the tiled kernel
+    size_t xc_bytes = 0;
 };
 
 namespace {
@@ -92,6 +94,9 @@ void free_device(dedisp_plan p)
         if (kv.second.d_base) (void)hipFree(kv.second.d_base);
     }
     p->blocks.clear();
+    if (p->d_xc) (void)hipFree(p->d_xc);
+    p->d_xc = nullptr;
+    p->xc_bytes = 0;
 }
 
 bool is_finite(double x) { return std::isfinite(x); }
@@ -123,34 +128,33 @@ bool build_delay_table(const dedisp_plan_s& p, const double* dms, int ndm,
     return true;
 }
 
-// Window tables for blocks of `db` consecutive DM rows: base[b][g] is the
-// smallest delay over the block and the 4 channels of group g, rounded down
-// to a multiple of 4; rel[b][c][k] = delay[b*db + k][c] - base[b][c/4]
-// (0 for padding rows past ndm).
+// Window tables for blocks of `db` consecutive DM rows: base[b][c] is the
+// smallest delay of channel c over the block, rounded down to a multiple of
+// 16 (so staged windows start on 16-byte boundaries); rel[b*db + k][c] =
+// delay[b*db + k][c] - base[b][c] (0 for padding rows past ndm), so one DM's
+// window offsets for consecutive channels are contiguous.
 void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
 {
     const int ndm = static_cast<int>(p.dms.size());
-    const int ng = p.nchans / 4;
+    const int nch = p.nchans;
     bt.db = db;
     bt.nblocks = (ndm + db - 1) / db;
-    bt.rel.assign(static_cast<size_t>(bt.nblocks) * p.nchans * db, 0);
-    bt.base.assign(static_cast<size_t>(bt.nblocks) * ng, 0);
+    bt.rel.assign(static_cast<size_t>(bt.nblocks) * db * nch, 0);
+    bt.base.assign(static_cast<size_t>(bt.nblocks) * nch, 0);
     bt.relmax = 0;
     for (int b = 0; b < bt.nblocks; ++b) {
         const int d0 = b * db, d1 = std::min(ndm, d0 + db);
-        for (int g = 0; g < ng; ++g) {
+        for (int c = 0; c < nch; ++c) {
             int mn = 0x7fffffff;
             for (int d = d0; d < d1; ++d)
-                for (int c = 4 * g; c < 4 * g + 4; ++c)
-                    mn = std::min(mn, p.table[static_cast<size_t>(d) * p.nchans + c]);
-            mn &= ~3;
-            bt.base[static_cast<size_t>(b) * ng + g] = mn;
-            for (int c = 4 * g; c < 4 * g + 4; ++c)
-                for (int d = d0; d < d1; ++d) {
-                    const int r = p.table[static_cast<size_t>(d) * p.nchans + c] - mn;
-                    bt.rel[static_cast<size_t>(d) * p.nchans + c] = r;
-                    bt.relmax = std::max(bt.relmax, r);
-                }
+                mn = std::min(mn, p.table[static_cast<size_t>(d) * nch + c]);
+            mn &= ~15;
+            bt.base[static_cast<size_t>(b) * nch + c] = mn;
+            for (int d = d0; d < d1; ++d) {
+                const int r = p.table[static_cast<size_t>(d) * nch + c] - mn;
+                bt.rel[static_cast<size_t>(d) * nch + c] = r;
+                bt.relmax = std::max(bt.relmax, r);
+            }
         }
     }
 }
@@ -169,14 +173,23 @@ const Shape* find_shape(const dedisp_tile_config& c, int nbits, int* index = nul
     return nullptr;
 }
 
+// Default shape: the first compiled tiled shape of this bit depth (the
+// shape list is ordered by measured speed on the survey-beam workload).
 dedisp_tile_config default_config(int nbits)
 {
     dedisp_tile_config c{};
-    c.kind = 0;
-    c.waves = 4;
-    c.dms_per_wave = 4;
-    c.words_per_lane = 5;
-    c.chunk_chans = nbits == 2 ? 32 : 16;
+    for (int i = 0; i < dedisp::shape_count(); ++i) {
+        const Shape& s = dedisp::shape_at(i);
+        if (s.kind == 0 && s.nbits == nbits) {
+            c.kind = 0;
+            c.waves = s.waves;
+            c.dms_per_wave = s.dpw;
+            c.words_per_lane = s.m;
+            c.chunk_chans = s.cc;
+            return c;
+        }
+    }
+    c.kind = 1;
     return c;
 }
 
@@ -238,14 +251,25 @@ dedisp_status ensure_block_tables(dedisp_plan p, int db, BlockTables** out)
     return DEDISP_OK;
 }
 
-// Window length (32-bit words per channel row in LDS) of shape s.
-int window_words(const BlockTables& bt, const Shape& s) { return (bt.relmax >> 2) + 64 * s.m + 1; }
+// Window length (32-bit words per channel row in LDS, a multiple of 4) of
+// shape s: a lane reads words up to (rel >> 2) + 64*m.
+int window_words(const BlockTables& bt, const Shape& s)
+{
+    return (((bt.relmax >> 2) + 64 * s.m + 1) + 3) & ~3;
+}
 
 bool shape_fits(const BlockTables& bt, const Shape& s)
 {
     const int rw = window_words(bt, s);
-    return rw <= s.pi * s.waves * 64 &&
+    return (rw >> 2) <= 64 * s.pi &&
            static_cast<long long>(s.cc) * rw * 4 <= dedisp::kMaxLdsBytes;
+}
+
+// The tiled path reads input rows as 32-bit words and keeps 2-bit sums in
+// 16-bit lanes.
+bool tiled_supported(const dedisp_plan_s& p)
+{
+    return p.row_bytes % 4 == 0 && (p.nbits == 8 || p.nchans <= 21845);
 }
 
 // Resolve the shape used for this plan: the requested one if its LDS window
@@ -263,7 +287,7 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
     if (want.kind == 1) order.clear();
     for (int i : order) {
         const Shape& s = dedisp::shape_at(i);
-        if (s.nbits != p->nbits || s.kind != 0 || p->nchans % 4) continue;
+        if (s.nbits != p->nbits || s.kind != 0 || !tiled_supported(*p)) continue;
         const int db = s.waves * s.dpw;
         const BlockTables* bt = nullptr;
         auto it = p->blocks.find(db);
@@ -307,6 +331,28 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
 
 long long tile_len(const Shape& s) { return 256LL * s.m; }
 
+// Row pitch of the channel-major scratch: the staged window of the last tile
+// may run up to 4*rw bytes past the last sample.
+long long xc_pitch(long long nsamps, int rw) { return ((nsamps + 4LL * rw + 63) / 64) * 64; }
+
+dedisp_status ensure_xc(dedisp_plan p, long long nsamps, int rw)
+{
+    const size_t need = static_cast<size_t>(xc_pitch(nsamps, rw)) * p->nchans;
+    if (p->d_xc && p->xc_bytes >= need) return DEDISP_OK;
+    if (p->d_xc) {
+        HIP_TRY(hipDeviceSynchronize());
+        (void)hipFree(p->d_xc);
+        p->d_xc = nullptr;
+        p->xc_bytes = 0;
+    }
+    if (hipMalloc(&p->d_xc, need) != hipSuccess) {
+        p->d_xc = nullptr;
+        return fail(DEDISP_ERR_OOM, "hipMalloc channel-major scratch");
+    }
+    p->xc_bytes = need;
+    return DEDISP_OK;
+}
+
 void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n0,
                const void* in1, long long nsamps, uint32_t* out, long long stride,
                BeamDesc& d)
@@ -325,6 +371,8 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
     d.ndm = static_cast<int>(p->dms.size());
     d.shape = lp.shape_index;
     if (lp.shape.kind == 0) {
+        d.xc = p->d_xc;
+        d.pitch = xc_pitch(nsamps, lp.rw);
         d.rel = lp.bt->d_rel;
         d.base = lp.bt->d_base;
         d.nblocks = lp.bt->nblocks;
@@ -336,15 +384,14 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
 
 hipError_t launch_desc(const BeamDesc& d, const LaunchPlan& lp, hipStream_t st)
 {
-    if (lp.shape.kind == 0) return dedisp::launch_tiled(d, lp.shape, lp.lds, st);
+    if (lp.shape.kind == 0) {
+        hipError_t e = dedisp::launch_unpack(d, lp.shape.nbits, st);
+        if (e != hipSuccess) return e;
+        return dedisp::launch_tiled(d, lp.shape, lp.lds, st);
+    }
     return dedisp::launch_untiled(d, lp.shape.nbits, st);
 }
 
-bool aligned_ok(dedisp_plan p, const void* ptr)
-{
-    // 8-bit rows are read as 32-bit words.
-    return p->nbits != 8 || (reinterpret_cast<uintptr_t>(ptr) & 3) == 0;
-}
 
 // --------------------------------------------------------------- tune cache
 
@@ -569,10 +616,20 @@ dedisp_status dedisp_execute(dedisp_plan p, const void* d_in, size_t nsamps, uin
     const size_t nout = nsamps - p->max_delay;
     if (stride == 0) stride = nout;
     if (stride < nout) return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < nsamps - max_delay");
-    if (!aligned_ok(p, d_in)) return fail(DEDISP_ERR_INVALID_ARG, "8-bit input must be 4-byte aligned");
     LaunchPlan lp;
     dedisp_status st = resolve_launch(p, p->cfg, true, lp);
     if (st != DEDISP_OK) return st;
+    if (lp.shape.kind == 0 && (reinterpret_cast<uintptr_t>(d_in) & 3)) {
+        // the corner turn reads 32-bit words
+        dedisp_tile_config u{};
+        u.kind = 1;
+        st = resolve_launch(p, u, true, lp);
+        if (st != DEDISP_OK) return st;
+    }
+    if (lp.shape.kind == 0) {
+        st = ensure_xc(p, static_cast<long long>(nsamps), lp.rw);
+        if (st != DEDISP_OK) return st;
+    }
     BeamDesc d;
     fill_desc(p, lp, d_in, static_cast<long long>(nsamps), nullptr,
               static_cast<long long>(nsamps), d_out, static_cast<long long>(stride), d);

@@ -19,8 +19,10 @@ struct BeamDesc {
     long long nout;           // nsamps - max_delay
     uint32_t* out;
     long long out_stride;     // elements between DM rows
+    uint8_t* xc;              // channel-major bytes written by the unpack kernel
+    long long pitch;          // bytes between channel rows of xc (multiple of 16)
     const int32_t* rel;       // [nblocks*DB][nchans] delay minus window start
-    const int32_t* base;      // [nblocks][nchans/4] window start per 4-channel group
+    const int32_t* base;      // [nblocks][nchans] window start (multiple of 16)
     const int32_t* table;     // [ndm][nchans] full delay table (untiled kernel)
     int nchans;
     int row_bytes;
@@ -42,7 +44,7 @@ struct Shape {
     int dpw;        // DMs per wave
     int m;          // 32-bit words per lane (4 samples each)
     int cc;         // channels staged per chunk
-    int pi;         // staging slabs: window length <= pi*waves*64 words
+    int pi;         // 16-byte pieces per lane per staged row: row <= 64*pi pieces
 };
 
 // Shapes compiled into the library (index = shape id).
@@ -51,6 +53,9 @@ const Shape& shape_at(int i);
 
 // Largest dynamic LDS a workgroup may use on this device (bytes).
 constexpr int kMaxLdsBytes = 160 * 1024;
+
+// Enqueue the corner turn (time-major packed -> channel-major bytes in d.xc).
+hipError_t launch_unpack(const BeamDesc& d, int nbits, hipStream_t st);
 
 // Enqueue the transform of one beam with the given shape.
 hipError_t launch_tiled(const BeamDesc& d, const Shape& s, int lds_bytes, hipStream_t st);

@@ -3,37 +3,50 @@
 //
 //     out[d][t] = sum_c in[t + delay[d][c]][c]
 //
-// LDS-tiled kernel.  A workgroup owns one time tile of 256*M output samples
-// and a block of DB = NW*DPW neighbouring trial DMs.  For each chunk of CC
-// channels it stages, per channel, the window of input samples that the
-// whole DM block needs ([tile start + smallest delay, ... + largest delay +
-// tile length)) into LDS, decoded to one byte per sample and laid out
-// channel-major with time contiguous.  That window is then read by all DB
-// DMs of the block: the temporal reuse the paper discusses in Section 2.2,
-// which on gfx950 pays because LDS is large and the kernel is bound by
-// integer adds, not by HBM.
+// Two kernels per beam.
 //
-// Each lane owns 4*M consecutive output samples of DPW DMs.  For one
-// (DM, channel) pair the delay is wave-uniform, so a lane reads M+1
-// consecutive 32-bit LDS words starting at its word offset plus delay/4 and
-// realigns them by delay%4 bytes with one v_alignbyte (2-bit data) or spreads
-// them into 16-bit lanes with v_perm (8-bit data).  Lanes are M words apart
-// with M odd, so the 64 lanes of a wave hit distinct LDS banks.
+// 1. Corner turn + unpack (k_unpack).  Reads the packed time-major input
+//    with coalesced loads (two row segments, so a stream's history and a new
+//    chunk need not be contiguous) and writes one byte per sample,
+//    channel-major: xc[c * pitch + t].  This is the "corner turn" the paper
+//    times separately (Table 2); it moves ~5 bytes per input sample, about 1%
+//    of the main kernel's time, and turns every later access into aligned
+//    contiguous 16-byte loads.
 //
-// The sums use bit-level parallelism (Section 2.3): 2-bit codes are added
-// four at a time in the 8-bit lanes of a 32-bit register, which is exact for
-// up to (2^8-1)/(2^2-1) = 85 channels, then flushed into 32-bit
-// accumulators; 8-bit codes are added two at a time in 16-bit lanes, exact
-// for up to 257 channels.  Every result is an exact integer sum.
+// 2. LDS-tiled shifted sum (k_tiled).  A workgroup owns one time tile of
+//    256*M output samples and a block of DB = NW*DPW neighbouring trial DMs.
+//    For each chunk of CC channels it stages, per channel, the window of
+//    samples the whole DM block needs -- [t0 + base, t0 + base + 4*rw) with
+//    base the block's smallest delay in that channel rounded down to 16 --
+//    into LDS.  Every DM of the block then reads its shifted slice of that
+//    window: the temporal reuse discussed in Section 2.2, which pays on
+//    gfx950 because LDS is large and the kernel is bound by integer adds.
+//    The loads of chunk k+1 are issued before chunk k is summed and land in
+//    registers, so their latency hides behind the arithmetic.
 //
-// Untiled kernel: one thread per 4 outputs of one DM, reading the input
-// straight from global memory.  Used when a DM block's delay spread is too
-// large for LDS (e.g. a DM list with huge gaps).
+//    Each lane owns 4*M consecutive output samples of DPW DMs.  For one
+//    (DM, channel) pair the delay is wave-uniform: a lane reads M+1
+//    consecutive 32-bit words at its own word offset plus delay/4 and
+//    realigns them by delay%4 bytes with v_alignbyte (2-bit data) or spreads
+//    them into 16-bit lanes with v_perm (8-bit data).  Lanes are M words apart
+//    with M odd, so the 64 lanes of a wave hit distinct LDS banks.  The
+//    per-(DM, channel) window offsets arrive through vector loads and
+//    v_readlane, never through scalar memory, so waits on LDS are never held
+//    up by scalar loads.
 //
-// Persistent kernel: a grid sized to the machine pulls (beam, tile, DM block)
-// work items from a global counter; beams may differ in channel count, bit
-// depth, length, DM list and tile shape.  Used for batches and for several
-// stream pushes in one launch.
+//    The sums use bit-level parallelism (Section 2.3): 2-bit codes are added
+//    four at a time in the 8-bit lanes of a register, exact for up to
+//    (2^8-1)/(2^2-1) = 85 channels, then flushed into 16-bit lanes (exact for
+//    up to 21845 channels); 8-bit codes are added two at a time in 16-bit
+//    lanes, exact for 257 channels, then flushed into 32-bit accumulators.
+//
+// Untiled kernel (k_untiled): one thread per 4 outputs of one DM reading the
+// packed input directly.  Used when a DM block's delay spread is too large
+// for LDS (e.g. a DM list with huge gaps) or the input is misaligned.
+//
+// Persistent kernel (k_persistent): a grid sized to the machine pulls
+// (beam, tile, DM block) work items from a global counter; beams may differ
+// in channel count, bit depth, length, DM list and tile shape.
 #include "dedisp_internal.h"
 
 namespace dedisp {
@@ -41,6 +54,15 @@ namespace dedisp {
 namespace {
 
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// Native 4 x 32-bit vector (one 16-byte load or store); unlike HIP's uint4
+// struct it stays in registers when held in arrays.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int lane_value(int v, int lane)
+{
+    return __builtin_amdgcn_readlane(v, lane);
+}
 
 // Address of input row r in the two-segment virtual input.
 __device__ __forceinline__ const uint8_t* row_ptr(const BeamDesc& b, long long r)
@@ -51,8 +73,8 @@ __device__ __forceinline__ const uint8_t* row_ptr(const BeamDesc& b, long long r
 
 // Map the hardware workgroup index to a logical one so that the workgroups
 // dispatched to one XCD (round-robin over 8 XCDs) get a contiguous range of
-// logical indices, i.e. all DM blocks of the same few time tiles: they read
-// the same input rows, which then stay in that XCD's L2.
+// logical indices, i.e. all DM blocks of the same few time tiles, which read
+// overlapping input windows through that XCD's L2.
 __device__ __forceinline__ int xcd_remap(int i, int n)
 {
     constexpr int kXcds = 8;
@@ -61,123 +83,98 @@ __device__ __forceinline__ int xcd_remap(int i, int n)
     return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
 }
 
-// Input staging.  Chunk k of a tile covers channel groups [G*k, G*k+G) (4
-// channels per group).  For group g the LDS holds rw words per channel; word
-// p = samples (t0 + base[g] + 4p) .. +3 of that channel, one byte each.
-// Thread x stages words p = x + i*NT (i < PI) of every group of the chunk.
-// Loading (global -> registers) and storing (registers -> LDS) are separate
-// so the loads of chunk k+1 can be in flight while chunk k is summed.
-// Rows past the end of the input are clamped to the last row: only outputs
-// t >= nout, which are never stored, read them.
-template <int NBITS, int G, int PI>
-struct Staging {
-    // 2-bit: one 32-bit word per item (byte k = row r+k, 4 channels per byte).
-    // 8-bit: four words per item (word k = row r+k, 4 channels per word).
-    static constexpr int W = NBITS == 2 ? 1 : 4;
-    uint32_t v[PI][G][W];
+// ------------------------------------------------------------ corner turn
 
-    // FAST: the tile's whole window lies in one input segment and before the
-    // last row, so row r is at seg + (r - seg_row0) * row_bytes.
-    template <int NT, bool FAST>
-    __device__ __forceinline__ void load(const BeamDesc& b, const int32_t* basep, long long t0,
-                                         int col0, int ngroups, int pi, const uint8_t* seg,
-                                         long long seg_row0)
-    {
-        const int rw = b.rw;
-        const long long last = b.nsamps - 1;
-        const long long rb = b.row_bytes;
+constexpr int kUT = 128;   // time rows per unpack tile
+constexpr int kUC = 128;   // channels per unpack tile
+constexpr int kUPitch = kUT + 16;
+
+// xc[c * pitch + t] = code of channel c at time t, for a 128 x 128 tile.
+// Requires row_bytes % 4 == 0 and 4-byte aligned row segments.
+template <int NBITS>
+__global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t tile[kUC * kUPitch];
+    const long long t0 = (long long)blockIdx.x * kUT;
+    const int c0 = blockIdx.y * kUC;
+    constexpr int WPR = kUC * NBITS / 32;          // 32-bit words per row segment
+    constexpr int CPW = 32 / NBITS;                // channels per word
+    // item = (row quad, word): four rows of one word -> CPW channel words
+    for (int it = threadIdx.x; it < (kUT / 4) * WPR; it += 256) {
+        const int w = it % WPR;
+        const int rq = it / WPR;
+        const int cw = c0 + w * CPW;               // first channel of the word
+        uint32_t v[4];
 #pragma unroll
-        for (int i = 0; i < PI; ++i) {
-            const int p = threadIdx.x + i * NT;
-            const long long p4 = 4LL * p;
+        for (int k = 0; k < 4; ++k) {
+            const long long t = t0 + 4 * rq + k;
+            v[k] = (t < b.nsamps && cw < b.nchans)
+                       ? *reinterpret_cast<const uint32_t*>(row_ptr(b, t) + (long long)cw * NBITS / 8)
+                       : 0u;
+        }
+        uint8_t* dst = tile + (size_t)(w * CPW) * kUPitch + 4 * rq;
+        if constexpr (NBITS == 2) {
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                // words p >= rw are outside the window: never stored, never read
-                if (i >= pi || p >= rw || g >= ngroups) continue;
-                const long long r = t0 + (long long)basep[g] + p4;
-                if constexpr (FAST) {
-                    const uint8_t* q = seg + (r - seg_row0) * rb + (NBITS == 2 ? col0 + g : 4 * (col0 + g));
-                    if constexpr (NBITS == 2) {
-                        uint32_t word = 0;
+            for (int q = 0; q < 4; ++q) {
+                // byte q of each row holds 4 channels -> one word of 4 times
+                const uint32_t sel = 0x0C0C0000u | ((uint32_t)(q + 4) << 8) | (uint32_t)q;
+                const uint32_t lo = __builtin_amdgcn_perm(v[1], v[0], sel);
+                const uint32_t hi = __builtin_amdgcn_perm(v[3], v[2], sel);
+                const uint32_t w4 = lo | (hi << 16);
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) word |= (uint32_t)q[k * rb] << (8 * k);
-                        v[i][g][0] = word;
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            v[i][g][k] = *reinterpret_cast<const uint32_t*>(q + k * rb);
-                    }
-                } else if constexpr (NBITS == 2) {
-                    uint32_t word = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const uint8_t* row = row_ptr(b, r + k < last ? r + k : last);
-                        word |= (uint32_t)row[col0 + g] << (8 * k);
-                    }
-                    v[i][g][0] = word;
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const uint8_t* row = row_ptr(b, r + k < last ? r + k : last);
-                        v[i][g][k] = *reinterpret_cast<const uint32_t*>(row + 4 * (col0 + g));
-                    }
-                }
+                for (int j = 0; j < 4; ++j)
+                    *reinterpret_cast<uint32_t*>(dst + (size_t)(4 * q + j) * kUPitch) =
+                        (w4 >> (2 * j)) & 0x03030303u;
             }
+        } else {
+            const uint32_t a01 = __builtin_amdgcn_perm(v[1], v[0], 0x05010400u);
+            const uint32_t a23 = __builtin_amdgcn_perm(v[3], v[2], 0x05010400u);
+            const uint32_t b01 = __builtin_amdgcn_perm(v[1], v[0], 0x07030602u);
+            const uint32_t b23 = __builtin_amdgcn_perm(v[3], v[2], 0x07030602u);
+            *reinterpret_cast<uint32_t*>(dst) = __builtin_amdgcn_perm(a23, a01, 0x05040100u);
+            *reinterpret_cast<uint32_t*>(dst + kUPitch) = __builtin_amdgcn_perm(a23, a01, 0x07060302u);
+            *reinterpret_cast<uint32_t*>(dst + 2 * kUPitch) = __builtin_amdgcn_perm(b23, b01, 0x05040100u);
+            *reinterpret_cast<uint32_t*>(dst + 3 * kUPitch) = __builtin_amdgcn_perm(b23, b01, 0x07060302u);
         }
     }
-
-    template <int NT>
-    __device__ __forceinline__ void load_any(bool fast, const BeamDesc& b, const int32_t* basep,
-                                             long long t0, int col0, int ngroups, int pi,
-                                             const uint8_t* seg, long long seg_row0)
-    {
-        if (fast) load<NT, true>(b, basep, t0, col0, ngroups, pi, seg, seg_row0);
-        else load<NT, false>(b, basep, t0, col0, ngroups, pi, seg, seg_row0);
+    __syncthreads();
+    // write 16-byte pieces: kUT/16 per channel row
+    for (int it = threadIdx.x; it < kUC * (kUT / 16); it += 256) {
+        const int c = it / (kUT / 16);
+        const int p = it % (kUT / 16);
+        if (c0 + c >= b.nchans) continue;
+        const long long t = t0 + 16 * p;
+        if (t >= b.nsamps) continue;
+        const u32x4 val = *reinterpret_cast<const u32x4*>(tile + (size_t)c * kUPitch + 16 * p);
+        *reinterpret_cast<u32x4*>(b.xc + (long long)(c0 + c) * b.pitch + t) = val;
     }
+}
 
-    template <int NT>
-    __device__ __forceinline__ void store(uint32_t* lds, int rw, int ngroups, int pi) const
-    {
-#pragma unroll
-        for (int i = 0; i < PI; ++i) {
-            const int p = threadIdx.x + i * NT;
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                if (i >= pi || p >= rw || g >= ngroups) continue;
-                uint32_t* dst = lds + (size_t)(g * 4) * rw + p;
-                if constexpr (NBITS == 2) {
-                    // channel q of the group is bits [2q, 2q+1] of every byte
-                    const uint32_t word = v[i][g][0];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) dst[(size_t)q * rw] = (word >> (2 * q)) & 0x03030303u;
-                } else {
-                    // 4x4 byte transpose: channel q gets byte q of rows r..r+3
-                    const uint32_t a01 = __builtin_amdgcn_perm(v[i][g][1], v[i][g][0], 0x05010400u);
-                    const uint32_t a23 = __builtin_amdgcn_perm(v[i][g][3], v[i][g][2], 0x05010400u);
-                    const uint32_t b01 = __builtin_amdgcn_perm(v[i][g][1], v[i][g][0], 0x07030602u);
-                    const uint32_t b23 = __builtin_amdgcn_perm(v[i][g][3], v[i][g][2], 0x07030602u);
-                    dst[0] = __builtin_amdgcn_perm(a23, a01, 0x05040100u);
-                    dst[(size_t)rw] = __builtin_amdgcn_perm(a23, a01, 0x07060302u);
-                    dst[(size_t)2 * rw] = __builtin_amdgcn_perm(b23, b01, 0x05040100u);
-                    dst[(size_t)3 * rw] = __builtin_amdgcn_perm(b23, b01, 0x07060302u);
-                }
-            }
-        }
-    }
-};
+// ------------------------------------------------------------ tiled sum
 
 // One (time tile, DM block) work item.
-template <int NBITS, int NW, int DPW, int M, int CC, int PI>
+//   xc   channel-major bytes, row pitch b.pitch (multiple of 16)
+//   base [nblocks][nchans]  window start (multiple of 16) of channel c
+//   rel  [nblocks*DB][nchans] delay - base of DM row, channel c
+// LDS: CC rows of rw words (rw % 4 == 0).
+template <int NBITS, int NW, int DPW, int M, int CC, int PM>
 __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block, uint32_t* lds)
 {
     static_assert(M % 2 == 1, "lanes must be an odd number of LDS words apart");
-    static_assert(CC % 4 == 0, "chunks are whole 4-channel groups");
+    static_assert(CC % NW == 0, "every wave stages the same number of channel rows");
+    static_assert((DPW * CC) % 64 == 0 && CC <= 64, "window offsets fill whole registers");
     static_assert(NBITS == 8 || CC <= 84, "2-bit lanes hold at most 85 codes");
-    constexpr int NT = NW * 64;
     constexpr int T = 256 * M;
     constexpr int DB = NW * DPW;
-    constexpr int G = CC / 4;
+    constexpr int CPW = CC / NW;           // channel rows staged per wave per chunk
+    constexpr int RV = DPW * CC / 64;      // registers of window offsets per wave
+    constexpr int KPR = 64 / CC;           // DMs per offset register
     constexpr int NSW = NBITS == 2 ? 1 : 2;
+    constexpr int NACC = NBITS == 2 ? 2 : 4;
+    constexpr int LANE_SUM = NBITS == 2 ? 85 : 257;
+    constexpr int FLUSH = LANE_SUM / CC;   // chunks between flushes of the packed lanes
+    static_assert(FLUSH >= 1, "chunk too large for the packed lanes");
+
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
     tile = wave_uniform(tile);
@@ -185,86 +182,117 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     const long long t0 = (long long)tile * T;
     const int nchans = b.nchans;
     const int rw = b.rw;
-    const int pi = (rw + NT - 1) / NT;
-    // Rows this tile can touch: [t0, t0 + 4*rw + max_delay).
-    const long long hi_row = t0 + 4LL * rw + (b.nsamps - b.nout);
-    const bool fast = hi_row <= b.nsamps && (hi_row <= b.n0 || t0 >= b.n0);
-    const uint8_t* seg = t0 >= b.n0 ? b.in1 : b.in0;
-    const long long seg_row0 = t0 >= b.n0 ? b.n0 : 0;
-    const int32_t* basep = b.base + (size_t)block * (size_t)(nchans >> 2);
-    // rel row of DM k of this wave: rel[(block*DB + wave*DPW + k)*nchans + c]
-    const int rel_row0 = wave_uniform((block * DB + wave * DPW) * nchans);
+    const int rq = rw >> 2;                // 16-byte pieces per row
+    const long long pitch = b.pitch;
+    const int32_t* base_row = b.base + (size_t)block * nchans;
+    const int32_t* rel_rows = b.rel + (size_t)(block * DB + wave * DPW) * nchans;
 
-    uint32_t acc[DPW][M][4];
+    // Packed-lane partial sums and wide accumulators.
+    // 2-bit: sw = four 8-bit lanes (samples 0..3); acc[0] = 16-bit lanes
+    // (samples 0, 2), acc[1] = (samples 1, 3).
+    // 8-bit: sw[0] = 16-bit lanes (samples 0, 1), sw[1] = (2, 3); acc = 32-bit.
     uint32_t sw[DPW][M][NSW];
+    uint32_t acc[DPW][M][NACC];
 #pragma unroll
     for (int k = 0; k < DPW; ++k)
 #pragma unroll
         for (int j = 0; j < M; ++j) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[k][j][e] = 0u;
-#pragma unroll
             for (int h = 0; h < NSW; ++h) sw[k][j][h] = 0u;
+#pragma unroll
+            for (int e = 0; e < NACC; ++e) acc[k][j][e] = 0u;
         }
 
-    Staging<NBITS, G, PI> stg;
-    stg.template load_any<NT>(fast, b, basep, t0, 0, min(G, nchans >> 2), pi, seg, seg_row0);
+    // Chunk prefetch registers.  Every load below is unconditional and in
+    // bounds (indices are clamped); results that are not needed are simply
+    // not stored, which keeps all of these arrays in registers.
+    u32x4 pf[CPW][PM];
+    int vbase_nxt = 0;         // lane i < CC: window start of channel c0 + i (next chunk)
+    int vrel_cur[RV], vrel_nxt[RV];
+    const int last_c = nchans - 1;
+    const int last_p = rq - 1;
+
+#define DEDISP_LOAD_BASE(C0)                                                        \
+    vbase_nxt = base_row[min((C0) + (lane < CC ? lane : 0), last_c)];
+#define DEDISP_LOAD_REL(C0, DST)                                                    \
+    _Pragma("unroll") for (int r = 0; r < RV; ++r) {                                \
+        const int idx = 64 * r + lane;                                              \
+        DST[r] = rel_rows[(size_t)(idx / CC) * nchans + min((C0) + idx % CC, last_c)]; \
+    }
+#define DEDISP_LOAD_DATA(C0)                                                        \
+    _Pragma("unroll") for (int i = 0; i < CPW; ++i) {                               \
+        const int cl = wave + NW * i;                                               \
+        const int bs = lane_value(vbase_nxt, cl);                                   \
+        const uint8_t* src = b.xc + (long long)min((C0) + cl, last_c) * pitch + t0 + bs; \
+        _Pragma("unroll") for (int q = 0; q < PM; ++q)                              \
+            pf[i][q] = *reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p)); \
+    }
+
+    DEDISP_LOAD_BASE(0)
+    DEDISP_LOAD_DATA(0)
+    DEDISP_LOAD_REL(0, vrel_nxt)
+    if (CC < nchans) {
+        DEDISP_LOAD_BASE(CC)
+    }
 
     int since_flush = 0;
     for (int c0 = 0; c0 < nchans; c0 += CC) {
         const int ncur = min(CC, nchans - c0);
+        __syncthreads();                       // everyone is done reading the previous chunk
+#pragma unroll
+        for (int i = 0; i < CPW; ++i) {
+            const int cl = wave + NW * i;
+            uint32_t* dst = lds + (size_t)cl * rw;
+#pragma unroll
+            for (int q = 0; q < PM; ++q) {
+                const int p = lane + 64 * q;
+                if (cl < ncur && p < rq) *reinterpret_cast<u32x4*>(dst + 4 * p) = pf[i][q];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RV; ++r) vrel_cur[r] = vrel_nxt[r];
         __syncthreads();
-        stg.template store<NT>(lds, rw, ncur >> 2, pi);
-        __syncthreads();
-        if (c0 + CC < nchans)
-            stg.template load_any<NT>(fast, b, basep + ((c0 + CC) >> 2), t0, (c0 + CC) >> 2,
-                                      min(G, (nchans - c0 - CC) >> 2), pi, seg, seg_row0);
+        if (c0 + CC < nchans) {
+            DEDISP_LOAD_DATA(c0 + CC)          // uses the window starts of chunk c0 + CC
+            DEDISP_LOAD_REL(c0 + CC, vrel_nxt)
+            if (c0 + 2 * CC < nchans) {
+                DEDISP_LOAD_BASE(c0 + 2 * CC)
+            }
+        }
+#undef DEDISP_LOAD_BASE
+#undef DEDISP_LOAD_REL
+#undef DEDISP_LOAD_DATA
 
         const uint32_t* lrow = lds + lane * M;
-        // delays of 4 channels x DPW DMs, fetched one step ahead
-        int4 rnext[DPW];
+        for (int c = 0; c < ncur; ++c) {
+            const uint32_t* row = lrow + (size_t)c * rw;
 #pragma unroll
-        for (int k = 0; k < DPW; ++k)
-            rnext[k] = *reinterpret_cast<const int4*>(b.rel + rel_row0 + k * nchans + c0);
-        for (int c = 0; c < ncur; c += 4) {
-            int4 rcur[DPW];
+            for (int k = 0; k < DPW; ++k) {
+                // window offset of (DM k, channel c): register k / KPR, lane (k % KPR)*CC + c
+                const int r = lane_value(vrel_cur[k / KPR], (k % KPR) * CC + c);
+                const uint32_t* src = row + (r >> 2);
+                const uint32_t s = (uint32_t)(r & 3);
+                uint32_t w[M + 1];
 #pragma unroll
-            for (int k = 0; k < DPW; ++k) rcur[k] = rnext[k];
-            if (c + 4 < ncur) {
+                for (int j = 0; j <= M; ++j) w[j] = src[j];
+                if constexpr (NBITS == 2) {
 #pragma unroll
-                for (int k = 0; k < DPW; ++k)
-                    rnext[k] = *reinterpret_cast<const int4*>(b.rel + rel_row0 + k * nchans + c0 + c + 4);
-            }
+                    for (int j = 0; j < M; ++j)
+                        sw[k][j][0] += __builtin_amdgcn_alignbyte(w[j + 1], w[j], s);
+                } else {
+                    // bytes s, s+1 -> 16-bit lanes of sw[0]; s+2, s+3 -> sw[1]
+                    const uint32_t sel_lo = s | 0x0C00u | ((s + 1u) << 16) | 0x0C000000u;
+                    const uint32_t sel_hi = sel_lo + 0x00020002u;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t* row = lrow + (size_t)(c + q) * rw;
-#pragma unroll
-                for (int k = 0; k < DPW; ++k) {
-                    const int r = q == 0 ? rcur[k].x : q == 1 ? rcur[k].y : q == 2 ? rcur[k].z : rcur[k].w;
-                    const uint32_t* src = row + (r >> 2);
-                    const uint32_t s = (uint32_t)(r & 3);
-                    uint32_t w[M + 1];
-#pragma unroll
-                    for (int j = 0; j <= M; ++j) w[j] = src[j];
-                    if constexpr (NBITS == 2) {
-#pragma unroll
-                        for (int j = 0; j < M; ++j)
-                            sw[k][j][0] += __builtin_amdgcn_alignbyte(w[j + 1], w[j], s);
-                    } else {
-                        // bytes s, s+1 -> 16-bit lanes of `lo`; s+2, s+3 -> `hi`
-                        const uint32_t sel_lo = s | 0x0C00u | ((s + 1u) << 16) | 0x0C000000u;
-                        const uint32_t sel_hi = sel_lo + 0x00020002u;
-#pragma unroll
-                        for (int j = 0; j < M; ++j) {
-                            sw[k][j][0] += __builtin_amdgcn_perm(w[j + 1], w[j], sel_lo);
-                            sw[k][j][1] += __builtin_amdgcn_perm(w[j + 1], w[j], sel_hi);
-                        }
+                    for (int j = 0; j < M; ++j) {
+                        sw[k][j][0] += __builtin_amdgcn_perm(w[j + 1], w[j], sel_lo);
+                        sw[k][j][1] += __builtin_amdgcn_perm(w[j + 1], w[j], sel_hi);
                     }
                 }
             }
         }
 
-        if (++since_flush == b.flush_every || c0 + CC >= nchans) {
+        if (++since_flush == FLUSH || c0 + CC >= nchans) {
             since_flush = 0;
 #pragma unroll
             for (int k = 0; k < DPW; ++k)
@@ -272,10 +300,8 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
                 for (int j = 0; j < M; ++j) {
                     if constexpr (NBITS == 2) {
                         const uint32_t v = sw[k][j][0];
-                        acc[k][j][0] += v & 0xFFu;
-                        acc[k][j][1] += (v >> 8) & 0xFFu;
-                        acc[k][j][2] += (v >> 16) & 0xFFu;
-                        acc[k][j][3] += v >> 24;
+                        acc[k][j][0] += v & 0x00FF00FFu;
+                        acc[k][j][1] += (v >> 8) & 0x00FF00FFu;
                     } else {
                         const uint32_t lo = sw[k][j][0], hi = sw[k][j][1];
                         acc[k][j][0] += lo & 0xFFFFu;
@@ -299,26 +325,37 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             const long long t = t0 + 4LL * (lane * M + j);
+            uint32_t o[4];
+            if constexpr (NBITS == 2) {
+                o[0] = acc[k][j][0] & 0xFFFFu;
+                o[1] = acc[k][j][1] & 0xFFFFu;
+                o[2] = acc[k][j][0] >> 16;
+                o[3] = acc[k][j][1] >> 16;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) o[e] = acc[k][j][e];
+            }
             if (vec && t + 3 < b.nout) {
-                *reinterpret_cast<uint4*>(orow + t) =
-                    make_uint4(acc[k][j][0], acc[k][j][1], acc[k][j][2], acc[k][j][3]);
+                *reinterpret_cast<u32x4*>(orow + t) = u32x4{o[0], o[1], o[2], o[3]};
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    if (t + e < b.nout) orow[t + e] = acc[k][j][e];
+                    if (t + e < b.nout) orow[t + e] = o[e];
             }
         }
     }
 }
 
-template <int NBITS, int NW, int DPW, int M, int CC, int PI>
+template <int NBITS, int NW, int DPW, int M, int CC, int PM>
 __global__ __launch_bounds__(NW * 64) void k_tiled(BeamDesc b)
 {
     extern __shared__ uint32_t lds_dyn[];
     const int n = b.ntiles * b.nblocks;
     const int logical = xcd_remap((int)blockIdx.x, n);
-    tile_body<NBITS, NW, DPW, M, CC, PI>(b, logical / b.nblocks, logical % b.nblocks, lds_dyn);
+    tile_body<NBITS, NW, DPW, M, CC, PM>(b, logical / b.nblocks, logical % b.nblocks, lds_dyn);
 }
+
+// ------------------------------------------------------------ untiled
 
 template <int NBITS>
 __device__ __forceinline__ uint32_t sample_at(const BeamDesc& b, long long r, int c)
@@ -351,32 +388,32 @@ __global__ __launch_bounds__(256) void k_untiled(BeamDesc b)
 
 // ---------------------------------------------------------------- shapes
 
-// (nbits, waves, DMs per wave, words per lane, channels per chunk, staging
-// slabs).  A slab is one staged word per thread per channel group, so a shape
-// fits a DM block whose window is at most slabs*waves*64 words long.
-#define DEDISP_SHAPES(X)        \
-    X(2, 4, 4, 5, 32, 2)        \
-    X(2, 4, 4, 5, 64, 2)        \
-    X(2, 4, 8, 3, 32, 2)        \
-    X(2, 4, 8, 5, 32, 2)        \
-    X(2, 4, 4, 3, 32, 2)        \
-    X(2, 4, 2, 7, 32, 3)        \
-    X(2, 8, 4, 5, 64, 1)        \
-    X(2, 8, 2, 5, 64, 1)        \
-    X(8, 4, 4, 5, 16, 2)        \
-    X(8, 4, 4, 5, 32, 2)        \
-    X(8, 4, 8, 3, 16, 2)        \
-    X(8, 4, 4, 3, 32, 2)        \
-    X(8, 8, 4, 3, 32, 1)        \
-    X(8, 8, 4, 5, 16, 1)
+// (nbits, waves, DMs per wave, words per lane, channels per chunk, pieces):
+// a tile is 256*words samples long; a staged channel row holds at most
+// 64*pieces 16-byte pieces (1024*pieces samples).
+#define DEDISP_SHAPES(X)          \
+    X(2, 8, 4, 5, 32, 2)          \
+    X(2, 8, 4, 5, 64, 2)          \
+    X(2, 8, 2, 5, 64, 2)          \
+    X(2, 8, 4, 3, 32, 2)          \
+    X(2, 4, 4, 5, 32, 2)          \
+    X(2, 4, 8, 5, 32, 2)          \
+    X(2, 4, 8, 3, 32, 2)          \
+    X(2, 16, 2, 5, 64, 2)         \
+    X(8, 8, 4, 5, 32, 2)          \
+    X(8, 8, 2, 5, 64, 2)          \
+    X(8, 8, 4, 3, 32, 2)          \
+    X(8, 4, 4, 5, 32, 2)          \
+    X(8, 4, 8, 3, 32, 2)          \
+    X(8, 16, 2, 5, 64, 2)
 
 struct ShapeEntry {
     Shape s;
     const void* fn;
 };
 
-#define DEDISP_ENTRY(NB, NW, DPW, M, CC, PI) \
-    {Shape{0, NB, NW, DPW, M, CC, PI}, reinterpret_cast<const void*>(&k_tiled<NB, NW, DPW, M, CC, PI>)},
+#define DEDISP_ENTRY(NB, NW, DPW, M, CC, PM) \
+    {Shape{0, NB, NW, DPW, M, CC, PM}, reinterpret_cast<const void*>(&k_tiled<NB, NW, DPW, M, CC, PM>)},
 
 const ShapeEntry kShapes[] = {
     DEDISP_SHAPES(DEDISP_ENTRY)
@@ -386,13 +423,13 @@ const ShapeEntry kShapes[] = {
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 // Persistent kernel: the shapes with kPersistentWaves waves.
-template <int NBITS, int NW, int DPW, int M, int CC, int PI>
+template <int NBITS, int NW, int DPW, int M, int CC, int PM>
 __device__ __forceinline__ bool run_if(int shape_id, int want, const BeamDesc& b, int tile,
                                        int block, uint32_t* lds)
 {
     if constexpr (NW == kPersistentWaves) {
         if (shape_id == want) {
-            tile_body<NBITS, NW, DPW, M, CC, PI>(b, tile, block, lds);
+            tile_body<NBITS, NW, DPW, M, CC, PM>(b, tile, block, lds);
             return true;
         }
     }
@@ -418,8 +455,8 @@ __global__ __launch_bounds__(kPersistentWaves * 64) void k_persistent(
         const int block = (int)(local % b.nblocks);
         int id = 0;
         bool done = false;
-#define DEDISP_RUN(NB, NW, DPW, M, CC, PI) \
-    if (!done) done = run_if<NB, NW, DPW, M, CC, PI>(b.shape, id, b, tile, block, lds_dyn); \
+#define DEDISP_RUN(NB, NW, DPW, M, CC, PM) \
+    if (!done) done = run_if<NB, NW, DPW, M, CC, PM>(b.shape, id, b, tile, block, lds_dyn); \
     ++id;
         DEDISP_SHAPES(DEDISP_RUN)
 #undef DEDISP_RUN
@@ -452,6 +489,18 @@ hipError_t ensure_lds_attr(int idx, const void* fn)
 
 int shape_count() { return kNumShapes; }
 const Shape& shape_at(int i) { return kShapes[i].s; }
+
+hipError_t launch_unpack(const BeamDesc& d, int nbits, hipStream_t st)
+{
+    const long long gx = (d.nsamps + kUT - 1) / kUT;
+    const long long gy = (d.nchans + kUC - 1) / kUC;
+    if (gx <= 0 || gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidValue;
+    BeamDesc arg = d;
+    void* args[] = {&arg};
+    const void* fn = nbits == 2 ? reinterpret_cast<const void*>(&k_unpack<2>)
+                                : reinterpret_cast<const void*>(&k_unpack<8>);
+    return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, 0, st);
+}
 
 hipError_t launch_tiled(const BeamDesc& d, const Shape& s, int lds_bytes, hipStream_t st)
 {
