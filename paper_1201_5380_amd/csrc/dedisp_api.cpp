@@ -5,6 +5,7 @@
 // HIP call.
 #include "dedisp.h"
 #include "dedisp_internal.h"
+#include "dedisp_host.h"
 
 #include <algorithm>
 #include <chrono>
@@ -21,7 +22,8 @@
 using dedisp::BeamDesc;
 using dedisp::Shape;
 
-namespace {
+namespace dedisp {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -37,12 +39,6 @@ dedisp_status hip_fail(hipError_t e, const char* where)
     return DEDISP_ERR_HIP;
 }
 
-#define HIP_TRY(call)                                                          \
-    do {                                                                       \
-        hipError_t e_ = (call);                                                \
-        if (e_ != hipSuccess) return hip_fail(e_, #call);                      \
-    } while (0)
-
 // Dispersion constant k_DM, MHz^2 pc^-1 cm^3 s (Section 1 of the paper).
 constexpr double kDispersionConstant = 4.148808e3;
 
@@ -51,38 +47,6 @@ constexpr double kDispersionConstant = 4.148808e3;
 // 65535/255 for 8-bit codes in 16-bit lanes.
 constexpr int kLaneSum2Bit = 85;
 constexpr int kLaneSum8Bit = 257;
-
-// Device tables for one DM-block size.
-struct BlockTables {
-    int db = 0;
-    int nblocks = 0;
-    int relmax = 0;
-    std::vector<int32_t> rel;    // [nblocks*db][nchans]
-    std::vector<int32_t> base;   // [nblocks][nchans]
-    int32_t* d_rel = nullptr;
-    int32_t* d_base = nullptr;
-};
-
-}  // namespace
-
-struct dedisp_plan_s {
-    int nchans = 0;
-    int nbits = 0;
-    double dt = 0, f_top = 0, df = 0;
-    int row_bytes = 0;
-    std::vector<double> dms;
-    std::vector<int32_t> table;     // [ndm][nchans]
-    int max_delay = 0;
-    bool has_dms = false;
-    dedisp_tile_config cfg{};
-    int device = -1;
-    int32_t* d_table = nullptr;
-    std::map<int, BlockTables> blocks;  // keyed by DM-block size
-    uint8_t* d_xc = nullptr;            // channel-major scratch for the tiled kernel
-    size_t xc_bytes = 0;
-};
-
-namespace {
 
 void free_device(dedisp_plan p)
 {
@@ -94,9 +58,7 @@ void free_device(dedisp_plan p)
         if (kv.second.d_base) (void)hipFree(kv.second.d_base);
     }
     p->blocks.clear();
-    if (p->d_xc) (void)hipFree(p->d_xc);
-    p->d_xc = nullptr;
-    p->xc_bytes = 0;
+    free_scratch(p->xc);
 }
 
 bool is_finite(double x) { return std::isfinite(x); }
@@ -159,7 +121,7 @@ void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
     }
 }
 
-const Shape* find_shape(const dedisp_tile_config& c, int nbits, int* index = nullptr)
+const Shape* find_shape(const dedisp_tile_config& c, int nbits, int* index)
 {
     for (int i = 0; i < dedisp::shape_count(); ++i) {
         const Shape& s = dedisp::shape_at(i);
@@ -192,15 +154,6 @@ dedisp_tile_config default_config(int nbits)
     c.kind = 1;
     return c;
 }
-
-// A concrete launch plan for one beam: shape, LDS size and the descriptor
-// fields that depend on it.
-struct LaunchPlan {
-    int shape_index = -1;
-    Shape shape{};
-    int cc = 0, rw = 0, lds = 0, flush_every = 1;
-    BlockTables* bt = nullptr;
-};
 
 dedisp_status ensure_device_table(dedisp_plan p)
 {
@@ -276,15 +229,21 @@ bool tiled_supported(const dedisp_plan_s& p)
 // fits, else the first compiled tiled shape of the same bit depth that fits,
 // else the untiled kernel.  Host-only (no HIP call) when `upload` is false.
 dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool upload,
-                             LaunchPlan& lp)
+                             LaunchPlan& lp, bool persistent_only)
 {
     int idx = -1;
     if (!find_shape(want, p->nbits, &idx)) return fail(DEDISP_ERR_INVALID_ARG, "unknown tile shape");
     std::vector<int> order{idx};
     for (int i = 0; i < dedisp::shape_count(); ++i)
         if (i != idx) order.push_back(i);
+    if (persistent_only) {
+        std::vector<int> keep;
+        for (int i : order)
+            if (dedisp::shape_at(i).persist) keep.push_back(i);
+        order.swap(keep);
+    }
     std::map<int, BlockTables> host_tables;
-    if (want.kind == 1) order.clear();
+    if (want.kind == 1 && !persistent_only) order.clear();
     for (int i : order) {
         const Shape& s = dedisp::shape_at(i);
         if (s.nbits != p->nbits || s.kind != 0 || !tiled_supported(*p)) continue;
@@ -335,27 +294,37 @@ long long tile_len(const Shape& s) { return 256LL * s.m; }
 // may run up to 4*rw bytes past the last sample.
 long long xc_pitch(long long nsamps, int rw) { return ((nsamps + 4LL * rw + 63) / 64) * 64; }
 
-dedisp_status ensure_xc(dedisp_plan p, long long nsamps, int rw)
+void free_scratch(Scratch& x)
 {
-    const size_t need = static_cast<size_t>(xc_pitch(nsamps, rw)) * p->nchans;
-    if (p->d_xc && p->xc_bytes >= need) return DEDISP_OK;
-    if (p->d_xc) {
-        HIP_TRY(hipDeviceSynchronize());
-        (void)hipFree(p->d_xc);
-        p->d_xc = nullptr;
-        p->xc_bytes = 0;
+    if (x.ptr) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(x.ptr);
     }
-    if (hipMalloc(&p->d_xc, need) != hipSuccess) {
-        p->d_xc = nullptr;
+    x.ptr = nullptr;
+    x.bytes = 0;
+}
+
+dedisp_status ensure_scratch(Scratch& x, size_t need)
+{
+    if (x.ptr && x.bytes >= need) return DEDISP_OK;
+    free_scratch(x);
+    if (hipMalloc(&x.ptr, need) != hipSuccess) {
+        x.ptr = nullptr;
         return fail(DEDISP_ERR_OOM, "hipMalloc channel-major scratch");
     }
-    p->xc_bytes = need;
+    x.bytes = need;
     return DEDISP_OK;
+}
+
+dedisp_status ensure_xc(const dedisp_plan_s& p, Scratch& x, long long nsamps, const LaunchPlan& lp)
+{
+    if (lp.shape.kind != 0) return DEDISP_OK;
+    return ensure_scratch(x, static_cast<size_t>(xc_pitch(nsamps, lp.rw)) * p.nchans);
 }
 
 void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n0,
                const void* in1, long long nsamps, uint32_t* out, long long stride,
-               BeamDesc& d)
+               uint8_t* xc, BeamDesc& d)
 {
     std::memset(&d, 0, sizeof(d));
     d.in0 = static_cast<const uint8_t*>(in0);
@@ -371,7 +340,7 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
     d.ndm = static_cast<int>(p->dms.size());
     d.shape = lp.shape_index;
     if (lp.shape.kind == 0) {
-        d.xc = p->d_xc;
+        d.xc = xc;
         d.pitch = xc_pitch(nsamps, lp.rw);
         d.rel = lp.bt->d_rel;
         d.base = lp.bt->d_base;
@@ -453,7 +422,10 @@ void write_cache(const char* path, const std::map<std::string, std::vector<doubl
     std::rename(tmp.c_str(), path);
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace dedisp
+
+using namespace dedisp::host;
 
 // =================================================================== C ABI
 
@@ -626,13 +598,11 @@ dedisp_status dedisp_execute(dedisp_plan p, const void* d_in, size_t nsamps, uin
         st = resolve_launch(p, u, true, lp);
         if (st != DEDISP_OK) return st;
     }
-    if (lp.shape.kind == 0) {
-        st = ensure_xc(p, static_cast<long long>(nsamps), lp.rw);
-        if (st != DEDISP_OK) return st;
-    }
+    st = ensure_xc(*p, p->xc, static_cast<long long>(nsamps), lp);
+    if (st != DEDISP_OK) return st;
     BeamDesc d;
     fill_desc(p, lp, d_in, static_cast<long long>(nsamps), nullptr,
-              static_cast<long long>(nsamps), d_out, static_cast<long long>(stride), d);
+              static_cast<long long>(nsamps), d_out, static_cast<long long>(stride), p->xc.ptr, d);
     hipError_t e = launch_desc(d, lp, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return DEDISP_OK;

@@ -1,0 +1,109 @@
+// Host-side internals shared by the library's translation units: the plan
+// object behind the opaque dedisp_plan handle and the helpers that turn a
+// plan plus buffers into kernel launches.  Not part of the ABI.
+#pragma once
+
+#include "dedisp.h"
+#include "dedisp_internal.h"
+
+#include <map>
+#include <string>
+#include <vector>
+
+#define HIP_TRY(call)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess) return ::dedisp::host::hip_fail(e_, #call);      \
+    } while (0)
+
+namespace dedisp {
+namespace host {
+
+// Record an error message for dedisp_last_error and return the status.
+dedisp_status fail(dedisp_status st, const std::string& msg);
+dedisp_status hip_fail(hipError_t e, const char* where);
+
+// Window tables of one DM-block size (see build_block_tables).
+struct BlockTables {
+    int db = 0;
+    int nblocks = 0;
+    int relmax = 0;
+    std::vector<int32_t> rel;    // [nblocks*db][nchans]
+    std::vector<int32_t> base;   // [nblocks][nchans]
+    int32_t* d_rel = nullptr;
+    int32_t* d_base = nullptr;
+};
+
+// A device buffer that only grows.
+struct Scratch {
+    uint8_t* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// A resolved launch for one beam: shape, LDS size and window length.
+struct LaunchPlan {
+    int shape_index = -1;
+    Shape shape{};
+    int cc = 0, rw = 0, lds = 0, flush_every = 1;
+    BlockTables* bt = nullptr;
+};
+
+const Shape* find_shape(const dedisp_tile_config& c, int nbits, int* index = nullptr);
+dedisp_tile_config default_config(int nbits);
+bool tiled_supported(const struct ::dedisp_plan_s& p);
+
+// Resolve the shape used for plan p (requested one if it fits, else another
+// tiled shape, else the untiled kernel).  `upload` makes the device tables.
+// With persistent_only, only shapes compiled into the persistent kernel are
+// considered before the untiled fallback.
+dedisp_status resolve_launch(::dedisp_plan p, const dedisp_tile_config& want, bool upload,
+                             LaunchPlan& lp, bool persistent_only = false);
+
+long long tile_len(const Shape& s);
+long long xc_pitch(long long nsamps, int rw);
+void free_scratch(Scratch& x);
+dedisp_status ensure_scratch(Scratch& x, size_t need);
+dedisp_status ensure_xc(const struct ::dedisp_plan_s& p, Scratch& x, long long nsamps,
+                        const LaunchPlan& lp);
+dedisp_status ensure_device_table(::dedisp_plan p);
+
+// Descriptor of one transform over the virtual input [in0 (n0 rows) | in1].
+void fill_desc(::dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n0,
+               const void* in1, long long nsamps, uint32_t* out, long long stride,
+               uint8_t* xc, BeamDesc& d);
+// Corner turn (tiled shapes) + transform, on one stream.
+hipError_t launch_desc(const BeamDesc& d, const LaunchPlan& lp, hipStream_t st);
+
+// One transform ready to enqueue.
+struct Item {
+    BeamDesc d{};
+    LaunchPlan lp;
+};
+// Enqueue every item on one stream: the corner turns, then the tiled items as
+// persistent launches of up to kMaxBatchDescs beams each (every tiled item
+// must use a persistent shape), then the untiled items one launch each.
+hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st);
+
+std::string cache_key(::dedisp_plan p, size_t nsamps);
+std::map<std::string, std::vector<double>> read_cache(const char* path);
+void write_cache(const char* path, const std::map<std::string, std::vector<double>>& m);
+
+}  // namespace host
+}  // namespace dedisp
+
+// The object behind dedisp_plan.
+struct dedisp_plan_s {
+    int nchans = 0;
+    int nbits = 0;
+    double dt = 0, f_top = 0, df = 0;
+    int row_bytes = 0;
+    std::vector<double> dms;
+    std::vector<int32_t> table;     // [ndm][nchans]
+    int max_delay = 0;
+    bool has_dms = false;
+    dedisp_tile_config cfg{};
+    int device = -1;
+    int32_t* d_table = nullptr;
+    std::map<int, dedisp::host::BlockTables> blocks;  // keyed by DM-block size
+    dedisp::host::Scratch xc;                          // channel-major scratch for execute
+};

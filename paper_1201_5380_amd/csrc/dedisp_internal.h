@@ -45,6 +45,7 @@ struct Shape {
     int m;          // 32-bit words per lane (4 samples each)
     int cc;         // channels staged per chunk
     int pi;         // 16-byte pieces per lane per staged row: row <= 64*pi pieces
+    int persist;    // also compiled into the persistent kernel
 };
 
 // Shapes compiled into the library (index = shape id).
@@ -61,13 +62,17 @@ hipError_t launch_unpack(const BeamDesc& d, int nbits, hipStream_t st);
 hipError_t launch_tiled(const BeamDesc& d, const Shape& s, int lds_bytes, hipStream_t st);
 hipError_t launch_untiled(const BeamDesc& d, int nbits, hipStream_t st);
 
-// Persistent launch over a device array of beam descriptors; every shape
-// used must have waves == kPersistentWaves.  counters: two device uint32
-// zeroed once at allocation; the kernel leaves them zero when it ends.
-constexpr int kPersistentWaves = 4;
-hipError_t launch_persistent(const BeamDesc* d_descs, int nbeams, long long total_work,
-                             unsigned int* d_counters, int lds_bytes, int grid,
-                             hipStream_t st);
+// Persistent launch over up to kMaxBatchDescs beams whose descriptors travel
+// in the kernel arguments (work_begin = prefix sum of ntiles*nblocks).  Every
+// beam must use a shape marked persistent; the LDS size is the largest any
+// beam needs.
+constexpr int kPersistentWaves = 8;
+constexpr int kMaxBatchDescs = 16;
+struct DescBlock {
+    BeamDesc d[kMaxBatchDescs];
+};
+hipError_t launch_persistent(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
+                             int grid, hipStream_t st);
 int persistent_max_grid(int lds_bytes);
 
 }  // namespace dedisp

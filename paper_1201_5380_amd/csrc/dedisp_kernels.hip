@@ -388,46 +388,53 @@ __global__ __launch_bounds__(256) void k_untiled(BeamDesc b)
 
 // ---------------------------------------------------------------- shapes
 
-// (nbits, waves, DMs per wave, words per lane, channels per chunk, pieces):
-// a tile is 256*words samples long; a staged channel row holds at most
-// 64*pieces 16-byte pieces (1024*pieces samples).
-#define DEDISP_SHAPES(X)          \
-    X(2, 8, 4, 5, 32, 2)          \
-    X(2, 8, 4, 5, 64, 2)          \
-    X(2, 8, 2, 5, 64, 2)          \
-    X(2, 8, 4, 3, 32, 2)          \
-    X(2, 4, 4, 5, 32, 2)          \
-    X(2, 4, 8, 5, 32, 2)          \
-    X(2, 4, 8, 3, 32, 2)          \
-    X(2, 16, 2, 5, 64, 2)         \
-    X(8, 8, 4, 5, 32, 2)          \
-    X(8, 8, 2, 5, 64, 2)          \
-    X(8, 8, 4, 3, 32, 2)          \
-    X(8, 4, 4, 5, 32, 2)          \
-    X(8, 4, 8, 3, 32, 2)          \
-    X(8, 16, 2, 5, 64, 2)
+// (nbits, waves, DMs per wave, words per lane, channels per chunk, pieces,
+// persistent): a tile is 256*words samples long; a staged channel row holds
+// at most 64*pieces 16-byte pieces (1024*pieces samples); shapes marked
+// persistent are also compiled into the multi-beam persistent kernel (which
+// allocates registers for the largest of them).  The first shape of each bit
+// depth is the default.
+#define DEDISP_SHAPES(X)             \
+    X(2, 8, 4, 5, 32, 2, 1)          \
+    X(2, 8, 4, 3, 32, 2, 1)          \
+    X(2, 8, 4, 5, 64, 2, 0)          \
+    X(2, 8, 2, 5, 64, 2, 0)          \
+    X(2, 4, 4, 5, 32, 2, 0)          \
+    X(2, 4, 8, 5, 32, 2, 0)          \
+    X(2, 4, 8, 3, 32, 2, 0)          \
+    X(2, 16, 2, 5, 64, 2, 0)         \
+    X(8, 8, 2, 5, 32, 2, 1)          \
+    X(8, 8, 4, 3, 32, 2, 0)          \
+    X(8, 8, 4, 5, 32, 2, 0)          \
+    X(8, 8, 2, 5, 64, 2, 0)          \
+    X(8, 4, 4, 5, 32, 2, 0)          \
+    X(8, 4, 8, 3, 32, 2, 0)          \
+    X(8, 16, 2, 5, 64, 2, 0)
 
 struct ShapeEntry {
     Shape s;
     const void* fn;
 };
 
-#define DEDISP_ENTRY(NB, NW, DPW, M, CC, PM) \
-    {Shape{0, NB, NW, DPW, M, CC, PM}, reinterpret_cast<const void*>(&k_tiled<NB, NW, DPW, M, CC, PM>)},
+#define DEDISP_ENTRY(NB, NW, DPW, M, CC, PM, PERSIST) \
+    {Shape{0, NB, NW, DPW, M, CC, PM, PERSIST}, reinterpret_cast<const void*>(&k_tiled<NB, NW, DPW, M, CC, PM>)},
 
 const ShapeEntry kShapes[] = {
     DEDISP_SHAPES(DEDISP_ENTRY)
-    {Shape{1, 2, 4, 1, 1, 0, 0}, reinterpret_cast<const void*>(&k_untiled<2>)},
-    {Shape{1, 8, 4, 1, 1, 0, 0}, reinterpret_cast<const void*>(&k_untiled<8>)},
+    {Shape{1, 2, 4, 1, 1, 0, 0, 0}, reinterpret_cast<const void*>(&k_untiled<2>)},
+    {Shape{1, 8, 4, 1, 1, 0, 0, 0}, reinterpret_cast<const void*>(&k_untiled<8>)},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
-// Persistent kernel: the shapes with kPersistentWaves waves.
-template <int NBITS, int NW, int DPW, int M, int CC, int PM>
+// Persistent kernel: the shapes marked persistent (all have
+// kPersistentWaves waves).  Work item i of beam b is (tile, DM block) =
+// divmod(i - work_begin, nblocks); workgroup g takes items g, g + grid, ...
+template <int NBITS, int NW, int DPW, int M, int CC, int PM, int PERSIST>
 __device__ __forceinline__ bool run_if(int shape_id, int want, const BeamDesc& b, int tile,
                                        int block, uint32_t* lds)
 {
-    if constexpr (NW == kPersistentWaves) {
+    if constexpr (PERSIST != 0) {
+        static_assert(NW == kPersistentWaves, "persistent shapes share one workgroup size");
         if (shape_id == want) {
             tile_body<NBITS, NW, DPW, M, CC, PM>(b, tile, block, lds);
             return true;
@@ -436,41 +443,27 @@ __device__ __forceinline__ bool run_if(int shape_id, int want, const BeamDesc& b
     return false;
 }
 
-__global__ __launch_bounds__(kPersistentWaves * 64) void k_persistent(
-    const BeamDesc* __restrict__ descs, int nbeams, long long total, unsigned int* counters)
+__global__ __launch_bounds__(kPersistentWaves * 64) void k_persistent(DescBlock blk, int nbeams,
+                                                                       int total)
 {
     extern __shared__ uint32_t lds_dyn[];
-    __shared__ unsigned int s_item;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = atomicAdd(&counters[0], 1u);
-        __syncthreads();
-        const long long item = (long long)wave_uniform((int)s_item);
-        if (item >= total) break;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
         int bi = 0;
-        while (bi + 1 < nbeams && descs[bi + 1].work_begin <= item) ++bi;
-        const BeamDesc& b = descs[bi];
-        const long long local = item - b.work_begin;
-        const int tile = (int)(local / b.nblocks);
-        const int block = (int)(local % b.nblocks);
+        while (bi + 1 < nbeams && blk.d[bi + 1].work_begin <= item) ++bi;
+        bi = wave_uniform(bi);
+        const BeamDesc& b = blk.d[bi];
+        const int local = item - (int)b.work_begin;
+        const int tile = local / b.nblocks;
+        const int block = local - tile * b.nblocks;
         int id = 0;
         bool done = false;
-#define DEDISP_RUN(NB, NW, DPW, M, CC, PM) \
-    if (!done) done = run_if<NB, NW, DPW, M, CC, PM>(b.shape, id, b, tile, block, lds_dyn); \
+#define DEDISP_RUN(NB, NW, DPW, M, CC, PM, PERSIST) \
+    if (!done) done = run_if<NB, NW, DPW, M, CC, PM, PERSIST>(b.shape, id, b, tile, block, lds_dyn); \
     ++id;
         DEDISP_SHAPES(DEDISP_RUN)
 #undef DEDISP_RUN
         (void)done;
-    }
-    // The last workgroup to finish re-arms the counters for the next launch.
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned int finished = atomicAdd(&counters[1], 1u);
-        if (finished == gridDim.x - 1) {
-            atomicExch(&counters[0], 0u);
-            atomicExch(&counters[1], 0u);
-            __threadfence();
-        }
+        __syncthreads();                     // LDS is reused by the next item
     }
 }
 
@@ -553,20 +546,19 @@ int persistent_max_grid(int lds_bytes)
     return ncu * per_cu;
 }
 
-hipError_t launch_persistent(const BeamDesc* d_descs, int nbeams, long long total_work,
-                             unsigned int* d_counters, int lds_bytes, int grid, hipStream_t st)
+hipError_t launch_persistent(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
+                             int grid, hipStream_t st)
 {
-    if (grid <= 0 || nbeams <= 0 || total_work <= 0 || total_work >= 0x7fffffffLL)
+    if (grid <= 0 || nbeams <= 0 || nbeams > kMaxBatchDescs || total_work <= 0)
         return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persistent),
                                        hipFuncAttributeMaxDynamicSharedMemorySize,
                                        kMaxLdsBytes);
     if (e != hipSuccess) return e;
-    const BeamDesc* a0 = d_descs;
+    DescBlock a0 = blk;
     int a1 = nbeams;
-    long long a2 = total_work;
-    unsigned int* a3 = d_counters;
-    void* args[] = {&a0, &a1, &a2, &a3};
+    int a2 = total_work;
+    void* args[] = {&a0, &a1, &a2};
     return hipLaunchKernel(reinterpret_cast<const void*>(&k_persistent), dim3(grid),
                            dim3(kPersistentWaves * 64), args, (size_t)lds_bytes, st);
 }

@@ -120,3 +120,26 @@ def test_set_tile_config_rejects_unknown_shape(native):
     plan = Plan(64, 64e-6, 1500.0, -1.0, 8)
     with pytest.raises(DedispError):
         plan.set_tile_config(dict(kind=0, waves=3, dms_per_wave=4, words_per_lane=5, chunk_chans=32))
+
+
+def test_stream_and_batch_validation_precedes_hip(native):
+    L = lib()
+    out = ctypes.c_void_p()
+    assert L.dedisp_stream_create(None, ctypes.byref(out)) == -1
+    plan = Plan(64, 64e-6, 1500.0, -1.0, 8)
+    assert L.dedisp_stream_create(plan.handle, ctypes.byref(out)) == -2      # no DM list
+    assert L.dedisp_stream_create(plan.handle, None) == -1
+    n = ctypes.c_size_t(7)
+    assert L.dedisp_stream_push(None, None, 0, None, 0, ctypes.byref(n), None) == -1
+    assert L.dedisp_stream_reset(None) == -1
+    from paper_1201_5380_amd._native import BeamStruct
+    arr = (BeamStruct * 1)()
+    assert L.dedisp_batch_create(arr, 1, None, None, ctypes.byref(out)) == -1   # NULL fields
+    arr[0].plan = plan.handle.value
+    arr[0].d_in = 1 << 20
+    arr[0].d_out = 1 << 20
+    arr[0].nsamps = 10
+    assert L.dedisp_batch_create(arr, 1, None, None, ctypes.byref(out)) == -2   # no DM list
+    plan.set_dm_list([0.0, 50.0])
+    assert L.dedisp_batch_create(arr, 1, None, None, ctypes.byref(out)) == -3   # too few samples
+    assert L.dedisp_batch_create(arr, 0, None, None, ctypes.byref(out)) == -1
