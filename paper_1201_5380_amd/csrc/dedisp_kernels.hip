@@ -397,19 +397,18 @@ __global__ __launch_bounds__(256) void k_untiled(BeamDesc b)
 #define DEDISP_SHAPES(X)             \
     X(2, 8, 4, 5, 32, 2, 1)          \
     X(2, 8, 4, 3, 32, 2, 1)          \
+    X(2, 8, 4, 5, 16, 4, 1)          \
     X(2, 8, 4, 5, 64, 2, 0)          \
     X(2, 8, 2, 5, 64, 2, 0)          \
     X(2, 4, 4, 5, 32, 2, 0)          \
-    X(2, 4, 8, 5, 32, 2, 0)          \
-    X(2, 4, 8, 3, 32, 2, 0)          \
     X(2, 16, 2, 5, 64, 2, 0)         \
     X(8, 8, 2, 5, 32, 2, 1)          \
+    X(8, 8, 4, 3, 16, 4, 1)          \
     X(8, 8, 4, 3, 32, 2, 0)          \
     X(8, 8, 4, 5, 32, 2, 0)          \
     X(8, 8, 2, 5, 64, 2, 0)          \
-    X(8, 4, 4, 5, 32, 2, 0)          \
-    X(8, 4, 8, 3, 32, 2, 0)          \
-    X(8, 16, 2, 5, 64, 2, 0)
+    X(8, 16, 2, 5, 64, 2, 0)         \
+    X(8, 4, 4, 5, 32, 2, 0)
 
 struct ShapeEntry {
     Shape s;
