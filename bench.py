@@ -48,7 +48,127 @@ def parse():
                     help="HBM bytes per launch measured by rocprofv3 counters, if present")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-systems", action="store_true",
+                    help="skip the batched and serving measurements")
+    ap.add_argument("--serve-seconds", type=float, default=12.0)
     return ap.parse_args()
+
+
+def device_codes(torch, gen, nsamps, nchans, nbits, dev):
+    """Seeded synthetic input made on the device (timing runs only): 2-bit level
+    codes with probabilities .16/.34/.34/.16 packed four per byte, or 8-bit
+    rint(N(128, 16)) clipped to [0, 255]."""
+    if nbits == 2:
+        u = torch.randint(0, 100, (nsamps, nchans), generator=gen, device=dev, dtype=torch.int16)
+        c = (u >= 16).to(torch.uint8) + (u >= 50).to(torch.uint8) + (u >= 84).to(torch.uint8)
+        c = c.view(nsamps, nchans // 4, 4)
+        return (c[..., 0] | (c[..., 1] << 2) | (c[..., 2] << 4) | (c[..., 3] << 6)).contiguous()
+    z = torch.randn((nsamps, nchans), generator=gen, device=dev) * 16.0 + 128.0
+    return z.round_().clamp_(0, 255).to(torch.uint8)
+
+
+def bench_batch(torch, dev, steps):
+    """The 13-beam batched workload: one graph launch vs the beams run one by one."""
+    from paper_1201_5380_amd import Batch, Plan, synth
+    gen = torch.Generator(device=dev)
+    beams, plain_ms, outputs, adds = [], [], 0, 0
+    for b in range(13):
+        prm = synth.batch_beam_params(b)
+        gen.manual_seed(b)
+        plan = Plan(prm["nchans"], prm["dt"], prm["f_top"], prm["df"], prm["nbits"]).set_dm_list(
+            synth.dm_list_linear(prm["ndm"], prm["dm_max"]))
+        n = prm["nsamps"]
+        inp = device_codes(torch, gen, n, prm["nchans"], prm["nbits"], dev)
+        out = torch.empty((plan.ndm, n - plan.max_delay), dtype=torch.int32, device=dev)
+        beams.append((plan, inp, n, out, 0))
+        outputs += plan.ndm * (n - plan.max_delay)
+        adds += plan.ndm * (n - plan.max_delay) * prm["nchans"]
+    # plain form: each beam alone with its own tuned shape
+    for plan, inp, n, out, _ in beams:
+        plan.tune(inp, out, n)
+        for _ in range(2):
+            plan.execute(inp, n, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            plan.execute(inp, n, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        plain_ms.append(e0.elapsed_time(e1) / steps)
+    batch = Batch(beams)
+    for _ in range(2):
+        batch.execute()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        batch.execute()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"workload": "13 beams: nchans 1024 (8-bit) / 512 (2-bit), Nt in [2^16, 2^19], "
+                        "256-1024 DMs up to DM_max in [300, 1500]",
+            "graph_ms": ms, "outputs_per_s": outputs / (ms * 1e-3),
+            "channel_adds_per_s": adds / (ms * 1e-3),
+            "plain_sum_ms": float(sum(plain_ms)),
+            "plain_outputs_per_s": outputs / (sum(plain_ms) * 1e-3),
+            "batched_over_plain": float(sum(plain_ms)) / ms}
+
+
+def bench_serve(torch, dev, seconds):
+    """32 streams, chunks of U[2^14, 2^18] samples arriving as a Poisson process at
+    4x real time per stream (aggregate ~14.4 chunks/s), 64 GB admission budget."""
+    from paper_1201_5380_amd import Plan, synth
+    from paper_1201_5380_amd.serve import GpuExecutor, Server
+    nstreams, nchans = 32, 1024
+    plan = Plan(nchans, 64e-6, 1581.8, -0.390625, 2).set_dm_list(synth.dm_list_linear(1024, 1000.0))
+    rb = plan.row_bytes
+    pool_rows = (1 << 19) + (1 << 18)
+    pool = torch.from_numpy(synth.pack(synth.stream_codes(0, pool_rows, nchans), 2)).pin_memory()
+    pool_np = pool.numpy().reshape(pool_rows, rb)
+    mean_len = ((1 << 14) + (1 << 18)) / 2
+    rate = nstreams * 4.0 / (mean_len * 64e-6)
+    narr = int(rate * seconds) + 1
+    t_arr, sids = synth.poisson_arrivals(narr, rate, nstreams, seed=5)
+    lens = {s: list(synth.stream_chunk_lengths(s, narr)) for s in range(nstreams)}
+    offs = [(s * 104729) % (1 << 19) for s in range(nstreams)]
+
+    def chunk_of(s):
+        L = int(lens[s].pop(0))
+        o = offs[s]
+        offs[s] = (o + L) % (1 << 19)
+        return pool_np[o:o + L]
+
+    def run(open_loop):
+        ex = GpuExecutor([plan] * nstreams, device=dev)
+        srv = Server(ex, nstreams, budget_bytes=64 << 30, max_tick=16, max_inflight_ticks=4).start()
+        reqs = []
+        t0 = time.perf_counter()
+        for ta, s in zip(t_arr, sids):
+            if open_loop:
+                delay = t0 + ta - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            reqs.append(srv.submit(int(s), chunk_of(int(s))))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        srv.stop()
+        st = srv.stats()
+        outs = sum(r.n_out for r in reqs) * plan.ndm
+        rt = np.array([r.nsamps * 64e-6 for r in reqs])
+        lat = np.array([r.latency for r in reqs])
+        st.update({"wall_s": wall, "outputs_per_s": outs / wall,
+                   "p99_latency_over_chunk_duration": float(np.percentile(lat / rt, 99))})
+        return st
+
+    open_loop = run(True)
+    offs[:] = [(s * 7919) % (1 << 19) for s in range(nstreams)]
+    lens.update({s: list(synth.stream_chunk_lengths(s, narr)) for s in range(nstreams)})
+    saturated = run(False)
+    return {"workload": "32 streams x 2-bit 1024 ch, 1024 DMs in [0, 1000); chunks U[2^14, 2^18] "
+                        f"samples, Poisson arrivals at {rate:.1f} chunks/s (4x real time per stream), "
+                        "64 GB budget",
+            "open_loop": open_loop, "saturated": saturated}
 
 
 def cpu_baseline(packed, nsamps, nchans, nbits, table, budget_s):
@@ -57,13 +177,13 @@ def cpu_baseline(packed, nsamps, nchans, nbits, table, budget_s):
     ndm = table.shape[0]
     nout = nsamps - int(table.max())
     mx = int(table.max())
-    # calibrate on one DM row, then size the sample to the budget
-    t0 = time.perf_counter()
-    oracle.dedisperse(packed, nsamps, nchans, nbits, table[:1], max_delay=mx)
-    one = time.perf_counter() - t0
+    # calibrate on one DM row per thread, then size the sample to the budget
     threads = oracle.max_threads()
-    k = int(max(threads, min(ndm, budget_s / max(one, 1e-6))))
-    k = max(1, min(ndm, (k // threads) * threads or threads))
+    t0 = time.perf_counter()
+    oracle.dedisperse(packed, nsamps, nchans, nbits, table[:threads], max_delay=mx)
+    per_round = time.perf_counter() - t0
+    rounds = max(1, int(budget_s / max(per_round, 1e-6)))
+    k = max(1, min(ndm, rounds * threads))
     t0 = time.perf_counter()
     oracle.dedisperse(packed, nsamps, nchans, nbits, table[:k], max_delay=mx)
     dt = time.perf_counter() - t0
@@ -195,6 +315,12 @@ def main():
         "tune_best_ms": tune_ms,
         "device": torch.cuda.get_device_name(0),
     }
+    if not args.no_systems:
+        del got, out
+        torch.cuda.empty_cache()
+        result["batched"] = bench_batch(torch, dev, max(3, args.steps // 4))
+        torch.cuda.empty_cache()
+        result["serving"] = bench_serve(torch, dev, args.serve_seconds)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(packed, nsamps, nchans, beam.nbits, table,
                                               args.cpu_seconds)
