@@ -54,31 +54,16 @@ def parse():
     return ap.parse_args()
 
 
-def device_codes(torch, gen, nsamps, nchans, nbits, dev):
-    """Seeded synthetic input made on the device (timing runs only): 2-bit level
-    codes with probabilities .16/.34/.34/.16 packed four per byte, or 8-bit
-    rint(N(128, 16)) clipped to [0, 255]."""
-    if nbits == 2:
-        u = torch.randint(0, 100, (nsamps, nchans), generator=gen, device=dev, dtype=torch.int16)
-        c = (u >= 16).to(torch.uint8) + (u >= 50).to(torch.uint8) + (u >= 84).to(torch.uint8)
-        c = c.view(nsamps, nchans // 4, 4)
-        return (c[..., 0] | (c[..., 1] << 2) | (c[..., 2] << 4) | (c[..., 3] << 6)).contiguous()
-    z = torch.randn((nsamps, nchans), generator=gen, device=dev) * 16.0 + 128.0
-    return z.round_().clamp_(0, 255).to(torch.uint8)
-
-
 def bench_batch(torch, dev, steps):
     """The 13-beam batched workload: one graph launch vs the beams run one by one."""
     from paper_1201_5380_amd import Batch, Plan, synth
-    gen = torch.Generator(device=dev)
     beams, plain_ms, outputs, adds = [], [], 0, 0
     for b in range(13):
         prm = synth.batch_beam_params(b)
-        gen.manual_seed(b)
         plan = Plan(prm["nchans"], prm["dt"], prm["f_top"], prm["df"], prm["nbits"]).set_dm_list(
             synth.dm_list_linear(prm["ndm"], prm["dm_max"]))
         n = prm["nsamps"]
-        inp = device_codes(torch, gen, n, prm["nchans"], prm["nbits"], dev)
+        inp = synth.device_codes(n, prm["nchans"], prm["nbits"], seed=b, device=dev)
         out = torch.empty((plan.ndm, n - plan.max_delay), dtype=torch.int32, device=dev)
         beams.append((plan, inp, n, out, 0))
         outputs += plan.ndm * (n - plan.max_delay)
@@ -111,6 +96,8 @@ def bench_batch(torch, dev, steps):
             "graph_ms": ms, "outputs_per_s": outputs / (ms * 1e-3),
             "channel_adds_per_s": adds / (ms * 1e-3),
             "plain_sum_ms": float(sum(plain_ms)),
+            "plain_ms_per_beam": [round(x, 3) for x in plain_ms],
+            "plain_tiles": [p.tile_config() for p, *_ in beams],
             "plain_outputs_per_s": outputs / (sum(plain_ms) * 1e-3),
             "batched_over_plain": float(sum(plain_ms)) / ms}
 

@@ -92,16 +92,18 @@ bool build_delay_table(const dedisp_plan_s& p, const double* dms, int ndm,
 
 // Window tables for blocks of `db` consecutive DM rows: base[b][c] is the
 // smallest delay of channel c over the block, rounded down to a multiple of
-// 16 (so staged windows start on 16-byte boundaries); rel[b*db + k][c] =
-// delay[b*db + k][c] - base[b][c] (0 for padding rows past ndm), so one DM's
-// window offsets for consecutive channels are contiguous.
+// 16 (so staged windows start on 16-byte boundaries); the window offset of
+// DM row d, channel c is delay[d][c] - base[b][c] (0 for padding rows past
+// ndm), stored for channel pairs: rel[d][p] = off(2p) | off(2p+1) << 16.
+// relmax is the largest offset (always < 2^16 for a shape that fits).
 void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
 {
     const int ndm = static_cast<int>(p.dms.size());
     const int nch = p.nchans;
+    const int np = (nch + 1) / 2;
     bt.db = db;
     bt.nblocks = (ndm + db - 1) / db;
-    bt.rel.assign(static_cast<size_t>(bt.nblocks) * db * nch, 0);
+    bt.rel.assign(static_cast<size_t>(bt.nblocks) * db * np, 0u);
     bt.base.assign(static_cast<size_t>(bt.nblocks) * nch, 0);
     bt.relmax = 0;
     for (int b = 0; b < bt.nblocks; ++b) {
@@ -114,8 +116,9 @@ void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
             bt.base[static_cast<size_t>(b) * nch + c] = mn;
             for (int d = d0; d < d1; ++d) {
                 const int r = p.table[static_cast<size_t>(d) * nch + c] - mn;
-                bt.rel[static_cast<size_t>(d) * nch + c] = r;
                 bt.relmax = std::max(bt.relmax, r);
+                const uint32_t v = static_cast<uint32_t>(std::min(r, 0xFFFF));
+                bt.rel[static_cast<size_t>(d) * np + c / 2] |= (c & 1) ? (v << 16) : v;
             }
         }
     }
@@ -186,7 +189,7 @@ dedisp_status ensure_block_tables(dedisp_plan p, int db, BlockTables** out)
     if (!bt.d_rel) {
         dedisp_status st = ensure_device_table(p);
         if (st != DEDISP_OK) return st;
-        const size_t rb = bt.rel.size() * sizeof(int32_t), bb = bt.base.size() * sizeof(int32_t);
+        const size_t rb = bt.rel.size() * sizeof(uint32_t), bb = bt.base.size() * sizeof(int32_t);
         if (hipMalloc(&bt.d_rel, rb) != hipSuccess) {
             bt.d_rel = nullptr;
             return fail(DEDISP_ERR_OOM, "hipMalloc window table");
@@ -214,7 +217,7 @@ int window_words(const BlockTables& bt, const Shape& s)
 bool shape_fits(const BlockTables& bt, const Shape& s)
 {
     const int rw = window_words(bt, s);
-    return (rw >> 2) <= 64 * s.pi &&
+    return bt.relmax < 0x10000 && (rw >> 2) <= 64 * s.pi &&
            static_cast<long long>(s.cc) * rw * 4 <= dedisp::kMaxLdsBytes;
 }
 

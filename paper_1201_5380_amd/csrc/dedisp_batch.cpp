@@ -6,6 +6,7 @@
 #include "dedisp_host.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -16,6 +17,14 @@ using namespace dedisp::host;
 
 namespace dedisp {
 namespace host {
+
+// DEDISP_PERSISTENT_LOOP=1 selects the looping persistent kernel instead of
+// the one-workgroup-per-item multi-beam kernel (for comparison).
+static bool use_persistent_loop()
+{
+    const char* v = std::getenv("DEDISP_PERSISTENT_LOOP");
+    return v && v[0] == '1';
+}
 
 hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st)
 {
@@ -38,17 +47,22 @@ hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st)
         int lds = 0;
         for (size_t i = g0; i < g1; ++i) {
             BeamDesc& d = tiled[i]->d;
-            d.work_begin = total;
-            total += static_cast<long long>(d.ntiles) * d.nblocks;
+            d.work_begin = total;   // a multiple of 8: see the multi-beam kernel
+            total += (static_cast<long long>(d.ntiles) * d.nblocks + 7) / 8 * 8;
             lds = std::max(lds, tiled[i]->lp.lds);
             blk.d[i - g0] = d;
         }
         if (total > 0x7fffffffLL) return hipErrorInvalidValue;
-        const int maxg = persistent_max_grid(lds);
-        if (maxg <= 0) return hipErrorInvalidValue;
-        const int grid = static_cast<int>(std::min<long long>(total, maxg));
-        hipError_t e = launch_persistent(blk, static_cast<int>(g1 - g0), static_cast<int>(total),
-                                         lds, grid, st);
+        hipError_t e;
+        if (use_persistent_loop()) {
+            const int maxg = persistent_max_grid(lds);
+            if (maxg <= 0) return hipErrorInvalidValue;
+            const int grid = static_cast<int>(std::min<long long>(total, maxg));
+            e = launch_persistent(blk, static_cast<int>(g1 - g0), static_cast<int>(total), lds,
+                                  grid, st);
+        } else {
+            e = launch_multi(blk, static_cast<int>(g1 - g0), static_cast<int>(total), lds, st);
+        }
         if (e != hipSuccess) return e;
     }
     for (const Item& it : items)

@@ -28,9 +28,9 @@ struct BlockTables {
     int db = 0;
     int nblocks = 0;
     int relmax = 0;
-    std::vector<int32_t> rel;    // [nblocks*db][nchans]
+    std::vector<uint32_t> rel;   // [nblocks*db][nchans/2], channel pairs packed 16+16 bits
     std::vector<int32_t> base;   // [nblocks][nchans]
-    int32_t* d_rel = nullptr;
+    uint32_t* d_rel = nullptr;
     int32_t* d_base = nullptr;
 };
 

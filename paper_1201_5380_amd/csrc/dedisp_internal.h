@@ -21,7 +21,7 @@ struct BeamDesc {
     long long out_stride;     // elements between DM rows
     uint8_t* xc;              // channel-major bytes written by the unpack kernel
     long long pitch;          // bytes between channel rows of xc (multiple of 16)
-    const int32_t* rel;       // [nblocks*DB][nchans] delay minus window start
+    const uint32_t* rel;      // [nblocks*DB][nchans/2] window offsets of channel pairs (16+16 bits)
     const int32_t* base;      // [nblocks][nchans] window start (multiple of 16)
     const int32_t* table;     // [ndm][nchans] full delay table (untiled kernel)
     int nchans;
@@ -62,8 +62,9 @@ hipError_t launch_unpack(const BeamDesc& d, int nbits, hipStream_t st);
 hipError_t launch_tiled(const BeamDesc& d, const Shape& s, int lds_bytes, hipStream_t st);
 hipError_t launch_untiled(const BeamDesc& d, int nbits, hipStream_t st);
 
-// Persistent launch over up to kMaxBatchDescs beams whose descriptors travel
-// in the kernel arguments (work_begin = prefix sum of ntiles*nblocks).  Every
+// Multi-beam launches over up to kMaxBatchDescs beams whose descriptors
+// travel in the kernel arguments (work_begin = prefix sum of ntiles*nblocks,
+// each rounded up to a multiple of 8).  Every
 // beam must use a shape marked persistent; the LDS size is the largest any
 // beam needs.
 constexpr int kPersistentWaves = 8;
@@ -71,6 +72,10 @@ constexpr int kMaxBatchDescs = 16;
 struct DescBlock {
     BeamDesc d[kMaxBatchDescs];
 };
+// One workgroup per work item of every beam in one launch.
+hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
+                        hipStream_t st);
+// Grid sized to the machine, workgroups looping over the items.
 hipError_t launch_persistent(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
                              int grid, hipStream_t st);
 int persistent_max_grid(int lds_bytes);

@@ -59,6 +59,19 @@ __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_rea
 // struct it stays in registers when held in arrays.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+__device__ __forceinline__ long long wave_uniform64(long long x)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(x & 0xffffffffLL));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(x >> 32));
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T* wave_uniform_ptr(T* p)
+{
+    return reinterpret_cast<T*>(wave_uniform64(reinterpret_cast<long long>(p)));
+}
+
 __device__ __forceinline__ int lane_value(int v, int lane)
 {
     return __builtin_amdgcn_readlane(v, lane);
@@ -155,20 +168,24 @@ __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
 // One (time tile, DM block) work item.
 //   xc   channel-major bytes, row pitch b.pitch (multiple of 16)
 //   base [nblocks][nchans]  window start (multiple of 16) of channel c
-//   rel  [nblocks*DB][nchans] delay - base of DM row, channel c
-// LDS: CC rows of rw words (rw % 4 == 0).
+//   rel  [nblocks*DB][nchans/2] window offsets (delay - base) of a DM row
+//        for channels 2p and 2p+1 in the low and high 16 bits
+// LDS: CC rows of rw words (rw % 4 == 0).  Channels are summed in pairs so
+// the two realigned words of a pair fold into an accumulator with one
+// three-operand add, and one v_readlane fetches both offsets.
 template <int NBITS, int NW, int DPW, int M, int CC, int PM>
 __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block, uint32_t* lds)
 {
     static_assert(M % 2 == 1, "lanes must be an odd number of LDS words apart");
     static_assert(CC % NW == 0, "every wave stages the same number of channel rows");
-    static_assert((DPW * CC) % 64 == 0 && CC <= 64, "window offsets fill whole registers");
+    static_assert(CC <= 128 && (64 % (CC / 2)) == 0, "offset pairs of one DM sit in one register");
     static_assert(NBITS == 8 || CC <= 84, "2-bit lanes hold at most 85 codes");
     constexpr int T = 256 * M;
     constexpr int DB = NW * DPW;
     constexpr int CPW = CC / NW;           // channel rows staged per wave per chunk
-    constexpr int RV = DPW * CC / 64;      // registers of window offsets per wave
-    constexpr int KPR = 64 / CC;           // DMs per offset register
+    constexpr int CP = CC / 2;             // channel pairs per chunk
+    constexpr int KPR = 64 / CP;           // DMs per offset register
+    constexpr int RV = (DPW + KPR - 1) / KPR;  // registers of offset pairs per wave
     constexpr int NSW = NBITS == 2 ? 1 : 2;
     constexpr int NACC = NBITS == 2 ? 2 : 4;
     constexpr int LANE_SUM = NBITS == 2 ? 85 : 257;
@@ -180,12 +197,20 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     tile = wave_uniform(tile);
     block = wave_uniform(block);
     const long long t0 = (long long)tile * T;
-    const int nchans = b.nchans;
-    const int rw = b.rw;
+    // Every descriptor field is wave-uniform; keep them in scalar registers
+    // (the persistent kernel reads descriptors through a dynamic index).
+    const int nchans = wave_uniform(b.nchans);
+    const int rw = wave_uniform(b.rw);
     const int rq = rw >> 2;                // 16-byte pieces per row
-    const long long pitch = b.pitch;
-    const int32_t* base_row = b.base + (size_t)block * nchans;
-    const int32_t* rel_rows = b.rel + (size_t)(block * DB + wave * DPW) * nchans;
+    const long long pitch = wave_uniform64(b.pitch);
+    const long long nout = wave_uniform64(b.nout);
+    const long long out_stride = wave_uniform64(b.out_stride);
+    const int ndm = wave_uniform(b.ndm);
+    const uint8_t* xc = wave_uniform_ptr(b.xc);
+    uint32_t* out = wave_uniform_ptr(b.out);
+    const int32_t* base_row = wave_uniform_ptr(b.base) + (size_t)block * nchans;
+    const int npairs = nchans >> 1;
+    const uint32_t* rel_rows = wave_uniform_ptr(b.rel) + (size_t)(block * DB + wave * DPW) * npairs;
 
     // Packed-lane partial sums and wide accumulators.
     // 2-bit: sw = four 8-bit lanes (samples 0..3); acc[0] = 16-bit lanes
@@ -208,7 +233,7 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     // not stored, which keeps all of these arrays in registers.
     u32x4 pf[CPW][PM];
     int vbase_nxt = 0;         // lane i < CC: window start of channel c0 + i (next chunk)
-    int vrel_cur[RV], vrel_nxt[RV];
+    uint32_t vrel_cur[RV], vrel_nxt[RV];
     const int last_c = nchans - 1;
     const int last_p = rq - 1;
 
@@ -217,13 +242,14 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
 #define DEDISP_LOAD_REL(C0, DST)                                                    \
     _Pragma("unroll") for (int r = 0; r < RV; ++r) {                                \
         const int idx = 64 * r + lane;                                              \
-        DST[r] = rel_rows[(size_t)(idx / CC) * nchans + min((C0) + idx % CC, last_c)]; \
+        DST[r] = rel_rows[(size_t)min(idx / CP, DPW - 1) * npairs +                 \
+                          min(((C0) >> 1) + idx % CP, npairs - 1)];                 \
     }
 #define DEDISP_LOAD_DATA(C0)                                                        \
     _Pragma("unroll") for (int i = 0; i < CPW; ++i) {                               \
         const int cl = wave + NW * i;                                               \
         const int bs = lane_value(vbase_nxt, cl);                                   \
-        const uint8_t* src = b.xc + (long long)min((C0) + cl, last_c) * pitch + t0 + bs; \
+        const uint8_t* src = xc + (long long)min((C0) + cl, last_c) * pitch + t0 + bs; \
         _Pragma("unroll") for (int q = 0; q < PM; ++q)                              \
             pf[i][q] = *reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p)); \
     }
@@ -264,29 +290,39 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
 #undef DEDISP_LOAD_DATA
 
         const uint32_t* lrow = lds + lane * M;
-        for (int c = 0; c < ncur; ++c) {
-            const uint32_t* row = lrow + (size_t)c * rw;
+        for (int c = 0; c < ncur; c += 2) {
+            const uint32_t* row0 = lrow + (size_t)c * rw;
+            const uint32_t* row1 = row0 + rw;
 #pragma unroll
             for (int k = 0; k < DPW; ++k) {
-                // window offset of (DM k, channel c): register k / KPR, lane (k % KPR)*CC + c
-                const int r = lane_value(vrel_cur[k / KPR], (k % KPR) * CC + c);
-                const uint32_t* src = row + (r >> 2);
-                const uint32_t s = (uint32_t)(r & 3);
-                uint32_t w[M + 1];
+                // offsets of (DM k, channels c, c+1): register k / KPR, lane (k % KPR)*CP + c/2
+                const uint32_t rr = (uint32_t)lane_value((int)vrel_cur[k / KPR], (k % KPR) * CP + (c >> 1));
+                const uint32_t r0 = rr & 0xFFFFu, r1 = rr >> 16;
+                const uint32_t* src0 = row0 + (r0 >> 2);
+                const uint32_t* src1 = row1 + (r1 >> 2);
+                const uint32_t s0 = r0 & 3u, s1 = r1 & 3u;
+                uint32_t w0[M + 1], w1[M + 1];
 #pragma unroll
-                for (int j = 0; j <= M; ++j) w[j] = src[j];
+                for (int j = 0; j <= M; ++j) {
+                    w0[j] = src0[j];
+                    w1[j] = src1[j];
+                }
                 if constexpr (NBITS == 2) {
 #pragma unroll
                     for (int j = 0; j < M; ++j)
-                        sw[k][j][0] += __builtin_amdgcn_alignbyte(w[j + 1], w[j], s);
+                        sw[k][j][0] += __builtin_amdgcn_alignbyte(w0[j + 1], w0[j], s0) +
+                                       __builtin_amdgcn_alignbyte(w1[j + 1], w1[j], s1);
                 } else {
                     // bytes s, s+1 -> 16-bit lanes of sw[0]; s+2, s+3 -> sw[1]
-                    const uint32_t sel_lo = s | 0x0C00u | ((s + 1u) << 16) | 0x0C000000u;
-                    const uint32_t sel_hi = sel_lo + 0x00020002u;
+                    const uint32_t lo0 = s0 | 0x0C00u | ((s0 + 1u) << 16) | 0x0C000000u;
+                    const uint32_t lo1 = s1 | 0x0C00u | ((s1 + 1u) << 16) | 0x0C000000u;
+                    const uint32_t hi0 = lo0 + 0x00020002u, hi1 = lo1 + 0x00020002u;
 #pragma unroll
                     for (int j = 0; j < M; ++j) {
-                        sw[k][j][0] += __builtin_amdgcn_perm(w[j + 1], w[j], sel_lo);
-                        sw[k][j][1] += __builtin_amdgcn_perm(w[j + 1], w[j], sel_hi);
+                        sw[k][j][0] += __builtin_amdgcn_perm(w0[j + 1], w0[j], lo0) +
+                                       __builtin_amdgcn_perm(w1[j + 1], w1[j], lo1);
+                        sw[k][j][1] += __builtin_amdgcn_perm(w0[j + 1], w0[j], hi0) +
+                                       __builtin_amdgcn_perm(w1[j + 1], w1[j], hi1);
                     }
                 }
             }
@@ -315,13 +351,12 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
         }
     }
 
-    const bool vec = ((b.out_stride & 3) == 0) &&
-                     ((reinterpret_cast<uintptr_t>(b.out) & 15) == 0);
+    const bool vec = ((out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
 #pragma unroll
     for (int k = 0; k < DPW; ++k) {
         const int d = block * DB + wave * DPW + k;
-        if (d >= b.ndm) continue;
-        uint32_t* orow = b.out + (size_t)d * (size_t)b.out_stride;
+        if (d >= ndm) continue;
+        uint32_t* orow = out + (size_t)d * (size_t)out_stride;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             const long long t = t0 + 4LL * (lane * M + j);
@@ -335,12 +370,12 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
 #pragma unroll
                 for (int e = 0; e < 4; ++e) o[e] = acc[k][j][e];
             }
-            if (vec && t + 3 < b.nout) {
+            if (vec && t + 3 < nout) {
                 *reinterpret_cast<u32x4*>(orow + t) = u32x4{o[0], o[1], o[2], o[3]};
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    if (t + e < b.nout) orow[t + e] = o[e];
+                    if (t + e < nout) orow[t + e] = o[e];
             }
         }
     }
@@ -403,7 +438,8 @@ __global__ __launch_bounds__(256) void k_untiled(BeamDesc b)
     X(2, 4, 4, 5, 32, 2, 0)          \
     X(2, 16, 2, 5, 64, 2, 0)         \
     X(8, 8, 2, 5, 32, 2, 1)          \
-    X(8, 8, 4, 3, 16, 4, 1)          \
+    X(8, 8, 2, 3, 16, 4, 1)          \
+    X(8, 8, 4, 3, 16, 4, 0)          \
     X(8, 8, 4, 3, 32, 2, 0)          \
     X(8, 8, 4, 5, 32, 2, 0)          \
     X(8, 8, 2, 5, 64, 2, 0)          \
@@ -442,26 +478,51 @@ __device__ __forceinline__ bool run_if(int shape_id, int want, const BeamDesc& b
     return false;
 }
 
+// Dispatch one work item to its beam's shape.  Beam b owns the items
+// [work_begin, work_begin + span) with span = ntiles*nblocks rounded up to a
+// multiple of 8 (work_begin is a multiple of 8), so the XCD remap below
+// applies within each beam: all eight XCDs sweep one beam at a time, each a
+// contiguous range of its (tile, DM block) items, as in a single-beam
+// launch.  Items past ntiles*nblocks are padding and return at once.
+__device__ __forceinline__ void run_item(const DescBlock& blk, int nbeams, int item, uint32_t* lds)
+{
+    int bi = 0;
+    while (bi + 1 < nbeams && blk.d[bi + 1].work_begin <= item) ++bi;
+    bi = wave_uniform(bi);
+    const BeamDesc& b = blk.d[bi];
+    const int nreal = b.ntiles * b.nblocks;
+    const int span = (nreal + 7) & ~7;
+    const int local = xcd_remap(item - (int)b.work_begin, span);
+    if (local >= nreal) return;
+    const int tile = local / b.nblocks;
+    const int block = local - tile * b.nblocks;
+    int id = 0;
+    bool done = false;
+#define DEDISP_RUN(NB, NW, DPW, M, CC, PM, PERSIST) \
+    if (!done) done = run_if<NB, NW, DPW, M, CC, PM, PERSIST>(b.shape, id, b, tile, block, lds); \
+    ++id;
+    DEDISP_SHAPES(DEDISP_RUN)
+#undef DEDISP_RUN
+    (void)done;
+}
+
+// Multi-beam launch, one workgroup per work item of every beam (the
+// hardware dispatcher balances the uneven items as workgroups finish).
+__global__ __launch_bounds__(kPersistentWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_multi(DescBlock blk, int nbeams,
+                                                                  int total)
+{
+    extern __shared__ uint32_t lds_dyn[];
+    run_item(blk, nbeams, (int)blockIdx.x, lds_dyn);
+}
+
+// Persistent variant: a grid sized to the machine; workgroup g takes items
+// g, g + grid, ...
 __global__ __launch_bounds__(kPersistentWaves * 64) void k_persistent(DescBlock blk, int nbeams,
                                                                        int total)
 {
     extern __shared__ uint32_t lds_dyn[];
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        int bi = 0;
-        while (bi + 1 < nbeams && blk.d[bi + 1].work_begin <= item) ++bi;
-        bi = wave_uniform(bi);
-        const BeamDesc& b = blk.d[bi];
-        const int local = item - (int)b.work_begin;
-        const int tile = local / b.nblocks;
-        const int block = local - tile * b.nblocks;
-        int id = 0;
-        bool done = false;
-#define DEDISP_RUN(NB, NW, DPW, M, CC, PM, PERSIST) \
-    if (!done) done = run_if<NB, NW, DPW, M, CC, PM, PERSIST>(b.shape, id, b, tile, block, lds_dyn); \
-    ++id;
-        DEDISP_SHAPES(DEDISP_RUN)
-#undef DEDISP_RUN
-        (void)done;
+        run_item(blk, nbeams, item, lds_dyn);
         __syncthreads();                     // LDS is reused by the next item
     }
 }
@@ -543,6 +604,21 @@ int persistent_max_grid(int lds_bytes)
         return 0;
     if (per_cu < 1) per_cu = 1;
     return ncu * per_cu;
+}
+
+hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
+                        hipStream_t st)
+{
+    if (nbeams <= 0 || nbeams > kMaxBatchDescs || total_work <= 0) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
+    if (e != hipSuccess) return e;
+    DescBlock a0 = blk;
+    int a1 = nbeams;
+    int a2 = total_work;
+    void* args[] = {&a0, &a1, &a2};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&k_multi), dim3(total_work),
+                           dim3(kPersistentWaves * 64), args, (size_t)lds_bytes, st);
 }
 
 hipError_t launch_persistent(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,

@@ -216,6 +216,32 @@ def batch_beam(b: int, nsamps: int | None = None) -> Beam:
                 dm_list_linear(p["ndm"], p["dm_max"]), codes, [])
 
 
+def device_codes(nsamps: int, nchans: int, nbits: int, seed: int, device="cuda",
+                 sd: float = 16.0):
+    """Seeded packed input made on the device with torch's generator (for sizes
+    where numpy generation would dominate a run): 2-bit level codes with
+    probabilities .16/.34/.34/.16 packed four per byte, or 8-bit
+    rint(N(128, sd)) clipped to [0, 255].  Returns a uint8 tensor
+    [nsamps][nchans*nbits/8]."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    if nbits == 2:
+        u = torch.randint(0, 100, (nsamps, nchans), generator=gen, device=device,
+                          dtype=torch.int16)
+        c = (u >= 16).to(torch.uint8) + (u >= 50).to(torch.uint8) + (u >= 84).to(torch.uint8)
+        del u
+        c = c.view(nsamps, nchans // 4, 4)
+        return (c[..., 0] | (c[..., 1] << 2) | (c[..., 2] << 4) | (c[..., 3] << 6)).contiguous()
+    out = torch.empty((nsamps, nchans), dtype=torch.uint8, device=device)
+    step = max(1, (1 << 26) // nchans)
+    for r0 in range(0, nsamps, step):
+        r1 = min(nsamps, r0 + step)
+        z = torch.randn((r1 - r0, nchans), generator=gen, device=device) * float(sd) + 128.0
+        out[r0:r1] = z.round_().clamp_(0, 255).to(torch.uint8)
+    return out
+
+
 def stream_chunk_lengths(stream: int, nchunks: int, lo: int = 1 << 14, hi: int = 1 << 18) -> np.ndarray:
     rng = np.random.default_rng([1000 + stream, 3])
     return rng.integers(lo, hi + 1, size=nchunks)

@@ -231,3 +231,32 @@ def test_survey_beam_full_size_sampled(native, cuda):
         win = got[:, lo:hi].astype(np.int64)
         dd, tt = np.unravel_index(int(win.argmax()), win.shape)
         assert (dd, tt + lo) == (p.dm_index, p.t0), p
+
+
+def test_large_beam_full_size_sampled(native, cuda):
+    """8-bit, 4096 channels, 2^20 samples of 54.6 us, 2048 DMs in [0, 2000).
+
+    The input is made on the device (seeded) and copied back for the oracle;
+    sampled outputs are compared point by point, the DM 0 row against the
+    channel sum over the whole output.
+    """
+    import torch
+    nsamps, nchans, ndm = 1 << 20, 4096, 2048
+    dms = synth.dm_list_linear(ndm, 2000.0)
+    plan = Plan(nchans, 54.6e-6, 1500.0, -0.09765625, 8).set_dm_list(dms)
+    table, mx = oracle.delay_table(nchans, 54.6e-6, 1500.0, -0.09765625, dms)
+    assert mx == 58003 and np.array_equal(plan.delay_table(), table)
+    inp = synth.device_codes(nsamps, nchans, 8, seed=2, device=cuda, sd=20.0)
+    out = plan.execute(inp.view(-1), nsamps)
+    torch.cuda.synchronize()
+    nout = nsamps - mx
+    assert tuple(out.shape) == (ndm, nout)
+    chansum = inp[:nout].sum(dim=1, dtype=torch.int32)
+    assert torch.equal(out[0], chansum)
+    host = inp.cpu().numpy()
+    rng = np.random.default_rng(7)
+    d = np.concatenate([rng.integers(0, ndm, 4000), [0, ndm - 1, ndm - 1]])
+    t = np.concatenate([rng.integers(0, nout, 4000), [nout - 1, 0, nout - 1]])
+    want = oracle.dedisperse_points(host, nsamps, nchans, 8, table, d, t)
+    got = out[torch.from_numpy(d).to(cuda), torch.from_numpy(t).to(cuda)]
+    assert np.array_equal(_out_np(got), want)
