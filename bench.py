@@ -256,13 +256,20 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     achieved_tadds = adds / (mean_ms * 1e-3) / 1e12
     alg_bytes = nsamps * nchans * beam.nbits // 8 + 4 * outputs + 4 * ndm * nchans
+    # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE /
+    # WRITE_SIZE counters (profiles/traffic.json), only while the kernel source
+    # and the tile shape are the ones the counters were taken on.
     traffic = None
     if os.path.exists(args.traffic_json):
         try:
+            import hashlib
             tj = json.load(open(args.traffic_json))
-            if tj.get("workload") == beam.name and tj.get("tile") == cfg:
+            src = os.path.join(ROOT, "paper_1201_5380_amd", "csrc", "dedisp_kernels.hip")
+            sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+            if (tj.get("workload") == beam.name and tj.get("tile") == cfg
+                    and tj.get("kernel_source_sha256") == sha):
                 traffic = tj.get("hbm_bytes_per_launch")
-        except Exception:
+        except (OSError, ValueError):
             traffic = None
 
     result = {

@@ -95,6 +95,14 @@ void dedisp_plan_destroy(dedisp_plan plan);
  * finite, or a delay does not fit in int32. */
 dedisp_status dedisp_set_dm_list(dedisp_plan plan, const double* dms, int ndm);
 
+/* Channel kill mask (Section 2.3): mask[c] = 1 sums channel c, 0 skips it;
+ * NULL (or all ones) restores every channel.  Host array of nchans int32,
+ * copied; entries other than 0/1 are INVALID_ARG.  The delay table, max_delay
+ * and the output range do not change.  Killed channels cost nothing in the
+ * tiled kernel: the corner turn leaves them out of the channel-major
+ * scratch.  Work enqueued with the plan must have finished. */
+dedisp_status dedisp_set_killmask(dedisp_plan plan, const int32_t* mask);
+
 /* Plan queries (host-only).  NO_DM_LIST before dedisp_set_dm_list for the
  * DM-dependent ones. */
 dedisp_status dedisp_get_nchans(dedisp_plan plan, int* nchans);

@@ -41,10 +41,10 @@ def _load():
                                        ctypes.c_double, _f64p, ctypes.c_int, _i32p, _i32p]
     lib.oracle_dedisperse.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                       _i32p, ctypes.c_int, ctypes.c_int32, _u32p,
-                                      ctypes.c_int64, ctypes.c_int]
+                                      ctypes.c_int64, ctypes.c_int, _i32p]
     lib.oracle_dedisperse_points.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                              _i32p, ctypes.c_int, ctypes.c_int32, _i64p, _i64p,
-                                             ctypes.c_int64, _u32p, ctypes.c_int]
+                                             ctypes.c_int64, _u32p, ctypes.c_int, _i32p]
     for f in ("oracle_partial_delay", "oracle_delay_table", "oracle_dedisperse",
               "oracle_dedisperse_points", "oracle_max_threads"):
         getattr(lib, f).restype = ctypes.c_int
@@ -83,8 +83,17 @@ def delay_table(nchans, dt, f_top, df, dms):
     return table, int(mx.value)
 
 
-def dedisperse(packed, nsamps, nchans, nbits, table, max_delay=None, nthreads=0):
-    """Full transform: uint32 [ndm][nsamps - max_delay]."""
+def _mask_arg(mask, nchans):
+    if mask is None:
+        return None, None
+    m = np.ascontiguousarray(mask, dtype=np.int32)
+    if m.shape != (nchans,):
+        raise OracleError("mask must have one entry per channel")
+    return m, _ptr(m, _i32p)
+
+
+def dedisperse(packed, nsamps, nchans, nbits, table, max_delay=None, nthreads=0, mask=None):
+    """Full transform: uint32 [ndm][nsamps - max_delay] (optional 0/1 channel kill mask)."""
     packed = np.ascontiguousarray(packed, dtype=np.uint8).reshape(-1)
     table = np.ascontiguousarray(table, dtype=np.int32)
     ndm = int(table.shape[0])
@@ -96,14 +105,15 @@ def dedisperse(packed, nsamps, nchans, nbits, table, max_delay=None, nthreads=0)
     if packed.size < int(nsamps) * nchans * nbits // 8:
         raise OracleError("input too short")
     out = np.zeros((ndm, nout), dtype=np.uint32)
+    m, mp = _mask_arg(mask, nchans)
     _check(_load().oracle_dedisperse(_ptr(packed, _u8p), int(nsamps), nchans, nbits,
                                      _ptr(table, _i32p), ndm, int(max_delay),
-                                     _ptr(out, _u32p), nout, int(nthreads)), "dedisperse")
+                                     _ptr(out, _u32p), nout, int(nthreads), mp), "dedisperse")
     return out
 
 
 def dedisperse_points(packed, nsamps, nchans, nbits, table, d_idx, t_idx, max_delay=None,
-                      nthreads=0):
+                      nthreads=0, mask=None):
     """The transform at the listed (d, t) points only: uint32 [npts]."""
     packed = np.ascontiguousarray(packed, dtype=np.uint8).reshape(-1)
     table = np.ascontiguousarray(table, dtype=np.int32)
@@ -114,10 +124,11 @@ def dedisperse_points(packed, nsamps, nchans, nbits, table, d_idx, t_idx, max_de
     if packed.size < int(nsamps) * nchans * nbits // 8:
         raise OracleError("input too short")
     out = np.zeros(d_idx.shape[0], dtype=np.uint32)
+    m, mp = _mask_arg(mask, nchans)
     _check(_load().oracle_dedisperse_points(_ptr(packed, _u8p), int(nsamps), nchans, nbits,
                                             _ptr(table, _i32p), int(table.shape[0]),
                                             int(max_delay), _ptr(d_idx, _i64p),
                                             _ptr(t_idx, _i64p), int(d_idx.shape[0]),
-                                            _ptr(out, _u32p), int(nthreads)),
+                                            _ptr(out, _u32p), int(nthreads), mp),
            "dedisperse_points")
     return out

@@ -118,10 +118,13 @@ static inline uint32_t oracle_sample(const uint8_t* in, int nchans, int nbits,
 /* The direct dedispersion transform, the "direct" equation of Section 2.1:
  *   D[d][t] = sum over nu = 0..N_nu-1 of A[nu][t + Delta t(d, nu)]
  * for 0 <= d < ndm and 0 <= t < nsamps - max_delay, written to
- * out[d * out_stride + t]. */
+ * out[d * out_stride + t].
+ * With a channel kill mask (Section 2.3; NULL = every channel on), each
+ * term is multiplied by mask[nu] in {0, 1}, the arithmetic form of the mask
+ * the paper describes; the delays and the output range are unchanged. */
 int oracle_dedisperse(const uint8_t* in, int64_t nsamps, int nchans, int nbits,
                       const int32_t* table, int ndm, int32_t max_delay,
-                      uint32_t* out, int64_t out_stride, int nthreads)
+                      uint32_t* out, int64_t out_stride, int nthreads, const int32_t* mask)
 {
     if (!in || !table || !out || ndm <= 0 || nchans <= 0) return ORACLE_BAD_ARG;
     if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
@@ -131,6 +134,9 @@ int oracle_dedisperse(const uint8_t* in, int64_t nsamps, int nchans, int nbits,
     if (out_stride < nout) return ORACLE_BAD_ARG;
     for (size_t i = 0; i < (size_t)ndm * (size_t)nchans; ++i)
         if (table[i] < 0 || table[i] > max_delay) return ORACLE_BAD_ARG;
+    if (mask)
+        for (int nu = 0; nu < nchans; ++nu)
+            if (mask[nu] != 0 && mask[nu] != 1) return ORACLE_BAD_ARG;
 
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -144,7 +150,8 @@ int oracle_dedisperse(const uint8_t* in, int64_t nsamps, int nchans, int nbits,
         for (int64_t t = 0; t < nout; ++t) {
             uint32_t sum = 0;
             for (int nu = 0; nu < nchans; ++nu)
-                sum += oracle_sample(in, nchans, nbits, t + delay[nu], nu);
+                sum += (mask ? (uint32_t)mask[nu] : 1u) *
+                       oracle_sample(in, nchans, nbits, t + delay[nu], nu);
             row[t] = sum;
         }
     }
@@ -156,7 +163,7 @@ int oracle_dedisperse(const uint8_t* in, int64_t nsamps, int nchans, int nbits,
 int oracle_dedisperse_points(const uint8_t* in, int64_t nsamps, int nchans, int nbits,
                              const int32_t* table, int ndm, int32_t max_delay,
                              const int64_t* d_idx, const int64_t* t_idx, int64_t npts,
-                             uint32_t* out, int nthreads)
+                             uint32_t* out, int nthreads, const int32_t* mask)
 {
     if (!in || !table || !out || !d_idx || !t_idx || npts < 0) return ORACLE_BAD_ARG;
     if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
@@ -177,7 +184,8 @@ int oracle_dedisperse_points(const uint8_t* in, int64_t nsamps, int nchans, int 
         const int64_t t = t_idx[i];
         uint32_t sum = 0;
         for (int nu = 0; nu < nchans; ++nu)
-            sum += oracle_sample(in, nchans, nbits, t + delay[nu], nu);
+            sum += (mask ? (uint32_t)mask[nu] : 1u) *
+                   oracle_sample(in, nchans, nbits, t + delay[nu], nu);
         out[i] = sum;
     }
     return ORACLE_OK;

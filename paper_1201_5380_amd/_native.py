@@ -53,6 +53,7 @@ SIGNATURES = {
     "dedisp_plan_create": (_i, [ctypes.POINTER(_vp), _i, _d, _d, _d, _i]),
     "dedisp_plan_destroy": (None, [_vp]),
     "dedisp_set_dm_list": (_i, [_vp, _pf64, _i]),
+    "dedisp_set_killmask": (_i, [_vp, _pi32]),
     "dedisp_get_nchans": (_i, [_vp, _pi]),
     "dedisp_get_nbits": (_i, [_vp, _pi]),
     "dedisp_get_dm_count": (_i, [_vp, _pi]),

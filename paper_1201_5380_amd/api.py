@@ -75,6 +75,18 @@ class Plan:
         self.ndm = int(arr.shape[0])
         return self
 
+    def set_killmask(self, mask):
+        """0/1 per channel (None = all channels on)."""
+        if mask is None:
+            check(lib().dedisp_set_killmask(self._h, None), "dedisp_set_killmask")
+            return self
+        m = np.ascontiguousarray(mask, dtype=np.int32)
+        if m.shape != (self.nchans,):
+            raise ValueError("kill mask needs one entry per channel")
+        check(lib().dedisp_set_killmask(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+              "dedisp_set_killmask")
+        return self
+
     @property
     def max_delay(self) -> int:
         v = ctypes.c_int()

@@ -59,6 +59,10 @@ void free_device(dedisp_plan p)
     }
     p->blocks.clear();
     free_scratch(p->xc);
+    if (p->d_chanmap) (void)hipFree(p->d_chanmap);
+    if (p->d_mask) (void)hipFree(p->d_mask);
+    p->d_chanmap = nullptr;
+    p->d_mask = nullptr;
 }
 
 bool is_finite(double x) { return std::isfinite(x); }
@@ -90,35 +94,40 @@ bool build_delay_table(const dedisp_plan_s& p, const double* dms, int ndm,
     return true;
 }
 
-// Window tables for blocks of `db` consecutive DM rows: base[b][c] is the
-// smallest delay of channel c over the block, rounded down to a multiple of
-// 16 (so staged windows start on 16-byte boundaries); the window offset of
-// DM row d, channel c is delay[d][c] - base[b][c] (0 for padding rows past
-// ndm), stored for channel pairs: rel[d][p] = off(2p) | off(2p+1) << 16.
+// Window tables for blocks of `db` consecutive DM rows, over the scratch
+// rows (the live channels in order, plus a zero row when their count is
+// odd): base[b][k] is the smallest delay of row k's channel over the block,
+// rounded down to a multiple of 16 (so staged windows start on 16-byte
+// boundaries); the window offset of DM row d, scratch row k is
+// delay[d][c(k)] - base[b][k] (0 for padding DM rows past ndm and for the
+// zero row), stored for row pairs: rel[d][p] = off(2p) | off(2p+1) << 16.
 // relmax is the largest offset (always < 2^16 for a shape that fits).
 void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
 {
     const int ndm = static_cast<int>(p.dms.size());
     const int nch = p.nchans;
-    const int np = (nch + 1) / 2;
+    const int nrow = p.nact_padded();     // scratch rows: live channels (+1 zero row if odd)
+    const int nlive = p.nact();
+    const int np = nrow / 2;
     bt.db = db;
     bt.nblocks = (ndm + db - 1) / db;
     bt.rel.assign(static_cast<size_t>(bt.nblocks) * db * np, 0u);
-    bt.base.assign(static_cast<size_t>(bt.nblocks) * nch, 0);
+    bt.base.assign(static_cast<size_t>(bt.nblocks) * nrow, 0);
     bt.relmax = 0;
     for (int b = 0; b < bt.nblocks; ++b) {
         const int d0 = b * db, d1 = std::min(ndm, d0 + db);
-        for (int c = 0; c < nch; ++c) {
+        for (int k = 0; k < nlive; ++k) {
+            const int c = p.source_channel(k);
             int mn = 0x7fffffff;
             for (int d = d0; d < d1; ++d)
                 mn = std::min(mn, p.table[static_cast<size_t>(d) * nch + c]);
             mn &= ~15;
-            bt.base[static_cast<size_t>(b) * nch + c] = mn;
+            bt.base[static_cast<size_t>(b) * nrow + k] = mn;
             for (int d = d0; d < d1; ++d) {
                 const int r = p.table[static_cast<size_t>(d) * nch + c] - mn;
                 bt.relmax = std::max(bt.relmax, r);
                 const uint32_t v = static_cast<uint32_t>(std::min(r, 0xFFFF));
-                bt.rel[static_cast<size_t>(d) * np + c / 2] |= (c & 1) ? (v << 16) : v;
+                bt.rel[static_cast<size_t>(d) * np + k / 2] |= (k & 1) ? (v << 16) : v;
             }
         }
     }
@@ -174,6 +183,21 @@ dedisp_status ensure_device_table(dedisp_plan p)
         }
         HIP_TRY(hipMemcpy(p->d_table, p->table.data(), bytes, hipMemcpyHostToDevice));
     }
+    if (!p->killmask.empty() && !p->d_chanmap) {
+        std::vector<int32_t> map(p->nchans, -1);
+        for (size_t k = 0; k < p->active.size(); ++k) map[p->active[k]] = static_cast<int32_t>(k);
+        const size_t bytes = map.size() * sizeof(int32_t);
+        if (hipMalloc(&p->d_chanmap, bytes) != hipSuccess) {
+            p->d_chanmap = nullptr;
+            return fail(DEDISP_ERR_OOM, "hipMalloc channel map");
+        }
+        if (hipMalloc(&p->d_mask, bytes) != hipSuccess) {
+            p->d_mask = nullptr;
+            return fail(DEDISP_ERR_OOM, "hipMalloc kill mask");
+        }
+        HIP_TRY(hipMemcpy(p->d_chanmap, map.data(), bytes, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_mask, p->killmask.data(), bytes, hipMemcpyHostToDevice));
+    }
     return DEDISP_OK;
 }
 
@@ -225,7 +249,7 @@ bool shape_fits(const BlockTables& bt, const Shape& s)
 // 16-bit lanes.
 bool tiled_supported(const dedisp_plan_s& p)
 {
-    return p.row_bytes % 4 == 0 && (p.nbits == 8 || p.nchans <= 21845);
+    return p.row_bytes % 4 == 0 && p.nact() >= 1 && (p.nbits == 8 || p.nchans <= 21845);
 }
 
 // Resolve the shape used for this plan: the requested one if its LDS window
@@ -322,7 +346,7 @@ dedisp_status ensure_scratch(Scratch& x, size_t need)
 dedisp_status ensure_xc(const dedisp_plan_s& p, Scratch& x, long long nsamps, const LaunchPlan& lp)
 {
     if (lp.shape.kind != 0) return DEDISP_OK;
-    return ensure_scratch(x, static_cast<size_t>(xc_pitch(nsamps, lp.rw)) * p.nchans);
+    return ensure_scratch(x, static_cast<size_t>(xc_pitch(nsamps, lp.rw)) * p.nact_padded());
 }
 
 void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n0,
@@ -338,6 +362,10 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
     d.out = out;
     d.out_stride = stride;
     d.table = p->d_table;
+    d.chanmap = p->d_chanmap;
+    d.mask = p->d_mask;
+    d.nact = p->nact_padded();
+    d.pad_row = (p->nact() & 1) ? p->nact() : -1;
     d.nchans = p->nchans;
     d.row_bytes = p->row_bytes;
     d.ndm = static_cast<int>(p->dms.size());
@@ -501,6 +529,27 @@ dedisp_status dedisp_set_dm_list(dedisp_plan p, const double* dms, int ndm)
     p->table.swap(table);
     p->max_delay = mx;
     p->has_dms = true;
+    return DEDISP_OK;
+}
+
+dedisp_status dedisp_set_killmask(dedisp_plan p, const int32_t* mask)
+{
+    if (!p) return fail(DEDISP_ERR_INVALID_ARG, "NULL plan");
+    std::vector<int32_t> km, act;
+    if (mask) {
+        bool all_on = true;
+        for (int c = 0; c < p->nchans; ++c) {
+            if (mask[c] != 0 && mask[c] != 1)
+                return fail(DEDISP_ERR_INVALID_ARG, "kill mask entries must be 0 or 1");
+            if (mask[c]) act.push_back(c);
+            else all_on = false;
+        }
+        if (!all_on) km.assign(mask, mask + p->nchans);
+        else act.clear();
+    }
+    free_device(p);
+    p->killmask.swap(km);
+    p->active.swap(act);
     return DEDISP_OK;
 }
 

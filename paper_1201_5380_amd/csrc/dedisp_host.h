@@ -106,4 +106,15 @@ struct dedisp_plan_s {
     int32_t* d_table = nullptr;
     std::map<int, dedisp::host::BlockTables> blocks;  // keyed by DM-block size
     dedisp::host::Scratch xc;                          // channel-major scratch for execute
+    // Channel kill mask (empty = every channel on): live channels in order,
+    // and the device copies the kernels read.
+    std::vector<int32_t> killmask;
+    std::vector<int32_t> active;
+    int32_t* d_chanmap = nullptr;
+    int32_t* d_mask = nullptr;
+
+    int nact() const { return killmask.empty() ? nchans : static_cast<int>(active.size()); }
+    // scratch rows the tiled kernel sums: live channels padded to an even count
+    int nact_padded() const { return (nact() + 1) & ~1; }
+    int source_channel(int row) const { return killmask.empty() ? row : active[row]; }
 };

@@ -24,6 +24,10 @@ struct BeamDesc {
     const uint32_t* rel;      // [nblocks*DB][nchans/2] window offsets of channel pairs (16+16 bits)
     const int32_t* base;      // [nblocks][nchans] window start (multiple of 16)
     const int32_t* table;     // [ndm][nchans] full delay table (untiled kernel)
+    const int32_t* chanmap;   // [nchans] scratch row of each channel, -1 = killed (NULL = identity)
+    const int32_t* mask;      // [nchans] 0/1 kill mask for the untiled kernel (NULL = all on)
+    int nact;                 // scratch rows the tiled kernel sums (live channels, padded to even)
+    int pad_row;              // scratch row the corner turn zero-fills, or -1
     int nchans;
     int row_bytes;
     int ndm;

@@ -151,15 +151,24 @@ __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
         }
     }
     __syncthreads();
-    // write 16-byte pieces: kUT/16 per channel row
+    // write 16-byte pieces: kUT/16 per channel row, to the channel's scratch
+    // row (killed channels have none)
     for (int it = threadIdx.x; it < kUC * (kUT / 16); it += 256) {
         const int c = it / (kUT / 16);
         const int p = it % (kUT / 16);
         if (c0 + c >= b.nchans) continue;
         const long long t = t0 + 16 * p;
         if (t >= b.nsamps) continue;
+        const int row = b.chanmap ? b.chanmap[c0 + c] : c0 + c;
+        if (row < 0) continue;
         const u32x4 val = *reinterpret_cast<const u32x4*>(tile + (size_t)c * kUPitch + 16 * p);
-        *reinterpret_cast<u32x4*>(b.xc + (long long)(c0 + c) * b.pitch + t) = val;
+        *reinterpret_cast<u32x4*>(b.xc + (long long)row * b.pitch + t) = val;
+    }
+    // the padding row (odd number of live channels) reads as zeros
+    if (b.pad_row >= 0 && blockIdx.y == 0 && threadIdx.x < kUT / 16) {
+        const long long t = t0 + 16 * threadIdx.x;
+        if (t < b.nsamps)
+            *reinterpret_cast<u32x4*>(b.xc + (long long)b.pad_row * b.pitch + t) = u32x4{0u, 0u, 0u, 0u};
     }
 }
 
@@ -199,7 +208,7 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     const long long t0 = (long long)tile * T;
     // Every descriptor field is wave-uniform; keep them in scalar registers
     // (the persistent kernel reads descriptors through a dynamic index).
-    const int nchans = wave_uniform(b.nchans);
+    const int nchans = wave_uniform(b.nact);   // live channels, in scratch-row order
     const int rw = wave_uniform(b.rw);
     const int rq = rw >> 2;                // 16-byte pieces per row
     const long long pitch = wave_uniform64(b.pitch);
@@ -409,6 +418,7 @@ __global__ __launch_bounds__(256) void k_untiled(BeamDesc b)
         const int32_t* dl = b.table + (size_t)d * b.nchans;
         uint32_t a[4] = {0u, 0u, 0u, 0u};
         for (int c = 0; c < b.nchans; ++c) {
+            if (b.mask && b.mask[c] == 0) continue;
             const int off = dl[c];
 #pragma unroll
             for (int e = 0; e < 4; ++e)

@@ -260,3 +260,38 @@ def test_large_beam_full_size_sampled(native, cuda):
     want = oracle.dedisperse_points(host, nsamps, nchans, 8, table, d, t)
     got = out[torch.from_numpy(d).to(cuda), torch.from_numpy(t).to(cuda)]
     assert np.array_equal(_out_np(got), want)
+
+
+@pytest.mark.parametrize("nbits,nchans", [(2, 256), (8, 192)])
+def test_kill_mask_every_shape(native, cuda, nbits, nchans):
+    """Killed channels are left out of the sum (oracle: each term times mask[c])."""
+    rng = np.random.default_rng(60 + nbits)
+    nsamps = 9000
+    dms = synth.dm_list_linear(40, 300.0)
+    df = -400.0 / nchans
+    maxc = 3 if nbits == 2 else 255
+    codes = rng.integers(0, maxc + 1, size=(nsamps, nchans), dtype=np.uint8)
+    packed = synth.pack(codes, nbits)
+    plan = Plan(nchans, 64e-6, 1581.8, df, nbits).set_dm_list(dms)
+    table = plan.delay_table()
+    masks = []
+    m = (rng.random(nchans) < 0.7).astype(np.int32)
+    m[0] = 0
+    m[-1] = 0
+    if m.sum() % 2 == 0:                       # an odd number of live channels
+        m[nchans // 2] ^= 1
+    masks.append(m)
+    one = np.zeros(nchans, np.int32)
+    one[nchans // 3] = 1
+    masks.append(one)
+    masks.append(np.zeros(nchans, np.int32))
+    for mask in masks:
+        plan.set_killmask(mask)
+        want = oracle.dedisperse(packed, nsamps, nchans, nbits, table, mask=mask)
+        cfgs = _configs_for(plan) if mask.sum() > 1 else [None]
+        for cfg in cfgs:
+            got = _run(plan, packed, nsamps, cuda, cfg)
+            assert np.array_equal(got, want), (int(mask.sum()), cfg)
+    plan.set_killmask(None)
+    assert np.array_equal(_run(plan, packed, nsamps, cuda),
+                          oracle.dedisperse(packed, nsamps, nchans, nbits, table))

@@ -227,3 +227,16 @@ def test_batch_full_size_sampled(native, cuda):
         want = oracle.dedisperse_points(packed, n, plan.nchans, plan.nbits, plan.delay_table(), d, t)
         got = out[torch.from_numpy(d).to(cuda), torch.from_numpy(t).to(cuda)]
         assert np.array_equal(_np(got), want), (plan.nchans, plan.nbits, n)
+
+
+def test_stream_with_kill_mask(native, cuda):
+    plan, rng = _stream_case(2, 512, 16, 300.0, 91)
+    mask = (rng.random(512) < 0.5).astype(np.int32)
+    plan.set_killmask(mask)
+    mx = plan.max_delay
+    lengths = [mx // 2, mx, 4000, 77, 2 * mx]
+    total = sum(lengths)
+    packed = synth.pack(_codes(rng, total, 512, 2), 2)
+    got = _run_stream(Stream(plan), plan, packed, lengths, cuda)
+    want = oracle.dedisperse(packed, total, 512, 2, plan.delay_table(), mask=mask)
+    assert np.array_equal(got, want)

@@ -332,3 +332,41 @@ def test_two_bit_pulses_land_at_injected_trials_and_times():
         win = out[:, lo:hi]
         dd, tt = np.unravel_index(int(win.argmax()), win.shape)
         assert (dd, tt + lo) == (d0, t0), (p, dd, tt + lo)
+
+
+# ---------------------------------------------------------------------------
+# channel kill mask (Section 2.3)
+# ---------------------------------------------------------------------------
+
+def test_kill_mask_push_brute_force_and_special_cases():
+    """Killed channels contribute nothing; delays and output range are unchanged."""
+    rng = np.random.default_rng(31)
+    nsamps, nchans, ndm, nbits = 260, 16, 7, 2
+    codes, table = _random_case(rng, nsamps, nchans, nbits, ndm, 40)
+    packed = synth.pack(codes, nbits)
+    mask = (rng.random(nchans) < 0.6).astype(np.int32)
+    mask[0] = 0
+    got = oracle.dedisperse(packed, nsamps, nchans, nbits, table, mask=mask)
+    # brute force with the killed channels zeroed in the input
+    want = _push_brute_force(codes * mask[None, :].astype(np.uint8), table)
+    assert np.array_equal(got.astype(np.int64), want)
+    # all on == no mask; all off == zero
+    assert np.array_equal(oracle.dedisperse(packed, nsamps, nchans, nbits, table,
+                                            mask=np.ones(nchans, np.int32)),
+                          oracle.dedisperse(packed, nsamps, nchans, nbits, table))
+    assert not oracle.dedisperse(packed, nsamps, nchans, nbits, table,
+                                 mask=np.zeros(nchans, np.int32)).any()
+    # disjoint masks add up
+    other = 1 - mask
+    both = (oracle.dedisperse(packed, nsamps, nchans, nbits, table, mask=mask).astype(np.int64)
+            + oracle.dedisperse(packed, nsamps, nchans, nbits, table, mask=other))
+    assert np.array_equal(both, oracle.dedisperse(packed, nsamps, nchans, nbits, table))
+    # one live channel: its own samples, shifted by its delay
+    one = np.zeros(nchans, np.int32)
+    one[5] = 1
+    out1 = oracle.dedisperse(packed, nsamps, nchans, nbits, table, mask=one)
+    nout = nsamps - int(table.max())
+    for d in range(ndm):
+        assert np.array_equal(out1[d], codes[table[d, 5]: table[d, 5] + nout, 5])
+    with pytest.raises(oracle.OracleError):
+        oracle.dedisperse(packed, nsamps, nchans, nbits, table, mask=np.full(nchans, 2, np.int32))
