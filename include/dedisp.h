@@ -225,7 +225,8 @@ typedef struct {
 /* Build a batch: pick a tile shape per beam (from `tune_cache_path` when it
  * holds the beam's key, else by timing the candidates on the beam's own
  * buffers and recording the result there), upload a device descriptor table
- * and a flat work list, and capture one persistent launch into a HIP graph.
+ * and a flat work list, and capture one multi-beam launch (one workgroup per
+ * work item of every beam) into a HIP graph.
  * Uses `stream` for tuning and capture and synchronises it.
  * Errors: INVALID_ARG, NO_DM_LIST, TOO_FEW_SAMPLES, OOM, HIP. */
 dedisp_status dedisp_batch_create(const dedisp_beam* beams, int nbeams,
@@ -235,7 +236,7 @@ dedisp_status dedisp_batch_create(const dedisp_beam* beams, int nbeams,
 /* Run every beam of the batch: one graph launch on `stream`. */
 dedisp_status dedisp_batch_execute(dedisp_batch b, void* stream);
 
-/* Run every beam with one persistent launch but without the graph (for
+/* Run every beam with the same multi-beam launch but without the graph (for
  * comparison and for callers that re-point buffers between runs). */
 dedisp_status dedisp_batch_execute_direct(dedisp_batch b, void* stream);
 

@@ -221,7 +221,7 @@ def push_many(streams: Sequence[Stream], chunks, outs, out_row_strides=None, str
 
 
 class Batch:
-    """A fixed set of beams run as one persistent, graph-captured launch (``dedisp_batch``)."""
+    """A fixed set of beams run as one multi-beam, graph-captured launch (``dedisp_batch``)."""
 
     def __init__(self, beams, tune_cache_path: str | None = None, stream=None):
         """``beams``: sequence of (plan, input tensor, nsamps, output tensor, out_row_stride)."""

@@ -1,7 +1,7 @@
 // Host side of the dedispersion library: argument validation, the delay
 // table, the per-DM-block window tables the LDS-tiled kernel consumes, kernel
 // selection and tuning, streams (overlap-save over time) and batches
-// (persistent, graph-captured launches).  All validation happens before any
+// (multi-beam, graph-captured launches).  All validation happens before any
 // HIP call.
 #include "dedisp.h"
 #include "dedisp_internal.h"
@@ -95,18 +95,18 @@ bool build_delay_table(const dedisp_plan_s& p, const double* dms, int ndm,
 }
 
 // Window tables for blocks of `db` consecutive DM rows, over the scratch
-// rows (the live channels in order, plus a zero row when their count is
-// odd): base[b][k] is the smallest delay of row k's channel over the block,
-// rounded down to a multiple of 16 (so staged windows start on 16-byte
-// boundaries); the window offset of DM row d, scratch row k is
+// rows (the live channels in order, then zero rows up to a multiple of 8):
+// base[b][k] is the smallest delay of row k's channel over the block,
+// rounded down to 16 bytes of scratch (32 two-bit or 16 eight-bit samples,
+// so staged windows start on 16-byte boundaries); the window offset of DM row d, scratch row k is
 // delay[d][c(k)] - base[b][k] (0 for padding DM rows past ndm and for the
-// zero row), stored for row pairs: rel[d][p] = off(2p) | off(2p+1) << 16.
+// zero rows), stored for row pairs: rel[d][p] = off(2p) | off(2p+1) << 16.
 // relmax is the largest offset (always < 2^16 for a shape that fits).
 void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
 {
     const int ndm = static_cast<int>(p.dms.size());
     const int nch = p.nchans;
-    const int nrow = p.nact_padded();     // scratch rows: live channels (+1 zero row if odd)
+    const int nrow = p.nact_padded();     // scratch rows: live channels, then zero rows
     const int nlive = p.nact();
     const int np = nrow / 2;
     bt.db = db;
@@ -121,7 +121,7 @@ void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
             int mn = 0x7fffffff;
             for (int d = d0; d < d1; ++d)
                 mn = std::min(mn, p.table[static_cast<size_t>(d) * nch + c]);
-            mn &= ~15;
+            mn &= p.nbits == 2 ? ~31 : ~15;
             bt.base[static_cast<size_t>(b) * nrow + k] = mn;
             for (int d = d0; d < d1; ++d) {
                 const int r = p.table[static_cast<size_t>(d) * nch + c] - mn;
@@ -231,11 +231,15 @@ dedisp_status ensure_block_tables(dedisp_plan p, int db, BlockTables** out)
     return DEDISP_OK;
 }
 
+// Samples per 32-bit word of the channel-major scratch: 2-bit codes are
+// stored as nibbles (8 per word), 8-bit codes as bytes (4 per word).
+int samples_per_word(int nbits) { return nbits == 2 ? 8 : 4; }
+
 // Window length (32-bit words per channel row in LDS, a multiple of 4) of
-// shape s: a lane reads words up to (rel >> 2) + 64*m.
+// shape s: a lane reads words up to rel / samples_per_word + 64*m.
 int window_words(const BlockTables& bt, const Shape& s)
 {
-    return (((bt.relmax >> 2) + 64 * s.m + 1) + 3) & ~3;
+    return ((bt.relmax / samples_per_word(s.nbits) + 64 * s.m + 1) + 3) & ~3;
 }
 
 bool shape_fits(const BlockTables& bt, const Shape& s)
@@ -256,21 +260,21 @@ bool tiled_supported(const dedisp_plan_s& p)
 // fits, else the first compiled tiled shape of the same bit depth that fits,
 // else the untiled kernel.  Host-only (no HIP call) when `upload` is false.
 dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool upload,
-                             LaunchPlan& lp, bool persistent_only)
+                             LaunchPlan& lp, bool multi_only)
 {
     int idx = -1;
     if (!find_shape(want, p->nbits, &idx)) return fail(DEDISP_ERR_INVALID_ARG, "unknown tile shape");
     std::vector<int> order{idx};
     for (int i = 0; i < dedisp::shape_count(); ++i)
         if (i != idx) order.push_back(i);
-    if (persistent_only) {
+    if (multi_only) {
         std::vector<int> keep;
         for (int i : order)
-            if (dedisp::shape_at(i).persist) keep.push_back(i);
+            if (dedisp::shape_at(i).multi) keep.push_back(i);
         order.swap(keep);
     }
     std::map<int, BlockTables> host_tables;
-    if (want.kind == 1 && !persistent_only) order.clear();
+    if (want.kind == 1 && !multi_only) order.clear();
     for (int i : order) {
         const Shape& s = dedisp::shape_at(i);
         if (s.nbits != p->nbits || s.kind != 0 || !tiled_supported(*p)) continue;
@@ -315,11 +319,15 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
     return DEDISP_OK;
 }
 
-long long tile_len(const Shape& s) { return 256LL * s.m; }
+long long tile_len(const Shape& s) { return 64LL * samples_per_word(s.nbits) * s.m; }
 
-// Row pitch of the channel-major scratch: the staged window of the last tile
-// may run up to 4*rw bytes past the last sample.
-long long xc_pitch(long long nsamps, int rw) { return ((nsamps + 4LL * rw + 63) / 64) * 64; }
+// Row pitch in bytes of the channel-major scratch: a staged window starts
+// before the last sample and spans 4*rw bytes.
+long long xc_pitch(long long nsamps, int nbits, int rw)
+{
+    const long long bytes = nbits == 2 ? (nsamps + 1) / 2 : nsamps;
+    return ((bytes + 4LL * rw + 63) / 64) * 64;
+}
 
 void free_scratch(Scratch& x)
 {
@@ -346,7 +354,7 @@ dedisp_status ensure_scratch(Scratch& x, size_t need)
 dedisp_status ensure_xc(const dedisp_plan_s& p, Scratch& x, long long nsamps, const LaunchPlan& lp)
 {
     if (lp.shape.kind != 0) return DEDISP_OK;
-    return ensure_scratch(x, static_cast<size_t>(xc_pitch(nsamps, lp.rw)) * p.nact_padded());
+    return ensure_scratch(x, static_cast<size_t>(xc_pitch(nsamps, lp.shape.nbits, lp.rw)) * p.nact_padded());
 }
 
 void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n0,
@@ -365,14 +373,14 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
     d.chanmap = p->d_chanmap;
     d.mask = p->d_mask;
     d.nact = p->nact_padded();
-    d.pad_row = (p->nact() & 1) ? p->nact() : -1;
+    d.pad_row = p->nact() < p->nact_padded() ? p->nact() : -1;
     d.nchans = p->nchans;
     d.row_bytes = p->row_bytes;
     d.ndm = static_cast<int>(p->dms.size());
     d.shape = lp.shape_index;
     if (lp.shape.kind == 0) {
         d.xc = xc;
-        d.pitch = xc_pitch(nsamps, lp.rw);
+        d.pitch = xc_pitch(nsamps, lp.shape.nbits, lp.rw);
         d.rel = lp.bt->d_rel;
         d.base = lp.bt->d_base;
         d.nblocks = lp.bt->nblocks;

@@ -1,5 +1,5 @@
 // Batches: several beams -- differing in channel count, bit depth, length,
-// DM list and tile shape -- dedispersed by one persistent launch (after one
+// DM list and tile shape -- dedispersed by one multi-beam launch (after one
 // corner-turn kernel per beam), captured once into a HIP graph.  Tile shapes
 // are chosen per beam by timing the candidates on the beam's own buffers,
 // with results kept in a JSON cache keyed by the beam's shape.
@@ -36,7 +36,7 @@ hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st)
     std::vector<Item*> tiled;
     for (Item& it : items) {
         if (it.lp.shape.kind == 0) {
-            if (!it.lp.shape.persist) return hipErrorInvalidValue;
+            if (!it.lp.shape.multi) return hipErrorInvalidValue;
             tiled.push_back(&it);
         }
     }
@@ -98,14 +98,14 @@ dedisp_tile_config config_of(const Shape& s)
     return c;
 }
 
-// Pick the fastest persistent shape for one beam: from the cache when it has
+// Pick the fastest multi-beam shape for one beam: from the cache when it has
 // the beam's key, else by timing each candidate (plain single-beam launches
 // on the beam's own buffers).
 dedisp_status tune_beam(const dedisp_beam& bm, std::map<std::string, std::vector<double>>& cache,
                         bool& cache_dirty, hipStream_t st, dedisp_tile_config& best)
 {
     dedisp_plan p = bm.plan;
-    const std::string key = "persistent:" + cache_key(p, bm.nsamps);
+    const std::string key = "multi:" + cache_key(p, bm.nsamps);
     auto hit = cache.find(key);
     if (hit != cache.end() && hit->second.size() >= 5) {
         dedisp_tile_config c{};
@@ -115,7 +115,7 @@ dedisp_status tune_beam(const dedisp_beam& bm, std::map<std::string, std::vector
         c.words_per_lane = static_cast<int>(hit->second[3]);
         c.chunk_chans = static_cast<int>(hit->second[4]);
         int idx = -1;
-        if (find_shape(c, p->nbits, &idx) && dedisp::shape_at(idx).persist) {
+        if (find_shape(c, p->nbits, &idx) && dedisp::shape_at(idx).multi) {
             best = c;
             return DEDISP_OK;
         }
@@ -123,7 +123,7 @@ dedisp_status tune_beam(const dedisp_beam& bm, std::map<std::string, std::vector
     std::vector<int> cands;
     for (int i = 0; i < dedisp::shape_count(); ++i) {
         const Shape& s = dedisp::shape_at(i);
-        if (s.nbits != p->nbits || !s.persist) continue;
+        if (s.nbits != p->nbits || !s.multi) continue;
         LaunchPlan probe;
         if (resolve_launch(p, config_of(s), false, probe, true) != DEDISP_OK || probe.shape_index != i)
             continue;

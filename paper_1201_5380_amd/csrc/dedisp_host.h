@@ -54,13 +54,13 @@ bool tiled_supported(const struct ::dedisp_plan_s& p);
 
 // Resolve the shape used for plan p (requested one if it fits, else another
 // tiled shape, else the untiled kernel).  `upload` makes the device tables.
-// With persistent_only, only shapes compiled into the persistent kernel are
+// With multi_only, only shapes compiled into the multi-beam kernels are
 // considered before the untiled fallback.
 dedisp_status resolve_launch(::dedisp_plan p, const dedisp_tile_config& want, bool upload,
-                             LaunchPlan& lp, bool persistent_only = false);
+                             LaunchPlan& lp, bool multi_only = false);
 
 long long tile_len(const Shape& s);
-long long xc_pitch(long long nsamps, int rw);
+long long xc_pitch(long long nsamps, int nbits, int rw);
 void free_scratch(Scratch& x);
 dedisp_status ensure_scratch(Scratch& x, size_t need);
 dedisp_status ensure_xc(const struct ::dedisp_plan_s& p, Scratch& x, long long nsamps,
@@ -80,8 +80,8 @@ struct Item {
     LaunchPlan lp;
 };
 // Enqueue every item on one stream: the corner turns, then the tiled items as
-// persistent launches of up to kMaxBatchDescs beams each (every tiled item
-// must use a persistent shape), then the untiled items one launch each.
+// multi-beam launches of up to kMaxBatchDescs beams each (every tiled item
+// must use a multi-beam shape), then the untiled items one launch each.
 hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st);
 
 std::string cache_key(::dedisp_plan p, size_t nsamps);
@@ -114,7 +114,8 @@ struct dedisp_plan_s {
     int32_t* d_mask = nullptr;
 
     int nact() const { return killmask.empty() ? nchans : static_cast<int>(active.size()); }
-    // scratch rows the tiled kernel sums: live channels padded to an even count
-    int nact_padded() const { return (nact() + 1) & ~1; }
+    // scratch rows the tiled kernel sums: live channels padded with zero rows
+    // to a multiple of 8 (the kernel sums whole groups of 8 channels)
+    int nact_padded() const { return (nact() + 7) & ~7; }
     int source_channel(int row) const { return killmask.empty() ? row : active[row]; }
 };

@@ -26,8 +26,8 @@ struct BeamDesc {
     const int32_t* table;     // [ndm][nchans] full delay table (untiled kernel)
     const int32_t* chanmap;   // [nchans] scratch row of each channel, -1 = killed (NULL = identity)
     const int32_t* mask;      // [nchans] 0/1 kill mask for the untiled kernel (NULL = all on)
-    int nact;                 // scratch rows the tiled kernel sums (live channels, padded to even)
-    int pad_row;              // scratch row the corner turn zero-fills, or -1
+    int nact;                 // scratch rows the tiled kernel sums (live channels, padded to a multiple of 8)
+    int pad_row;              // first of the scratch rows [pad_row, nact) the corner turn zero-fills, or -1
     int nchans;
     int row_bytes;
     int ndm;
@@ -49,7 +49,7 @@ struct Shape {
     int m;          // 32-bit words per lane (4 samples each)
     int cc;         // channels staged per chunk
     int pi;         // 16-byte pieces per lane per staged row: row <= 64*pi pieces
-    int persist;    // also compiled into the persistent kernel
+    int multi;      // also compiled into the multi-beam kernels
 };
 
 // Shapes compiled into the library (index = shape id).
@@ -69,9 +69,9 @@ hipError_t launch_untiled(const BeamDesc& d, int nbits, hipStream_t st);
 // Multi-beam launches over up to kMaxBatchDescs beams whose descriptors
 // travel in the kernel arguments (work_begin = prefix sum of ntiles*nblocks,
 // each rounded up to a multiple of 8).  Every
-// beam must use a shape marked persistent; the LDS size is the largest any
+// beam must use a shape marked multi; the LDS size is the largest any
 // beam needs.
-constexpr int kPersistentWaves = 8;
+constexpr int kMultiWaves = 8;
 constexpr int kMaxBatchDescs = 16;
 struct DescBlock {
     BeamDesc d[kMaxBatchDescs];

@@ -7,46 +7,50 @@
 //
 // 1. Corner turn + unpack (k_unpack).  Reads the packed time-major input
 //    with coalesced loads (two row segments, so a stream's history and a new
-//    chunk need not be contiguous) and writes one byte per sample,
-//    channel-major: xc[c * pitch + t].  This is the "corner turn" the paper
-//    times separately (Table 2); it moves ~5 bytes per input sample, about 1%
-//    of the main kernel's time, and turns every later access into aligned
-//    contiguous 16-byte loads.
+//    chunk need not be contiguous) and writes it channel-major, one scratch
+//    row per live channel: 2-bit codes as nibbles (two samples per byte,
+//    eight per 32-bit word), 8-bit codes as bytes.  This is the "corner turn"
+//    the paper times separately (Table 2); it costs about 1% of the main
+//    kernel's time and turns every later access into aligned contiguous
+//    16-byte loads.
 //
 // 2. LDS-tiled shifted sum (k_tiled).  A workgroup owns one time tile of
-//    256*M output samples and a block of DB = NW*DPW neighbouring trial DMs.
-//    For each chunk of CC channels it stages, per channel, the window of
-//    samples the whole DM block needs -- [t0 + base, t0 + base + 4*rw) with
-//    base the block's smallest delay in that channel rounded down to 16 --
-//    into LDS.  Every DM of the block then reads its shifted slice of that
-//    window: the temporal reuse discussed in Section 2.2, which pays on
-//    gfx950 because LDS is large and the kernel is bound by integer adds.
-//    The loads of chunk k+1 are issued before chunk k is summed and land in
-//    registers, so their latency hides behind the arithmetic.
+//    64*M scratch words per lane-row (512*M samples of 2-bit or 256*M of
+//    8-bit data) and a block of DB = NW*DPW neighbouring trial DMs.  For
+//    each chunk of CC channels it stages, per channel, the window of samples
+//    the whole DM block needs -- it starts at t0 + base, base being the
+//    block's smallest delay in that channel rounded down to 16 bytes of
+//    scratch -- into LDS.  Every DM of the block then reads its shifted slice
+//    of that window: the temporal reuse discussed in Section 2.2, which pays
+//    on gfx950 because LDS is large and the kernel is bound by integer adds
+//    and LDS reads.  The loads of chunk k+1 are issued before chunk k is
+//    summed and land in registers, so their latency hides behind the
+//    arithmetic.
 //
-//    Each lane owns 4*M consecutive output samples of DPW DMs.  For one
-//    (DM, channel) pair the delay is wave-uniform: a lane reads M+1
-//    consecutive 32-bit words at its own word offset plus delay/4 and
-//    realigns them by delay%4 bytes with v_alignbyte (2-bit data) or spreads
-//    them into 16-bit lanes with v_perm (8-bit data).  Lanes are M words apart
-//    with M odd, so the 64 lanes of a wave hit distinct LDS banks.  The
-//    per-(DM, channel) window offsets arrive through vector loads and
-//    v_readlane, never through scalar memory, so waits on LDS are never held
-//    up by scalar loads.
+//    Each lane owns M consecutive scratch words (8*M or 4*M output samples)
+//    of DPW DMs.  For one (DM, channel) pair the delay is wave-uniform: a
+//    lane reads M+1 consecutive words at its own word offset plus the
+//    delay's whole words and realigns them by the remainder with v_alignbit
+//    (nibble granularity, 2-bit data) or spreads them into 16-bit lanes with
+//    v_perm (8-bit data).  Lanes are M words apart with M odd, so the 64
+//    lanes of a wave hit distinct LDS banks.  The per-(DM, channel) window
+//    offsets arrive through vector loads and v_readlane, never through
+//    scalar memory, so waits on LDS are never held up by scalar loads.
 //
-//    The sums use bit-level parallelism (Section 2.3): 2-bit codes are added
-//    four at a time in the 8-bit lanes of a register, exact for up to
-//    (2^8-1)/(2^2-1) = 85 channels, then flushed into 16-bit lanes (exact for
-//    up to 21845 channels); 8-bit codes are added two at a time in 16-bit
-//    lanes, exact for 257 channels, then flushed into 32-bit accumulators.
+//    The sums use bit-level parallelism (Section 2.3).  2-bit codes are
+//    added eight at a time in the 4-bit lanes of a register (exact for up to
+//    (2^4-1)/(2^2-1) = 5 codes, so flushed every 4 channels), then in 8-bit
+//    lanes (85 codes) and finally in 16-bit lanes (21845 codes).  8-bit
+//    codes are added two at a time in 16-bit lanes (257 codes), then in
+//    32-bit accumulators.
 //
 // Untiled kernel (k_untiled): one thread per 4 outputs of one DM reading the
 // packed input directly.  Used when a DM block's delay spread is too large
 // for LDS (e.g. a DM list with huge gaps) or the input is misaligned.
 //
-// Persistent kernel (k_persistent): a grid sized to the machine pulls
-// (beam, tile, DM block) work items from a global counter; beams may differ
-// in channel count, bit depth, length, DM list and tile shape.
+// Multi-beam kernels (k_multi, k_persistent): one launch over the (beam,
+// time tile, DM block) work items of up to 16 beams that may differ in
+// channel count, bit depth, length, DM list and tile shape.
 #include "dedisp_internal.h"
 
 namespace dedisp {
@@ -100,19 +104,30 @@ __device__ __forceinline__ int xcd_remap(int i, int n)
 
 constexpr int kUT = 128;   // time rows per unpack tile
 constexpr int kUC = 128;   // channels per unpack tile
-constexpr int kUPitch = kUT + 16;
 
-// xc[c * pitch + t] = code of channel c at time t, for a 128 x 128 tile.
-// Requires row_bytes % 4 == 0 and 4-byte aligned row segments.
+// Bytes of channel-major scratch per sample: 2-bit codes are stored two per
+// byte (sample 2i in the low nibble of byte i, 2i+1 in the high nibble),
+// 8-bit codes one per byte.
+template <int NBITS>
+struct Store {
+    static constexpr int kSamplesPerByte = NBITS == 2 ? 2 : 1;
+    static constexpr int kRowBytes = kUT / kSamplesPerByte;      // per channel per unpack tile
+    static constexpr int kPitch = kRowBytes + 16;                 // LDS row pitch of the unpack tile
+};
+
+// xc[row * pitch + byte] for a 128 x 128 (time x channel) tile, where row is
+// the channel's scratch row (killed channels have none).  Requires
+// row_bytes % 4 == 0 and 4-byte aligned input rows.
 template <int NBITS>
 __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t tile[kUC * kUPitch];
+    using S = Store<NBITS>;
+    __shared__ __attribute__((aligned(16))) uint8_t tile[kUC * S::kPitch];
     const long long t0 = (long long)blockIdx.x * kUT;
     const int c0 = blockIdx.y * kUC;
     constexpr int WPR = kUC * NBITS / 32;          // 32-bit words per row segment
     constexpr int CPW = 32 / NBITS;                // channels per word
-    // item = (row quad, word): four rows of one word -> CPW channel words
+    // item = (row quad, word): four rows of one word -> CPW channels x 4 times
     for (int it = threadIdx.x; it < (kUT / 4) * WPR; it += 256) {
         const int w = it % WPR;
         const int rq = it / WPR;
@@ -125,60 +140,70 @@ __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
                        ? *reinterpret_cast<const uint32_t*>(row_ptr(b, t) + (long long)cw * NBITS / 8)
                        : 0u;
         }
-        uint8_t* dst = tile + (size_t)(w * CPW) * kUPitch + 4 * rq;
         if constexpr (NBITS == 2) {
+            uint8_t* dst = tile + (size_t)(w * CPW) * S::kPitch + 2 * rq;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                // byte q of each row holds 4 channels -> one word of 4 times
+                // byte q of each row holds 4 channels -> [t0 t1 t2 t3] bytes
                 const uint32_t sel = 0x0C0C0000u | ((uint32_t)(q + 4) << 8) | (uint32_t)q;
                 const uint32_t lo = __builtin_amdgcn_perm(v[1], v[0], sel);
                 const uint32_t hi = __builtin_amdgcn_perm(v[3], v[2], sel);
                 const uint32_t w4 = lo | (hi << 16);
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    *reinterpret_cast<uint32_t*>(dst + (size_t)(4 * q + j) * kUPitch) =
-                        (w4 >> (2 * j)) & 0x03030303u;
+                for (int j = 0; j < 4; ++j) {
+                    // channel 4q+j: code of time k at bits [8k, 8k+1]; pack to nibbles
+                    const uint32_t x = (w4 >> (2 * j)) & 0x03030303u;
+                    const uint32_t y = x | (x >> 4);          // byte 0: t0|t1<<4, byte 2: t2|t3<<4
+                    *reinterpret_cast<uint16_t*>(dst + (size_t)(4 * q + j) * S::kPitch) =
+                        (uint16_t)((y & 0xFFu) | ((y >> 8) & 0xFF00u));
+                }
             }
         } else {
+            uint8_t* dst = tile + (size_t)(w * CPW) * S::kPitch + 4 * rq;
             const uint32_t a01 = __builtin_amdgcn_perm(v[1], v[0], 0x05010400u);
             const uint32_t a23 = __builtin_amdgcn_perm(v[3], v[2], 0x05010400u);
             const uint32_t b01 = __builtin_amdgcn_perm(v[1], v[0], 0x07030602u);
             const uint32_t b23 = __builtin_amdgcn_perm(v[3], v[2], 0x07030602u);
             *reinterpret_cast<uint32_t*>(dst) = __builtin_amdgcn_perm(a23, a01, 0x05040100u);
-            *reinterpret_cast<uint32_t*>(dst + kUPitch) = __builtin_amdgcn_perm(a23, a01, 0x07060302u);
-            *reinterpret_cast<uint32_t*>(dst + 2 * kUPitch) = __builtin_amdgcn_perm(b23, b01, 0x05040100u);
-            *reinterpret_cast<uint32_t*>(dst + 3 * kUPitch) = __builtin_amdgcn_perm(b23, b01, 0x07060302u);
+            *reinterpret_cast<uint32_t*>(dst + S::kPitch) = __builtin_amdgcn_perm(a23, a01, 0x07060302u);
+            *reinterpret_cast<uint32_t*>(dst + 2 * S::kPitch) = __builtin_amdgcn_perm(b23, b01, 0x05040100u);
+            *reinterpret_cast<uint32_t*>(dst + 3 * S::kPitch) = __builtin_amdgcn_perm(b23, b01, 0x07060302u);
         }
     }
     __syncthreads();
-    // write 16-byte pieces: kUT/16 per channel row, to the channel's scratch
-    // row (killed channels have none)
-    for (int it = threadIdx.x; it < kUC * (kUT / 16); it += 256) {
-        const int c = it / (kUT / 16);
-        const int p = it % (kUT / 16);
+    // write 16-byte pieces to each channel's scratch row (killed channels
+    // have none); pieces past the last sample hold zeros
+    constexpr int PPR = S::kRowBytes / 16;          // pieces per channel row
+    const long long byte0 = t0 / S::kSamplesPerByte;
+    for (int it = threadIdx.x; it < kUC * PPR; it += 256) {
+        const int c = it / PPR;
+        const int p = it % PPR;
         if (c0 + c >= b.nchans) continue;
-        const long long t = t0 + 16 * p;
-        if (t >= b.nsamps) continue;
+        if (t0 + 16LL * S::kSamplesPerByte * p >= b.nsamps) continue;
         const int row = b.chanmap ? b.chanmap[c0 + c] : c0 + c;
         if (row < 0) continue;
-        const u32x4 val = *reinterpret_cast<const u32x4*>(tile + (size_t)c * kUPitch + 16 * p);
-        *reinterpret_cast<u32x4*>(b.xc + (long long)row * b.pitch + t) = val;
+        const u32x4 val = *reinterpret_cast<const u32x4*>(tile + (size_t)c * S::kPitch + 16 * p);
+        *reinterpret_cast<u32x4*>(b.xc + (long long)row * b.pitch + byte0 + 16 * p) = val;
     }
-    // the padding row (odd number of live channels) reads as zeros
-    if (b.pad_row >= 0 && blockIdx.y == 0 && threadIdx.x < kUT / 16) {
-        const long long t = t0 + 16 * threadIdx.x;
-        if (t < b.nsamps)
-            *reinterpret_cast<u32x4*>(b.xc + (long long)b.pad_row * b.pitch + t) = u32x4{0u, 0u, 0u, 0u};
+    // the padding rows (live channels up to a multiple of 8) read as zeros
+    if (b.pad_row >= 0 && blockIdx.y == 0 && threadIdx.x < PPR * (b.nact - b.pad_row)) {
+        const int r = b.pad_row + threadIdx.x / PPR;
+        const int p = threadIdx.x % PPR;
+        if (t0 + 16LL * S::kSamplesPerByte * p < b.nsamps)
+            *reinterpret_cast<u32x4*>(b.xc + (long long)r * b.pitch + byte0 + 16 * p) =
+                u32x4{0u, 0u, 0u, 0u};
     }
 }
 
 // ------------------------------------------------------------ tiled sum
 
 // One (time tile, DM block) work item.
-//   xc   channel-major bytes, row pitch b.pitch (multiple of 16)
-//   base [nblocks][nchans]  window start (multiple of 16) of channel c
-//   rel  [nblocks*DB][nchans/2] window offsets (delay - base) of a DM row
-//        for channels 2p and 2p+1 in the low and high 16 bits
+//   xc   channel-major scratch, b.pitch bytes per row: 2-bit codes two per
+//        byte (8 samples per 32-bit word), 8-bit codes one per byte (4 per word)
+//   base [nblocks][nact]  window start of scratch row k, in samples (a
+//        multiple of 16 bytes of scratch)
+//   rel  [nblocks*DB][nact/2] window offsets (delay - base, in samples) of a
+//        DM row for scratch rows 2p and 2p+1 in the low and high 16 bits
 // LDS: CC rows of rw words (rw % 4 == 0).  Channels are summed in pairs so
 // the two realigned words of a pair fold into an accumulator with one
 // three-operand add, and one v_readlane fetches both offsets.
@@ -187,19 +212,35 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
 {
     static_assert(M % 2 == 1, "lanes must be an odd number of LDS words apart");
     static_assert(CC % NW == 0, "every wave stages the same number of channel rows");
-    static_assert(CC <= 128 && (64 % (CC / 2)) == 0, "offset pairs of one DM sit in one register");
-    static_assert(NBITS == 8 || CC <= 84, "2-bit lanes hold at most 85 codes");
-    constexpr int T = 256 * M;
+    static_assert(CC <= 84, "2-bit byte lanes hold 85 codes");
+    static_assert((64 % (CC / 2)) == 0, "offset pairs of one DM sit in one register");
+    constexpr int SPW = NBITS == 2 ? 8 : 4;      // samples per 32-bit LDS word
+    constexpr int SPB = NBITS == 2 ? 2 : 1;      // samples per scratch byte
+    constexpr int T = 64 * M * SPW;              // tile length in samples
     constexpr int DB = NW * DPW;
-    constexpr int CPW = CC / NW;           // channel rows staged per wave per chunk
-    constexpr int CP = CC / 2;             // channel pairs per chunk
-    constexpr int KPR = 64 / CP;           // DMs per offset register
-    constexpr int RV = (DPW + KPR - 1) / KPR;  // registers of offset pairs per wave
-    constexpr int NSW = NBITS == 2 ? 1 : 2;
-    constexpr int NACC = NBITS == 2 ? 2 : 4;
-    constexpr int LANE_SUM = NBITS == 2 ? 85 : 257;
-    constexpr int FLUSH = LANE_SUM / CC;   // chunks between flushes of the packed lanes
+    constexpr int CPW = CC / NW;                 // channel rows staged per wave per chunk
+    constexpr int CP = CC / 2;                   // channel pairs per chunk
+    constexpr int KPR = 64 / CP;                 // DMs per offset register
+    constexpr int RV = (DPW + KPR - 1) / KPR;    // registers of offset pairs per wave
+    // Packed lanes:
+    //  2-bit: a realigned word holds eight 4-bit lanes (samples 0..7), and a
+    //         group of 4 channels sums into them exactly (at most 12 < 16).
+    //         Every 8 channels the two group sums g, h are folded into
+    //           E += (g & 0x0F0F0F0F) + (h & 0x0F0F0F0F)   byte lanes: samples 0, 2, 4, 6
+    //           S += (g >> 4) + (h >> 4)
+    //         and every FLUSH chunks the odd samples are recovered as
+    //           O = S - ((E & 0xFFFFFF00) >> 4)            byte lanes: samples 1, 3, 5, 7
+    //         (each group sum's lowest nibble is below 16, so its shift
+    //         drops nothing but that nibble; the even nibbles it moves are
+    //         exactly E's upper three byte lanes shifted down by 4 bits).
+    //         E and O are exact up to 85 codes per lane, and are flushed into
+    //         16-bit lanes w16[0..3] = samples {0,4}, {2,6}, {1,5}, {3,7}.
+    //  8-bit: sw[0] = 16-bit lanes (samples 0, 1), sw[1] = (2, 3), exact for
+    //         257 codes, flushed every FLUSH chunks into 32-bit acc[0..3].
+    constexpr int NACC = 4;
+    constexpr int FLUSH = NBITS == 2 ? 85 / CC : 257 / CC;
     static_assert(FLUSH >= 1, "chunk too large for the packed lanes");
+    static_assert(CC % 8 == 0, "channels are summed in groups of 8");
 
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
@@ -207,8 +248,8 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     block = wave_uniform(block);
     const long long t0 = (long long)tile * T;
     // Every descriptor field is wave-uniform; keep them in scalar registers
-    // (the persistent kernel reads descriptors through a dynamic index).
-    const int nchans = wave_uniform(b.nact);   // live channels, in scratch-row order
+    // (the multi-beam kernels read descriptors through a dynamic index).
+    const int nchans = wave_uniform(b.nact);   // scratch rows, a multiple of 8
     const int rw = wave_uniform(b.rw);
     const int rq = rw >> 2;                // 16-byte pieces per row
     const long long pitch = wave_uniform64(b.pitch);
@@ -221,18 +262,13 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     const int npairs = nchans >> 1;
     const uint32_t* rel_rows = wave_uniform_ptr(b.rel) + (size_t)(block * DB + wave * DPW) * npairs;
 
-    // Packed-lane partial sums and wide accumulators.
-    // 2-bit: sw = four 8-bit lanes (samples 0..3); acc[0] = 16-bit lanes
-    // (samples 0, 2), acc[1] = (samples 1, 3).
-    // 8-bit: sw[0] = 16-bit lanes (samples 0, 1), sw[1] = (2, 3); acc = 32-bit.
-    uint32_t sw[DPW][M][NSW];
+    uint32_t sw[DPW][M][2];
     uint32_t acc[DPW][M][NACC];
 #pragma unroll
     for (int k = 0; k < DPW; ++k)
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-#pragma unroll
-            for (int h = 0; h < NSW; ++h) sw[k][j][h] = 0u;
+            sw[k][j][0] = sw[k][j][1] = 0u;
 #pragma unroll
             for (int e = 0; e < NACC; ++e) acc[k][j][e] = 0u;
         }
@@ -258,7 +294,7 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     _Pragma("unroll") for (int i = 0; i < CPW; ++i) {                               \
         const int cl = wave + NW * i;                                               \
         const int bs = lane_value(vbase_nxt, cl);                                   \
-        const uint8_t* src = xc + (long long)min((C0) + cl, last_c) * pitch + t0 + bs; \
+        const uint8_t* src = xc + (long long)min((C0) + cl, last_c) * pitch + (t0 + bs) / SPB; \
         _Pragma("unroll") for (int q = 0; q < PM; ++q)                              \
             pf[i][q] = *reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p)); \
     }
@@ -272,7 +308,7 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
 
     int since_flush = 0;
     for (int c0 = 0; c0 < nchans; c0 += CC) {
-        const int ncur = min(CC, nchans - c0);
+        const int ncur = min(CC, nchans - c0);  // a multiple of 8
         __syncthreads();                       // everyone is done reading the previous chunk
 #pragma unroll
         for (int i = 0; i < CPW; ++i) {
@@ -299,29 +335,55 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
 #undef DEDISP_LOAD_DATA
 
         const uint32_t* lrow = lds + lane * M;
-        for (int c = 0; c < ncur; c += 2) {
-            const uint32_t* row0 = lrow + (size_t)c * rw;
-            const uint32_t* row1 = row0 + rw;
+        if constexpr (NBITS == 2) {
+            for (int c = 0; c < ncur; c += 8) {
 #pragma unroll
-            for (int k = 0; k < DPW; ++k) {
-                // offsets of (DM k, channels c, c+1): register k / KPR, lane (k % KPR)*CP + c/2
-                const uint32_t rr = (uint32_t)lane_value((int)vrel_cur[k / KPR], (k % KPR) * CP + (c >> 1));
-                const uint32_t r0 = rr & 0xFFFFu, r1 = rr >> 16;
-                const uint32_t* src0 = row0 + (r0 >> 2);
-                const uint32_t* src1 = row1 + (r1 >> 2);
-                const uint32_t s0 = r0 & 3u, s1 = r1 & 3u;
-                uint32_t w0[M + 1], w1[M + 1];
+                for (int k = 0; k < DPW; ++k) {
+                    // offsets of (DM k, channels c+2q, c+2q+1): register k / KPR,
+                    // lane (k % KPR)*CP + c/2 + q
+                    uint32_t rr[4];
 #pragma unroll
-                for (int j = 0; j <= M; ++j) {
-                    w0[j] = src0[j];
-                    w1[j] = src1[j];
+                    for (int q = 0; q < 4; ++q)
+                        rr[q] = (uint32_t)lane_value((int)vrel_cur[k / KPR], (k % KPR) * CP + (c >> 1) + q);
+                    uint32_t w[8][M + 1], sh[8];
+#pragma unroll
+                    for (int h = 0; h < 8; ++h) {
+                        const uint32_t r = (h & 1) ? (rr[h >> 1] >> 16) : (rr[h >> 1] & 0xFFFFu);
+                        const uint32_t* src = lrow + (size_t)(c + h) * rw + r / SPW;
+#pragma unroll
+                        for (int j = 0; j <= M; ++j) w[h][j] = src[j];
+                        sh[h] = 4u * (r & 7u);                 // nibble shift
+                    }
+#pragma unroll
+                    for (int j = 0; j < M; ++j) {
+                        uint32_t a[8];
+#pragma unroll
+                        for (int h = 0; h < 8; ++h)
+                            a[h] = __builtin_amdgcn_alignbit(w[h][j + 1], w[h][j], sh[h]);
+                        const uint32_t g = (a[0] + a[1]) + (a[2] + a[3]);
+                        const uint32_t g2 = (a[4] + a[5]) + (a[6] + a[7]);
+                        sw[k][j][0] += (g & 0x0F0F0F0Fu) + (g2 & 0x0F0F0F0Fu);
+                        sw[k][j][1] += (g >> 4) + (g2 >> 4);
+                    }
                 }
-                if constexpr (NBITS == 2) {
+            }
+        } else {
+            for (int c = 0; c < ncur; c += 2) {
+                const uint32_t* row0 = lrow + (size_t)c * rw;
+                const uint32_t* row1 = row0 + rw;
 #pragma unroll
-                    for (int j = 0; j < M; ++j)
-                        sw[k][j][0] += __builtin_amdgcn_alignbyte(w0[j + 1], w0[j], s0) +
-                                       __builtin_amdgcn_alignbyte(w1[j + 1], w1[j], s1);
-                } else {
+                for (int k = 0; k < DPW; ++k) {
+                    const uint32_t rr = (uint32_t)lane_value((int)vrel_cur[k / KPR], (k % KPR) * CP + (c >> 1));
+                    const uint32_t r0 = rr & 0xFFFFu, r1 = rr >> 16;
+                    const uint32_t* src0 = row0 + r0 / SPW;
+                    const uint32_t* src1 = row1 + r1 / SPW;
+                    uint32_t w0[M + 1], w1[M + 1];
+#pragma unroll
+                    for (int j = 0; j <= M; ++j) {
+                        w0[j] = src0[j];
+                        w1[j] = src1[j];
+                    }
+                    const uint32_t s0 = r0 & 3u, s1 = r1 & 3u;
                     // bytes s, s+1 -> 16-bit lanes of sw[0]; s+2, s+3 -> sw[1]
                     const uint32_t lo0 = s0 | 0x0C00u | ((s0 + 1u) << 16) | 0x0C000000u;
                     const uint32_t lo1 = s1 | 0x0C00u | ((s1 + 1u) << 16) | 0x0C000000u;
@@ -344,9 +406,12 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
                     if constexpr (NBITS == 2) {
-                        const uint32_t v = sw[k][j][0];
-                        acc[k][j][0] += v & 0x00FF00FFu;
-                        acc[k][j][1] += (v >> 8) & 0x00FF00FFu;
+                        const uint32_t e = sw[k][j][0];
+                        const uint32_t o = sw[k][j][1] - ((e & 0xFFFFFF00u) >> 4);
+                        acc[k][j][0] += e & 0x00FF00FFu;           // samples 0, 4
+                        acc[k][j][1] += (e >> 8) & 0x00FF00FFu;    // samples 2, 6
+                        acc[k][j][2] += o & 0x00FF00FFu;           // samples 1, 5
+                        acc[k][j][3] += (o >> 8) & 0x00FF00FFu;    // samples 3, 7
                     } else {
                         const uint32_t lo = sw[k][j][0], hi = sw[k][j][1];
                         acc[k][j][0] += lo & 0xFFFFu;
@@ -354,8 +419,8 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
                         acc[k][j][2] += hi & 0xFFFFu;
                         acc[k][j][3] += hi >> 16;
                     }
-#pragma unroll
-                    for (int h = 0; h < NSW; ++h) sw[k][j][h] = 0u;
+                    sw[k][j][0] = 0u;
+                    sw[k][j][1] = 0u;
                 }
         }
     }
@@ -368,23 +433,31 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
         uint32_t* orow = out + (size_t)d * (size_t)out_stride;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
-            const long long t = t0 + 4LL * (lane * M + j);
-            uint32_t o[4];
+            const long long t = t0 + (long long)SPW * (lane * M + j);
+            uint32_t o[SPW];
             if constexpr (NBITS == 2) {
-                o[0] = acc[k][j][0] & 0xFFFFu;
-                o[1] = acc[k][j][1] & 0xFFFFu;
-                o[2] = acc[k][j][0] >> 16;
-                o[3] = acc[k][j][1] >> 16;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    o[4 * h + 0] = (acc[k][j][0] >> (16 * h)) & 0xFFFFu;
+                    o[4 * h + 1] = (acc[k][j][2] >> (16 * h)) & 0xFFFFu;
+                    o[4 * h + 2] = (acc[k][j][1] >> (16 * h)) & 0xFFFFu;
+                    o[4 * h + 3] = (acc[k][j][3] >> (16 * h)) & 0xFFFFu;
+                }
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) o[e] = acc[k][j][e];
             }
-            if (vec && t + 3 < nout) {
-                *reinterpret_cast<u32x4*>(orow + t) = u32x4{o[0], o[1], o[2], o[3]};
-            } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (t + e < nout) orow[t + e] = o[e];
+            for (int g = 0; g < SPW / 4; ++g) {
+                const long long tg = t + 4 * g;
+                if (vec && tg + 3 < nout) {
+                    *reinterpret_cast<u32x4*>(orow + tg) =
+                        u32x4{o[4 * g], o[4 * g + 1], o[4 * g + 2], o[4 * g + 3]};
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (tg + e < nout) orow[tg + e] = o[4 * g + e];
+                }
             }
         }
     }
@@ -434,19 +507,21 @@ __global__ __launch_bounds__(256) void k_untiled(BeamDesc b)
 // ---------------------------------------------------------------- shapes
 
 // (nbits, waves, DMs per wave, words per lane, channels per chunk, pieces,
-// persistent): a tile is 256*words samples long; a staged channel row holds
-// at most 64*pieces 16-byte pieces (1024*pieces samples); shapes marked
-// persistent are also compiled into the multi-beam persistent kernel (which
-// allocates registers for the largest of them).  The first shape of each bit
-// depth is the default.
+// multi): a tile is 64*words scratch words long (512*words 2-bit or
+// 256*words 8-bit samples); a staged channel row holds at most 64*pieces
+// 16-byte pieces (2048*pieces 2-bit or 1024*pieces 8-bit samples); shapes
+// marked multi are also compiled into the multi-beam kernels (which allocate
+// registers for the largest of them).  The first shape of each bit depth is
+// the default.
 #define DEDISP_SHAPES(X)             \
-    X(2, 8, 4, 5, 32, 2, 1)          \
-    X(2, 8, 4, 3, 32, 2, 1)          \
-    X(2, 8, 4, 5, 16, 4, 1)          \
-    X(2, 8, 4, 5, 64, 2, 0)          \
-    X(2, 8, 2, 5, 64, 2, 0)          \
-    X(2, 4, 4, 5, 32, 2, 0)          \
-    X(2, 16, 2, 5, 64, 2, 0)         \
+    X(2, 8, 2, 3, 32, 2, 1)          \
+    X(2, 8, 2, 3, 16, 4, 1)          \
+    X(2, 8, 2, 1, 32, 2, 1)          \
+    X(2, 8, 4, 3, 32, 2, 0)          \
+    X(2, 8, 2, 5, 32, 2, 0)          \
+    X(2, 8, 4, 3, 16, 4, 0)          \
+    X(2, 16, 2, 3, 64, 2, 0)         \
+    X(2, 16, 1, 5, 64, 2, 0)         \
     X(8, 8, 2, 5, 32, 2, 1)          \
     X(8, 8, 2, 3, 16, 4, 1)          \
     X(8, 8, 4, 3, 16, 4, 0)          \
@@ -461,8 +536,8 @@ struct ShapeEntry {
     const void* fn;
 };
 
-#define DEDISP_ENTRY(NB, NW, DPW, M, CC, PM, PERSIST) \
-    {Shape{0, NB, NW, DPW, M, CC, PM, PERSIST}, reinterpret_cast<const void*>(&k_tiled<NB, NW, DPW, M, CC, PM>)},
+#define DEDISP_ENTRY(NB, NW, DPW, M, CC, PM, MULTI) \
+    {Shape{0, NB, NW, DPW, M, CC, PM, MULTI}, reinterpret_cast<const void*>(&k_tiled<NB, NW, DPW, M, CC, PM>)},
 
 const ShapeEntry kShapes[] = {
     DEDISP_SHAPES(DEDISP_ENTRY)
@@ -471,15 +546,14 @@ const ShapeEntry kShapes[] = {
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
-// Persistent kernel: the shapes marked persistent (all have
-// kPersistentWaves waves).  Work item i of beam b is (tile, DM block) =
-// divmod(i - work_begin, nblocks); workgroup g takes items g, g + grid, ...
-template <int NBITS, int NW, int DPW, int M, int CC, int PM, int PERSIST>
+// Multi-beam kernels: the shapes marked multi (all have kMultiWaves
+// waves).
+template <int NBITS, int NW, int DPW, int M, int CC, int PM, int MULTI>
 __device__ __forceinline__ bool run_if(int shape_id, int want, const BeamDesc& b, int tile,
                                        int block, uint32_t* lds)
 {
-    if constexpr (PERSIST != 0) {
-        static_assert(NW == kPersistentWaves, "persistent shapes share one workgroup size");
+    if constexpr (MULTI != 0) {
+        static_assert(NW == kMultiWaves, "multi-beam shapes share one workgroup size");
         if (shape_id == want) {
             tile_body<NBITS, NW, DPW, M, CC, PM>(b, tile, block, lds);
             return true;
@@ -508,8 +582,8 @@ __device__ __forceinline__ void run_item(const DescBlock& blk, int nbeams, int i
     const int block = local - tile * b.nblocks;
     int id = 0;
     bool done = false;
-#define DEDISP_RUN(NB, NW, DPW, M, CC, PM, PERSIST) \
-    if (!done) done = run_if<NB, NW, DPW, M, CC, PM, PERSIST>(b.shape, id, b, tile, block, lds); \
+#define DEDISP_RUN(NB, NW, DPW, M, CC, PM, MULTI) \
+    if (!done) done = run_if<NB, NW, DPW, M, CC, PM, MULTI>(b.shape, id, b, tile, block, lds); \
     ++id;
     DEDISP_SHAPES(DEDISP_RUN)
 #undef DEDISP_RUN
@@ -518,7 +592,7 @@ __device__ __forceinline__ void run_item(const DescBlock& blk, int nbeams, int i
 
 // Multi-beam launch, one workgroup per work item of every beam (the
 // hardware dispatcher balances the uneven items as workgroups finish).
-__global__ __launch_bounds__(kPersistentWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_multi(DescBlock blk, int nbeams,
+__global__ __launch_bounds__(kMultiWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_multi(DescBlock blk, int nbeams,
                                                                   int total)
 {
     extern __shared__ uint32_t lds_dyn[];
@@ -527,7 +601,7 @@ __global__ __launch_bounds__(kPersistentWaves * 64) __attribute__((amdgpu_waves_
 
 // Persistent variant: a grid sized to the machine; workgroup g takes items
 // g, g + grid, ...
-__global__ __launch_bounds__(kPersistentWaves * 64) void k_persistent(DescBlock blk, int nbeams,
+__global__ __launch_bounds__(kMultiWaves * 64) void k_persistent(DescBlock blk, int nbeams,
                                                                        int total)
 {
     extern __shared__ uint32_t lds_dyn[];
@@ -609,7 +683,7 @@ int persistent_max_grid(int lds_bytes)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persistent),
                               hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&k_persistent), kPersistentWaves * 64,
+            &per_cu, reinterpret_cast<const void*>(&k_persistent), kMultiWaves * 64,
             (size_t)lds_bytes) != hipSuccess)
         return 0;
     if (per_cu < 1) per_cu = 1;
@@ -628,7 +702,7 @@ hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int ld
     int a2 = total_work;
     void* args[] = {&a0, &a1, &a2};
     return hipLaunchKernel(reinterpret_cast<const void*>(&k_multi), dim3(total_work),
-                           dim3(kPersistentWaves * 64), args, (size_t)lds_bytes, st);
+                           dim3(kMultiWaves * 64), args, (size_t)lds_bytes, st);
 }
 
 hipError_t launch_persistent(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
@@ -645,7 +719,7 @@ hipError_t launch_persistent(const DescBlock& blk, int nbeams, int total_work, i
     int a2 = total_work;
     void* args[] = {&a0, &a1, &a2};
     return hipLaunchKernel(reinterpret_cast<const void*>(&k_persistent), dim3(grid),
-                           dim3(kPersistentWaves * 64), args, (size_t)lds_bytes, st);
+                           dim3(kMultiWaves * 64), args, (size_t)lds_bytes, st);
 }
 
 }  // namespace dedisp

@@ -10,7 +10,7 @@
 // input (the time-division processing of Section 6 of the paper, without
 // dropping the samples at chunk boundaries).
 //
-// dedisp_stream_push_many runs several streams' pushes as one persistent
+// dedisp_stream_push_many runs several streams' pushes as one multi-beam
 // launch: the continuous-batching step of a serving loop.
 #include "dedisp_host.h"
 
@@ -53,7 +53,7 @@ dedisp_status check_stream(dedisp_stream s)
 
 // Validate a push and build its launch (no device work yet).
 dedisp_status prepare_push(dedisp_stream s, const void* chunk, size_t L, uint32_t* out,
-                           size_t stride, bool persistent, PushPlan& pp)
+                           size_t stride, bool multi, PushPlan& pp)
 {
     dedisp_status st = check_stream(s);
     if (st != DEDISP_OK) return st;
@@ -69,7 +69,7 @@ dedisp_status prepare_push(dedisp_stream s, const void* chunk, size_t L, uint32_
     if (stride < pp.nout) return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < new outputs");
     dedisp_plan p = s->plan;
     LaunchPlan lp;
-    st = resolve_launch(p, p->cfg, true, lp, persistent);
+    st = resolve_launch(p, p->cfg, true, lp, multi);
     if (st != DEDISP_OK) return st;
     if (lp.shape.kind == 0 && (reinterpret_cast<uintptr_t>(chunk) & 3)) {
         dedisp_tile_config u{};

@@ -5,7 +5,7 @@ time.  A scheduler thread admits them under a device-memory budget, groups
 the admitted head-of-line chunks of distinct streams into a *tick*, copies
 them to the device on a copy stream, and enqueues the tick as one batched
 launch (``dedisp_stream_push_many``: one corner turn per chunk, then a single
-persistent kernel over every chunk's tiles) on the compute stream, without
+multi-beam kernel over every chunk's tiles) on the compute stream, without
 waiting for earlier ticks: new requests are admitted while others are on the
 GPU and their work overlaps there.  A completion thread waits for each tick's
 event, stamps every request's completion time and releases its memory, which
