@@ -45,8 +45,17 @@ def _load():
     lib.oracle_dedisperse_points.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                              _i32p, ctypes.c_int, ctypes.c_int32, _i64p, _i64p,
                                              ctypes.c_int64, _u32p, ctypes.c_int, _i32p]
+    lib.oracle_diagonal_dm.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, _f64p]
+    lib.oracle_scrunch_factor.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
+    lib.oracle_scrunch.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, _u32p]
+    lib.oracle_dedisperse_values.argtypes = [_u32p, ctypes.c_int64, ctypes.c_int, _i32p,
+                                             ctypes.c_int, ctypes.c_int32, _u32p,
+                                             ctypes.c_int64, ctypes.c_int, _i32p]
     for f in ("oracle_partial_delay", "oracle_delay_table", "oracle_dedisperse",
-              "oracle_dedisperse_points", "oracle_max_threads"):
+              "oracle_dedisperse_points", "oracle_max_threads", "oracle_diagonal_dm",
+              "oracle_scrunch_factor", "oracle_scrunch", "oracle_dedisperse_values"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -132,3 +141,78 @@ def dedisperse_points(packed, nsamps, nchans, nbits, table, d_idx, t_idx, max_de
                                             _ptr(out, _u32p), int(nthreads), mp),
            "dedisperse_points")
     return out
+
+
+# ---------------------------------------------------------------- time-scrunching
+
+
+def diagonal_dm(nchans, dt, f_top, df) -> float:
+    """The band's diagonal DM: one sample of delay between its last two channels."""
+    v = ctypes.c_double()
+    _check(_load().oracle_diagonal_dm(nchans, dt, f_top, df, ctypes.byref(v)), "diagonal_dm")
+    return float(v.value)
+
+
+def scrunch_factor(dm, dm_diag, max_factor) -> int:
+    return int(_load().oracle_scrunch_factor(float(dm), float(dm_diag), int(max_factor)))
+
+
+def scrunch(packed, nsamps, nchans, nbits, s):
+    """Scrunched samples: uint32 [nsamps // s][nchans], each the sum of s samples."""
+    packed = np.ascontiguousarray(packed, dtype=np.uint8).reshape(-1)
+    if packed.size < int(nsamps) * nchans * nbits // 8:
+        raise OracleError("input too short")
+    out = np.zeros((max(int(nsamps) // int(s), 1), nchans), dtype=np.uint32)
+    _check(_load().oracle_scrunch(_ptr(packed, _u8p), int(nsamps), nchans, nbits, int(s),
+                                  _ptr(out, _u32p)), "scrunch")
+    return out[: int(nsamps) // int(s)]
+
+
+def dedisperse_values(x, table, max_delay=None, nthreads=0, mask=None):
+    """Direct transform of unpacked time-major values x [n][nchans]: uint32 [ndm][n - max_delay]."""
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    n, nchans = x.shape
+    table = np.ascontiguousarray(table, dtype=np.int32)
+    ndm = int(table.shape[0])
+    if max_delay is None:
+        max_delay = int(table.max())
+    nout = n - int(max_delay)
+    if nout <= 0:
+        raise OracleError("too few samples")
+    out = np.zeros((ndm, nout), dtype=np.uint32)
+    m, mp = _mask_arg(mask, nchans)
+    _check(_load().oracle_dedisperse_values(_ptr(x, _u32p), n, nchans, _ptr(table, _i32p), ndm,
+                                            int(max_delay), _ptr(out, _u32p), nout,
+                                            int(nthreads), mp), "dedisperse_values")
+    return out
+
+
+def scrunch_factors(nchans, dt, f_top, df, dms, max_factor):
+    """Per-trial scrunch factors for a DM list."""
+    dd = diagonal_dm(nchans, dt, f_top, df)
+    return np.array([scrunch_factor(dm, dd, max_factor) for dm in dms], dtype=np.int32)
+
+
+def dedisperse_scrunched(packed, nsamps, nchans, nbits, dt, f_top, df, dms, factors,
+                         nthreads=0, mask=None):
+    """The time-scrunched transform: each factor group dedispersed at its own
+    resolution.  Returns (out, nout) with out uint32 [ndm][max nout] (row d
+    valid up to nout[d], zero after) and nout int64 [ndm]."""
+    dms = np.asarray(dms, dtype=np.float64)
+    factors = np.asarray(factors, dtype=np.int64)
+    groups = {}
+    for s in sorted(set(int(v) for v in factors)):
+        rows = np.nonzero(factors == s)[0]
+        table, mx = delay_table(nchans, dt * s, f_top, df, dms[rows])
+        n_s = int(nsamps) // s
+        if n_s - mx <= 0:
+            raise OracleError("too few samples for scrunch group %d" % s)
+        x = scrunch(packed, nsamps, nchans, nbits, s)
+        groups[s] = (rows, dedisperse_values(x, table, mx, nthreads, mask))
+    width = max(g[1].shape[1] for g in groups.values())
+    out = np.zeros((len(dms), width), dtype=np.uint32)
+    nout = np.zeros(len(dms), dtype=np.int64)
+    for s, (rows, o) in groups.items():
+        out[rows, : o.shape[1]] = o
+        nout[rows] = o.shape[1]
+    return out, nout

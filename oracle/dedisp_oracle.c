@@ -191,6 +191,113 @@ int oracle_dedisperse_points(const uint8_t* in, int64_t nsamps, int nchans, int 
     return ORACLE_OK;
 }
 
+/* ------------------------------------------------------------------------
+ * Time-scrunching (Section 2.1).  Beyond the "diagonal" DM -- where the
+ * dispersion trail crosses more than one time sample per frequency channel
+ * -- the time resolution is halved by adding adjacent pairs of samples, and
+ * halved again at twice that DM, and so on.  The trials of a scrunched group
+ * are then dedispersed with the same direct sum at the coarser resolution.
+ *
+ * Readings fixed here:
+ *   - the diagonal DM is the DM at which the delay between the last two
+ *     channels of the band (where the trail is steepest) is one sample:
+ *     1 / (Delta T(N-1) - Delta T(N-2));
+ *   - a trial scrunches by 2 once its DM exceeds the diagonal, by 4 once it
+ *     exceeds twice the diagonal, and so on (up to a caller-given maximum);
+ *   - a group with factor s uses the delay equation with the sampling time
+ *     s*dtau, scrunched sample t' is the sum of samples s*t' .. s*t'+s-1
+ *     (a trailing partial group of fewer than s samples is dropped), and the
+ *     group's outputs exist for t' < nsamps/s - (largest delay of the group).
+ * ------------------------------------------------------------------------ */
+
+/* The diagonal DM of the band. */
+int oracle_diagonal_dm(int nchans, double dt, double f_top, double df, double* dm)
+{
+    if (!dm) return ORACLE_BAD_ARG;
+    if (oracle_check_params(nchans, dt, f_top, df, 8) != ORACLE_OK) return ORACLE_BAD_ARG;
+    if (nchans < 2) {
+        *dm = HUGE_VAL;             /* one channel: no trail to smear */
+        return ORACLE_OK;
+    }
+    const double inv_top2 = 1.0 / (f_top * f_top);
+    const double scale = ORACLE_K_DM / dt;
+    const double fa = f_top + (double)(nchans - 2) * df;
+    const double fb = f_top + (double)(nchans - 1) * df;
+    const double dTa = scale * (1.0 / (fa * fa) - inv_top2);
+    const double dTb = scale * (1.0 / (fb * fb) - inv_top2);
+    *dm = 1.0 / (dTb - dTa);
+    return ORACLE_OK;
+}
+
+/* The scrunch factor of one trial DM: 1 up to the diagonal, then doubling
+ * each time the DM exceeds the next power-of-two multiple of it. */
+int oracle_scrunch_factor(double dm, double dm_diag, int max_factor)
+{
+    int s = 1;
+    double threshold = dm_diag;
+    while (s < max_factor && dm > threshold) {
+        s *= 2;
+        threshold *= 2.0;
+    }
+    return s;
+}
+
+/* x[t'][c] = sum over i < s of A[c][s*t' + i], for t' < nsamps / s, as
+ * unpacked time-major uint32 values. */
+int oracle_scrunch(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int s,
+                   uint32_t* out)
+{
+    if (!in || !out || nsamps < 0 || s < 1) return ORACLE_BAD_ARG;
+    if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
+    if (nbits == 2 && nchans % 4) return ORACLE_BAD_ARG;
+    const int64_t n = nsamps / s;
+    for (int64_t tp = 0; tp < n; ++tp)
+        for (int nu = 0; nu < nchans; ++nu) {
+            uint32_t sum = 0;
+            for (int i = 0; i < s; ++i)
+                sum += oracle_sample(in, nchans, nbits, tp * s + i, nu);
+            out[(size_t)tp * (size_t)nchans + (size_t)nu] = sum;
+        }
+    return ORACLE_OK;
+}
+
+/* The direct transform (the "direct" equation of Section 2.1) of unpacked
+ * time-major values x[t][c] (such as scrunched samples), with an optional
+ * 0/1 channel kill mask, for 0 <= t < nsamps - max_delay. */
+int oracle_dedisperse_values(const uint32_t* x, int64_t nsamps, int nchans,
+                             const int32_t* table, int ndm, int32_t max_delay,
+                             uint32_t* out, int64_t out_stride, int nthreads,
+                             const int32_t* mask)
+{
+    if (!x || !table || !out || ndm <= 0 || nchans <= 0) return ORACLE_BAD_ARG;
+    if (nsamps <= (int64_t)max_delay) return ORACLE_TOO_FEW_SAMPLES;
+    const int64_t nout = nsamps - (int64_t)max_delay;
+    if (out_stride < nout) return ORACLE_BAD_ARG;
+    for (size_t i = 0; i < (size_t)ndm * (size_t)nchans; ++i)
+        if (table[i] < 0 || table[i] > max_delay) return ORACLE_BAD_ARG;
+    if (mask)
+        for (int nu = 0; nu < nchans; ++nu)
+            if (mask[nu] != 0 && mask[nu] != 1) return ORACLE_BAD_ARG;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int d = 0; d < ndm; ++d) {
+        const int32_t* delay = table + (size_t)d * nchans;
+        uint32_t* row = out + (size_t)d * (size_t)out_stride;
+        for (int64_t t = 0; t < nout; ++t) {
+            uint32_t sum = 0;
+            for (int nu = 0; nu < nchans; ++nu)
+                sum += (mask ? (uint32_t)mask[nu] : 1u) *
+                       x[(size_t)(t + delay[nu]) * (size_t)nchans + (size_t)nu];
+            row[t] = sum;
+        }
+    }
+    return ORACLE_OK;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

@@ -13,7 +13,14 @@ against things other than itself:
   responses, linearity, time-shift equivariance, textbook reductions (the DM 0
   row is a plain channel sum, one channel is a copy, constant input), 2-bit
   decoding against numpy's own bit packer, and recovery of injected pulses at
-  the trial and time they were injected (the analogue of Fig. 1).
+  the trial and time they were injected (the analogue of Fig. 1);
+* the channel kill mask (Section 2.3) against the brute force on masked input;
+* time-scrunching (Section 2.1): scrunched samples against a numpy
+  reshape-sum, the diagonal DM against exact rational arithmetic (and the
+  steepest channel pair being the band's last), the factor rule against its
+  closed form, every factor group against the push brute force at s times
+  the sampling time, DM 0 against the s-sums of the plain channel sum, the
+  impulse response, and time-shift equivariance by whole scrunched samples.
 """
 from fractions import Fraction
 
@@ -370,3 +377,137 @@ def test_kill_mask_push_brute_force_and_special_cases():
         assert np.array_equal(out1[d], codes[table[d, 5]: table[d, 5] + nout, 5])
     with pytest.raises(oracle.OracleError):
         oracle.dedisperse(packed, nsamps, nchans, nbits, table, mask=np.full(nchans, 2, np.int32))
+
+
+# ---------------------------------------------------------------------------
+# time-scrunching (Section 2.1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nbits,nchans,nsamps,s", [
+    (2, 8, 101, 1), (2, 16, 203, 2), (8, 5, 77, 4), (8, 12, 300, 8), (2, 4, 64, 64), (8, 3, 50, 3)])
+def test_scrunch_is_reshape_sum(nbits, nchans, nsamps, s):
+    """Scrunched sample t' is the sum of samples s*t' .. s*t'+s-1; a ragged tail is dropped."""
+    rng = np.random.default_rng(nsamps + s)
+    codes = rng.integers(0, 256 if nbits == 8 else 4, size=(nsamps, nchans), dtype=np.uint8)
+    got = oracle.scrunch(synth.pack(codes, nbits), nsamps, nchans, nbits, s)
+    n = nsamps // s
+    want = codes[: n * s].astype(np.uint32).reshape(n, s, nchans).sum(axis=1)
+    assert got.shape == want.shape and np.array_equal(got, want)
+
+
+def test_dedisperse_values_matches_brute_force_and_packed_path():
+    rng = np.random.default_rng(41)
+    nsamps, nchans, ndm = 240, 12, 9
+    x = rng.integers(0, 40000, size=(nsamps, nchans)).astype(np.uint32)
+    _, table = _random_case(rng, nsamps, nchans, 8, ndm, 33)
+    got = oracle.dedisperse_values(x, table)
+    assert np.array_equal(got.astype(np.int64), _push_brute_force(x.astype(np.int64), table))
+    codes = rng.integers(0, 256, size=(nsamps, nchans), dtype=np.uint8)
+    assert np.array_equal(oracle.dedisperse_values(codes.astype(np.uint32), table),
+                          oracle.dedisperse(codes, nsamps, nchans, 8, table))
+
+
+@pytest.mark.parametrize("case", ["tiny", "survey", "large"])
+def test_diagonal_dm_exact_and_steepest_at_band_end(case):
+    """DM_diag = 1 / (Delta T(N-1) - Delta T(N-2)) in exact arithmetic, and the
+    last channel pair is where the trail is steepest (so the diagonal there
+    bounds every channel pair)."""
+    nch_s, dt_s, f0_s, df_s, _, _ = CASES[case]
+    nch = int(nch_s)
+    K, dt, f0, dfr = Fraction("4148.808"), Fraction(dt_s), Fraction(f0_s), Fraction(df_s)
+    inv0 = 1 / (f0 * f0)
+
+    def dT(c):
+        f = f0 + c * dfr
+        return K / dt * (1 / (f * f) - inv0)
+    exact = 1 / (dT(nch - 1) - dT(nch - 2))
+    got = oracle.diagonal_dm(nch, float(dt_s), float(f0_s), float(df_s))
+    assert abs(Fraction(got) - exact) <= exact * Fraction(1, 10**12)
+    # steepest pair is the last one (checked on a spread of pairs)
+    steps = [dT(c + 1) - dT(c) for c in range(0, nch - 1, max(1, (nch - 1) // 17))]
+    assert max(steps) < dT(nch - 1) - dT(nch - 2)
+    # at the diagonal DM the delays of the last two channels differ by one sample
+    tab, _ = oracle.delay_table(nch, float(dt_s), float(f0_s), float(df_s), np.array([got]))
+    assert tab[0, nch - 1] - tab[0, nch - 2] == 1
+
+
+def test_scrunch_factor_rule():
+    """1 up to the diagonal, then 2^ceil(log2(DM / DM_diag)), capped."""
+    dd = 32.6
+    for dm in np.concatenate([np.linspace(0, 5000, 997), dd * 2.0 ** np.arange(0, 8)]):
+        want = 1 if dm <= dd else int(2 ** np.ceil(np.log2(dm / dd)))
+        assert oracle.scrunch_factor(dm, dd, 1 << 20) == want, dm
+        assert oracle.scrunch_factor(dm, dd, 8) == min(want, 8)
+    assert oracle.scrunch_factor(1e9, dd, 1) == 1
+
+
+def _scrunch_case(nbits, seed, nsamps=1500, nchans=32, ndm=24, dm_max=400.0):
+    rng = np.random.default_rng(seed)
+    codes = rng.integers(0, 256 if nbits == 8 else 4, size=(nsamps, nchans), dtype=np.uint8)
+    prm = dict(nchans=nchans, dt=64e-6, f_top=1500.0, df=-2.0)
+    dms = synth.dm_list_linear(ndm, dm_max)
+    return codes, prm, dms
+
+
+@pytest.mark.parametrize("nbits", [2, 8])
+def test_scrunched_transform_reductions_and_brute_force(nbits):
+    codes, prm, dms = _scrunch_case(nbits, 50 + nbits)
+    nsamps, nchans = codes.shape
+    packed = synth.pack(codes, nbits)
+    args = (packed, nsamps, nchans, nbits, prm["dt"], prm["f_top"], prm["df"], dms)
+    # all factors 1: the plain transform
+    table, mx = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], dms)
+    out1, n1 = oracle.dedisperse_scrunched(*args, np.ones(len(dms), np.int32))
+    assert np.all(n1 == nsamps - mx)
+    assert np.array_equal(out1, oracle.dedisperse(packed, nsamps, nchans, nbits, table))
+    # mixed factors: each group is a push brute force over s-sums at dt*s
+    factors = oracle.scrunch_factors(nchans, prm["dt"], prm["f_top"], prm["df"], dms, 8)
+    assert set(factors.tolist()) >= {1, 2, 4}
+    out, nout = oracle.dedisperse_scrunched(*args, factors)
+    for s in sorted(set(factors.tolist())):
+        rows = np.nonzero(factors == s)[0]
+        tab_s, mx_s = oracle.delay_table(nchans, prm["dt"] * s, prm["f_top"], prm["df"], dms[rows])
+        n = nsamps // s
+        x = codes[: n * s].astype(np.int64).reshape(n, s, nchans).sum(axis=1)
+        want = _push_brute_force(x, tab_s)
+        assert np.all(nout[rows] == n - mx_s)
+        assert np.array_equal(out[rows, : n - mx_s].astype(np.int64), want)
+        assert not out[rows, n - mx_s:].any()
+    # DM 0 with factor s: the s-sums of the full-resolution DM 0 row
+    full0 = codes.sum(axis=1, dtype=np.int64)
+    for s in (2, 4):
+        o, n = oracle.dedisperse_scrunched(*args[:7], np.array([0.0]), np.array([s]))
+        m = nsamps // s
+        assert n[0] == m and np.array_equal(o[0].astype(np.int64),
+                                            full0[: m * s].reshape(m, s).sum(axis=1))
+
+
+def test_scrunched_impulse_and_time_shift():
+    nbits, nsamps, nchans = 8, 900, 16
+    prm = dict(dt=64e-6, f_top=1500.0, df=-2.0)
+    dms = synth.dm_list_linear(16, 600.0)
+    factors = oracle.scrunch_factors(nchans, prm["dt"], prm["f_top"], prm["df"], dms, 16)
+    for c, ts in ((3, 700), (15, 611), (0, 899)):
+        codes = np.zeros((nsamps, nchans), np.uint8)
+        codes[ts, c] = 1
+        out, nout = oracle.dedisperse_scrunched(codes, nsamps, nchans, nbits, prm["dt"],
+                                                prm["f_top"], prm["df"], dms, factors)
+        for d, s in enumerate(factors):
+            tab, _ = oracle.delay_table(nchans, prm["dt"] * s, prm["f_top"], prm["df"], dms[d:d + 1])
+            want = np.zeros(nout[d], np.uint32)
+            t = ts // s - tab[0, c]
+            if ts < (nsamps // s) * s and 0 <= t < nout[d]:
+                want[t] = 1
+            assert np.array_equal(out[d, : nout[d]], want), (c, ts, d)
+    # shifting the input by 16 samples (the largest factor) shifts every group
+    # by 16 / s scrunched samples
+    assert factors.max() == 16
+    rng = np.random.default_rng(9)
+    codes = rng.integers(0, 256, size=(nsamps, nchans), dtype=np.uint8)
+    full, nf = oracle.dedisperse_scrunched(codes, nsamps, nchans, nbits, prm["dt"], prm["f_top"],
+                                           prm["df"], dms, factors)
+    sh, ns = oracle.dedisperse_scrunched(codes[16:], nsamps - 16, nchans, nbits, prm["dt"],
+                                         prm["f_top"], prm["df"], dms, factors)
+    for d, s in enumerate(factors):
+        k = 16 // s
+        assert np.array_equal(sh[d, : ns[d]], full[d, k: k + ns[d]])
