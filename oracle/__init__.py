@@ -53,7 +53,20 @@ def _load():
     lib.oracle_dedisperse_values.argtypes = [_u32p, ctypes.c_int64, ctypes.c_int, _i32p,
                                              ctypes.c_int, ctypes.c_int32, _u32p,
                                              ctypes.c_int64, ctypes.c_int, _i32p]
-    for f in ("oracle_partial_delay", "oracle_delay_table", "oracle_dedisperse",
+    lib.oracle_dedisperse_scrunched_points.argtypes = [
+        _u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int,
+        ctypes.c_int32, _i64p, _i64p, ctypes.c_int64, _u32p, ctypes.c_int, _i32p]
+    lib.oracle_subband_lengths.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, _i32p,
+                                           ctypes.c_int, _i32p, ctypes.c_int, _i64p, _i64p]
+    lib.oracle_subband_step1.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, _i32p, ctypes.c_int, ctypes.c_int64, _u32p,
+                                         ctypes.c_int, _i32p]
+    lib.oracle_subband_step2.argtypes = [_u32p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                         ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_int64, _u32p, ctypes.c_int64,
+                                         ctypes.c_int]
+    for f in ("oracle_subband_lengths", "oracle_subband_step1", "oracle_subband_step2",
+              "oracle_dedisperse_scrunched_points", "oracle_partial_delay", "oracle_delay_table", "oracle_dedisperse",
               "oracle_dedisperse_points", "oracle_max_threads", "oracle_diagonal_dm",
               "oracle_scrunch_factor", "oracle_scrunch", "oracle_dedisperse_values"):
         getattr(lib, f).restype = ctypes.c_int
@@ -216,3 +229,88 @@ def dedisperse_scrunched(packed, nsamps, nchans, nbits, dt, f_top, df, dms, fact
         out[rows, : o.shape[1]] = o
         nout[rows] = o.shape[1]
     return out, nout
+
+
+def dedisperse_scrunched_points(packed, nsamps, nchans, nbits, dt, f_top, df, dms, factors,
+                                d_idx, t_idx, nthreads=0, mask=None):
+    """The time-scrunched transform at the listed (d, t') points only: uint32 [npts]."""
+    packed = np.ascontiguousarray(packed, dtype=np.uint8).reshape(-1)
+    if packed.size < int(nsamps) * nchans * nbits // 8:
+        raise OracleError("input too short")
+    dms = np.asarray(dms, dtype=np.float64)
+    factors = np.asarray(factors, dtype=np.int64)
+    d_idx = np.asarray(d_idx, dtype=np.int64)
+    t_idx = np.asarray(t_idx, dtype=np.int64)
+    out = np.zeros(d_idx.shape[0], dtype=np.uint32)
+    m, mp = _mask_arg(mask, nchans)
+    for s in sorted(set(int(v) for v in factors)):
+        rows = np.nonzero(factors == s)[0]
+        table, mx = delay_table(nchans, dt * s, f_top, df, dms[rows])
+        local = np.full(len(dms), -1, dtype=np.int64)
+        local[rows] = np.arange(len(rows))
+        sel = np.nonzero(factors[d_idx] == s)[0]
+        if sel.size == 0:
+            continue
+        dl = np.ascontiguousarray(local[d_idx[sel]])
+        tl = np.ascontiguousarray(t_idx[sel])
+        o = np.zeros(sel.size, dtype=np.uint32)
+        _check(_load().oracle_dedisperse_scrunched_points(
+            _ptr(packed, _u8p), int(nsamps), nchans, nbits, s, _ptr(table, _i32p),
+            int(table.shape[0]), int(mx), _ptr(dl, _i64p), _ptr(tl, _i64p), int(sel.size),
+            _ptr(o, _u32p), int(nthreads), mp), "dedisperse_scrunched_points")
+        out[sel] = o
+    return out
+
+
+# ---------------------------------------------------------------- sub-band dedispersion
+
+
+def subband_nominal_dms(dms, ngroup):
+    """The nominal DM of every group of ngroup consecutive trials: its first trial."""
+    dms = np.asarray(dms, dtype=np.float64)
+    return dms[::int(ngroup)].copy()
+
+
+def subband_lengths(nsamps, nchans, nsub, tab_nom, tab):
+    tab_nom = np.ascontiguousarray(tab_nom, dtype=np.int32)
+    tab = np.ascontiguousarray(tab, dtype=np.int32)
+    l1, no = ctypes.c_int64(), ctypes.c_int64()
+    _check(_load().oracle_subband_lengths(int(nsamps), nchans, int(nsub), _ptr(tab_nom, _i32p),
+                                          int(tab_nom.shape[0]), _ptr(tab, _i32p), int(tab.shape[0]),
+                                          ctypes.byref(l1), ctypes.byref(no)), "subband_lengths")
+    return int(l1.value), int(no.value)
+
+
+def dedisperse_subband(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub, ngroup,
+                       nthreads=0, mask=None, return_intermediate=False):
+    """Two-step sub-band transform: uint32 [ndm][nout] (and S [nsb][nnom][len1])."""
+    packed = np.ascontiguousarray(packed, dtype=np.uint8).reshape(-1)
+    if packed.size < int(nsamps) * nchans * nbits // 8:
+        raise OracleError("input too short")
+    dms = np.asarray(dms, dtype=np.float64)
+    tab, _ = delay_table(nchans, dt, f_top, df, dms)
+    nom = subband_nominal_dms(dms, ngroup)
+    tab_nom, _ = delay_table(nchans, dt, f_top, df, nom)
+    len1, nout = subband_lengths(nsamps, nchans, nsub, tab_nom, tab)
+    nsb = nchans // nsub
+    S = np.zeros((nsb, len(nom), len1), dtype=np.uint32)
+    m, mp = _mask_arg(mask, nchans)
+    _check(_load().oracle_subband_step1(_ptr(packed, _u8p), int(nsamps), nchans, nbits, int(nsub),
+                                        _ptr(tab_nom, _i32p), len(nom), len1, _ptr(S, _u32p),
+                                        int(nthreads), mp), "subband_step1")
+    out = np.zeros((len(dms), nout), dtype=np.uint32)
+    _check(_load().oracle_subband_step2(_ptr(S, _u32p), nsb, len(nom), len1, nchans, int(nsub),
+                                        _ptr(tab, _i32p), len(dms), int(ngroup), nout,
+                                        _ptr(out, _u32p), nout, int(nthreads)), "subband_step2")
+    return (out, S) if return_intermediate else out
+
+
+def subband_effective_delays(nchans, dt, f_top, df, dms, nsub, ngroup):
+    """E[d][c] = dt(d, n*nsub) + dt(m, c) - dt(m, n*nsub): the delay each input sample of the
+    two-step method is taken at (n = c // nsub, m = d // ngroup)."""
+    dms = np.asarray(dms, dtype=np.float64)
+    tab, _ = delay_table(nchans, dt, f_top, df, dms)
+    tab_nom, _ = delay_table(nchans, dt, f_top, df, subband_nominal_dms(dms, ngroup))
+    first = (np.arange(nchans) // nsub) * nsub
+    m = np.arange(len(dms)) // ngroup
+    return (tab[:, first] + tab_nom[m] - tab_nom[m][:, first]).astype(np.int64)

@@ -298,6 +298,149 @@ int oracle_dedisperse_values(const uint32_t* x, int64_t nsamps, int nchans,
     return ORACLE_OK;
 }
 
+/* The scrunched transform of one factor group at the listed (d, t') points:
+ * sum over channels of the s input samples that make up scrunched sample
+ * t' + delay[d][c], table being the group's delay table at s times the
+ * sampling time.  For checking sampled outputs of inputs too large to
+ * transform whole on a CPU. */
+int oracle_dedisperse_scrunched_points(const uint8_t* in, int64_t nsamps, int nchans, int nbits,
+                                       int s, const int32_t* table, int ndm, int32_t max_delay,
+                                       const int64_t* d_idx, const int64_t* t_idx, int64_t npts,
+                                       uint32_t* out, int nthreads, const int32_t* mask)
+{
+    if (!in || !table || !out || !d_idx || !t_idx || npts < 0 || s < 1) return ORACLE_BAD_ARG;
+    if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
+    if (nbits == 2 && nchans % 4) return ORACLE_BAD_ARG;
+    const int64_t n = nsamps / s;
+    if (n <= (int64_t)max_delay) return ORACLE_TOO_FEW_SAMPLES;
+    const int64_t nout = n - (int64_t)max_delay;
+    for (int64_t i = 0; i < npts; ++i)
+        if (d_idx[i] < 0 || d_idx[i] >= ndm || t_idx[i] < 0 || t_idx[i] >= nout)
+            return ORACLE_BAD_ARG;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < npts; ++i) {
+        const int32_t* delay = table + (size_t)d_idx[i] * nchans;
+        uint32_t sum = 0;
+        for (int nu = 0; nu < nchans; ++nu) {
+            const int64_t t0 = (t_idx[i] + delay[nu]) * s;
+            uint32_t v = 0;
+            for (int j = 0; j < s; ++j) v += oracle_sample(in, nchans, nbits, t0 + j, nu);
+            sum += (mask ? (uint32_t)mask[nu] : 1u) * v;
+        }
+        out[i] = sum;
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Sub-band dedispersion (Section 4, with the sub-bands aligned on their
+ * early edge as Appendix B assumes).  The nchans channels form nsb = nchans /
+ * nsub sub-bands of nsub channels, sub-band n starting at channel n*nsub.
+ * The trials form groups of ngroup consecutive list entries; the group's
+ * first trial is its nominal DM.
+ *
+ * Step 1 dedisperses each sub-band at every nominal DM, relative to the
+ * sub-band's first channel:
+ *   S[n][m][t] = sum over j < nsub of A[n*nsub + j][t + dt(m, n*nsub + j) - dt(m, n*nsub)]
+ * for t < len1 = nsamps - (largest such relative delay over n, m, j).
+ * Step 2 dedisperses, for every trial d of nominal m = d / ngroup, the
+ * "miniature filterbank" of the nsb sub-band series of m with the trial's
+ * delay at each sub-band's first channel:
+ *   D[d][t] = sum over n of S[n][m][t + dt(d, n*nsub)]
+ * for t < nout = len1 - (largest dt(d, n*nsub)).
+ * dt(m, c) are rows of the delay table at the nominal DMs (tab_nom, [nnom]
+ * rows), dt(d, c) rows of the trials' table (tab, [ndm] rows).
+ * ------------------------------------------------------------------------ */
+
+/* len1 and nout of the two-step definition above. */
+int oracle_subband_lengths(int64_t nsamps, int nchans, int nsub, const int32_t* tab_nom,
+                           int nnom, const int32_t* tab, int ndm, int64_t* len1, int64_t* nout)
+{
+    if (!tab_nom || !tab || !len1 || !nout || nsub <= 0 || nchans % nsub) return ORACLE_BAD_ARG;
+    int32_t mx1 = 0, mx2 = 0;
+    for (int m = 0; m < nnom; ++m)
+        for (int c = 0; c < nchans; ++c) {
+            const int32_t r = tab_nom[(size_t)m * nchans + c] - tab_nom[(size_t)m * nchans + (c / nsub) * nsub];
+            if (r < 0) return ORACLE_BAD_ARG;
+            if (r > mx1) mx1 = r;
+        }
+    for (int d = 0; d < ndm; ++d)
+        for (int n = 0; n < nchans / nsub; ++n) {
+            const int32_t v = tab[(size_t)d * nchans + n * nsub];
+            if (v < 0) return ORACLE_BAD_ARG;
+            if (v > mx2) mx2 = v;
+        }
+    *len1 = nsamps - mx1;
+    *nout = *len1 - mx2;
+    return (*len1 > 0 && *nout > 0) ? ORACLE_OK : ORACLE_TOO_FEW_SAMPLES;
+}
+
+/* Step 1: S [nsb][nnom][len1], with an optional 0/1 channel kill mask. */
+int oracle_subband_step1(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int nsub,
+                         const int32_t* tab_nom, int nnom, int64_t len1, uint32_t* S,
+                         int nthreads, const int32_t* mask)
+{
+    if (!in || !tab_nom || !S || nsub <= 0 || nchans % nsub || nnom <= 0 || len1 <= 0)
+        return ORACLE_BAD_ARG;
+    if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
+    const int nsb = nchans / nsub;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+    for (int n = 0; n < nsb; ++n)
+        for (int m = 0; m < nnom; ++m) {
+            const int32_t* dl = tab_nom + (size_t)m * nchans;
+            const int c0 = n * nsub;
+            uint32_t* row = S + ((size_t)n * nnom + m) * (size_t)len1;
+            for (int64_t t = 0; t < len1; ++t) {
+                uint32_t sum = 0;
+                for (int j = 0; j < nsub; ++j) {
+                    const int c = c0 + j;
+                    const int64_t ts = t + dl[c] - dl[c0];
+                    if (ts >= nsamps) continue;           /* not reached for t < len1 */
+                    sum += (mask ? (uint32_t)mask[c] : 1u) * oracle_sample(in, nchans, nbits, ts, c);
+                }
+                row[t] = sum;
+            }
+        }
+    return ORACLE_OK;
+}
+
+/* Step 2: D [ndm][out_stride], t < nout. */
+int oracle_subband_step2(const uint32_t* S, int nsb, int nnom, int64_t len1, int nchans, int nsub,
+                         const int32_t* tab, int ndm, int ngroup, int64_t nout, uint32_t* out,
+                         int64_t out_stride, int nthreads)
+{
+    if (!S || !tab || !out || nsub <= 0 || nsb * nsub != nchans || ngroup <= 0) return ORACLE_BAD_ARG;
+    if ((ndm + ngroup - 1) / ngroup > nnom || out_stride < nout) return ORACLE_BAD_ARG;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int d = 0; d < ndm; ++d) {
+        const int m = d / ngroup;
+        const int32_t* dl = tab + (size_t)d * nchans;
+        uint32_t* row = out + (size_t)d * (size_t)out_stride;
+        for (int64_t t = 0; t < nout; ++t) {
+            uint32_t sum = 0;
+            for (int n = 0; n < nsb; ++n)
+                sum += S[((size_t)n * nnom + m) * (size_t)len1 + (size_t)(t + dl[n * nsub])];
+            row[t] = sum;
+        }
+    }
+    return ORACLE_OK;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

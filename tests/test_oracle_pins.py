@@ -20,7 +20,13 @@ against things other than itself:
   steepest channel pair being the band's last), the factor rule against its
   closed form, every factor group against the push brute force at s times
   the sampling time, DM 0 against the s-sums of the plain channel sum, the
-  impulse response, and time-shift equivariance by whole scrunched samples.
+  impulse response, and time-shift equivariance by whole scrunched samples;
+* sub-band dedispersion (Section 4): the two-step result against the push
+  brute force at the composed delays it takes each sample at, the two
+  reductions to the direct transform (one trial per nominal DM, one channel
+  per sub-band), the delay error within Appendix B's smearing bound (and
+  zero at nominal trials), the kill mask, and a pulse on a nominal trial's
+  trail summed whole at its trial and time only.
 """
 from fractions import Fraction
 
@@ -511,3 +517,119 @@ def test_scrunched_impulse_and_time_shift():
     for d, s in enumerate(factors):
         k = 16 // s
         assert np.array_equal(sh[d, : ns[d]], full[d, k: k + ns[d]])
+
+
+def test_scrunched_points_agree_with_full_scrunched_transform():
+    for nbits in (2, 8):
+        codes, prm, dms = _scrunch_case(nbits, 70 + nbits)
+        nsamps, nchans = codes.shape
+        packed = synth.pack(codes, nbits)
+        factors = oracle.scrunch_factors(nchans, prm["dt"], prm["f_top"], prm["df"], dms, 8)
+        mask = (np.arange(nchans) % 5 != 2).astype(np.int32)
+        full, nout = oracle.dedisperse_scrunched(packed, nsamps, nchans, nbits, prm["dt"],
+                                                 prm["f_top"], prm["df"], dms, factors, mask=mask)
+        rng = np.random.default_rng(nbits)
+        d = rng.integers(0, len(dms), 400)
+        t = (rng.random(400) * nout[d]).astype(np.int64)
+        pts = oracle.dedisperse_scrunched_points(packed, nsamps, nchans, nbits, prm["dt"],
+                                                 prm["f_top"], prm["df"], dms, factors, d, t,
+                                                 mask=mask)
+        assert np.array_equal(pts, full[d, t])
+
+
+# ---------------------------------------------------------------------------
+# sub-band dedispersion (Section 4, early-edge alignment of Appendix B)
+# ---------------------------------------------------------------------------
+
+def _subband_case(seed, nbits=2, nsamps=2500, nchans=64, ndm=40, dm_max=300.0):
+    rng = np.random.default_rng(seed)
+    codes = rng.integers(0, 256 if nbits == 8 else 4, size=(nsamps, nchans), dtype=np.uint8)
+    prm = dict(dt=64e-6, f_top=1500.0, df=-2.0)
+    return codes, prm, synth.dm_list_linear(ndm, dm_max)
+
+
+def _effective_table(nchans, prm, dms, nsub, ngroup):
+    """Composed delay of channel c for trial d, from the two delay tables."""
+    tab, _ = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], dms)
+    nom = dms[::ngroup]
+    tnom, _ = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], nom)
+    eff = np.zeros_like(tab, dtype=np.int64)
+    for d in range(len(dms)):
+        m = d // ngroup
+        for c in range(nchans):
+            e = (c // nsub) * nsub
+            eff[d, c] = int(tab[d, e]) + int(tnom[m, c]) - int(tnom[m, e])
+    return tab, eff
+
+
+@pytest.mark.parametrize("nbits,nsub,ngroup", [(2, 8, 4), (8, 16, 5), (2, 32, 8), (8, 4, 3)])
+def test_subband_is_direct_sum_at_composed_delays(nbits, nsub, ngroup):
+    """Step 2 of step 1 takes input sample (c, t + E[d][c]) exactly once, so the
+    two-step result is the push brute force with the composed table E."""
+    codes, prm, dms = _subband_case(100 + nsub, nbits)
+    nsamps, nchans = codes.shape
+    got = oracle.dedisperse_subband(synth.pack(codes, nbits), nsamps, nchans, nbits, prm["dt"],
+                                    prm["f_top"], prm["df"], dms, nsub, ngroup)
+    _, eff = _effective_table(nchans, prm, dms, nsub, ngroup)
+    bf = _push_brute_force(codes.astype(np.int64), eff)
+    nout = got.shape[1]
+    assert nout <= bf.shape[1]
+    assert np.array_equal(got.astype(np.int64), bf[:, :nout])
+
+
+@pytest.mark.parametrize("nbits", [2, 8])
+def test_subband_reduces_to_direct(nbits):
+    """One trial per group (every trial its own nominal DM) or one channel per
+    sub-band: no approximation is left, so it is the direct transform."""
+    codes, prm, dms = _subband_case(7, nbits)
+    nsamps, nchans = codes.shape
+    packed = synth.pack(codes, nbits)
+    tab, _ = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], dms)
+    direct = oracle.dedisperse(packed, nsamps, nchans, nbits, tab)
+    for nsub, ngroup in ((16, 1), (1, 8)):
+        got = oracle.dedisperse_subband(packed, nsamps, nchans, nbits, prm["dt"], prm["f_top"],
+                                        prm["df"], dms, nsub, ngroup)
+        assert np.array_equal(got, direct[:, : got.shape[1]]), (nsub, ngroup)
+
+
+@pytest.mark.parametrize("nchans,nsub,ngroup,dm_max", [(64, 8, 4, 300.0), (1024, 32, 16, 1000.0),
+                                                       (256, 16, 8, 2000.0)])
+def test_subband_delay_error_within_appendix_b_bound(nchans, nsub, ngroup, dm_max):
+    """|E - dt| is bounded by (trial DM - nominal DM) x the DeltaT spread of the
+    last sub-band (Appendix B's smearing bound), plus the four roundings."""
+    prm = dict(dt=64e-6, f_top=1581.8, df=-400.0 / nchans)
+    dms = synth.dm_list_linear(nchans, dm_max)[: 4 * ngroup + 3]
+    tab, eff = _effective_table(nchans, prm, dms, nsub, ngroup)
+    dT = oracle.partial_delay(nchans, prm["dt"], prm["f_top"], prm["df"])
+    spread = dT[nchans - 1] - dT[nchans - nsub]
+    dmdiff = np.array([dms[d] - dms[(d // ngroup) * ngroup] for d in range(len(dms))])
+    err = np.abs(eff - tab)
+    assert np.all(err <= dmdiff[:, None] * spread + 2.0)
+    # trials that are their own nominal DM have no error at all
+    assert not err[::ngroup].any()
+    # and the bound is not vacuous: the largest error approaches it
+    assert err.max() >= dmdiff.max() * spread - 2.0
+
+
+def test_subband_kill_mask_and_pulse():
+    codes, prm, dms = _subband_case(21, 2, nsamps=3000, nchans=64, ndm=48, dm_max=300.0)
+    nsamps, nchans = codes.shape
+    rng = np.random.default_rng(4)
+    mask = (rng.random(nchans) < 0.7).astype(np.int32)
+    nsub, ngroup = 8, 4
+    got = oracle.dedisperse_subband(synth.pack(codes, 2), nsamps, nchans, 2, prm["dt"],
+                                    prm["f_top"], prm["df"], dms, nsub, ngroup, mask=mask)
+    _, eff = _effective_table(nchans, prm, dms, nsub, ngroup)
+    bf = _push_brute_force((codes * mask[None, :].astype(np.uint8)).astype(np.int64), eff)
+    assert np.array_equal(got.astype(np.int64), bf[:, : got.shape[1]])
+    # on a flat background, a pulse on the trail of a nominal trial (28, the
+    # first of group 7) is summed whole at that trial and time and nowhere else
+    tab, _ = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], dms)
+    pulsed = np.ones_like(codes)
+    t0 = 700
+    pulsed[t0 + tab[28], np.arange(nchans)] = 3
+    out = oracle.dedisperse_subband(synth.pack(pulsed, 2), nsamps, nchans, 2, prm["dt"],
+                                    prm["f_top"], prm["df"], dms, nsub, ngroup)
+    assert out[28, t0] == 3 * nchans
+    out[28, t0] = 0
+    assert out.max() < 3 * nchans
