@@ -102,6 +102,59 @@ def bench_batch(torch, dev, steps):
             "batched_over_plain": float(sum(plain_ms)) / ms}
 
 
+def bench_scrunched(torch, dev, plan, inp, nsamps, steps, direct_ms):
+    """The survey beam with time-scrunching (Section 2.1): default factors up
+    to 64, each factor group tuned; the same input as the direct transform."""
+    factors = plan.default_scrunch_factors(64)
+    plan.set_scrunching(factors)
+    lens = plan.output_lengths(nsamps)
+    out = torch.empty((plan.ndm, int(lens.max())), dtype=torch.int32, device=dev)
+    tune_ms = plan.tune(inp, out, nsamps)
+    for _ in range(2):
+        plan.execute(inp, nsamps, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        plan.execute(inp, nsamps, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.set_scrunching(None)
+    groups = {int(f): int((factors == f).sum()) for f in sorted(set(factors.tolist()))}
+    return {"workload": "survey beam, default scrunch factors (1 up to the diagonal DM, doubling "
+                        "at each power-of-two multiple of it, at most 64)",
+            "diagonal_dm": plan.diagonal_dm(), "trials_per_factor": groups,
+            "ms": ms, "tune_ms": tune_ms, "outputs": int(lens.sum()),
+            "outputs_per_s": float(lens.sum()) / (ms * 1e-3),
+            "speedup_vs_direct": direct_ms / ms}
+
+
+def bench_subband(torch, dev, plan, inp, nsamps, steps, direct_ms, nsub=32, ngroup=32):
+    """The survey beam with sub-band dedispersion (Section 4): 32-channel
+    sub-bands, 32 trials per nominal DM (the balanced choice N'_DM = N'_nu),
+    each pass tuned; the same input as the direct transform."""
+    plan.set_subband(nsub, ngroup)
+    nout = int(plan.output_lengths(nsamps)[0])
+    out = torch.empty((plan.ndm, nout), dtype=torch.int32, device=dev)
+    tune_ms = plan.tune(inp, out, nsamps)
+    for _ in range(2):
+        plan.execute(inp, nsamps, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        plan.execute(inp, nsamps, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan.set_subband(0, 0)
+    return {"workload": f"survey beam, sub-bands of {nsub} channels, {ngroup} trials per nominal DM",
+            "ms": ms, "tune_ms": tune_ms, "nout": nout,
+            "outputs_per_s": plan.ndm * nout / (ms * 1e-3),
+            "speedup_vs_direct": direct_ms / ms}
+
+
 def bench_serve(torch, dev, seconds):
     """32 streams, chunks of U[2^14, 2^18] samples arriving as a Poisson process at
     4x real time per stream (aggregate ~14.4 chunks/s), 64 GB admission budget."""
@@ -311,6 +364,12 @@ def main():
     }
     if not args.no_systems:
         del got, out
+        torch.cuda.empty_cache()
+        result["scrunched"] = bench_scrunched(torch, dev, plan, inp, nsamps,
+                                              max(3, args.steps // 2), mean_ms)
+        torch.cuda.empty_cache()
+        result["subband"] = bench_subband(torch, dev, plan, inp, nsamps,
+                                          max(3, args.steps // 2), mean_ms)
         torch.cuda.empty_cache()
         result["batched"] = bench_batch(torch, dev, max(3, args.steps // 4))
         torch.cuda.empty_cache()

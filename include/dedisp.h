@@ -116,12 +116,75 @@ dedisp_status dedisp_get_delay_table(dedisp_plan plan, int32_t* host_out);
 
 /* The transform over one resident block of input.
  * d_in: device, nsamps rows of the input layout above.
- * d_out: device, ndm rows of out_row_stride (0 = nsamps - max_delay)
- * uint32 elements; only t < nsamps - max_delay is written.
+ * d_out: device, ndm rows of out_row_stride (0 = nsamps - max_delay, or
+ * the longest row under time-scrunching) uint32 elements; only
+ * t < nsamps - max_delay is written (under time-scrunching, the row lengths
+ * dedisp_get_output_lengths gives).
  * Errors: INVALID_ARG (null pointer, stride too small), NO_DM_LIST,
- * TOO_FEW_SAMPLES (nsamps <= max_delay), OOM, HIP. */
+ * TOO_FEW_SAMPLES (nsamps <= max_delay, or nsamps/s <= the largest delay of
+ * a scrunch group), OOM, HIP. */
 dedisp_status dedisp_execute(dedisp_plan plan, const void* d_in, size_t nsamps,
                              uint32_t* d_out, size_t out_row_stride, void* stream);
+
+/* ----------------------------------------------------- time-scrunching */
+
+/* Section 2.1: once a trial's dispersion trail crosses more than one sample
+ * per channel (beyond the "diagonal" DM) the time resolution can be reduced
+ * by adding adjacent samples, halving the work of those trials.
+ *
+ * The diagonal DM of the band: the DM at which the delay between the last
+ * two channels -- the steepest part of the trail -- is one sample,
+ * 1 / (DeltaT(nchans-1) - DeltaT(nchans-2)) with DeltaT of the partial_delay
+ * equation.  +inf for a single channel.  Host-only. */
+dedisp_status dedisp_get_diagonal_dm(dedisp_plan plan, double* dm);
+
+/* The default factor of every trial of the DM list, written to host array
+ * `factors` (ndm int32): 1 up to the diagonal DM, 2 once the DM exceeds it,
+ * 4 once it exceeds twice the diagonal, and so on, capped at `max_factor`
+ * (a power of two in [1, 64]).  Host-only.
+ * Errors: INVALID_ARG, NO_DM_LIST. */
+dedisp_status dedisp_default_scrunch_factors(dedisp_plan plan, int max_factor, int32_t* factors);
+
+/* Switch time-scrunching on with one factor per trial (host array of ndm
+ * int32 powers of two in [1, 64], copied) or off (NULL, or all factors 1).
+ * A trial with factor s is dedispersed from s-sample sums, sample t' of a
+ * channel being the sum of input samples s*t' .. s*t'+s-1 (a trailing
+ * partial group is dropped), with the delay equation evaluated at the
+ * sampling time s*dt.  Row d then holds nsamps/s - (largest delay of the
+ * trials sharing its factor) outputs at resolution s*dt.  Setting a new DM
+ * list switches scrunching off; the delay table and max_delay queries keep
+ * describing the full-resolution list.  Streams and batches reject a plan
+ * with scrunching on (UNSUPPORTED).  Work enqueued with the plan must have
+ * finished.  Errors: INVALID_ARG, NO_DM_LIST, OOM. */
+dedisp_status dedisp_set_scrunching(dedisp_plan plan, const int32_t* factors);
+
+/* Valid outputs of every row for an input of nsamps rows, written to host
+ * array `nout` (ndm entries): nsamps - max_delay without scrunching.
+ * Host-only.  Errors: INVALID_ARG, NO_DM_LIST, TOO_FEW_SAMPLES. */
+dedisp_status dedisp_get_output_lengths(dedisp_plan plan, size_t nsamps, size_t* nout);
+
+/* ----------------------------------------------- sub-band dedispersion */
+
+/* Section 4: the channels form nchans/nsub sub-bands of nsub channels and
+ * the trials groups of ngroup consecutive list entries, each group's first
+ * trial being its nominal DM.  Step 1 dedisperses every sub-band at every
+ * nominal DM, with delays relative to the sub-band's first channel; step 2
+ * dedisperses, for each trial, the nominal DM's sub-band series with the
+ * trial's delay at each sub-band's first channel (the early-edge alignment
+ * of Appendix B).  Sample c of trial d is thus taken at delay
+ * dt(d, n*nsub) + dt(m, c) - dt(m, n*nsub) (n = c/nsub, m = d/ngroup): an
+ * approximation of the direct transform whose error Appendix B bounds, and
+ * the direct transform itself when ngroup = 1.  Outputs exist for
+ * t < len1 - (largest step-2 delay), len1 = nsamps - (largest step-1
+ * delay); dedisp_get_output_lengths gives it.  The sub-band sums are kept
+ * on the device in 8 or 16 bits (at most 3*nsub or 255*nsub).
+ * nsub: a multiple of 8 dividing nchans (255*nsub <= 32767 for 8-bit
+ * data); ngroup >= 1; (0, 0) switches sub-band mode off.  Setting a new DM
+ * list switches it off; it excludes time-scrunching (UNSUPPORTED) and
+ * streams and batches reject such a plan.  Needs 4-byte aligned input rows.
+ * Work enqueued with the plan must have finished.
+ * Errors: INVALID_ARG, NO_DM_LIST, UNSUPPORTED, OOM. */
+dedisp_status dedisp_set_subband(dedisp_plan plan, int nsub, int ngroup);
 
 /* ----------------------------------------------------- kernel selection */
 
@@ -147,6 +210,8 @@ dedisp_status dedisp_tile_config_get(int index, dedisp_tile_config* cfg);
  * (must be one of the compiled shapes; chunk_chans a multiple of 4 in
  * [4, 256]).  Host-only.  INVALID_ARG for an unknown shape. */
 dedisp_status dedisp_set_tile_config(dedisp_plan plan, const dedisp_tile_config* cfg);
+/* (Under time-scrunching the shape also applies to every scrunch group
+ * whose scratch format has it; dedisp_tune picks one per group.) */
 
 /* The tile shape the next compute call on `nsamps` samples will use
  * (after falling back if the chosen one does not fit in LDS). */

@@ -60,6 +60,11 @@ SIGNATURES = {
     "dedisp_get_max_delay": (_i, [_vp, _pi]),
     "dedisp_get_delay_table": (_i, [_vp, _pi32]),
     "dedisp_execute": (_i, [_vp, _vp, _sz, _vp, _sz, _vp]),
+    "dedisp_get_diagonal_dm": (_i, [_vp, ctypes.POINTER(_d)]),
+    "dedisp_default_scrunch_factors": (_i, [_vp, _i, _pi32]),
+    "dedisp_set_scrunching": (_i, [_vp, _pi32]),
+    "dedisp_get_output_lengths": (_i, [_vp, _sz, _psz]),
+    "dedisp_set_subband": (_i, [_vp, _i, _i]),
     "dedisp_tile_config_count": (_i, []),
     "dedisp_tile_config_get": (_i, [_i, _PTC]),
     "dedisp_set_tile_config": (_i, [_vp, _PTC]),

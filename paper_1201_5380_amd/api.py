@@ -73,6 +73,8 @@ class Plan:
         check(lib().dedisp_set_dm_list(self._h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                        int(arr.shape[0])), "dedisp_set_dm_list")
         self.ndm = int(arr.shape[0])
+        self._scrunched = False
+        self._subband = False
         return self
 
     def set_killmask(self, mask):
@@ -86,6 +88,48 @@ class Plan:
         check(lib().dedisp_set_killmask(self._h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
               "dedisp_set_killmask")
         return self
+
+    # ------------------------------------------------ time-scrunching
+
+    def diagonal_dm(self) -> float:
+        v = ctypes.c_double()
+        check(lib().dedisp_get_diagonal_dm(self._h, ctypes.byref(v)), "dedisp_get_diagonal_dm")
+        return float(v.value)
+
+    def default_scrunch_factors(self, max_factor: int = 64) -> np.ndarray:
+        out = np.zeros(self.ndm, dtype=np.int32)
+        check(lib().dedisp_default_scrunch_factors(self._h, int(max_factor),
+                                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+              "dedisp_default_scrunch_factors")
+        return out
+
+    def set_scrunching(self, factors):
+        """Per-trial factors (powers of two up to 64); None switches scrunching off."""
+        if factors is None:
+            check(lib().dedisp_set_scrunching(self._h, None), "dedisp_set_scrunching")
+            self._scrunched = False
+            return self
+        f = np.ascontiguousarray(factors, dtype=np.int32)
+        if f.shape != (self.ndm,):
+            raise ValueError("one scrunch factor per trial DM")
+        check(lib().dedisp_set_scrunching(self._h, f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+              "dedisp_set_scrunching")
+        self._scrunched = bool((f > 1).any())
+        return self
+
+    def set_subband(self, nsub: int, ngroup: int):
+        """Sub-band dedispersion with nsub channels per sub-band and ngroup
+        trials per nominal DM; (0, 0) switches it off."""
+        check(lib().dedisp_set_subband(self._h, int(nsub), int(ngroup)), "dedisp_set_subband")
+        self._subband = bool(nsub)
+        return self
+
+    def output_lengths(self, nsamps: int) -> np.ndarray:
+        out = np.zeros(self.ndm, dtype=np.uintp)
+        check(lib().dedisp_get_output_lengths(self._h, int(nsamps),
+                                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_size_t))),
+              "dedisp_get_output_lengths")
+        return out.astype(np.int64)
 
     @property
     def max_delay(self) -> int:
@@ -109,6 +153,9 @@ class Plan:
         return c.as_dict()
 
     def nout(self, nsamps: int) -> int:
+        """Longest output row for nsamps input rows."""
+        if getattr(self, "_scrunched", False) or getattr(self, "_subband", False):
+            return int(self.output_lengths(nsamps).max())
         return int(nsamps) - self.max_delay
 
     def alloc_output(self, nsamps: int, device="cuda"):

@@ -21,6 +21,10 @@
 
 using dedisp::BeamDesc;
 using dedisp::Shape;
+using dedisp::kFmtNib;
+using dedisp::kFmtByte;
+using dedisp::kFmtByteS;
+using dedisp::kFmtHalf;
 
 namespace dedisp {
 namespace host {
@@ -42,11 +46,7 @@ dedisp_status hip_fail(hipError_t e, const char* where)
 // Dispersion constant k_DM, MHz^2 pc^-1 cm^3 s (Section 1 of the paper).
 constexpr double kDispersionConstant = 4.148808e3;
 
-// Largest number of codes that can be summed in one packed lane without a
-// carry into the next: 255/3 for 2-bit codes in 8-bit lanes (Section 2.3),
-// 65535/255 for 8-bit codes in 16-bit lanes.
-constexpr int kLaneSum2Bit = 85;
-constexpr int kLaneSum8Bit = 257;
+void destroy_groups(dedisp_plan p);
 
 void free_device(dedisp_plan p)
 {
@@ -111,33 +111,45 @@ void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
     const int np = nrow / 2;
     bt.db = db;
     bt.nblocks = (ndm + db - 1) / db;
-    bt.rel.assign(static_cast<size_t>(bt.nblocks) * db * np, 0u);
-    bt.base.assign(static_cast<size_t>(bt.nblocks) * nrow, 0);
+    const size_t rel_per_group = static_cast<size_t>(bt.nblocks) * db * np;
+    const size_t base_per_group = static_cast<size_t>(bt.nblocks) * nrow;
+    bt.rel.assign(rel_per_group * p.ngroups, 0u);
+    bt.base.assign(base_per_group * p.ngroups, 0);
     bt.relmax = 0;
-    for (int b = 0; b < bt.nblocks; ++b) {
+    for (int g = 0; g < p.ngroups; ++g) {
+        const int32_t* table = p.table.data() + static_cast<size_t>(g) * ndm * nch;
+        uint32_t* rel = bt.rel.data() + g * rel_per_group;
+        int32_t* base = bt.base.data() + g * base_per_group;
+        for (int b = 0; b < bt.nblocks; ++b) {
         const int d0 = b * db, d1 = std::min(ndm, d0 + db);
         for (int k = 0; k < nlive; ++k) {
             const int c = p.source_channel(k);
             int mn = 0x7fffffff;
             for (int d = d0; d < d1; ++d)
-                mn = std::min(mn, p.table[static_cast<size_t>(d) * nch + c]);
-            mn &= p.nbits == 2 ? ~31 : ~15;
-            bt.base[static_cast<size_t>(b) * nrow + k] = mn;
+                mn = std::min(mn, table[static_cast<size_t>(d) * nch + c]);
+            mn &= ~(16 * dedisp::fmt_bytes_den(p.fmt) / dedisp::fmt_bytes_num(p.fmt) - 1);
+            base[static_cast<size_t>(b) * nrow + k] = mn;
             for (int d = d0; d < d1; ++d) {
-                const int r = p.table[static_cast<size_t>(d) * nch + c] - mn;
+                const int r = table[static_cast<size_t>(d) * nch + c] - mn;
                 bt.relmax = std::max(bt.relmax, r);
                 const uint32_t v = static_cast<uint32_t>(std::min(r, 0xFFFF));
-                bt.rel[static_cast<size_t>(d) * np + k / 2] |= (k & 1) ? (v << 16) : v;
+                rel[static_cast<size_t>(d) * np + k / 2] |= (k & 1) ? (v << 16) : v;
             }
+        }
         }
     }
 }
 
-const Shape* find_shape(const dedisp_tile_config& c, int nbits, int* index)
+bool shape_matches(const Shape& s, const dedisp_plan_s& p)
+{
+    return s.kind == 0 ? s.fmt == p.fmt : s.fmt == p.nbits;
+}
+
+const Shape* find_shape(const dedisp_tile_config& c, const dedisp_plan_s& p, int* index)
 {
     for (int i = 0; i < dedisp::shape_count(); ++i) {
         const Shape& s = dedisp::shape_at(i);
-        if (s.nbits != nbits || s.kind != c.kind) continue;
+        if (!shape_matches(s, p) || s.kind != c.kind) continue;
         if (s.kind == 1 || (s.waves == c.waves && s.dpw == c.dms_per_wave &&
                             s.m == c.words_per_lane && s.cc == c.chunk_chans)) {
             if (index) *index = i;
@@ -147,14 +159,13 @@ const Shape* find_shape(const dedisp_tile_config& c, int nbits, int* index)
     return nullptr;
 }
 
-// Default shape: the first compiled tiled shape of this bit depth (the
-// shape list is ordered by measured speed on the survey-beam workload).
-dedisp_tile_config default_config(int nbits)
+// Default shape: the first compiled tiled shape of this scratch format.
+dedisp_tile_config default_config(int fmt)
 {
     dedisp_tile_config c{};
     for (int i = 0; i < dedisp::shape_count(); ++i) {
         const Shape& s = dedisp::shape_at(i);
-        if (s.kind == 0 && s.nbits == nbits) {
+        if (s.kind == 0 && s.fmt == fmt) {
             c.kind = 0;
             c.waves = s.waves;
             c.dms_per_wave = s.dpw;
@@ -231,15 +242,11 @@ dedisp_status ensure_block_tables(dedisp_plan p, int db, BlockTables** out)
     return DEDISP_OK;
 }
 
-// Samples per 32-bit word of the channel-major scratch: 2-bit codes are
-// stored as nibbles (8 per word), 8-bit codes as bytes (4 per word).
-int samples_per_word(int nbits) { return nbits == 2 ? 8 : 4; }
-
 // Window length (32-bit words per channel row in LDS, a multiple of 4) of
-// shape s: a lane reads words up to rel / samples_per_word + 64*m.
+// shape s: a lane reads words up to rel / (samples per word) + 64*m.
 int window_words(const BlockTables& bt, const Shape& s)
 {
-    return ((bt.relmax / samples_per_word(s.nbits) + 64 * s.m + 1) + 3) & ~3;
+    return ((bt.relmax / dedisp::fmt_samples_per_word(s.fmt) + 64 * s.m + 1) + 3) & ~3;
 }
 
 bool shape_fits(const BlockTables& bt, const Shape& s)
@@ -249,11 +256,21 @@ bool shape_fits(const BlockTables& bt, const Shape& s)
            static_cast<long long>(s.cc) * rw * 4 <= dedisp::kMaxLdsBytes;
 }
 
-// The tiled path reads input rows as 32-bit words and keeps 2-bit sums in
-// 16-bit lanes.
+// The tiled path reads input rows as 32-bit words and keeps unscrunched
+// 2-bit sums in 16-bit lanes.
 bool tiled_supported(const dedisp_plan_s& p)
 {
-    return p.row_bytes % 4 == 0 && p.nact() >= 1 && (p.nbits == 8 || p.nchans <= 21845);
+    return (p.internal || p.row_bytes % 4 == 0) && p.nact() >= 1 &&
+           (p.fmt != kFmtNib || p.nact_padded() <= 21845);
+}
+
+// Channels summed into the packed lanes of the small-value formats between
+// flushes: an even count whose sum cannot carry out of a lane.
+int flush_channels(const dedisp_plan_s& p)
+{
+    const int v = p.value_bound();
+    const int lane_max = p.fmt == kFmtByteS ? 255 : 65535;
+    return std::max(2, std::min(1 << 20, lane_max / v) & ~1);
 }
 
 // Resolve the shape used for this plan: the requested one if its LDS window
@@ -263,7 +280,7 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
                              LaunchPlan& lp, bool multi_only)
 {
     int idx = -1;
-    if (!find_shape(want, p->nbits, &idx)) return fail(DEDISP_ERR_INVALID_ARG, "unknown tile shape");
+    if (!find_shape(want, *p, &idx)) return fail(DEDISP_ERR_INVALID_ARG, "unknown tile shape");
     std::vector<int> order{idx};
     for (int i = 0; i < dedisp::shape_count(); ++i)
         if (i != idx) order.push_back(i);
@@ -277,7 +294,7 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
     if (want.kind == 1 && !multi_only) order.clear();
     for (int i : order) {
         const Shape& s = dedisp::shape_at(i);
-        if (s.nbits != p->nbits || s.kind != 0 || !tiled_supported(*p)) continue;
+        if (s.fmt != p->fmt || s.kind != 0 || !tiled_supported(*p)) continue;
         const int db = s.waves * s.dpw;
         const BlockTables* bt = nullptr;
         auto it = p->blocks.find(db);
@@ -297,8 +314,8 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
         lp.cc = s.cc;
         lp.rw = window_words(*bt, s);
         lp.lds = s.cc * lp.rw * 4;
-        const int lane_sum = p->nbits == 2 ? kLaneSum2Bit : kLaneSum8Bit;
-        lp.flush_every = std::max(1, lane_sum / s.cc);
+        lp.nbits = p->nbits;
+        lp.flush_every = flush_channels(*p);
         lp.bt = nullptr;
         if (upload) {
             BlockTables* dbt = nullptr;
@@ -308,10 +325,22 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
         }
         return DEDISP_OK;
     }
+    if (p->internal) {
+        // a grouped pass: read the scratch straight from global memory
+        lp.shape_index = -1;
+        lp.shape = Shape{2, p->fmt, 4, 1, 1, 0, 0, 0};
+        lp.nbits = p->nbits;
+        lp.cc = lp.rw = lp.lds = 0;
+        lp.flush_every = 1;
+        lp.bt = nullptr;
+        if (upload) return ensure_device_table(p);
+        return DEDISP_OK;
+    }
     dedisp_tile_config u{};
     u.kind = 1;
-    if (!find_shape(u, p->nbits, &idx)) return fail(DEDISP_ERR_UNSUPPORTED, "no untiled kernel");
+    if (!find_shape(u, *p, &idx)) return fail(DEDISP_ERR_UNSUPPORTED, "no untiled kernel");
     lp.shape_index = idx;
+    lp.nbits = p->nbits;
     lp.shape = dedisp::shape_at(idx);
     lp.cc = lp.rw = lp.lds = 0;
     lp.bt = nullptr;
@@ -319,13 +348,15 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
     return DEDISP_OK;
 }
 
-long long tile_len(const Shape& s) { return 64LL * samples_per_word(s.nbits) * s.m; }
+long long tile_len(const Shape& s) { return 64LL * dedisp::fmt_samples_per_word(s.fmt) * s.m; }
 
-// Row pitch in bytes of the channel-major scratch: a staged window starts
-// before the last sample and spans 4*rw bytes.
-long long xc_pitch(long long nsamps, int nbits, int rw)
+// Row pitch in bytes of the channel-major scratch holding nsamps samples of
+// format fmt: a staged window starts before the last sample and spans 4*rw
+// bytes.
+long long xc_pitch(long long nsamps, int fmt, int rw)
 {
-    const long long bytes = nbits == 2 ? (nsamps + 1) / 2 : nsamps;
+    const long long num = dedisp::fmt_bytes_num(fmt), den = dedisp::fmt_bytes_den(fmt);
+    const long long bytes = (nsamps * num + den - 1) / den;
     return ((bytes + 4LL * rw + 63) / 64) * 64;
 }
 
@@ -354,7 +385,8 @@ dedisp_status ensure_scratch(Scratch& x, size_t need)
 dedisp_status ensure_xc(const dedisp_plan_s& p, Scratch& x, long long nsamps, const LaunchPlan& lp)
 {
     if (lp.shape.kind != 0) return DEDISP_OK;
-    return ensure_scratch(x, static_cast<size_t>(xc_pitch(nsamps, lp.shape.nbits, lp.rw)) * p.nact_padded());
+    const long long ns = nsamps / p.scrunch;
+    return ensure_scratch(x, static_cast<size_t>(xc_pitch(ns, lp.shape.fmt, lp.rw)) * p.nact_padded());
 }
 
 void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n0,
@@ -366,7 +398,12 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
     d.in1 = static_cast<const uint8_t*>(in1);
     d.n0 = n0;
     d.nsamps = nsamps;
-    d.nout = nsamps - p->max_delay;
+    d.nout = nsamps / p->scrunch - p->max_delay;
+    d.scrunch = p->scrunch;
+    d.rowmap = nullptr;
+    d.ngroups = 1;
+    d.ndm_last = static_cast<int>(p->dms.size());
+    d.out_bytes = 4;
     d.out = out;
     d.out_stride = stride;
     d.table = p->d_table;
@@ -380,7 +417,7 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
     d.shape = lp.shape_index;
     if (lp.shape.kind == 0) {
         d.xc = xc;
-        d.pitch = xc_pitch(nsamps, lp.shape.nbits, lp.rw);
+        d.pitch = xc_pitch(nsamps / p->scrunch, lp.shape.fmt, lp.rw);
         d.rel = lp.bt->d_rel;
         d.base = lp.bt->d_base;
         d.nblocks = lp.bt->nblocks;
@@ -393,11 +430,11 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
 hipError_t launch_desc(const BeamDesc& d, const LaunchPlan& lp, hipStream_t st)
 {
     if (lp.shape.kind == 0) {
-        hipError_t e = dedisp::launch_unpack(d, lp.shape.nbits, st);
+        hipError_t e = dedisp::launch_unpack(d, lp.nbits, lp.shape.fmt, st);
         if (e != hipSuccess) return e;
         return dedisp::launch_tiled(d, lp.shape, lp.lds, st);
     }
-    return dedisp::launch_untiled(d, lp.shape.nbits, st);
+    return dedisp::launch_untiled(d, lp.nbits, st);
 }
 
 
@@ -408,7 +445,8 @@ std::string cache_key(dedisp_plan p, size_t nsamps)
     size_t bucket = 1;
     while (bucket < nsamps) bucket <<= 1;
     std::ostringstream os;
-    os << "nbits=" << p->nbits << ",nchans=" << p->nchans << ",ndm=" << p->dms.size()
+    os << "nbits=" << p->nbits << ",fmt=" << p->fmt << ",scrunch=" << p->scrunch
+       << ",nchans=" << p->nchans << ",ndm=" << p->dms.size()
        << ",max_delay=" << p->max_delay << ",nsamps<=" << bucket;
     return os.str();
 }
@@ -461,6 +499,74 @@ void write_cache(const char* path, const std::map<std::string, std::vector<doubl
     std::rename(tmp.c_str(), path);
 }
 
+void destroy_subband(dedisp_plan p)
+{
+    if (p->sb_step1 || p->sb_step2) (void)hipDeviceSynchronize();
+    dedisp_plan_destroy(p->sb_step1);
+    dedisp_plan_destroy(p->sb_step2);
+    p->sb_step1 = p->sb_step2 = nullptr;
+    free_scratch(p->sb_xc2);
+    p->sb_nsub = p->sb_ngroup = 0;
+}
+
+// An internal plan for one pass of a grouped (sub-band) transform.
+dedisp_plan new_internal(const dedisp_plan_s& p)
+{
+    dedisp_plan q = new (std::nothrow) dedisp_plan_s;
+    if (!q) return nullptr;
+    q->nbits = p.nbits;
+    q->dt = p.dt;
+    q->f_top = p.f_top;
+    q->df = p.df;
+    q->row_bytes = 4;
+    q->internal = true;
+    q->has_dms = true;
+    return q;
+}
+
+void destroy_groups(dedisp_plan p)
+{
+    if (!p->groups.empty()) (void)hipDeviceSynchronize();
+    for (auto& g : p->groups) {
+        if (g.d_rows) (void)hipFree(g.d_rows);
+        dedisp_plan_destroy(g.sub);
+    }
+    p->groups.clear();
+    p->scrunch_factors.clear();
+}
+
+// Time-scrunching: the diagonal DM of the band (Section 2.1), where the delay
+// between the last two channels -- the steepest part of the trail -- is one
+// sample.
+double diagonal_dm(const dedisp_plan_s& p)
+{
+    if (p.nchans < 2) return HUGE_VAL;
+    const double inv_f0_sq = 1.0 / (p.f_top * p.f_top);
+    const double samples_per_unit = kDispersionConstant / p.dt;
+    const double fa = p.f_top + static_cast<double>(p.nchans - 2) * p.df;
+    const double fb = p.f_top + static_cast<double>(p.nchans - 1) * p.df;
+    const double dTa = samples_per_unit * (1.0 / (fa * fa) - inv_f0_sq);
+    const double dTb = samples_per_unit * (1.0 / (fb * fb) - inv_f0_sq);
+    return 1.0 / (dTb - dTa);
+}
+
+// Scratch format of a scrunch group: sums of up to 8 two-bit codes stay in
+// byte lanes (four samples per add); larger sums, and every 8-bit sum, in
+// 16-bit lanes.
+int scrunch_format(int nbits, int s)
+{
+    if (s == 1) return nbits == 2 ? kFmtNib : kFmtByte;
+    return (nbits == 2 && s <= 8) ? kFmtByteS : kFmtHalf;
+}
+
+constexpr int kMaxScrunch = 64;
+
+// Valid outputs per row of a scrunch group for nsamps input rows (<= 0: too few).
+long long group_nout(const ScrunchGroup& g, size_t nsamps)
+{
+    return static_cast<long long>(nsamps / g.s) - g.sub->max_delay;
+}
+
 }  // namespace host
 }  // namespace dedisp
 
@@ -509,7 +615,8 @@ dedisp_status dedisp_plan_create(dedisp_plan* out, int nchans, double dt_s, doub
     p->f_top = f_top_mhz;
     p->df = df_mhz;
     p->row_bytes = nchans * nbits / 8;
-    p->cfg = default_config(nbits);
+    p->fmt = nbits == 2 ? kFmtNib : kFmtByte;
+    p->cfg = default_config(p->fmt);
     *out = p;
     return DEDISP_OK;
 }
@@ -517,6 +624,8 @@ dedisp_status dedisp_plan_create(dedisp_plan* out, int nchans, double dt_s, doub
 void dedisp_plan_destroy(dedisp_plan p)
 {
     if (!p) return;
+    destroy_subband(p);
+    destroy_groups(p);
     free_device(p);
     delete p;
 }
@@ -532,6 +641,8 @@ dedisp_status dedisp_set_dm_list(dedisp_plan p, const double* dms, int ndm)
     int mx = 0;
     if (!build_delay_table(*p, dms, ndm, table, mx))
         return fail(DEDISP_ERR_INVALID_ARG, "a delay does not fit in int32");
+    destroy_subband(p);
+    destroy_groups(p);
     free_device(p);
     p->dms.assign(dms, dms + ndm);
     p->table.swap(table);
@@ -554,6 +665,10 @@ dedisp_status dedisp_set_killmask(dedisp_plan p, const int32_t* mask)
         }
         if (!all_on) km.assign(mask, mask + p->nchans);
         else act.clear();
+    }
+    for (auto& g : p->groups) {
+        dedisp_status st = dedisp_set_killmask(g.sub, mask);
+        if (st != DEDISP_OK) return st;
     }
     free_device(p);
     p->killmask.swap(km);
@@ -617,8 +732,12 @@ dedisp_status dedisp_tile_config_get(int i, dedisp_tile_config* c)
 dedisp_status dedisp_set_tile_config(dedisp_plan p, const dedisp_tile_config* c)
 {
     if (!p || !c) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
-    if (!find_shape(*c, p->nbits)) return fail(DEDISP_ERR_INVALID_ARG, "unknown tile shape");
+    if (!find_shape(*c, *p)) return fail(DEDISP_ERR_INVALID_ARG, "unknown tile shape");
     p->cfg = *c;
+    for (auto& g : p->groups)
+        if (find_shape(*c, *g.sub)) g.sub->cfg = *c;
+    for (dedisp_plan q : {p->sb_step1, p->sb_step2})
+        if (q && c->kind == 0 && find_shape(*c, *q)) q->cfg = *c;
     return DEDISP_OK;
 }
 
@@ -637,15 +756,204 @@ dedisp_status dedisp_get_tile_config(dedisp_plan p, dedisp_tile_config* c)
     return DEDISP_OK;
 }
 
+static dedisp_status execute_groups(dedisp_plan p, const void* d_in, size_t nsamps,
+                                    uint32_t* d_out, size_t stride, void* stream)
+{
+    if (nsamps > (1ULL << 40)) return fail(DEDISP_ERR_INVALID_ARG, "nsamps too large");
+    long long width = 0;
+    for (const auto& g : p->groups) {
+        const long long n = group_nout(g, nsamps);
+        if (n <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps / s <= max delay of a scrunch group");
+        width = std::max(width, n);
+    }
+    if (stride == 0) stride = static_cast<size_t>(width);
+    if (stride < static_cast<size_t>(width))
+        return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < longest output row");
+    // resolve every group first (all validation before any launch)
+    std::vector<LaunchPlan> lps(p->groups.size());
+    size_t need = 0;
+    for (size_t i = 0; i < p->groups.size(); ++i) {
+        dedisp_plan sub = p->groups[i].sub;
+        dedisp_status st = resolve_launch(sub, sub->cfg, true, lps[i]);
+        if (st != DEDISP_OK) return st;
+        if (lps[i].shape.kind == 0 && (reinterpret_cast<uintptr_t>(d_in) & 3)) {
+            dedisp_tile_config u{};
+            u.kind = 1;
+            st = resolve_launch(sub, u, true, lps[i]);
+            if (st != DEDISP_OK) return st;
+        }
+        if (lps[i].shape.kind == 0) {
+            const long long ns = static_cast<long long>(nsamps) / sub->scrunch;
+            need = std::max(need, static_cast<size_t>(xc_pitch(ns, lps[i].shape.fmt, lps[i].rw)) *
+                                      sub->nact_padded());
+        }
+        ScrunchGroup& g = p->groups[i];
+        if (!g.d_rows) {
+            const size_t bytes = g.rows.size() * sizeof(int32_t);
+            if (hipMalloc(&g.d_rows, bytes) != hipSuccess) {
+                g.d_rows = nullptr;
+                return fail(DEDISP_ERR_OOM, "hipMalloc scrunch row map");
+            }
+            HIP_TRY(hipMemcpy(g.d_rows, g.rows.data(), bytes, hipMemcpyHostToDevice));
+        }
+    }
+    // the groups run one after another on one stream and share one scratch
+    dedisp_status st = ensure_scratch(p->xc, std::max<size_t>(need, 1));
+    if (st != DEDISP_OK) return st;
+    for (size_t i = 0; i < p->groups.size(); ++i) {
+        BeamDesc d;
+        fill_desc(p->groups[i].sub, lps[i], d_in, static_cast<long long>(nsamps), nullptr,
+                  static_cast<long long>(nsamps), d_out, static_cast<long long>(stride),
+                  p->xc.ptr, d);
+        d.rowmap = p->groups[i].d_rows;
+        hipError_t e = launch_desc(d, lps[i], static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    }
+    return DEDISP_OK;
+}
+
+// Sub-band dedispersion: sub-band sums of step 1 (lengths len1) and the
+// outputs of step 2 (nout) for nsamps input rows.
+static void subband_lengths(const dedisp_plan_s& p, size_t nsamps, long long& len1, long long& nout)
+{
+    len1 = static_cast<long long>(nsamps) - p.sb_step1->max_delay;
+    nout = len1 - p.sb_step2->max_delay;
+}
+
+static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsamps,
+                                     uint32_t* d_out, size_t stride, void* stream)
+{
+    if (nsamps > (1ULL << 40)) return fail(DEDISP_ERR_INVALID_ARG, "nsamps too large");
+    dedisp_plan s1 = p->sb_step1, s2 = p->sb_step2;
+    long long len1 = 0, nout = 0;
+    subband_lengths(*p, nsamps, len1, nout);
+    if (len1 <= 0 || nout <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps too short for the sub-band passes");
+    if (stride == 0) stride = static_cast<size_t>(nout);
+    if (stride < static_cast<size_t>(nout)) return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < nout");
+    if (reinterpret_cast<uintptr_t>(d_in) & 3)
+        return fail(DEDISP_ERR_INVALID_ARG, "sub-band passes need 4-byte aligned input");
+    LaunchPlan lp1, lp2;
+    dedisp_status st = resolve_launch(s1, s1->cfg, true, lp1);
+    if (st != DEDISP_OK) return st;
+    st = resolve_launch(s2, s2->cfg, true, lp2);
+    if (st != DEDISP_OK) return st;
+    st = ensure_device_table(p);
+    if (st != DEDISP_OK) return st;
+    const int nsub = p->sb_nsub, ngroup = p->sb_ngroup;
+    const int nsb = p->nchans / nsub, nsb_p = s2->nchans, nnom = s1->ndm_last;
+    const long long pitch1 = xc_pitch(static_cast<long long>(nsamps), p->fmt, lp1.rw);
+    const long long pitch2 = xc_pitch(len1, s2->fmt, lp2.rw);
+    st = ensure_scratch(p->xc, static_cast<size_t>(pitch1) * p->nchans);
+    if (st != DEDISP_OK) return st;
+    st = ensure_scratch(p->sb_xc2, static_cast<size_t>(pitch2) * nsb_p * nnom);
+    if (st != DEDISP_OK) return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+
+    // corner turn: every channel keeps its row (killed channels are zeros)
+    BeamDesc d0;
+    std::memset(&d0, 0, sizeof(d0));
+    d0.in0 = static_cast<const uint8_t*>(d_in);
+    d0.n0 = d0.nsamps = static_cast<long long>(nsamps);
+    d0.xc = p->xc.ptr;
+    d0.pitch = pitch1;
+    d0.mask = p->d_mask;
+    d0.nact = p->nchans;
+    d0.pad_row = -1;
+    d0.nchans = p->nchans;
+    d0.row_bytes = p->row_bytes;
+    d0.scrunch = 1;
+    d0.ngroups = 1;
+    d0.out_bytes = 4;
+    hipError_t e = dedisp::launch_unpack(d0, p->nbits, p->fmt, hs);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    if (nsb_p > nsb) {
+        e = dedisp::launch_zero(p->sb_xc2.ptr + static_cast<long long>(nsb) * pitch2,
+                                static_cast<long long>(nsb_p) * pitch2,
+                                static_cast<long long>(nsb_p - nsb) * pitch2, nnom, hs);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    }
+    // step 1: every sub-band at every nominal DM, written as narrow sums into
+    // row m*nsb_p + n of the intermediate scratch
+    BeamDesc d1;
+    std::memset(&d1, 0, sizeof(d1));
+    d1.xc = p->xc.ptr;
+    d1.pitch = pitch1;
+    d1.nact = nsub;
+    d1.pad_row = -1;
+    d1.nchans = nsub;
+    d1.ndm = d1.ndm_last = nnom;
+    d1.nout = len1;
+    if (lp1.shape.kind == 0) {
+        d1.rel = lp1.bt->d_rel;
+        d1.base = lp1.bt->d_base;
+        d1.nblocks = lp1.bt->nblocks;
+        d1.ntiles = static_cast<int>((len1 + tile_len(lp1.shape) - 1) / tile_len(lp1.shape));
+        d1.g_rel = static_cast<long long>(lp1.bt->nblocks) * lp1.bt->db * (nsub / 2);
+        d1.g_base = static_cast<long long>(lp1.bt->nblocks) * nsub;
+    }
+    d1.table = s1->d_table;
+    d1.rw = lp1.rw;
+    d1.flush_every = lp1.flush_every;
+    d1.shape = lp1.shape_index;
+    d1.scrunch = 1;
+    d1.ngroups = nsb;
+    d1.g_xc = static_cast<long long>(nsub) * pitch1;
+    d1.out = reinterpret_cast<uint32_t*>(p->sb_xc2.ptr);
+    d1.out_bytes = dedisp::fmt_bytes_num(s2->fmt);
+    d1.out_stride = static_cast<long long>(nsb_p) * pitch2;
+    d1.g_out = pitch2;
+    e = lp1.shape.kind == 0 ? dedisp::launch_tiled(d1, lp1.shape, lp1.lds, hs)
+                            : dedisp::launch_untiled_xc(d1, s1->fmt, hs);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    // step 2: for every nominal DM, its trials over the miniature filterbank
+    BeamDesc d2;
+    std::memset(&d2, 0, sizeof(d2));
+    d2.xc = p->sb_xc2.ptr;
+    d2.pitch = pitch2;
+    d2.nact = nsb_p;
+    d2.pad_row = -1;
+    d2.nchans = nsb_p;
+    d2.ndm = ngroup;
+    d2.ndm_last = s2->ndm_last;
+    d2.nout = nout;
+    if (lp2.shape.kind == 0) {
+        d2.rel = lp2.bt->d_rel;
+        d2.base = lp2.bt->d_base;
+        d2.nblocks = lp2.bt->nblocks;
+        d2.ntiles = static_cast<int>((nout + tile_len(lp2.shape) - 1) / tile_len(lp2.shape));
+        d2.g_rel = static_cast<long long>(lp2.bt->nblocks) * lp2.bt->db * (nsb_p / 2);
+        d2.g_base = static_cast<long long>(lp2.bt->nblocks) * nsb_p;
+    }
+    d2.table = s2->d_table;
+    d2.rw = lp2.rw;
+    d2.flush_every = lp2.flush_every;
+    d2.shape = lp2.shape_index;
+    d2.scrunch = 1;
+    d2.ngroups = nnom;
+    d2.g_xc = static_cast<long long>(nsb_p) * pitch2;
+    d2.out = d_out;
+    d2.out_bytes = 4;
+    d2.out_stride = static_cast<long long>(stride);
+    d2.g_out = static_cast<long long>(ngroup) * static_cast<long long>(stride);
+    e = lp2.shape.kind == 0 ? dedisp::launch_tiled(d2, lp2.shape, lp2.lds, hs)
+                            : dedisp::launch_untiled_xc(d2, s2->fmt, hs);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return DEDISP_OK;
+}
+
 dedisp_status dedisp_execute(dedisp_plan p, const void* d_in, size_t nsamps, uint32_t* d_out,
                              size_t stride, void* stream)
 {
     if (!p || !d_in || !d_out) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
-    if (nsamps <= static_cast<size_t>(p->max_delay))
+    if (p->sb_step1) return execute_subband(p, d_in, nsamps, d_out, stride, stream);
+    if (!p->groups.empty()) return execute_groups(p, d_in, nsamps, d_out, stride, stream);
+    // (an internal scrunch-group plan, run on its own while tuning, sums
+    // p->scrunch input rows per sample)
+    if (nsamps / p->scrunch <= static_cast<size_t>(p->max_delay))
         return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps <= max_delay");
     if (nsamps > (1ULL << 40)) return fail(DEDISP_ERR_INVALID_ARG, "nsamps too large");
-    const size_t nout = nsamps - p->max_delay;
+    const size_t nout = nsamps / p->scrunch - p->max_delay;
     if (stride == 0) stride = nout;
     if (stride < nout) return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < nsamps - max_delay");
     LaunchPlan lp;
@@ -673,7 +981,86 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
 {
     if (!p || !d_in || !d_out) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
-    if (nsamps <= static_cast<size_t>(p->max_delay))
+    if (p->sb_step1) {
+        // each pass in turn: time whole transforms over the pass's shapes
+        long long len1 = 0, nout = 0;
+        subband_lengths(*p, nsamps, len1, nout);
+        if (len1 <= 0 || nout <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps too short for the sub-band passes");
+        hipStream_t hs = static_cast<hipStream_t>(stream);
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        float best_total = 0.f;
+        for (dedisp_plan q : {p->sb_step1, p->sb_step2}) {
+            float best = 1e30f;
+            dedisp_tile_config best_cfg = q->cfg;
+            for (int i = 0; i < dedisp::shape_count(); ++i) {
+                const Shape& s = dedisp::shape_at(i);
+                if (s.kind != 0 || !shape_matches(s, *q)) continue;
+                dedisp_tile_config c{};
+                c.kind = 0;
+                c.waves = s.waves;
+                c.dms_per_wave = s.dpw;
+                c.words_per_lane = s.m;
+                c.chunk_chans = s.cc;
+                LaunchPlan probe;
+                if (resolve_launch(q, c, false, probe) != DEDISP_OK || probe.shape_index != i) continue;
+                const dedisp_tile_config saved = q->cfg;
+                q->cfg = c;
+                dedisp_status rc = dedisp_execute(p, d_in, nsamps, d_out, stride, stream);
+                float ms = 0.f;
+                if (rc == DEDISP_OK) {
+                    HIP_TRY(hipEventRecord(e0, hs));
+                    for (int r = 0; r < 3 && rc == DEDISP_OK; ++r)
+                        rc = dedisp_execute(p, d_in, nsamps, d_out, stride, stream);
+                    HIP_TRY(hipEventRecord(e1, hs));
+                    HIP_TRY(hipEventSynchronize(e1));
+                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                    ms /= 3;
+                }
+                q->cfg = saved;
+                if (rc != DEDISP_OK) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return rc;
+                }
+                if (ms < best) {
+                    best = ms;
+                    best_cfg = c;
+                }
+            }
+            q->cfg = best_cfg;
+            // each timing is a whole transform: the last pass's best is the
+            // tuned transform's time
+            if (best < 1e29f) best_total = best;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (best_ms) *best_ms = best_total;
+        return DEDISP_OK;
+    }
+    if (!p->groups.empty()) {
+        // each scrunch group on its own (its rows land at the top of d_out,
+        // which the next execute overwrites)
+        size_t width = 0;
+        for (const auto& g : p->groups) {
+            const long long n = group_nout(g, nsamps);
+            if (n <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps / s <= max delay of a scrunch group");
+            width = std::max(width, static_cast<size_t>(n));
+        }
+        if (stride == 0) stride = width;
+        if (stride < width) return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < longest output row");
+        float total = 0.f;
+        for (auto& g : p->groups) {
+            float ms = 0.f;
+            dedisp_status st = dedisp_tune(g.sub, d_in, nsamps, d_out, stride, stream, cache_path, &ms);
+            if (st != DEDISP_OK) return st;
+            total += ms;
+        }
+        if (best_ms) *best_ms = total;
+        return DEDISP_OK;
+    }
+    if (nsamps / p->scrunch <= static_cast<size_t>(p->max_delay))
         return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps <= max_delay");
     hipStream_t st = static_cast<hipStream_t>(stream);
     const std::string key = cache_key(p, nsamps);
@@ -686,7 +1073,7 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
         c.dms_per_wave = static_cast<int>(hit->second[2]);
         c.words_per_lane = static_cast<int>(hit->second[3]);
         c.chunk_chans = static_cast<int>(hit->second[4]);
-        if (find_shape(c, p->nbits)) {
+        if (find_shape(c, *p)) {
             p->cfg = c;
             if (best_ms) *best_ms = hit->second.size() > 5 ? static_cast<float>(hit->second[5]) : 0.f;
             return DEDISP_OK;
@@ -700,7 +1087,7 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
     dedisp_tile_config best_cfg = saved;
     for (int i = 0; i < dedisp::shape_count(); ++i) {
         const Shape& s = dedisp::shape_at(i);
-        if (s.nbits != p->nbits) continue;
+        if (!shape_matches(s, *p)) continue;
         {
             dedisp_tile_config c{};
             c.kind = s.kind;
@@ -755,6 +1142,200 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
                       static_cast<double>(best_cfg.words_per_lane),
                       static_cast<double>(best_cfg.chunk_chans), static_cast<double>(best)};
         write_cache(cache_path, cache);
+    }
+    return DEDISP_OK;
+}
+
+dedisp_status dedisp_get_diagonal_dm(dedisp_plan p, double* dm)
+{
+    if (!p || !dm) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    *dm = diagonal_dm(*p);
+    return DEDISP_OK;
+}
+
+dedisp_status dedisp_default_scrunch_factors(dedisp_plan p, int max_factor, int32_t* factors)
+{
+    if (!p || !factors) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
+    if (max_factor < 1 || max_factor > kMaxScrunch || (max_factor & (max_factor - 1)))
+        return fail(DEDISP_ERR_INVALID_ARG, "max_factor must be a power of two in [1, 64]");
+    const double diag = diagonal_dm(*p);
+    for (size_t d = 0; d < p->dms.size(); ++d) {
+        int s = 1;
+        double threshold = diag;
+        while (s < max_factor && p->dms[d] > threshold) {
+            s *= 2;
+            threshold *= 2.0;
+        }
+        factors[d] = s;
+    }
+    return DEDISP_OK;
+}
+
+dedisp_status dedisp_set_scrunching(dedisp_plan p, const int32_t* factors)
+{
+    if (!p) return fail(DEDISP_ERR_INVALID_ARG, "NULL plan");
+    if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
+    if (p->scrunch != 1 || p->internal) return fail(DEDISP_ERR_INVALID_ARG, "not a user plan");
+    if (p->sb_step1 && factors)
+        return fail(DEDISP_ERR_UNSUPPORTED, "time-scrunching and sub-band dedispersion are exclusive");
+    const int ndm = static_cast<int>(p->dms.size());
+    bool any = false;
+    if (factors) {
+        for (int d = 0; d < ndm; ++d) {
+            const int s = factors[d];
+            if (s < 1 || s > kMaxScrunch || (s & (s - 1)))
+                return fail(DEDISP_ERR_INVALID_ARG, "scrunch factors must be powers of two in [1, 64]");
+            any |= s > 1;
+        }
+    }
+    destroy_groups(p);
+    if (!any) return DEDISP_OK;
+    p->scrunch_factors.assign(factors, factors + ndm);
+    for (int s = 1; s <= kMaxScrunch; s *= 2) {
+        ScrunchGroup g;
+        g.s = s;
+        std::vector<double> dms;
+        for (int d = 0; d < ndm; ++d)
+            if (factors[d] == s) {
+                g.rows.push_back(d);
+                dms.push_back(p->dms[d]);
+            }
+        if (g.rows.empty()) continue;
+        dedisp_plan sub = new (std::nothrow) dedisp_plan_s;
+        if (!sub) {
+            destroy_groups(p);
+            return fail(DEDISP_ERR_OOM, "plan allocation");
+        }
+        sub->nchans = p->nchans;
+        sub->nbits = p->nbits;
+        sub->dt = p->dt * s;
+        sub->f_top = p->f_top;
+        sub->df = p->df;
+        sub->row_bytes = p->row_bytes;
+        sub->scrunch = s;
+        sub->fmt = scrunch_format(p->nbits, s);
+        sub->cfg = default_config(sub->fmt);
+        sub->killmask = p->killmask;
+        sub->active = p->active;
+        g.sub = sub;
+        p->groups.push_back(g);
+        std::vector<int32_t> table;
+        int mx = 0;
+        if (!build_delay_table(*sub, dms.data(), static_cast<int>(dms.size()), table, mx)) {
+            destroy_groups(p);
+            return fail(DEDISP_ERR_INVALID_ARG, "a delay does not fit in int32");
+        }
+        sub->dms = dms;
+        sub->table.swap(table);
+        sub->max_delay = mx;
+        sub->has_dms = true;
+    }
+    return DEDISP_OK;
+}
+
+dedisp_status dedisp_set_subband(dedisp_plan p, int nsub, int ngroup)
+{
+    if (!p) return fail(DEDISP_ERR_INVALID_ARG, "NULL plan");
+    if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
+    if (p->internal || p->scrunch != 1) return fail(DEDISP_ERR_INVALID_ARG, "not a user plan");
+    if (nsub == 0 && ngroup == 0) {
+        destroy_subband(p);
+        return DEDISP_OK;
+    }
+    if (nsub < 8 || nsub % 8 || p->nchans % nsub)
+        return fail(DEDISP_ERR_INVALID_ARG, "nsub must be a multiple of 8 that divides nchans");
+    if (ngroup < 1) return fail(DEDISP_ERR_INVALID_ARG, "ngroup must be positive");
+    if (!p->groups.empty())
+        return fail(DEDISP_ERR_UNSUPPORTED, "time-scrunching and sub-band dedispersion are exclusive");
+    if (p->row_bytes % 4) return fail(DEDISP_ERR_UNSUPPORTED, "sub-band passes need whole 32-bit words per row");
+    const int vsum = (p->nbits == 2 ? 3 : 255) * nsub;      // largest sub-band sum
+    if (vsum > 32767) return fail(DEDISP_ERR_UNSUPPORTED, "sub-band sums do not fit 16 bits");
+    const int ndm = static_cast<int>(p->dms.size());
+    const int nnom = (ndm + ngroup - 1) / ngroup;
+    const int nsb = p->nchans / nsub;
+    const int nsb_p = (nsb + 7) & ~7;
+    if (nnom > 65535 || nsb > 65535) return fail(DEDISP_ERR_UNSUPPORTED, "too many sub-bands or nominal DMs");
+    std::vector<double> nom(nnom);
+    for (int m = 0; m < nnom; ++m) nom[m] = p->dms[static_cast<size_t>(m) * ngroup];
+    std::vector<int32_t> tab_nom;
+    int mx = 0;
+    if (!build_delay_table(*p, nom.data(), nnom, tab_nom, mx))
+        return fail(DEDISP_ERR_INVALID_ARG, "a delay does not fit in int32");
+    dedisp_plan s1 = new_internal(*p), s2 = new_internal(*p);
+    if (!s1 || !s2) {
+        dedisp_plan_destroy(s1);
+        dedisp_plan_destroy(s2);
+        return fail(DEDISP_ERR_OOM, "plan allocation");
+    }
+    // step 1: group n = sub-band n, rows = nominal DMs, delays relative to
+    // the sub-band's first channel
+    s1->nchans = nsub;
+    s1->fmt = p->fmt;
+    s1->ngroups = nsb;
+    s1->dms = nom;
+    s1->ndm_last = nnom;
+    s1->table.assign(static_cast<size_t>(nsb) * nnom * nsub, 0);
+    s1->max_delay = 0;
+    for (int n = 0; n < nsb; ++n)
+        for (int m = 0; m < nnom; ++m)
+            for (int j = 0; j < nsub; ++j) {
+                const int32_t* row = tab_nom.data() + static_cast<size_t>(m) * p->nchans + n * nsub;
+                const int32_t v = row[j] - row[0];
+                s1->table[(static_cast<size_t>(n) * nnom + m) * nsub + j] = v;
+                s1->max_delay = std::max(s1->max_delay, static_cast<int>(v));
+            }
+    s1->cfg = default_config(s1->fmt);
+    // step 2: group m = nominal DM m, rows = its trials, channels = sub-bands
+    // (padded with zero rows to a multiple of 8), delays of each sub-band's
+    // first channel
+    s2->nchans = nsb_p;
+    s2->fmt = vsum <= 24 ? kFmtByteS : kFmtHalf;
+    s2->vbound = vsum;
+    s2->ngroups = nnom;
+    s2->dms.assign(ngroup, 0.0);
+    s2->ndm_last = ndm - (nnom - 1) * ngroup;
+    s2->table.assign(static_cast<size_t>(nnom) * ngroup * nsb_p, 0);
+    s2->max_delay = 0;
+    for (int m = 0; m < nnom; ++m)
+        for (int k = 0; k < ngroup; ++k) {
+            const int d = std::min(m * ngroup + k, ndm - 1);
+            for (int n = 0; n < nsb; ++n) {
+                const int32_t v = p->table[static_cast<size_t>(d) * p->nchans + n * nsub];
+                s2->table[(static_cast<size_t>(m) * ngroup + k) * nsb_p + n] = v;
+                s2->max_delay = std::max(s2->max_delay, static_cast<int>(v));
+            }
+        }
+    s2->cfg = default_config(s2->fmt);
+    destroy_subband(p);
+    p->sb_nsub = nsub;
+    p->sb_ngroup = ngroup;
+    p->sb_step1 = s1;
+    p->sb_step2 = s2;
+    return DEDISP_OK;
+}
+
+dedisp_status dedisp_get_output_lengths(dedisp_plan p, size_t nsamps, size_t* nout)
+{
+    if (!p || !nout) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
+    if (p->sb_step1) {
+        long long len1 = 0, n = 0;
+        subband_lengths(*p, nsamps, len1, n);
+        if (len1 <= 0 || n <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps too short for the sub-band passes");
+        for (size_t d = 0; d < p->dms.size(); ++d) nout[d] = static_cast<size_t>(n);
+        return DEDISP_OK;
+    }
+    if (p->groups.empty()) {
+        if (nsamps <= static_cast<size_t>(p->max_delay))
+            return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps <= max_delay");
+        for (size_t d = 0; d < p->dms.size(); ++d) nout[d] = nsamps - p->max_delay;
+        return DEDISP_OK;
+    }
+    for (const auto& g : p->groups) {
+        const long long n = group_nout(g, nsamps);
+        if (n <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps / s <= max delay of a scrunch group");
+        for (int32_t r : g.rows) nout[r] = static_cast<size_t>(n);
     }
     return DEDISP_OK;
 }

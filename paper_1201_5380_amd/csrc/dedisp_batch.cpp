@@ -30,7 +30,7 @@ hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st)
 {
     for (const Item& it : items)
         if (it.lp.shape.kind == 0) {
-            hipError_t e = launch_unpack(it.d, it.lp.shape.nbits, st);
+            hipError_t e = launch_unpack(it.d, it.lp.nbits, it.lp.shape.fmt, st);
             if (e != hipSuccess) return e;
         }
     std::vector<Item*> tiled;
@@ -67,7 +67,7 @@ hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st)
     }
     for (const Item& it : items)
         if (it.lp.shape.kind != 0) {
-            hipError_t e = launch_untiled(it.d, it.lp.shape.nbits, st);
+            hipError_t e = launch_untiled(it.d, it.lp.nbits, st);
             if (e != hipSuccess) return e;
         }
     return hipSuccess;
@@ -115,7 +115,7 @@ dedisp_status tune_beam(const dedisp_beam& bm, std::map<std::string, std::vector
         c.words_per_lane = static_cast<int>(hit->second[3]);
         c.chunk_chans = static_cast<int>(hit->second[4]);
         int idx = -1;
-        if (find_shape(c, p->nbits, &idx) && dedisp::shape_at(idx).multi) {
+        if (find_shape(c, *p, &idx) && dedisp::shape_at(idx).multi) {
             best = c;
             return DEDISP_OK;
         }
@@ -123,7 +123,7 @@ dedisp_status tune_beam(const dedisp_beam& bm, std::map<std::string, std::vector
     std::vector<int> cands;
     for (int i = 0; i < dedisp::shape_count(); ++i) {
         const Shape& s = dedisp::shape_at(i);
-        if (s.nbits != p->nbits || !s.multi) continue;
+        if (!shape_matches(s, *p) || s.kind != 0 || !s.multi) continue;
         LaunchPlan probe;
         if (resolve_launch(p, config_of(s), false, probe, true) != DEDISP_OK || probe.shape_index != i)
             continue;
@@ -188,6 +188,8 @@ dedisp_status dedisp_batch_create(const dedisp_beam* beams, int nbeams, const ch
         const dedisp_beam& b = beams[i];
         if (!b.plan || !b.d_in || !b.d_out) return fail(DEDISP_ERR_INVALID_ARG, "NULL beam field");
         if (!b.plan->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "beam without DM list");
+        if (!b.plan->groups.empty() || b.plan->sb_step1)
+            return fail(DEDISP_ERR_UNSUPPORTED, "batches support the direct transform only");
         if (b.nsamps <= static_cast<size_t>(b.plan->max_delay))
             return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "beam nsamps <= max_delay");
         if (b.nsamps > (1ULL << 40)) return fail(DEDISP_ERR_INVALID_ARG, "beam too long");

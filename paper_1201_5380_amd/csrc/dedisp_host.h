@@ -44,12 +44,17 @@ struct Scratch {
 struct LaunchPlan {
     int shape_index = -1;
     Shape shape{};
+    int nbits = 0;       // input bit depth (selects the corner-turn kernel)
     int cc = 0, rw = 0, lds = 0, flush_every = 1;
     BlockTables* bt = nullptr;
 };
 
-const Shape* find_shape(const dedisp_tile_config& c, int nbits, int* index = nullptr);
-dedisp_tile_config default_config(int nbits);
+// Shapes usable by plan p: tiled shapes of its scratch format, the untiled
+// kernel of its input bit depth.
+bool shape_matches(const Shape& s, const struct ::dedisp_plan_s& p);
+const Shape* find_shape(const dedisp_tile_config& c, const struct ::dedisp_plan_s& p,
+                        int* index = nullptr);
+dedisp_tile_config default_config(int fmt);
 bool tiled_supported(const struct ::dedisp_plan_s& p);
 
 // Resolve the shape used for plan p (requested one if it fits, else another
@@ -60,7 +65,7 @@ dedisp_status resolve_launch(::dedisp_plan p, const dedisp_tile_config& want, bo
                              LaunchPlan& lp, bool multi_only = false);
 
 long long tile_len(const Shape& s);
-long long xc_pitch(long long nsamps, int nbits, int rw);
+long long xc_pitch(long long nsamps, int fmt, int rw);
 void free_scratch(Scratch& x);
 dedisp_status ensure_scratch(Scratch& x, size_t need);
 dedisp_status ensure_xc(const struct ::dedisp_plan_s& p, Scratch& x, long long nsamps,
@@ -91,10 +96,21 @@ void write_cache(const char* path, const std::map<std::string, std::vector<doubl
 }  // namespace host
 }  // namespace dedisp
 
+// A group of trials that share one time-scrunching factor: an internal plan
+// over those DMs at s times the sampling time, and the output row of each.
+struct ScrunchGroup {
+    int s = 1;
+    std::vector<int32_t> rows;
+    struct dedisp_plan_s* sub = nullptr;
+    int32_t* d_rows = nullptr;
+};
+
 // The object behind dedisp_plan.
 struct dedisp_plan_s {
     int nchans = 0;
     int nbits = 0;
+    int fmt = 0;                    // scratch sample format (dedisp::Fmt)
+    int scrunch = 1;                // input samples summed per scratch sample
     double dt = 0, f_top = 0, df = 0;
     int row_bytes = 0;
     std::vector<double> dms;
@@ -112,6 +128,25 @@ struct dedisp_plan_s {
     std::vector<int32_t> active;
     int32_t* d_chanmap = nullptr;
     int32_t* d_mask = nullptr;
+    // Time-scrunching (empty = off): factor per trial and the groups.
+    std::vector<int32_t> scrunch_factors;
+    std::vector<ScrunchGroup> groups;
+    // Sub-band dedispersion (0 = off): channels per sub-band, trials per
+    // nominal DM, the two grouped passes and the intermediate scratch.
+    int sb_nsub = 0, sb_ngroup = 0;
+    struct dedisp_plan_s* sb_step1 = nullptr;
+    struct dedisp_plan_s* sb_step2 = nullptr;
+    dedisp::host::Scratch sb_xc2;
+    // Internal plans of grouped passes: the table holds ngroups blocks of
+    // [ndm][nchans]; the last group has ndm_last valid rows; vbound (when
+    // set) bounds one scratch sample.
+    bool internal = false;
+    int ngroups = 1;
+    int ndm_last = 0;
+    int vbound = 0;
+
+    // largest value of one scratch sample
+    int value_bound() const { return vbound ? vbound : (nbits == 2 ? 3 : 255) * scrunch; }
 
     int nact() const { return killmask.empty() ? nchans : static_cast<int>(active.size()); }
     // scratch rows the tiled kernel sums: live channels padded with zero rows

@@ -7,6 +7,17 @@
 
 namespace dedisp {
 
+// Sample format of the channel-major scratch the LDS-tiled kernel sums.
+enum Fmt : int {
+    kFmtNib = 0,     // 2-bit codes, two per byte (eight per 32-bit word)
+    kFmtByte = 1,    // 8-bit codes, one per byte
+    kFmtByteS = 2,   // byte values at most 127 (time-scrunched 2-bit codes)
+    kFmtHalf = 3,    // 16-bit values at most 32767 (time-scrunched 8-bit, or heavily scrunched 2-bit, codes)
+};
+constexpr int fmt_bytes_num(int fmt) { return fmt == kFmtHalf ? 2 : 1; }    // bytes per sample =
+constexpr int fmt_bytes_den(int fmt) { return fmt == kFmtNib ? 2 : 1; }     //   num / den
+constexpr int fmt_samples_per_word(int fmt) { return 4 * fmt_bytes_den(fmt) / fmt_bytes_num(fmt); }
+
 // One beam (or one stream push) as the kernels see it.  The input is a
 // virtual concatenation of two row segments so that a stream's resident
 // history and a new chunk can be summed without copying them together:
@@ -16,16 +27,17 @@ struct BeamDesc {
     const uint8_t* in1;
     long long n0;
     long long nsamps;
-    long long nout;           // nsamps - max_delay
+    long long nout;           // outputs per DM row: nsamps / scrunch - max_delay
     uint32_t* out;
-    long long out_stride;     // elements between DM rows
-    uint8_t* xc;              // channel-major bytes written by the unpack kernel
+    long long out_stride;     // between DM rows: elements (out_bytes 4) or bytes (1, 2)
+    uint8_t* xc;              // channel-major scratch written by the unpack or scrunch kernel
     long long pitch;          // bytes between channel rows of xc (multiple of 16)
     const uint32_t* rel;      // [nblocks*DB][nchans/2] window offsets of channel pairs (16+16 bits)
-    const int32_t* base;      // [nblocks][nchans] window start (multiple of 16)
+    const int32_t* base;      // [nblocks][nchans] window start (multiple of 16 bytes of scratch)
     const int32_t* table;     // [ndm][nchans] full delay table (untiled kernel)
     const int32_t* chanmap;   // [nchans] scratch row of each channel, -1 = killed (NULL = identity)
     const int32_t* mask;      // [nchans] 0/1 kill mask for the untiled kernel (NULL = all on)
+    const int32_t* rowmap;    // [ndm] output row of each DM row (NULL = identity)
     int nact;                 // scratch rows the tiled kernel sums (live channels, padded to a multiple of 8)
     int pad_row;              // first of the scratch rows [pad_row, nact) the corner turn zero-fills, or -1
     int nchans;
@@ -34,19 +46,30 @@ struct BeamDesc {
     int nblocks;              // ceil(ndm / DB)
     int ntiles;               // ceil(nout / tile length)
     int rw;                   // LDS row length in 32-bit words
-    int flush_every;          // chunks between packed-lane flushes
+    int flush_every;          // channels between packed-lane flushes (small-value formats)
     int shape;                // index into the compiled shape list
-    int pad_;
+    int scrunch;              // samples summed per scratch sample (1 = none)
+    // Grouped launches (sub-band dedispersion): gridDim.y = ngroups groups,
+    // group g reading its scratch, window tables and writing its outputs at
+    // the offsets below times g.  ngroups = 1 and offsets 0 otherwise.
+    int ngroups;
+    int ndm_last;             // DM rows of the last group (the others have ndm)
+    int out_bytes;            // 4: uint32 outputs; 1 or 2: narrow sums into a scratch
+    int pad2_;
+    long long g_xc;           // bytes
+    long long g_rel;          // elements of rel
+    long long g_base;         // elements of base
+    long long g_out;          // elements (out_bytes 4) or bytes (1, 2)
     long long work_begin;     // first global work item of this beam
 };
 
 // A compiled kernel shape.
 struct Shape {
     int kind;       // 0 = LDS-tiled, 1 = untiled
-    int nbits;
+    int fmt;        // scratch sample format (tiled) or input bit depth (untiled)
     int waves;
     int dpw;        // DMs per wave
-    int m;          // 32-bit words per lane (4 samples each)
+    int m;          // 32-bit scratch words per lane
     int cc;         // channels staged per chunk
     int pi;         // 16-byte pieces per lane per staged row: row <= 64*pi pieces
     int multi;      // also compiled into the multi-beam kernels
@@ -59,12 +82,21 @@ const Shape& shape_at(int i);
 // Largest dynamic LDS a workgroup may use on this device (bytes).
 constexpr int kMaxLdsBytes = 160 * 1024;
 
-// Enqueue the corner turn (time-major packed -> channel-major bytes in d.xc).
-hipError_t launch_unpack(const BeamDesc& d, int nbits, hipStream_t st);
+// Enqueue the corner turn (time-major packed -> channel-major scratch of
+// format fmt in d.xc), summing d.scrunch consecutive samples when above 1.
+hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st);
+
+// Zero `bytes` (a multiple of 16) at base + g*group_stride for g < ngroups.
+hipError_t launch_zero(uint8_t* base, long long group_stride, long long bytes, int ngroups,
+                       hipStream_t st);
 
 // Enqueue the transform of one beam with the given shape.
 hipError_t launch_tiled(const BeamDesc& d, const Shape& s, int lds_bytes, hipStream_t st);
 hipError_t launch_untiled(const BeamDesc& d, int nbits, hipStream_t st);
+// Untiled pass over the channel-major scratch of format fmt (grouped passes
+// of sub-band dedispersion whose delay spread does not fit in LDS);
+// d.table is [ngroups][ndm][nact].
+hipError_t launch_untiled_xc(const BeamDesc& d, int fmt, hipStream_t st);
 
 // Multi-beam launches over up to kMaxBatchDescs beams whose descriptors
 // travel in the kernel arguments (work_begin = prefix sum of ntiles*nblocks,
@@ -76,6 +108,7 @@ constexpr int kMaxBatchDescs = 16;
 struct DescBlock {
     BeamDesc d[kMaxBatchDescs];
 };
+static_assert(sizeof(DescBlock) + 16 <= 4096, "multi-beam descriptors must fit the kernel arguments");
 // One workgroup per work item of every beam in one launch.
 hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
                         hipStream_t st);

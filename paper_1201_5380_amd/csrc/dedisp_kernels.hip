@@ -62,6 +62,7 @@ __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_rea
 // Native 4 x 32-bit vector (one 16-byte load or store); unlike HIP's uint4
 // struct it stays in registers when held in arrays.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ long long wave_uniform64(long long x)
 {
@@ -182,7 +183,11 @@ __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
         if (t0 + 16LL * S::kSamplesPerByte * p >= b.nsamps) continue;
         const int row = b.chanmap ? b.chanmap[c0 + c] : c0 + c;
         if (row < 0) continue;
-        const u32x4 val = *reinterpret_cast<const u32x4*>(tile + (size_t)c * S::kPitch + 16 * p);
+        // without a channel map (sub-band passes keep every channel's row),
+        // killed channels are written as zeros
+        const bool killed = b.mask && b.mask[c0 + c] == 0;
+        const u32x4 val = killed ? u32x4{0u, 0u, 0u, 0u}
+                                 : *reinterpret_cast<const u32x4*>(tile + (size_t)c * S::kPitch + 16 * p);
         *reinterpret_cast<u32x4*>(b.xc + (long long)row * b.pitch + byte0 + 16 * p) = val;
     }
     // the padding rows (live channels up to a multiple of 8) read as zeros
@@ -195,11 +200,91 @@ __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
     }
 }
 
+// ------------------------------------------------------------ scrunching corner turn
+
+// Time-scrunching corner turn (Section 2.1): scratch sample t' of a live
+// channel is the sum of input samples s*t' .. s*t'+s-1 (s = b.scrunch),
+// written channel-major as one byte (OB = 1) or one 16-bit word (OB = 2)
+// per scrunched sample.  A workgroup covers SC channels (32 input words of a
+// row) and ST scrunched samples; lanes 0..31 of a wave read consecutive
+// words of one row.  Requires row_bytes % 4 == 0, 4-byte aligned rows and
+// 3*s (2-bit) or 255*s (8-bit) below the format's value bound.
+template <int NBITS, int OB>
+__global__ __launch_bounds__(256) void k_scrunch(BeamDesc b)
+{
+    constexpr int SC = NBITS == 2 ? 512 : 128;     // channels per workgroup
+    constexpr int ST = NBITS == 2 ? 32 : 64;       // scrunched samples per workgroup
+    constexpr int RB = ST * OB;                    // tile bytes per channel row
+    constexpr int LP = RB + 16;                    // LDS row pitch in bytes
+    static_assert(NBITS == 2 || OB == 2, "8-bit sums need 16 bits");
+    __shared__ __attribute__((aligned(16))) uint8_t tile[SC * LP];
+    const int s = b.scrunch;
+    const long long ns = b.nsamps / s;             // whole scrunched samples
+    const long long tp0 = (long long)blockIdx.x * ST;
+    const int c0 = blockIdx.y * SC;
+    const int w = threadIdx.x & 31;                // input word within the row segment
+    const int cw = c0 + w * (32 / NBITS);          // first channel of that word
+    auto put = [&](int ch, int q, uint32_t v) {
+        if constexpr (OB == 1) tile[(size_t)ch * LP + q] = (uint8_t)v;
+        else reinterpret_cast<uint16_t*>(tile + (size_t)ch * LP)[q] = (uint16_t)v;
+    };
+    for (int q = threadIdx.x >> 5; q < ST; q += 8) {
+        const long long tp = tp0 + q;
+        const bool live = tp < ns && cw < b.nchans;
+        if constexpr (NBITS == 8) {
+            uint32_t lo = 0u, hi = 0u;             // 16-bit lanes: channels (0, 2) and (1, 3) of the word
+            if (live)
+                for (int i = 0; i < s; ++i) {
+                    const uint32_t v = *reinterpret_cast<const uint32_t*>(row_ptr(b, tp * s + i) + cw);
+                    lo += v & 0x00FF00FFu;
+                    hi += (v >> 8) & 0x00FF00FFu;
+                }
+            put(4 * w + 0, q, lo & 0xFFFFu);
+            put(4 * w + 1, q, hi & 0xFFFFu);
+            put(4 * w + 2, q, lo >> 16);
+            put(4 * w + 3, q, hi >> 16);
+        } else {
+            uint32_t g[4] = {0u, 0u, 0u, 0u};      // byte k of g[j]: channel 4k + j of the word
+            if (live)
+                for (int i = 0; i < s; ++i) {
+                    const uint32_t v = *reinterpret_cast<const uint32_t*>(row_ptr(b, tp * s + i) + cw / 4);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) g[j] += (v >> (2 * j)) & 0x03030303u;
+                }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) put(16 * w + 4 * k + j, q, (g[j] >> (8 * k)) & 0xFFu);
+        }
+    }
+    __syncthreads();
+    // 16-byte pieces to each live channel's scratch row; samples past the
+    // last whole scrunched sample hold zeros
+    constexpr int PPR = RB / 16;
+    const long long byte0 = tp0 * OB;
+    for (int it = threadIdx.x; it < SC * PPR; it += 256) {
+        const int c = it / PPR;
+        const int p = it % PPR;
+        if (c0 + c >= b.nchans) continue;
+        const int row = b.chanmap ? b.chanmap[c0 + c] : c0 + c;
+        if (row < 0) continue;
+        *reinterpret_cast<u32x4*>(b.xc + (long long)row * b.pitch + byte0 + 16 * p) =
+            *reinterpret_cast<const u32x4*>(tile + (size_t)c * LP + 16 * p);
+    }
+    if (b.pad_row >= 0 && blockIdx.y == 0 && threadIdx.x < PPR * (b.nact - b.pad_row)) {
+        const int r = b.pad_row + threadIdx.x / PPR;
+        const int p = threadIdx.x % PPR;
+        *reinterpret_cast<u32x4*>(b.xc + (long long)r * b.pitch + byte0 + 16 * p) =
+            u32x4{0u, 0u, 0u, 0u};
+    }
+}
+
 // ------------------------------------------------------------ tiled sum
 
 // One (time tile, DM block) work item.
-//   xc   channel-major scratch, b.pitch bytes per row: 2-bit codes two per
-//        byte (8 samples per 32-bit word), 8-bit codes one per byte (4 per word)
+//   xc   channel-major scratch, b.pitch bytes per row, in format FMT: 2-bit
+//        codes two per byte (8 samples per 32-bit word), 8-bit codes or
+//        small sums one per byte (4 per word), or 16-bit sums (2 per word)
 //   base [nblocks][nact]  window start of scratch row k, in samples (a
 //        multiple of 16 bytes of scratch)
 //   rel  [nblocks*DB][nact/2] window offsets (delay - base, in samples) of a
@@ -207,15 +292,17 @@ __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
 // LDS: CC rows of rw words (rw % 4 == 0).  Channels are summed in pairs so
 // the two realigned words of a pair fold into an accumulator with one
 // three-operand add, and one v_readlane fetches both offsets.
-template <int NBITS, int NW, int DPW, int M, int CC, int PM>
-__device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block, uint32_t* lds)
+template <int FMT, int NW, int DPW, int M, int CC, int PM>
+__device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block, int group,
+                                          uint32_t* lds)
 {
     static_assert(M % 2 == 1, "lanes must be an odd number of LDS words apart");
     static_assert(CC % NW == 0, "every wave stages the same number of channel rows");
     static_assert(CC <= 84, "2-bit byte lanes hold 85 codes");
     static_assert((64 % (CC / 2)) == 0, "offset pairs of one DM sit in one register");
-    constexpr int SPW = NBITS == 2 ? 8 : 4;      // samples per 32-bit LDS word
-    constexpr int SPB = NBITS == 2 ? 2 : 1;      // samples per scratch byte
+    constexpr int SPW = fmt_samples_per_word(FMT);   // samples per 32-bit LDS word
+    constexpr int BNUM = fmt_bytes_num(FMT);         // scratch bytes per sample =
+    constexpr int BDEN = fmt_bytes_den(FMT);         //   BNUM / BDEN
     constexpr int T = 64 * M * SPW;              // tile length in samples
     constexpr int DB = NW * DPW;
     constexpr int CPW = CC / NW;                 // channel rows staged per wave per chunk
@@ -237,15 +324,24 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     //         16-bit lanes w16[0..3] = samples {0,4}, {2,6}, {1,5}, {3,7}.
     //  8-bit: sw[0] = 16-bit lanes (samples 0, 1), sw[1] = (2, 3), exact for
     //         257 codes, flushed every FLUSH chunks into 32-bit acc[0..3].
+    //  Small byte values (at most V <= 127): sw[0] = byte lanes (samples
+    //         0..3) realigned with v_alignbit, flushed every b.flush_every
+    //         channels (an even count with flush_every * V <= 255) into
+    //         32-bit acc[0..3].
+    //  16-bit values (at most V <= 32767): sw[0] = 16-bit lanes (samples 0,
+    //         1) realigned with v_alignbit, flushed every b.flush_every
+    //         channels (even, flush_every * V <= 65535) into acc[0..1].
     constexpr int NACC = 4;
-    constexpr int FLUSH = NBITS == 2 ? 85 / CC : 257 / CC;
-    static_assert(FLUSH >= 1, "chunk too large for the packed lanes");
+    constexpr bool kFixedFlush = FMT == kFmtNib || FMT == kFmtByte;
+    constexpr int FLUSH = FMT == kFmtNib ? 85 / CC : 257 / CC;
+    static_assert(!kFixedFlush || FLUSH >= 1, "chunk too large for the packed lanes");
     static_assert(CC % 8 == 0, "channels are summed in groups of 8");
 
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
     tile = wave_uniform(tile);
     block = wave_uniform(block);
+    group = wave_uniform(group);
     const long long t0 = (long long)tile * T;
     // Every descriptor field is wave-uniform; keep them in scalar registers
     // (the multi-beam kernels read descriptors through a dynamic index).
@@ -256,11 +352,13 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     const long long nout = wave_uniform64(b.nout);
     const long long out_stride = wave_uniform64(b.out_stride);
     const int ndm = wave_uniform(b.ndm);
-    const uint8_t* xc = wave_uniform_ptr(b.xc);
+    const uint8_t* xc = wave_uniform_ptr(b.xc) + group * wave_uniform64(b.g_xc);
     uint32_t* out = wave_uniform_ptr(b.out);
-    const int32_t* base_row = wave_uniform_ptr(b.base) + (size_t)block * nchans;
+    const int32_t* base_row = wave_uniform_ptr(b.base) + group * wave_uniform64(b.g_base) +
+                              (size_t)block * nchans;
     const int npairs = nchans >> 1;
-    const uint32_t* rel_rows = wave_uniform_ptr(b.rel) + (size_t)(block * DB + wave * DPW) * npairs;
+    const uint32_t* rel_rows = wave_uniform_ptr(b.rel) + group * wave_uniform64(b.g_rel) +
+                               (size_t)(block * DB + wave * DPW) * npairs;
 
     uint32_t sw[DPW][M][2];
     uint32_t acc[DPW][M][NACC];
@@ -294,7 +392,7 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     _Pragma("unroll") for (int i = 0; i < CPW; ++i) {                               \
         const int cl = wave + NW * i;                                               \
         const int bs = lane_value(vbase_nxt, cl);                                   \
-        const uint8_t* src = xc + (long long)min((C0) + cl, last_c) * pitch + (t0 + bs) / SPB; \
+        const uint8_t* src = xc + (long long)min((C0) + cl, last_c) * pitch + (t0 + bs) * BNUM / BDEN; \
         _Pragma("unroll") for (int q = 0; q < PM; ++q)                              \
             pf[i][q] = *reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p)); \
     }
@@ -306,7 +404,8 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
         DEDISP_LOAD_BASE(CC)
     }
 
-    int since_flush = 0;
+    int since_flush = 0;                       // chunks (fixed flush) or channels (runtime flush)
+    const int flush_chans = wave_uniform(b.flush_every);
     for (int c0 = 0; c0 < nchans; c0 += CC) {
         const int ncur = min(CC, nchans - c0);  // a multiple of 8
         __syncthreads();                       // everyone is done reading the previous chunk
@@ -335,7 +434,7 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
 #undef DEDISP_LOAD_DATA
 
         const uint32_t* lrow = lds + lane * M;
-        if constexpr (NBITS == 2) {
+        if constexpr (FMT == kFmtNib) {
             for (int c = 0; c < ncur; c += 8) {
 #pragma unroll
                 for (int k = 0; k < DPW; ++k) {
@@ -367,7 +466,7 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
                     }
                 }
             }
-        } else {
+        } else if constexpr (FMT == kFmtByte) {
             for (int c = 0; c < ncur; c += 2) {
                 const uint32_t* row0 = lrow + (size_t)c * rw;
                 const uint32_t* row1 = row0 + rw;
@@ -397,15 +496,60 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
                     }
                 }
             }
+        } else {
+            // small byte values or 16-bit values, runtime flush interval
+            for (int c = 0; c < ncur; c += 2) {
+                const uint32_t* row0 = lrow + (size_t)c * rw;
+                const uint32_t* row1 = row0 + rw;
+#pragma unroll
+                for (int k = 0; k < DPW; ++k) {
+                    const uint32_t rr = (uint32_t)lane_value((int)vrel_cur[k / KPR], (k % KPR) * CP + (c >> 1));
+                    const uint32_t r0 = rr & 0xFFFFu, r1 = rr >> 16;
+                    const uint32_t* src0 = row0 + r0 / SPW;
+                    const uint32_t* src1 = row1 + r1 / SPW;
+                    uint32_t w0[M + 1], w1[M + 1];
+#pragma unroll
+                    for (int j = 0; j <= M; ++j) {
+                        w0[j] = src0[j];
+                        w1[j] = src1[j];
+                    }
+                    // bit shift of the window start within its word
+                    const uint32_t s0 = (r0 % SPW) * (32u / SPW), s1 = (r1 % SPW) * (32u / SPW);
+#pragma unroll
+                    for (int j = 0; j < M; ++j)
+                        sw[k][j][0] += __builtin_amdgcn_alignbit(w0[j + 1], w0[j], s0) +
+                                       __builtin_amdgcn_alignbit(w1[j + 1], w1[j], s1);
+                }
+                since_flush += 2;
+                if (since_flush + 2 > flush_chans) {
+                    since_flush = 0;
+#pragma unroll
+                    for (int k = 0; k < DPW; ++k)
+#pragma unroll
+                        for (int j = 0; j < M; ++j) {
+                            const uint32_t v = sw[k][j][0];
+                            if constexpr (FMT == kFmtByteS) {
+                                acc[k][j][0] += v & 0xFFu;
+                                acc[k][j][1] += (v >> 8) & 0xFFu;
+                                acc[k][j][2] += (v >> 16) & 0xFFu;
+                                acc[k][j][3] += v >> 24;
+                            } else {
+                                acc[k][j][0] += v & 0xFFFFu;
+                                acc[k][j][1] += v >> 16;
+                            }
+                            sw[k][j][0] = 0u;
+                        }
+                }
+            }
         }
 
-        if (++since_flush == FLUSH || c0 + CC >= nchans) {
+        if (kFixedFlush && (++since_flush == FLUSH || c0 + CC >= nchans)) {
             since_flush = 0;
 #pragma unroll
             for (int k = 0; k < DPW; ++k)
 #pragma unroll
                 for (int j = 0; j < M; ++j) {
-                    if constexpr (NBITS == 2) {
+                    if constexpr (FMT == kFmtNib) {
                         const uint32_t e = sw[k][j][0];
                         const uint32_t o = sw[k][j][1] - ((e & 0xFFFFFF00u) >> 4);
                         acc[k][j][0] += e & 0x00FF00FFu;           // samples 0, 4
@@ -425,17 +569,91 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
         }
     }
 
-    const bool vec = ((out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
+    if constexpr (!kFixedFlush) {
+        if (since_flush > 0) {
+#pragma unroll
+            for (int k = 0; k < DPW; ++k)
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    const uint32_t v = sw[k][j][0];
+                    if constexpr (FMT == kFmtByteS) {
+                        acc[k][j][0] += v & 0xFFu;
+                        acc[k][j][1] += (v >> 8) & 0xFFu;
+                        acc[k][j][2] += (v >> 16) & 0xFFu;
+                        acc[k][j][3] += v >> 24;
+                    } else {
+                        acc[k][j][0] += v & 0xFFFFu;
+                        acc[k][j][1] += v >> 16;
+                    }
+                }
+        }
+    }
+
+    // 16-byte stores need 16-byte aligned rows (SPW >= 4), 8-byte stores
+    // 8-byte aligned rows (SPW == 2)
+    constexpr int VW = SPW >= 4 ? 4 : 2;
+    const bool vec = ((out_stride & (VW - 1)) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(out) & (4 * VW - 1)) == 0);
+    const int32_t* rowmap = wave_uniform_ptr(b.rowmap);
+    const int ndm_here = group == wave_uniform(b.ngroups) - 1 ? wave_uniform(b.ndm_last) : ndm;
+    const int out_bytes = wave_uniform(b.out_bytes);
+    const long long g_out = wave_uniform64(b.g_out);
 #pragma unroll
     for (int k = 0; k < DPW; ++k) {
         const int d = block * DB + wave * DPW + k;
-        if (d >= ndm) continue;
-        uint32_t* orow = out + (size_t)d * (size_t)out_stride;
+        if (d >= ndm_here) continue;
+        const int orow_idx = rowmap ? wave_uniform(rowmap[d]) : d;
+        if (out_bytes != 4) {
+            // narrow sums written into a channel-major scratch: row stride
+            // and group offset in bytes
+            uint8_t* nrow = reinterpret_cast<uint8_t*>(out) + group * g_out +
+                            (long long)orow_idx * out_stride;
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const long long t = t0 + (long long)SPW * (lane * M + j);
+                uint32_t o[SPW];
+                if constexpr (FMT == kFmtNib) {
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        o[4 * h + 0] = (acc[k][j][0] >> (16 * h)) & 0xFFFFu;
+                        o[4 * h + 1] = (acc[k][j][2] >> (16 * h)) & 0xFFFFu;
+                        o[4 * h + 2] = (acc[k][j][1] >> (16 * h)) & 0xFFFFu;
+                        o[4 * h + 3] = (acc[k][j][3] >> (16 * h)) & 0xFFFFu;
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < SPW; ++e) o[e] = acc[k][j][e];
+                }
+                if (t + SPW <= nout) {
+                    if (out_bytes == 1) {
+#pragma unroll
+                        for (int g4 = 0; g4 < SPW / 4; ++g4)
+                            *reinterpret_cast<uint32_t*>(nrow + t + 4 * g4) =
+                                o[4 * g4] | (o[4 * g4 + 1] << 8) | (o[4 * g4 + 2] << 16) | (o[4 * g4 + 3] << 24);
+                    } else {
+#pragma unroll
+                        for (int g2 = 0; g2 < SPW / 2; ++g2)
+                            *reinterpret_cast<uint32_t*>(nrow + 2 * (t + 2 * g2)) =
+                                o[2 * g2] | (o[2 * g2 + 1] << 16);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < SPW; ++e) {
+                        if (t + e < nout) {
+                            if (out_bytes == 1) nrow[t + e] = (uint8_t)o[e];
+                            else reinterpret_cast<uint16_t*>(nrow)[t + e] = (uint16_t)o[e];
+                        }
+                    }
+                }
+            }
+            continue;
+        }
+        uint32_t* orow = out + group * g_out + (size_t)orow_idx * (size_t)out_stride;
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             const long long t = t0 + (long long)SPW * (lane * M + j);
             uint32_t o[SPW];
-            if constexpr (NBITS == 2) {
+            if constexpr (FMT == kFmtNib) {
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     o[4 * h + 0] = (acc[k][j][0] >> (16 * h)) & 0xFFFFu;
@@ -445,31 +663,35 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
                 }
             } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) o[e] = acc[k][j][e];
+                for (int e = 0; e < SPW; ++e) o[e] = acc[k][j][e];
             }
 #pragma unroll
-            for (int g = 0; g < SPW / 4; ++g) {
-                const long long tg = t + 4 * g;
-                if (vec && tg + 3 < nout) {
-                    *reinterpret_cast<u32x4*>(orow + tg) =
-                        u32x4{o[4 * g], o[4 * g + 1], o[4 * g + 2], o[4 * g + 3]};
+            for (int g = 0; g < SPW / VW; ++g) {
+                const long long tg = t + VW * g;
+                if (vec && tg + VW - 1 < nout) {
+                    if constexpr (VW == 4)
+                        *reinterpret_cast<u32x4*>(orow + tg) =
+                            u32x4{o[4 * g], o[4 * g + 1], o[4 * g + 2], o[4 * g + 3]};
+                    else
+                        *reinterpret_cast<u32x2*>(orow + tg) = u32x2{o[2 * g], o[2 * g + 1]};
                 } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (tg + e < nout) orow[tg + e] = o[4 * g + e];
+                    for (int e = 0; e < VW; ++e)
+                        if (tg + e < nout) orow[tg + e] = o[VW * g + e];
                 }
             }
         }
     }
 }
 
-template <int NBITS, int NW, int DPW, int M, int CC, int PM>
+template <int FMT, int NW, int DPW, int M, int CC, int PM>
 __global__ __launch_bounds__(NW * 64) void k_tiled(BeamDesc b)
 {
     extern __shared__ uint32_t lds_dyn[];
     const int n = b.ntiles * b.nblocks;
     const int logical = xcd_remap((int)blockIdx.x, n);
-    tile_body<NBITS, NW, DPW, M, CC, PM>(b, logical / b.nblocks, logical % b.nblocks, lds_dyn);
+    tile_body<FMT, NW, DPW, M, CC, PM>(b, logical / b.nblocks, logical % b.nblocks, (int)blockIdx.y,
+                                       lds_dyn);
 }
 
 // ------------------------------------------------------------ untiled
@@ -482,11 +704,14 @@ __device__ __forceinline__ uint32_t sample_at(const BeamDesc& b, long long r, in
     else return (row[c >> 2] >> (2 * (c & 3))) & 3u;
 }
 
+// With b.scrunch = s > 1, output t of a DM row sums, per channel, the s
+// input samples that make up scrunched sample t + delay.
 template <int NBITS>
 __global__ __launch_bounds__(256) void k_untiled(BeamDesc b)
 {
     const long long t = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;
     if (t >= b.nout) return;
+    const int s = b.scrunch;
     for (int d = blockIdx.y; d < b.ndm; d += gridDim.y) {
         const int32_t* dl = b.table + (size_t)d * b.nchans;
         uint32_t a[4] = {0u, 0u, 0u, 0u};
@@ -495,49 +720,117 @@ __global__ __launch_bounds__(256) void k_untiled(BeamDesc b)
             const int off = dl[c];
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (t + e < b.nout) a[e] += sample_at<NBITS>(b, t + e + off, c);
+                if (t + e < b.nout)
+                    for (int i = 0; i < s; ++i)
+                        a[e] += sample_at<NBITS>(b, (t + e + off) * s + i, c);
         }
-        uint32_t* orow = b.out + (size_t)d * (size_t)b.out_stride;
+        uint32_t* orow = b.out + (size_t)(b.rowmap ? b.rowmap[d] : d) * (size_t)b.out_stride;
 #pragma unroll
         for (int e = 0; e < 4; ++e)
             if (t + e < b.nout) orow[t + e] = a[e];
     }
 }
 
+// Untiled pass over a channel-major scratch (grouped passes whose delay
+// spread is too large for LDS): one thread per 4 outputs of one DM row of
+// group blockIdx.z, reading scratch samples of format FMT straight from
+// global memory.  table: [ngroups][ndm][nact] delays of the scratch rows.
+template <int FMT>
+__device__ __forceinline__ uint32_t xc_sample(const uint8_t* row, long long t)
+{
+    if constexpr (FMT == kFmtNib) return (row[t >> 1] >> (4 * (t & 1))) & 0xFu;
+    else if constexpr (FMT == kFmtHalf) return reinterpret_cast<const uint16_t*>(row)[t];
+    else return row[t];
+}
+
+template <int FMT>
+__global__ __launch_bounds__(256) void k_untiled_xc(BeamDesc b)
+{
+    const long long t = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (t >= b.nout) return;
+    const int g = blockIdx.z;
+    const int ndm_here = g == b.ngroups - 1 ? b.ndm_last : b.ndm;
+    const uint8_t* xc = b.xc + g * b.g_xc;
+    for (int d = blockIdx.y; d < ndm_here; d += gridDim.y) {
+        const int32_t* dl = b.table + ((size_t)g * b.ndm + d) * b.nact;
+        uint32_t a[4] = {0u, 0u, 0u, 0u};
+        for (int k = 0; k < b.nact; ++k) {
+            const uint8_t* row = xc + (long long)k * b.pitch;
+            const long long off = dl[k];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t + e < b.nout) a[e] += xc_sample<FMT>(row, t + e + off);
+        }
+        if (b.out_bytes == 4) {
+            uint32_t* orow = b.out + g * b.g_out + (size_t)d * (size_t)b.out_stride;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t + e < b.nout) orow[t + e] = a[e];
+        } else {
+            uint8_t* nrow = reinterpret_cast<uint8_t*>(b.out) + g * b.g_out + (long long)d * b.out_stride;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t + e < b.nout) {
+                    if (b.out_bytes == 1) nrow[t + e] = (uint8_t)a[e];
+                    else reinterpret_cast<uint16_t*>(nrow)[t + e] = (uint16_t)a[e];
+                }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- zero fill
+
+// Zero [base + g*group_stride, + bytes) for g = blockIdx.y with 16-byte
+// stores (a fill kernel rather than a memset, so the launch can sit in a
+// captured graph).
+__global__ __launch_bounds__(256) void k_zero(uint8_t* base, long long group_stride, long long n16)
+{
+    u32x4* p = reinterpret_cast<u32x4*>(base + (long long)blockIdx.y * group_stride);
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n16; i += (long long)gridDim.x * 256)
+        p[i] = u32x4{0u, 0u, 0u, 0u};
+}
+
 // ---------------------------------------------------------------- shapes
 
-// (nbits, waves, DMs per wave, words per lane, channels per chunk, pieces,
-// multi): a tile is 64*words scratch words long (512*words 2-bit or
-// 256*words 8-bit samples); a staged channel row holds at most 64*pieces
-// 16-byte pieces (2048*pieces 2-bit or 1024*pieces 8-bit samples); shapes
-// marked multi are also compiled into the multi-beam kernels (which allocate
-// registers for the largest of them).  The first shape of each bit depth is
-// the default.
-#define DEDISP_SHAPES(X)             \
-    X(2, 8, 2, 3, 32, 2, 1)          \
-    X(2, 8, 2, 3, 16, 4, 1)          \
-    X(2, 8, 2, 1, 32, 2, 1)          \
-    X(2, 8, 4, 3, 32, 2, 0)          \
-    X(2, 8, 2, 5, 32, 2, 0)          \
-    X(2, 8, 4, 3, 16, 4, 0)          \
-    X(2, 16, 2, 3, 64, 2, 0)         \
-    X(2, 16, 1, 5, 64, 2, 0)         \
-    X(8, 8, 2, 5, 32, 2, 1)          \
-    X(8, 8, 2, 3, 16, 4, 1)          \
-    X(8, 8, 4, 3, 16, 4, 0)          \
-    X(8, 8, 4, 3, 32, 2, 0)          \
-    X(8, 8, 4, 5, 32, 2, 0)          \
-    X(8, 8, 2, 5, 64, 2, 0)          \
-    X(8, 16, 2, 5, 64, 2, 0)         \
-    X(8, 4, 4, 5, 32, 2, 0)
+// (scratch format, waves, DMs per wave, words per lane, channels per chunk,
+// pieces, multi): a tile is 64*words scratch words long (512*words 2-bit,
+// 256*words byte or 128*words 16-bit samples); a staged channel row holds at
+// most 64*pieces 16-byte pieces; shapes marked multi are also compiled into
+// the multi-beam kernels (which allocate registers for the largest of them).
+// The first shape of each format is its default.
+#define DEDISP_SHAPES(X)                   \
+    X(kFmtNib, 8, 2, 3, 32, 2, 1)          \
+    X(kFmtNib, 8, 2, 3, 16, 4, 1)          \
+    X(kFmtNib, 8, 2, 1, 32, 2, 1)          \
+    X(kFmtNib, 8, 4, 3, 32, 2, 0)          \
+    X(kFmtNib, 8, 2, 5, 32, 2, 0)          \
+    X(kFmtNib, 8, 4, 3, 16, 4, 0)          \
+    X(kFmtNib, 16, 2, 3, 64, 2, 0)         \
+    X(kFmtNib, 16, 1, 5, 64, 2, 0)         \
+    X(kFmtByte, 8, 2, 5, 32, 2, 1)         \
+    X(kFmtByte, 8, 2, 3, 16, 4, 1)         \
+    X(kFmtByte, 8, 4, 3, 16, 4, 0)         \
+    X(kFmtByte, 8, 4, 3, 32, 2, 0)         \
+    X(kFmtByte, 8, 4, 5, 32, 2, 0)         \
+    X(kFmtByte, 8, 2, 5, 64, 2, 0)         \
+    X(kFmtByte, 16, 2, 5, 64, 2, 0)        \
+    X(kFmtByte, 4, 4, 5, 32, 2, 0)         \
+    X(kFmtByteS, 8, 2, 3, 32, 2, 0)        \
+    X(kFmtByteS, 8, 2, 3, 16, 4, 0)        \
+    X(kFmtByteS, 16, 1, 5, 64, 2, 0)       \
+    X(kFmtByteS, 8, 2, 5, 32, 2, 0)        \
+    X(kFmtHalf, 8, 2, 3, 32, 2, 0)         \
+    X(kFmtHalf, 8, 2, 3, 16, 4, 0)         \
+    X(kFmtHalf, 16, 1, 5, 64, 2, 0)        \
+    X(kFmtHalf, 8, 2, 5, 32, 2, 0)
 
 struct ShapeEntry {
     Shape s;
     const void* fn;
 };
 
-#define DEDISP_ENTRY(NB, NW, DPW, M, CC, PM, MULTI) \
-    {Shape{0, NB, NW, DPW, M, CC, PM, MULTI}, reinterpret_cast<const void*>(&k_tiled<NB, NW, DPW, M, CC, PM>)},
+#define DEDISP_ENTRY(FMT, NW, DPW, M, CC, PM, MULTI) \
+    {Shape{0, FMT, NW, DPW, M, CC, PM, MULTI}, reinterpret_cast<const void*>(&k_tiled<FMT, NW, DPW, M, CC, PM>)},
 
 const ShapeEntry kShapes[] = {
     DEDISP_SHAPES(DEDISP_ENTRY)
@@ -548,14 +841,14 @@ constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 // Multi-beam kernels: the shapes marked multi (all have kMultiWaves
 // waves).
-template <int NBITS, int NW, int DPW, int M, int CC, int PM, int MULTI>
+template <int FMT, int NW, int DPW, int M, int CC, int PM, int MULTI>
 __device__ __forceinline__ bool run_if(int shape_id, int want, const BeamDesc& b, int tile,
                                        int block, uint32_t* lds)
 {
     if constexpr (MULTI != 0) {
         static_assert(NW == kMultiWaves, "multi-beam shapes share one workgroup size");
         if (shape_id == want) {
-            tile_body<NBITS, NW, DPW, M, CC, PM>(b, tile, block, lds);
+            tile_body<FMT, NW, DPW, M, CC, PM>(b, tile, block, 0, lds);
             return true;
         }
     }
@@ -582,8 +875,8 @@ __device__ __forceinline__ void run_item(const DescBlock& blk, int nbeams, int i
     const int block = local - tile * b.nblocks;
     int id = 0;
     bool done = false;
-#define DEDISP_RUN(NB, NW, DPW, M, CC, PM, MULTI) \
-    if (!done) done = run_if<NB, NW, DPW, M, CC, PM, MULTI>(b.shape, id, b, tile, block, lds); \
+#define DEDISP_RUN(FMT, NW, DPW, M, CC, PM, MULTI) \
+    if (!done) done = run_if<FMT, NW, DPW, M, CC, PM, MULTI>(b.shape, id, b, tile, block, lds); \
     ++id;
     DEDISP_SHAPES(DEDISP_RUN)
 #undef DEDISP_RUN
@@ -627,13 +920,27 @@ hipError_t ensure_lds_attr(int idx, const void* fn)
 int shape_count() { return kNumShapes; }
 const Shape& shape_at(int i) { return kShapes[i].s; }
 
-hipError_t launch_unpack(const BeamDesc& d, int nbits, hipStream_t st)
+hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st)
 {
+    BeamDesc arg = d;
+    void* args[] = {&arg};
+    if (d.scrunch > 1) {
+        const long long sc = nbits == 2 ? 512 : 128, stl = nbits == 2 ? 32 : 64;
+        const long long ns = d.nsamps / d.scrunch;
+        const long long gx = (ns + stl - 1) / stl;
+        const long long gy = (d.nchans + sc - 1) / sc;
+        if (gx <= 0 || gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidValue;
+        const void* fn = nullptr;
+        if (nbits == 2 && fmt == kFmtByteS) fn = reinterpret_cast<const void*>(&k_scrunch<2, 1>);
+        else if (nbits == 2 && fmt == kFmtHalf) fn = reinterpret_cast<const void*>(&k_scrunch<2, 2>);
+        else if (nbits == 8 && fmt == kFmtHalf) fn = reinterpret_cast<const void*>(&k_scrunch<8, 2>);
+        if (!fn) return hipErrorInvalidValue;
+        return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, 0, st);
+    }
     const long long gx = (d.nsamps + kUT - 1) / kUT;
     const long long gy = (d.nchans + kUC - 1) / kUC;
     if (gx <= 0 || gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidValue;
-    BeamDesc arg = d;
-    void* args[] = {&arg};
+    if ((nbits == 2) != (fmt == kFmtNib)) return hipErrorInvalidValue;
     const void* fn = nbits == 2 ? reinterpret_cast<const void*>(&k_unpack<2>)
                                 : reinterpret_cast<const void*>(&k_unpack<8>);
     return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, 0, st);
@@ -644,7 +951,7 @@ hipError_t launch_tiled(const BeamDesc& d, const Shape& s, int lds_bytes, hipStr
     int idx = -1;
     for (int i = 0; i < kNumShapes; ++i) {
         const Shape& k = kShapes[i].s;
-        if (k.kind == 0 && k.nbits == s.nbits && k.waves == s.waves && k.dpw == s.dpw &&
+        if (k.kind == 0 && k.fmt == s.fmt && k.waves == s.waves && k.dpw == s.dpw &&
             k.m == s.m && k.cc == s.cc && k.pi == s.pi) {
             idx = i;
             break;
@@ -654,11 +961,40 @@ hipError_t launch_tiled(const BeamDesc& d, const Shape& s, int lds_bytes, hipStr
     hipError_t e = ensure_lds_attr(idx, kShapes[idx].fn);
     if (e != hipSuccess) return e;
     const long long n = (long long)d.ntiles * d.nblocks;
-    if (n <= 0 || n > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (n <= 0 || n > 0x7fffffffLL || d.ngroups < 1 || d.ngroups > 65535) return hipErrorInvalidValue;
     BeamDesc arg = d;
     void* args[] = {&arg};
-    return hipLaunchKernel(kShapes[idx].fn, dim3((unsigned)n), dim3(s.waves * 64), args,
-                           (size_t)lds_bytes, st);
+    return hipLaunchKernel(kShapes[idx].fn, dim3((unsigned)n, (unsigned)d.ngroups), dim3(s.waves * 64),
+                           args, (size_t)lds_bytes, st);
+}
+
+hipError_t launch_zero(uint8_t* base, long long group_stride, long long bytes, int ngroups,
+                       hipStream_t st)
+{
+    if (bytes <= 0 || ngroups <= 0) return hipSuccess;
+    if ((bytes & 15) || (reinterpret_cast<uintptr_t>(base) & 15) || (group_stride & 15) ||
+        ngroups > 65535)
+        return hipErrorInvalidValue;
+    const long long n16 = bytes / 16;
+    const long long nb = (n16 + 255) / 256;
+    const long long gx = nb < 4096 ? nb : 4096;
+    void* args[] = {&base, &group_stride, const_cast<long long*>(&n16)};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&k_zero), dim3((unsigned)gx, (unsigned)ngroups),
+                           dim3(256), args, 0, st);
+}
+
+hipError_t launch_untiled_xc(const BeamDesc& d, int fmt, hipStream_t st)
+{
+    const long long nthreads = (d.nout + 3) / 4;
+    const long long gx = (nthreads + 255) / 256;
+    if (gx <= 0 || gx > 0x7fffffffLL || d.ngroups < 1 || d.ngroups > 65535) return hipErrorInvalidValue;
+    const unsigned gy = (unsigned)(d.ndm < 65535 ? d.ndm : 65535);
+    BeamDesc arg = d;
+    void* args[] = {&arg};
+    const void* fn = fmt == kFmtNib    ? reinterpret_cast<const void*>(&k_untiled_xc<kFmtNib>)
+                     : fmt == kFmtHalf ? reinterpret_cast<const void*>(&k_untiled_xc<kFmtHalf>)
+                                       : reinterpret_cast<const void*>(&k_untiled_xc<kFmtByte>);
+    return hipLaunchKernel(fn, dim3((unsigned)gx, gy, (unsigned)d.ngroups), dim3(256), args, 0, st);
 }
 
 hipError_t launch_untiled(const BeamDesc& d, int nbits, hipStream_t st)

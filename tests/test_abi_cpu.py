@@ -143,3 +143,141 @@ def test_stream_and_batch_validation_precedes_hip(native):
     plan.set_dm_list([0.0, 50.0])
     assert L.dedisp_batch_create(arr, 1, None, None, ctypes.byref(out)) == -3   # too few samples
     assert L.dedisp_batch_create(arr, 0, None, None, ctypes.byref(out)) == -1
+
+
+# ---------------------------------------------------------------------------
+# time-scrunching: host logic against the oracle (no GPU needed)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_diagonal_dm_and_default_factors_match_oracle(native, name):
+    nchans, nbits, dt, f0, df, ndm, dm_max = WORKLOADS[name]
+    dms = synth.dm_list_linear(ndm, dm_max)
+    plan = Plan(nchans, dt, f0, df, nbits).set_dm_list(dms)
+    assert plan.diagonal_dm() == oracle.diagonal_dm(nchans, dt, f0, df)
+    for mf in (1, 2, 8, 64):
+        assert np.array_equal(plan.default_scrunch_factors(mf),
+                              oracle.scrunch_factors(nchans, dt, f0, df, dms, mf))
+
+
+def test_single_channel_has_no_diagonal(native):
+    plan = Plan(4, 64e-6, 1500.0, -1.0, 2).set_dm_list([0.0])
+    assert plan.diagonal_dm() > 0
+    one = Plan(1, 64e-6, 1500.0, -1.0, 8)
+    assert np.isinf(one.diagonal_dm())
+
+
+def test_output_lengths_match_oracle_groups(native):
+    nchans, nbits, dt, f0, df, ndm, dm_max = WORKLOADS["survey"]
+    dms = synth.dm_list_linear(ndm, dm_max)
+    plan = Plan(nchans, dt, f0, df, nbits).set_dm_list(dms)
+    nsamps = 1 << 19
+    assert np.all(plan.output_lengths(nsamps) == nsamps - plan.max_delay)
+    factors = plan.default_scrunch_factors(64)
+    plan.set_scrunching(factors)
+    got = plan.output_lengths(nsamps)
+    for s in sorted(set(factors.tolist())):
+        rows = np.nonzero(factors == s)[0]
+        _, mx = oracle.delay_table(nchans, dt * s, f0, df, dms[rows])
+        assert np.all(got[rows] == nsamps // s - mx), s
+    assert plan.nout(nsamps) == got.max()
+    # unsorted lists and arbitrary (valid) factors
+    rng = np.random.default_rng(3)
+    perm = rng.permutation(ndm)
+    plan.set_dm_list(dms[perm])
+    f2 = (2 ** rng.integers(0, 7, size=ndm)).astype(np.int32)
+    plan.set_scrunching(f2)
+    got = plan.output_lengths(nsamps)
+    for s in sorted(set(f2.tolist())):
+        rows = np.nonzero(f2 == s)[0]
+        _, mx = oracle.delay_table(nchans, dt * s, f0, df, dms[perm][rows])
+        assert np.all(got[rows] == nsamps // s - mx)
+
+
+def test_scrunching_validation_precedes_hip(native):
+    L = lib()
+    plan = Plan(64, 64e-6, 1500.0, -1.0, 8)
+    f = np.ones(4, np.int32)
+    fp = f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    assert L.dedisp_set_scrunching(plan.handle, fp) == -2                  # no DM list
+    plan.set_dm_list([0.0, 100.0, 200.0, 300.0])
+    for bad in ([1, 3, 1, 1], [1, 1, 0, 1], [128, 1, 1, 1], [-2, 1, 1, 1]):
+        b = np.array(bad, np.int32)
+        assert L.dedisp_set_scrunching(plan.handle, b.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == -1
+    out = np.zeros(4, np.int32)
+    assert L.dedisp_default_scrunch_factors(plan.handle, 3, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == -1
+    assert L.dedisp_default_scrunch_factors(plan.handle, 128, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == -1
+    plan.set_scrunching([1, 2, 4, 8])
+    mx8 = oracle.delay_table(64, 64e-6 * 8, 1500.0, -1.0, np.array([300.0]))[1]
+    p16 = ctypes.c_void_p(1 << 20)
+    n_small = 8 * (mx8 + 1) - 1                                             # group 8 has no output
+    assert L.dedisp_execute(plan.handle, p16, n_small, p16, 0, None) == -3
+    nout = (ctypes.c_size_t * 4)()
+    assert L.dedisp_get_output_lengths(plan.handle, n_small, nout) == -3
+    lens = plan.output_lengths(5000)
+    assert L.dedisp_execute(plan.handle, p16, 5000, p16, int(lens.max()) - 1, None) == -1  # stride
+    # streams and batches refuse a scrunching plan before touching the device
+    h = ctypes.c_void_p()
+    assert L.dedisp_stream_create(plan.handle, ctypes.byref(h)) == -6
+    from paper_1201_5380_amd._native import BeamStruct
+    arr = (BeamStruct * 1)()
+    arr[0].plan = plan.handle.value
+    arr[0].d_in = 1 << 20
+    arr[0].d_out = 1 << 20
+    arr[0].nsamps = 5000
+    assert L.dedisp_batch_create(arr, 1, None, None, ctypes.byref(h)) == -6
+    # off again: every row back to full resolution
+    plan.set_scrunching(None)
+    assert np.all(plan.output_lengths(5000) == 5000 - plan.max_delay)
+    plan.set_scrunching([1, 1, 1, 1])
+    assert np.all(plan.output_lengths(5000) == 5000 - plan.max_delay)
+    assert L.dedisp_stream_create(plan.handle, None) == -1
+
+
+# ---------------------------------------------------------------------------
+# sub-band dedispersion: host logic against the oracle (no GPU needed)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,nsub,ngroup", [("survey", 32, 32), ("survey", 16, 7), ("tiny", 8, 4),
+                                              ("large", 64, 16), ("batch-512", 8, 1)])
+def test_subband_output_lengths_match_oracle(native, name, nsub, ngroup):
+    nchans, nbits, dt, f0, df, ndm, dm_max = WORKLOADS[name]
+    dms = synth.dm_list_linear(ndm, dm_max)
+    plan = Plan(nchans, dt, f0, df, nbits).set_dm_list(dms)
+    plan.set_subband(nsub, ngroup)
+    tab, _ = oracle.delay_table(nchans, dt, f0, df, dms)
+    tnom, _ = oracle.delay_table(nchans, dt, f0, df, oracle.subband_nominal_dms(dms, ngroup))
+    nsamps = 1 << 20
+    _, nout = oracle.subband_lengths(nsamps, nchans, nsub, tnom, tab)
+    assert np.all(plan.output_lengths(nsamps) == nout)
+    assert plan.nout(nsamps) == nout
+    plan.set_subband(0, 0)
+    assert np.all(plan.output_lengths(nsamps) == nsamps - plan.max_delay)
+
+
+def test_subband_validation_precedes_hip(native):
+    L = lib()
+    plan = Plan(64, 64e-6, 1500.0, -1.0, 8)
+    assert L.dedisp_set_subband(plan.handle, 8, 4) == -2                    # no DM list
+    plan.set_dm_list(synth.dm_list_linear(32, 100.0))
+    for nsub, ngroup in ((4, 4), (12, 4), (24, 4), (0, 4), (8, 0), (-8, 2)):
+        assert L.dedisp_set_subband(plan.handle, nsub, ngroup) == -1, (nsub, ngroup)
+    wide = Plan(512, 64e-6, 1500.0, -0.5, 8).set_dm_list([0.0, 10.0])
+    assert L.dedisp_set_subband(wide.handle, 256, 1) == -6                  # 255*256 > 16 bits
+    assert L.dedisp_set_subband(plan.handle, 8, 4) == 0
+    # exclusive with time-scrunching, both ways
+    f = np.array([1] * 16 + [2] * 16, np.int32)
+    assert L.dedisp_set_scrunching(plan.handle, f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == -6
+    p16 = ctypes.c_void_p(1 << 20)
+    assert L.dedisp_execute(plan.handle, p16, 100, p16, 0, None) == -3      # too short
+    lens = plan.output_lengths(5000)
+    assert L.dedisp_execute(plan.handle, p16, 5000, p16, int(lens[0]) - 1, None) == -1
+    assert L.dedisp_execute(plan.handle, ctypes.c_void_p((1 << 20) + 2), 5000, p16, 0, None) == -1
+    h = ctypes.c_void_p()
+    assert L.dedisp_stream_create(plan.handle, ctypes.byref(h)) == -6
+    plan.set_subband(0, 0)
+    plan.set_scrunching(f)
+    assert L.dedisp_set_subband(plan.handle, 8, 4) == -6
+    # a new DM list clears both modes
+    plan.set_dm_list(synth.dm_list_linear(32, 100.0))
+    assert np.all(plan.output_lengths(5000) == 5000 - plan.max_delay)

@@ -1,0 +1,117 @@
+"""GPU parity of sub-band dedispersion (Section 4) against the oracle, bit for bit.
+
+The library runs the corner turn, then step 1 (every sub-band at every
+nominal DM, one grouped launch of the tiled kernel writing 8- or 16-bit sums
+into an intermediate scratch) and step 2 (every nominal DM's trials over the
+sub-band series, a second grouped launch).  Outputs are compared whole with
+the oracle's two-step definition.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1201_5380_amd import Plan, synth, tile_configs
+
+pytestmark = pytest.mark.gpu
+
+SENTINEL = 0x5EEDF00D
+
+
+def _run(plan, packed, nsamps, dev, width):
+    import torch
+    inp = torch.from_numpy(np.ascontiguousarray(packed.reshape(-1))).to(dev)
+    out = torch.full((plan.ndm, width), SENTINEL, dtype=torch.int32, device=dev)
+    plan.execute(inp, nsamps, out=out, out_row_stride=width)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32)
+
+
+def _codes(rng, nsamps, nchans, nbits):
+    if nbits == 2:
+        c = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+        c[::89] = 3
+    else:
+        c = np.clip(np.rint(rng.normal(128, 40, size=(nsamps, nchans))), 0, 255).astype(np.uint8)
+        c[::89] = 255
+    return c
+
+
+@pytest.mark.parametrize("nbits,nchans,nsub,ngroup,ndm,nsamps", [
+    (2, 256, 8, 8, 70, 20011),      # 8-bit intermediate sums (at most 24)
+    (2, 256, 32, 16, 64, 16003),    # 16-bit intermediate sums
+    (8, 128, 16, 5, 43, 15007),     # 8-bit codes: 16-bit sums, last group short
+    (2, 192, 8, 4, 33, 17001),      # 24 sub-bands: zero padding rows in step 2
+])
+def test_subband_every_shape_bit_exact(native, cuda, nbits, nchans, nsub, ngroup, ndm, nsamps):
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    dms = synth.dm_list_linear(ndm, 600.0)
+    rng = np.random.default_rng(nchans * 7 + nsub)
+    codes = _codes(rng, nsamps, nchans, nbits)
+    packed = synth.pack(codes, nbits)
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms)
+    plan.set_subband(nsub, ngroup)
+    want = oracle.dedisperse_subband(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub, ngroup)
+    nout = want.shape[1]
+    assert np.all(plan.output_lengths(nsamps) == nout)
+    width = nout + 3
+    ran = 0
+    seen = set()
+    for cfg in tile_configs():
+        key = tuple(sorted(cfg.items()))
+        if cfg["kind"] != 0 or key in seen:
+            continue
+        seen.add(key)
+        try:
+            plan.set_tile_config(cfg)
+        except Exception:
+            continue
+        got = _run(plan, packed, nsamps, cuda, width)
+        assert np.array_equal(got[:, :nout], want), cfg
+        assert np.all(got[:, nout:] == SENTINEL)
+        ran += 1
+    assert ran >= 3
+
+
+def test_subband_kill_mask_and_direct_reduction(native, cuda):
+    nbits, nchans, nsamps = 2, 512, 15013
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    dms = synth.dm_list_linear(96, 500.0)
+    rng = np.random.default_rng(17)
+    codes = _codes(rng, nsamps, nchans, nbits)
+    packed = synth.pack(codes, nbits)
+    mask = (rng.random(nchans) < 0.75).astype(np.int32)
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms)
+    plan.set_killmask(mask)
+    plan.set_subband(16, 12)
+    want = oracle.dedisperse_subband(packed, nsamps, nchans, nbits, dt, f_top, df, dms, 16, 12,
+                                     mask=mask)
+    got = _run(plan, packed, nsamps, cuda, want.shape[1])
+    assert np.array_equal(got, want)
+    # one trial per nominal DM: the sub-band result is the direct transform
+    plan.set_subband(16, 1)
+    n1 = int(plan.output_lengths(nsamps)[0])
+    got1 = _run(plan, packed, nsamps, cuda, n1)
+    plan.set_subband(0, 0)
+    direct = _run(plan, packed, nsamps, cuda, nsamps - plan.max_delay)
+    assert np.array_equal(got1, direct[:, :n1])
+
+
+def test_survey_beam_subband_full_size(native, cuda):
+    """The benchmark's survey beam with 32-channel sub-bands and 32 trials per
+    nominal DM, whole, against the oracle's two steps."""
+    import torch
+    b = synth.survey_beam()
+    plan = Plan(b.nchans, b.dt, b.f_top, b.df, b.nbits).set_dm_list(b.dms)
+    otab, _ = oracle.delay_table(b.nchans, b.dt, b.f_top, b.df, b.dms)
+    b.inject(lambda i: otab[i])
+    packed = b.packed()
+    plan.set_subband(32, 32)
+    want = oracle.dedisperse_subband(packed, b.nsamps, b.nchans, b.nbits, b.dt, b.f_top, b.df,
+                                     b.dms, 32, 32)
+    nout = want.shape[1]
+    inp = torch.from_numpy(packed.reshape(-1)).to(cuda)
+    out = torch.empty((plan.ndm, nout), dtype=torch.int32, device=cuda)
+    plan.execute(inp, b.nsamps, out=out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want)
