@@ -65,7 +65,9 @@ def _load():
                                          ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_int64, _u32p, ctypes.c_int64,
                                          ctypes.c_int]
-    for f in ("oracle_subband_lengths", "oracle_subband_step1", "oracle_subband_step2",
+    lib.oracle_reduce_output.argtypes = [_u32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_void_p]
+    for f in ("oracle_reduce_output", "oracle_subband_lengths", "oracle_subband_step1", "oracle_subband_step2",
               "oracle_dedisperse_scrunched_points", "oracle_partial_delay", "oracle_delay_table", "oracle_dedisperse",
               "oracle_dedisperse_points", "oracle_max_threads", "oracle_diagonal_dm",
               "oracle_scrunch_factor", "oracle_scrunch", "oracle_dedisperse_values"):
@@ -314,3 +316,18 @@ def subband_effective_delays(nchans, dt, f_top, df, dms, nsub, ngroup):
     first = (np.arange(nchans) // nsub) * nsub
     m = np.arange(len(dms)) // ngroup
     return (tab[:, first] + tab_nom[m] - tab_nom[m][:, first]).astype(np.int64)
+
+
+# ---------------------------------------------------------------- output bit depth
+
+
+def reduce_output(sums, nbits, shift=0):
+    """min(sums >> shift, 2^nbits - 1) as uint8 / uint16 / uint32 (same shape)."""
+    sums = np.ascontiguousarray(sums, dtype=np.uint32)
+    dtype = {8: np.uint8, 16: np.uint16, 32: np.uint32}.get(int(nbits))
+    if dtype is None:
+        raise OracleError("nbits must be 8, 16 or 32")
+    out = np.zeros(sums.shape, dtype=dtype)
+    _check(_load().oracle_reduce_output(_ptr(sums, _u32p), int(sums.size), int(nbits), int(shift),
+                                        out.ctypes.data_as(ctypes.c_void_p)), "reduce_output")
+    return out

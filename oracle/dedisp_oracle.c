@@ -441,6 +441,29 @@ int oracle_subband_step2(const uint32_t* S, int nsb, int nnom, int64_t len1, int
     return ORACLE_OK;
 }
 
+/* ------------------------------------------------------------------------
+ * Output bit depth (Section 4: the final output is written with a chosen
+ * number of bits per sample).  The paper does not say how a sum is brought
+ * to 8 or 16 bits; the reading fixed here is a right shift by `shift` bits
+ * followed by saturation at the largest value of the width:
+ *   out = min(sum >> shift, 2^nbits - 1),
+ * so an output is exact whenever the shifted sum fits.
+ * ------------------------------------------------------------------------ */
+int oracle_reduce_output(const uint32_t* sums, int64_t n, int nbits, int shift, void* out)
+{
+    if (!sums || !out || n < 0 || shift < 0 || shift > 31) return ORACLE_BAD_ARG;
+    if (nbits != 8 && nbits != 16 && nbits != 32) return ORACLE_BAD_ARG;
+    const uint64_t top = nbits == 32 ? 0xFFFFFFFFull : ((1ull << nbits) - 1ull);
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t v = (uint64_t)(sums[i] >> shift);
+        if (v > top) v = top;
+        if (nbits == 8) ((uint8_t*)out)[i] = (uint8_t)v;
+        else if (nbits == 16) ((uint16_t*)out)[i] = (uint16_t)v;
+        else ((uint32_t*)out)[i] = (uint32_t)v;
+    }
+    return ORACLE_OK;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

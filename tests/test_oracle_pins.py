@@ -633,3 +633,26 @@ def test_subband_kill_mask_and_pulse():
     assert out[28, t0] == 3 * nchans
     out[28, t0] = 0
     assert out.max() < 3 * nchans
+
+
+# ---------------------------------------------------------------------------
+# output bit depth (reading: shift right, then saturate)
+# ---------------------------------------------------------------------------
+
+def test_reduce_output_definition():
+    rng = np.random.default_rng(12)
+    sums = np.concatenate([rng.integers(0, 1 << 20, 5000), [0, 1, 255, 256, 65535, 65536,
+                                                             (1 << 32) - 1]]).astype(np.uint32)
+    for nbits, top in ((8, 255), (16, 65535), (32, (1 << 32) - 1)):
+        for shift in (0, 1, 4, 12, 31):
+            got = oracle.reduce_output(sums, nbits, shift)
+            want = np.minimum(sums.astype(np.uint64) >> shift, top)
+            assert np.array_equal(got.astype(np.uint64), want), (nbits, shift)
+    # exact whenever the shifted sum fits; monotone; 32 bits and no shift is the identity
+    small = rng.integers(0, 256, 1000).astype(np.uint32)
+    assert np.array_equal(oracle.reduce_output(small, 8), small.astype(np.uint8))
+    assert np.array_equal(oracle.reduce_output(sums, 32), sums)
+    srt = np.sort(sums)
+    assert np.all(np.diff(oracle.reduce_output(srt, 8, 3).astype(np.int64)) >= 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.reduce_output(sums, 12)
