@@ -67,7 +67,15 @@ def _load():
                                          ctypes.c_int]
     lib.oracle_reduce_output.argtypes = [_u32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_void_p]
-    for f in ("oracle_reduce_output", "oracle_subband_lengths", "oracle_subband_step1", "oracle_subband_step2",
+    lib.oracle_tree.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                _u32p, _i32p]
+    lib.oracle_tree_combine_tables.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_int, _f64p, ctypes.c_int,
+                                               _i32p, _i32p]
+    lib.oracle_tree_combine.argtypes = [_u32p, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _i32p,
+                                        _i32p, ctypes.c_int, ctypes.c_int64, _u32p]
+    for f in ("oracle_tree", "oracle_tree_combine_tables", "oracle_tree_combine",
+              "oracle_reduce_output", "oracle_subband_lengths", "oracle_subband_step1", "oracle_subband_step2",
               "oracle_dedisperse_scrunched_points", "oracle_partial_delay", "oracle_delay_table", "oracle_dedisperse",
               "oracle_dedisperse_points", "oracle_max_threads", "oracle_diagonal_dm",
               "oracle_scrunch_factor", "oracle_scrunch", "oracle_dedisperse_values"):
@@ -330,4 +338,54 @@ def reduce_output(sums, nbits, shift=0):
     out = np.zeros(sums.shape, dtype=dtype)
     _check(_load().oracle_reduce_output(_ptr(sums, _u32p), int(sums.size), int(nbits), int(shift),
                                         out.ctypes.data_as(ctypes.c_void_p)), "reduce_output")
+    return out
+
+
+# ---------------------------------------------------------------- tree dedispersion
+
+
+def tree(packed, nsamps, nchans, nbits, k, mask=None):
+    """k steps of the tree algorithm: uint32 [nchans][nsamps - (2^k - 1)]; row b*2^k + d'
+    holds the block of 2^k channels starting at b*2^k at tree DM d'."""
+    packed = np.ascontiguousarray(packed, dtype=np.uint8).reshape(-1)
+    if packed.size < int(nsamps) * nchans * nbits // 8:
+        raise OracleError("input too short")
+    n_out = int(nsamps) - ((1 << int(k)) - 1)
+    if n_out <= 0:
+        raise OracleError("too few samples")
+    out = np.zeros((nchans, n_out), dtype=np.uint32)
+    m, mp = _mask_arg(mask, nchans)
+    _check(_load().oracle_tree(_ptr(packed, _u8p), int(nsamps), nchans, nbits, int(k),
+                               _ptr(out, _u32p), mp), "tree")
+    return out
+
+
+def tree_combine_tables(nchans, dt, f_top, df, nsub, dms):
+    """(d'_n(d), dt''_n(d)) as int32 [ndm][nchans / nsub] each."""
+    dms = np.ascontiguousarray(dms, dtype=np.float64)
+    nsb = nchans // nsub
+    dp = np.zeros((len(dms), nsb), dtype=np.int32)
+    dd = np.zeros((len(dms), nsb), dtype=np.int32)
+    _check(_load().oracle_tree_combine_tables(nchans, dt, f_top, df, int(nsub), _ptr(dms, _f64p),
+                                              len(dms), _ptr(dp, _i32p), _ptr(dd, _i32p)),
+           "tree_combine_tables")
+    return dp, dd
+
+
+def dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub, mask=None):
+    """Piecewise linear tree (Section 3): stage 1 = log2(nsub) tree steps, stage 2 = the
+    sub-band combination.  uint32 [ndm][nout]."""
+    k = int(nsub).bit_length() - 1
+    if (1 << k) != int(nsub):
+        raise OracleError("nsub must be a power of two")
+    S = tree(packed, nsamps, nchans, nbits, k, mask=mask)
+    len1 = S.shape[1]
+    dp, dd = tree_combine_tables(nchans, dt, f_top, df, nsub, dms)
+    nout = len1 - int(dd.max())
+    if nout <= 0:
+        raise OracleError("too few samples")
+    out = np.zeros((len(dms), nout), dtype=np.uint32)
+    _check(_load().oracle_tree_combine(_ptr(S, _u32p), nchans, len1, int(nsub), _ptr(dp, _i32p),
+                                       _ptr(dd, _i32p), len(dms), nout, _ptr(out, _u32p)),
+           "tree_combine")
     return out

@@ -26,6 +26,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 #ifdef _OPENMP
 #include <omp.h>
@@ -435,6 +436,134 @@ int oracle_subband_step2(const uint32_t* S, int nsb, int nnom, int64_t len1, int
             uint32_t sum = 0;
             for (int n = 0; n < nsb; ++n)
                 sum += S[((size_t)n * nnom + m) * (size_t)len1 + (size_t)(t + dl[n * nsub])];
+            row[t] = sum;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Tree dedispersion (Section 3).  Step i (radix r = 2^i) builds, out of
+ * place, A^{i+1}[2v][t]   = A^i[Phi(r, 2v)][t] + A^i[Phi(r, 2v+1)][t + Theta(i, 2v)]
+ *            A^{i+1}[2v+1][t] = A^i[Phi(r, 2v)][t] + A^i[Phi(r, 2v+1)][t + Theta(i, 2v+1)]
+ * with the delay function Theta(i, v) = ((v mod 2^{i+1}) + 1) / 2 and the
+ * shuffle Phi(r, v) = (v mod 2) r + v/2 + (v/(2r)) r, divisions truncating.
+ * After k steps, rows b*2^k + d' (d' < 2^k) hold the tree transform of the
+ * block of 2^k channels starting at b*2^k at tree DM d'.  Reading fixed here:
+ * a step is defined where every sample it reads exists, so A^{i+1} has 2^i
+ * fewer samples than A^i and k steps leave nsamps - (2^k - 1).
+ * ------------------------------------------------------------------------ */
+
+static int oracle_tree_theta(int i, int v) { return ((v % (1 << (i + 1))) + 1) / 2; }
+
+static int oracle_tree_phi(int r, int v) { return (v % 2) * r + v / 2 + (v / (2 * r)) * r; }
+
+/* k steps of the tree over every channel (nchans a multiple of 2^k), with an
+ * optional 0/1 kill mask applied to the input: out [nchans][nsamps - (2^k - 1)]. */
+int oracle_tree(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k,
+                uint32_t* out, const int32_t* mask)
+{
+    if (!in || !out || k < 0 || k > 20 || nchans <= 0 || nchans % (1 << k)) return ORACLE_BAD_ARG;
+    if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
+    const int64_t n_out = nsamps - ((1 << k) - 1);
+    if (n_out <= 0) return ORACLE_TOO_FEW_SAMPLES;
+    const size_t cells = (size_t)nchans * (size_t)nsamps;
+    uint32_t* a = (uint32_t*)malloc(cells * sizeof(uint32_t));
+    uint32_t* b = (uint32_t*)malloc(cells * sizeof(uint32_t));
+    if (!a || !b) {
+        free(a);
+        free(b);
+        return ORACLE_BAD_ARG;
+    }
+    /* A^0 = the input, channel-major */
+    for (int v = 0; v < nchans; ++v)
+        for (int64_t t = 0; t < nsamps; ++t)
+            a[(size_t)v * nsamps + t] = (mask ? (uint32_t)mask[v] : 1u) * oracle_sample(in, nchans, nbits, t, v);
+    int64_t len = nsamps;
+    for (int i = 0; i < k; ++i) {
+        const int r = 1 << i;
+        const int64_t next = len - r;       /* largest Theta(i, .) is 2^i */
+        for (int v = 0; v < nchans / 2; ++v) {
+            const uint32_t* lo = a + (size_t)oracle_tree_phi(r, 2 * v) * nsamps;
+            const uint32_t* hi = a + (size_t)oracle_tree_phi(r, 2 * v + 1) * nsamps;
+            const int th0 = oracle_tree_theta(i, 2 * v), th1 = oracle_tree_theta(i, 2 * v + 1);
+            uint32_t* o0 = b + (size_t)(2 * v) * nsamps;
+            uint32_t* o1 = b + (size_t)(2 * v + 1) * nsamps;
+            for (int64_t t = 0; t < next; ++t) {
+                o0[t] = lo[t] + hi[t + th0];
+                o1[t] = lo[t] + hi[t + th1];
+            }
+        }
+        uint32_t* tmp = a;
+        a = b;
+        b = tmp;
+        len = next;
+    }
+    for (int v = 0; v < nchans; ++v)
+        for (int64_t t = 0; t < n_out; ++t)
+            out[(size_t)v * n_out + t] = a[(size_t)v * nsamps + t];
+    free(a);
+    free(b);
+    return ORACLE_OK;
+}
+
+/* Stage 2 of the piecewise linear tree (Section 3, eq. combining_subbands):
+ * with sub-bands of nsub = 2^k channels (sub-band n starting at channel
+ * v_n = n*nsub; v_{nsb} = nchans is the channel just past the band),
+ *   d'_n(d)  = round(DM(d) [DeltaT(v_{n+1}) - DeltaT(v_n)])
+ *   dt''_n(d) = round(DM(d) * sum over m < n of [DeltaT(v_{m+1}) - DeltaT(v_m)])
+ * (the sum runs over the sub-bands before n, so each sub-band's series, which
+ * the tree aligns on its first channel, is placed at the delay of that
+ * channel), both evaluated in binary64 in this order, and
+ *   D[d][t] = sum over n of S[n*nsub + d'_n(d)][t + dt''_n(d)]
+ * for t < len1 - (largest dt''), S being the k-step tree output of length
+ * len1.  Every d'_n(d) must be below nsub (DMs up to the piecewise diagonal);
+ * the tables dprime and dpp [ndm][nsb] are returned for inspection. */
+int oracle_tree_combine_tables(int nchans, double dt, double f_top, double df, int nsub,
+                               const double* dms, int ndm, int32_t* dprime, int32_t* dpp)
+{
+    if (!dms || !dprime || !dpp || nsub <= 0 || nchans % nsub) return ORACLE_BAD_ARG;
+    if (oracle_check_params(nchans, dt, f_top, df, 8) != ORACLE_OK) return ORACLE_BAD_ARG;
+    if (!(f_top + (double)nchans * df > 0.0)) return ORACLE_BAD_ARG;
+    const int nsb = nchans / nsub;
+    const double inv_top2 = 1.0 / (f_top * f_top);
+    const double scale = ORACLE_K_DM / dt;
+    for (int d = 0; d < ndm; ++d) {
+        double acc = 0.0;
+        for (int n = 0; n < nsb; ++n) {
+            const double fa = f_top + (double)(n * nsub) * df;
+            const double fb = f_top + (double)((n + 1) * nsub) * df;
+            const double step = scale * (1.0 / (fb * fb) - inv_top2) - scale * (1.0 / (fa * fa) - inv_top2);
+            const double dp = round(dms[d] * step);
+            const double dd = round(dms[d] * acc);
+            if (!(dp >= 0.0) || dp >= (double)nsub || !(dd >= 0.0) || dd > 2.0e9) return ORACLE_BAD_ARG;
+            dprime[(size_t)d * nsb + n] = (int32_t)dp;
+            dpp[(size_t)d * nsb + n] = (int32_t)dd;
+            acc += step;
+        }
+    }
+    return ORACLE_OK;
+}
+
+int oracle_tree_combine(const uint32_t* S, int nchans, int64_t len1, int nsub,
+                        const int32_t* dprime, const int32_t* dpp, int ndm, int64_t nout,
+                        uint32_t* out)
+{
+    if (!S || !dprime || !dpp || !out || nsub <= 0 || nchans % nsub || nout <= 0) return ORACLE_BAD_ARG;
+    const int nsb = nchans / nsub;
+    for (int d = 0; d < ndm; ++d)
+        for (int n = 0; n < nsb; ++n)
+            if (nout + dpp[(size_t)d * nsb + n] > len1 || dprime[(size_t)d * nsb + n] >= nsub)
+                return ORACLE_BAD_ARG;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int d = 0; d < ndm; ++d) {
+        uint32_t* row = out + (size_t)d * (size_t)nout;
+        for (int64_t t = 0; t < nout; ++t) {
+            uint32_t sum = 0;
+            for (int n = 0; n < nsb; ++n) {
+                const int32_t dp = dprime[(size_t)d * nsb + n];
+                sum += S[((size_t)n * nsub + dp) * (size_t)len1 + (size_t)(t + dpp[(size_t)d * nsb + n])];
+            }
             row[t] = sum;
         }
     }

@@ -26,7 +26,16 @@ against things other than itself:
   reductions to the direct transform (one trial per nominal DM, one channel
   per sub-band), the delay error within Appendix B's smearing bound (and
   zero at nominal trials), the kill mask, and a pulse on a nominal trial's
-  trail summed whole at its trial and time only.
+  trail summed whole at its trial and time only;
+* tree dedispersion (Section 3): two channels in closed form; the impulse
+  response of k steps -- every channel once per tree DM row, at delays equal
+  to a recursion on indices derived from the steps' shuffle and delay
+  functions, from 0 to d' and never decreasing, near the linear trail --; the
+  full-band tree against the push brute force at those delays (DM 0 = the
+  channel sum); the piecewise linear tree against the brute force at its
+  composed delays, within Appendix A's bound, and with one sub-band reducing
+  to picking a tree row;
+* the reduced output bit depth by its invariants.
 """
 from fractions import Fraction
 
@@ -656,3 +665,145 @@ def test_reduce_output_definition():
     assert np.all(np.diff(oracle.reduce_output(srt, 8, 3).astype(np.int64)) >= 0)
     with pytest.raises(oracle.OracleError):
         oracle.reduce_output(sums, 12)
+
+
+# ---------------------------------------------------------------------------
+# tree dedispersion (Section 3)
+# ---------------------------------------------------------------------------
+
+def _tree_impulse_delays(nchans, k):
+    """For every (tree DM d', channel c) of each block, the delay at which the
+    k-step tree takes channel c: from impulse inputs, requiring that every
+    channel contributes exactly one unit sample to every row of its block."""
+    n = 3 * (1 << k) + 8
+    ts = (1 << k) + 2
+    B = 1 << k
+    delays = np.full((nchans, B), -1, dtype=np.int64)   # [row][channel within block]
+    for c in range(nchans):
+        codes = np.zeros((n, nchans), np.uint8)
+        codes[ts, c] = 1
+        out = oracle.tree(codes, n, nchans, 8, k)
+        blk = c // B
+        for row in range(nchans):
+            nz = np.nonzero(out[row])[0]
+            if row // B != blk:
+                assert nz.size == 0
+                continue
+            assert nz.size == 1 and out[row, nz[0]] == 1, (c, row)
+            delays[row, c % B] = ts - nz[0]
+    return delays
+
+
+def test_tree_two_channels_closed_form():
+    """One step on two channels: D'_0 = A0[t] + A1[t], D'_1 = A0[t] + A1[t+1]."""
+    rng = np.random.default_rng(2)
+    codes = rng.integers(0, 256, size=(50, 2), dtype=np.uint8)
+    out = oracle.tree(codes, 50, 2, 8, 1)
+    a = codes.astype(np.uint32)
+    assert np.array_equal(out[0], a[:49, 0] + a[:49, 1])
+    assert np.array_equal(out[1], a[:49, 0] + a[1:50, 1])
+
+
+def _tree_delay_recursion(k):
+    """Delays of the k-step tree from the structure of its steps, on indices
+    only: the last step joins two half-blocks of 2^(k-1) channels (its shuffle
+    takes tree DM v of the first and of the second half) and delays the second
+    by Theta = v for output 2v and v + 1 for output 2v + 1, so
+    delay_k(2v + b, c) = delay_{k-1}(v, c)                 for c in the first half,
+                         v + b + delay_{k-1}(v, c - half)   for c in the second."""
+    if k == 0:
+        return np.zeros((1, 1), dtype=np.int64)
+    sub = _tree_delay_recursion(k - 1)
+    half = 1 << (k - 1)
+    out = np.zeros((2 * half, 2 * half), dtype=np.int64)
+    for v in range(half):
+        for b in (0, 1):
+            out[2 * v + b, :half] = sub[v]
+            out[2 * v + b, half:] = v + b + sub[v]
+    return out
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_tree_is_a_direct_sum_along_staircase_trails(k):
+    """Every channel enters every tree DM row of its block exactly once, at the
+    delay the recursion above gives; the delays start at 0, end at d' on the
+    block's last channel, never decrease, and approximate the linear trail
+    d' c / (N - 1) of the paper's eq. tree to within half a sample per step
+    (the rounding is a staircase, not the nearest integer, beyond 4 channels)."""
+    B = 1 << k
+    nchans = 2 * B
+    delays = _tree_impulse_delays(nchans, k)
+    rec = _tree_delay_recursion(k)
+    c = np.arange(B)
+    for row in range(nchans):
+        dprime = row % B
+        dl = delays[row]
+        assert np.array_equal(dl, rec[dprime]), (row, dl, rec[dprime])
+        assert dl[0] == 0 and dl[-1] == dprime
+        assert np.all(np.diff(dl) >= 0)
+        assert np.all(np.abs(dl - dprime * c / (B - 1)) <= 0.5 * k + 1e-12)
+    if k <= 2:   # up to 4 channels the staircase is the nearest-integer trail
+        for d in range(B):
+            assert np.array_equal(rec[d], np.floor(d * c / (B - 1) + 0.5).astype(np.int64))
+
+
+def test_tree_full_band_equals_direct_sum_at_its_delays():
+    """The full tree over 64 channels against the push brute force at the
+    impulse-derived delays, on random data (linearity plus the single-sample
+    impulse response make the tree this direct sum)."""
+    k, nchans, nsamps = 6, 64, 400
+    delays = _tree_impulse_delays(nchans, k)
+    rng = np.random.default_rng(8)
+    codes = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+    got = oracle.tree(synth.pack(codes, 2), nsamps, nchans, 2, k)
+    want = _push_brute_force(codes.astype(np.int64), delays)
+    assert np.array_equal(got.astype(np.int64), want[:, : got.shape[1]])
+    # DM 0 is the channel sum
+    assert np.array_equal(got[0], codes.sum(axis=1, dtype=np.uint32)[: got.shape[1]])
+
+
+def test_piecewise_tree_reductions_and_error_bound():
+    nchans, nsamps, nsub = 64, 3000, 16
+    prm = dict(dt=64e-6, f_top=1581.8, df=-400.0 / nchans)
+    dT = oracle.partial_delay(nchans, **prm)
+    # the piecewise diagonal (eq. tree_dm_limit with the channel past the band)
+    fb = prm["f_top"] + nchans * prm["df"]
+    fa = prm["f_top"] + (nchans - nsub) * prm["df"]
+    dTN = 4.148808e3 / prm["dt"] * (1 / fb ** 2 - 1 / prm["f_top"] ** 2)
+    dTa = 4.148808e3 / prm["dt"] * (1 / fa ** 2 - 1 / prm["f_top"] ** 2)
+    diag = (nsub - 0.5) / (dTN - dTa)
+    dms = np.linspace(0.0, diag * 0.999, 24)
+    rng = np.random.default_rng(5)
+    codes = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+    packed = synth.pack(codes, 2)
+    out = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, 2, prm["dt"], prm["f_top"],
+                                           prm["df"], dms, nsub)
+    # it is the direct sum at the composed delays E[d][c] = dt''_n(d) + tree delay
+    dp, dd = oracle.tree_combine_tables(nchans, prm["dt"], prm["f_top"], prm["df"], nsub, dms)
+    tdel = _tree_impulse_delays(nsub, int(nsub).bit_length() - 1)     # [d'][j]
+    E = np.zeros((len(dms), nchans), dtype=np.int64)
+    for d in range(len(dms)):
+        for c in range(nchans):
+            n, j = divmod(c, nsub)
+            E[d, c] = dd[d, n] + tdel[dp[d, n], j]
+    bf = _push_brute_force(codes.astype(np.int64), E)
+    assert np.array_equal(out.astype(np.int64), bf[:, : out.shape[1]])
+    # DM 0 is the channel sum; trail error within Appendix A's bound (in
+    # samples) plus the roundings (tree, d', dt'') and the one-channel slope
+    # difference between d' over nsub channels and the tree's nsub - 1 steps
+    assert np.array_equal(out[0], codes.sum(axis=1, dtype=np.uint32)[: out.shape[1]])
+    tab, _ = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], dms)
+    lam = -prm["df"] / prm["f_top"] * nchans
+    for d in range(len(dms)):
+        t_tree = 0.75 * dms[d] * 4.148808e3 / prm["f_top"] ** 2 * (nsub / nchans) ** 2 \
+            * lam ** 2 / (1 - lam) ** 4 / prm["dt"]
+        bound = t_tree + 0.5 + 0.5 + 0.5 + dp[d].max() / nsub + 0.5
+        assert np.abs(E[d] - tab[d]).max() <= bound, (d, np.abs(E[d] - tab[d]).max(), bound)
+    # one sub-band spanning the band: stage 2 picks tree row d'_0(d) unshifted
+    dp1, dd1 = oracle.tree_combine_tables(nchans, prm["dt"], prm["f_top"], prm["df"], nchans,
+                                          dms[:4] * 0.2)
+    full = oracle.tree(packed, nsamps, nchans, 2, 6)
+    one = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, 2, prm["dt"], prm["f_top"],
+                                           prm["df"], dms[:4] * 0.2, nchans)
+    for d in range(4):
+        assert dd1[d, 0] == 0 and np.array_equal(one[d], full[dp1[d, 0], : one.shape[1]])
