@@ -155,6 +155,42 @@ def bench_subband(torch, dev, plan, inp, nsamps, steps, direct_ms, nsub=32, ngro
             "speedup_vs_direct": direct_ms / ms}
 
 
+def bench_tree(torch, dev, beam, inp, nsamps, steps, nsub=32):
+    """The survey beam through the piecewise linear tree (Section 3) with
+    32-channel sub-bands, for the trials up to the tree's diagonal DM, against
+    the direct transform of the same trials."""
+    from paper_1201_5380_amd import Plan
+    k = 4.148808e3 / beam.dt
+    fb = beam.f_top + beam.nchans * beam.df
+    fa = beam.f_top + (beam.nchans - nsub) * beam.df
+    diag = (nsub - 0.5) / (k * (1 / fb ** 2 - 1 / beam.f_top ** 2) - k * (1 / fa ** 2 - 1 / beam.f_top ** 2))
+    dms = beam.dms[beam.dms < diag]
+
+    def timed(plan):
+        nout = int(plan.output_lengths(nsamps)[0])
+        out = torch.empty((plan.ndm, nout), dtype=torch.int32, device=dev)
+        plan.tune(inp, out, nsamps)
+        for _ in range(2):
+            plan.execute(inp, nsamps, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            plan.execute(inp, nsamps, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, nout
+
+    direct = Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(dms)
+    d_ms, _ = timed(direct)
+    tree = Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(dms).set_tree(nsub)
+    t_ms, nout = timed(tree)
+    return {"workload": f"survey beam, {len(dms)} trials up to the piecewise tree's diagonal "
+                        f"DM {diag:.2f}, sub-bands of {nsub} channels",
+            "ms": t_ms, "nout": nout, "outputs_per_s": len(dms) * nout / (t_ms * 1e-3),
+            "direct_ms_same_trials": d_ms, "speedup_vs_direct": d_ms / t_ms}
+
+
 def bench_serve(torch, dev, seconds):
     """32 streams, chunks of U[2^14, 2^18] samples arriving as a Poisson process at
     4x real time per stream (aggregate ~14.4 chunks/s), 64 GB admission budget."""
@@ -370,6 +406,8 @@ def main():
         torch.cuda.empty_cache()
         result["subband"] = bench_subband(torch, dev, plan, inp, nsamps,
                                           max(3, args.steps // 2), mean_ms)
+        torch.cuda.empty_cache()
+        result["tree"] = bench_tree(torch, dev, beam, inp, nsamps, max(3, args.steps // 2))
         torch.cuda.empty_cache()
         result["batched"] = bench_batch(torch, dev, max(3, args.steps // 4))
         torch.cuda.empty_cache()

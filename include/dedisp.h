@@ -117,7 +117,8 @@ dedisp_status dedisp_get_delay_table(dedisp_plan plan, int32_t* host_out);
 /* The transform over one resident block of input.
  * d_in: device, nsamps rows of the input layout above.
  * d_out: device, ndm rows of out_row_stride (0 = nsamps - max_delay, or
- * the longest row under time-scrunching) uint32 elements; only
+ * the longest row under time-scrunching) elements of the plan's output
+ * format (uint32 unless dedisp_set_output_format chose 8 or 16 bits); only
  * t < nsamps - max_delay is written (under time-scrunching, the row lengths
  * dedisp_get_output_lengths gives).
  * Errors: INVALID_ARG (null pointer, stride too small), NO_DM_LIST,
@@ -162,6 +163,42 @@ dedisp_status dedisp_set_scrunching(dedisp_plan plan, const int32_t* factors);
  * array `nout` (ndm entries): nsamps - max_delay without scrunching.
  * Host-only.  Errors: INVALID_ARG, NO_DM_LIST, TOO_FEW_SAMPLES. */
 dedisp_status dedisp_get_output_lengths(dedisp_plan plan, size_t nsamps, size_t* nout);
+
+/* ------------------------------------------- piecewise linear tree */
+
+/* Section 3: tree dedispersion over sub-bands of nsub channels (a power of
+ * two in [8, 128] dividing nchans), combined into the plan's DM trials.
+ * Stage 1 applies the tree algorithm's first log2(nsub) steps -- the
+ * out-of-place updates with the delay function Theta and the shuffle Phi --
+ * to every sub-band, giving its series at the nsub tree DMs
+ * (linear trails from 0 to d' samples across the sub-band).  Stage 2 sums,
+ * for each trial d, sub-band n's series at tree DM
+ * d'_n(d) = round(DM(d) [DeltaT(v_{n+1}) - DeltaT(v_n)]) delayed by
+ * dt''_n(d) = round(DM(d) * sum over m < n of [DeltaT(v_{m+1}) - DeltaT(v_m)])
+ * (v_n = n*nsub; v_{nchans/nsub} = nchans is the channel just past the band),
+ * evaluated in binary64 in that order.  An approximation of the direct
+ * transform whose error Appendix A bounds.  Outputs exist for
+ * t < nsamps - (nsub - 1) - (largest dt''); dedisp_get_output_lengths gives
+ * it.  Every trial must keep d'_n(d) < nsub (DMs up to the piecewise
+ * diagonal), else UNSUPPORTED.  nsub = 0 switches the mode off; a new DM
+ * list does too.  Excludes time-scrunching and sub-band mode; streams and
+ * batches reject such a plan.  Needs 4-byte aligned input rows and a band
+ * whose edge past the last channel is above zero frequency.
+ * Errors: INVALID_ARG, NO_DM_LIST, UNSUPPORTED. */
+dedisp_status dedisp_set_tree(dedisp_plan plan, int nsub);
+
+/* ------------------------------------------------------ output format */
+
+/* Output width (Section 4: the final output is written with a chosen number
+ * of bits per sample): nbits = 32 (default), 16 or 8, and every output is
+ * min(sum >> shift, 2^nbits - 1) -- exact whenever the shifted sum fits
+ * (with 2-bit data a 16-bit output is exact up to 21845 channels).  d_out of
+ * every compute call then holds uint8 / uint16 / uint32 elements, and row
+ * strides count those elements.  Applies to execute, streams, batches,
+ * time-scrunching and sub-band mode alike.  Host-only.
+ * Errors: INVALID_ARG (nbits not 8/16/32, shift outside [0, 31]). */
+dedisp_status dedisp_set_output_format(dedisp_plan plan, int nbits, int shift);
+dedisp_status dedisp_get_output_format(dedisp_plan plan, int* nbits, int* shift);
 
 /* ----------------------------------------------- sub-band dedispersion */
 

@@ -65,6 +65,9 @@ SIGNATURES = {
     "dedisp_set_scrunching": (_i, [_vp, _pi32]),
     "dedisp_get_output_lengths": (_i, [_vp, _sz, _psz]),
     "dedisp_set_subband": (_i, [_vp, _i, _i]),
+    "dedisp_set_tree": (_i, [_vp, _i]),
+    "dedisp_set_output_format": (_i, [_vp, _i, _i]),
+    "dedisp_get_output_format": (_i, [_vp, _pi, _pi]),
     "dedisp_tile_config_count": (_i, []),
     "dedisp_tile_config_get": (_i, [_i, _PTC]),
     "dedisp_set_tile_config": (_i, [_vp, _PTC]),

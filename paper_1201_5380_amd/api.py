@@ -3,7 +3,8 @@
 Thin wrappers that marshal torch tensors (device memory) and streams into the
 library's plain-pointer entry points; every step of the transform runs in the
 HIP kernels.  Output buffers are torch.int32 tensors holding the library's
-uint32 sums (every sum is below 2^31: at most 255 * nchans).
+uint32 sums (every sum is below 2^31: at most 255 * nchans), or uint8 /
+int16 (holding uint16) tensors under a reduced output format.
 """
 from __future__ import annotations
 
@@ -75,6 +76,7 @@ class Plan:
         self.ndm = int(arr.shape[0])
         self._scrunched = False
         self._subband = False
+        self._tree = False
         return self
 
     def set_killmask(self, mask):
@@ -117,6 +119,24 @@ class Plan:
         self._scrunched = bool((f > 1).any())
         return self
 
+    def set_output_format(self, nbits: int = 32, shift: int = 0):
+        """Outputs as min(sum >> shift, 2^nbits - 1) in uint8 / uint16 / uint32."""
+        check(lib().dedisp_set_output_format(self._h, int(nbits), int(shift)),
+              "dedisp_set_output_format")
+        self.out_nbits, self.out_shift = int(nbits), int(shift)
+        return self
+
+    def output_dtype(self):
+        """torch dtype of output buffers (uint16 outputs are held as int16)."""
+        import torch
+        return {8: torch.uint8, 16: torch.int16, 32: torch.int32}[getattr(self, "out_nbits", 32)]
+
+    def set_tree(self, nsub: int):
+        """Piecewise linear tree over sub-bands of nsub channels (0 = off)."""
+        check(lib().dedisp_set_tree(self._h, int(nsub)), "dedisp_set_tree")
+        self._tree = bool(nsub)
+        return self
+
     def set_subband(self, nsub: int, ngroup: int):
         """Sub-band dedispersion with nsub channels per sub-band and ngroup
         trials per nominal DM; (0, 0) switches it off."""
@@ -154,13 +174,14 @@ class Plan:
 
     def nout(self, nsamps: int) -> int:
         """Longest output row for nsamps input rows."""
-        if getattr(self, "_scrunched", False) or getattr(self, "_subband", False):
+        if getattr(self, "_scrunched", False) or getattr(self, "_subband", False) or \
+                getattr(self, "_tree", False):
             return int(self.output_lengths(nsamps).max())
         return int(nsamps) - self.max_delay
 
     def alloc_output(self, nsamps: int, device="cuda"):
         import torch
-        return torch.empty((self.ndm, self.nout(nsamps)), dtype=torch.int32, device=device)
+        return torch.empty((self.ndm, self.nout(nsamps)), dtype=self.output_dtype(), device=device)
 
     def _check_input(self, inp, nsamps):
         if nsamps is None:

@@ -403,9 +403,11 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
     d.rowmap = nullptr;
     d.ngroups = 1;
     d.ndm_last = static_cast<int>(p->dms.size());
-    d.out_bytes = 4;
     d.out = out;
-    d.out_stride = stride;
+    d.out_bytes = p->out_nbits / 8;
+    d.out_shift = p->out_shift;
+    // narrow outputs: row stride in bytes
+    d.out_stride = d.out_bytes == 4 ? stride : stride * d.out_bytes;
     d.table = p->d_table;
     d.chanmap = p->d_chanmap;
     d.mask = p->d_mask;
@@ -497,6 +499,18 @@ void write_cache(const char* path, const std::map<std::string, std::vector<doubl
         f << "}\n";
     }
     std::rename(tmp.c_str(), path);
+}
+
+void destroy_tree(dedisp_plan p)
+{
+    if (p->d_tree_rows || p->d_tree_delay) (void)hipDeviceSynchronize();
+    if (p->d_tree_rows) (void)hipFree(p->d_tree_rows);
+    if (p->d_tree_delay) (void)hipFree(p->d_tree_delay);
+    p->d_tree_rows = p->d_tree_delay = nullptr;
+    p->tree_rows.clear();
+    p->tree_delay.clear();
+    p->tree_nsub = 0;
+    p->tree_maxdelay = 0;
 }
 
 void destroy_subband(dedisp_plan p)
@@ -624,6 +638,7 @@ dedisp_status dedisp_plan_create(dedisp_plan* out, int nchans, double dt_s, doub
 void dedisp_plan_destroy(dedisp_plan p)
 {
     if (!p) return;
+    destroy_tree(p);
     destroy_subband(p);
     destroy_groups(p);
     free_device(p);
@@ -641,6 +656,7 @@ dedisp_status dedisp_set_dm_list(dedisp_plan p, const double* dms, int ndm)
     int mx = 0;
     if (!build_delay_table(*p, dms, ndm, table, mx))
         return fail(DEDISP_ERR_INVALID_ARG, "a delay does not fit in int32");
+    destroy_tree(p);
     destroy_subband(p);
     destroy_groups(p);
     free_device(p);
@@ -932,11 +948,100 @@ static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsa
     d2.ngroups = nnom;
     d2.g_xc = static_cast<long long>(nsb_p) * pitch2;
     d2.out = d_out;
-    d2.out_bytes = 4;
-    d2.out_stride = static_cast<long long>(stride);
-    d2.g_out = static_cast<long long>(ngroup) * static_cast<long long>(stride);
+    d2.out_bytes = p->out_nbits / 8;
+    d2.out_shift = p->out_shift;
+    {
+        const long long unit = d2.out_bytes == 4 ? 1 : d2.out_bytes;   // narrow: bytes
+        d2.out_stride = static_cast<long long>(stride) * unit;
+        d2.g_out = static_cast<long long>(ngroup) * static_cast<long long>(stride) * unit;
+    }
     e = lp2.shape.kind == 0 ? dedisp::launch_tiled(d2, lp2.shape, lp2.lds, hs)
                             : dedisp::launch_untiled_xc(d2, s2->fmt, hs);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return DEDISP_OK;
+}
+
+// Piecewise linear tree: stage-1 length and outputs for nsamps input rows.
+static void tree_lengths(const dedisp_plan_s& p, size_t nsamps, long long& len1, long long& nout)
+{
+    len1 = static_cast<long long>(nsamps) - (p.tree_nsub - 1);
+    nout = len1 - p.tree_maxdelay;
+}
+
+static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps, uint32_t* d_out,
+                                  size_t stride, void* stream)
+{
+    if (nsamps > (1ULL << 40)) return fail(DEDISP_ERR_INVALID_ARG, "nsamps too large");
+    long long len1 = 0, nout = 0;
+    tree_lengths(*p, nsamps, len1, nout);
+    if (len1 <= 0 || nout <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps too short for the tree passes");
+    if (stride == 0) stride = static_cast<size_t>(nout);
+    if (stride < static_cast<size_t>(nout)) return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < nout");
+    if (reinterpret_cast<uintptr_t>(d_in) & 3)
+        return fail(DEDISP_ERR_INVALID_ARG, "tree passes need 4-byte aligned input");
+    dedisp_status st = ensure_device_table(p);
+    if (st != DEDISP_OK) return st;
+    const int nsub = p->tree_nsub, nsb = p->nchans / nsub;
+    if (!p->d_tree_rows) {
+        const size_t bytes = p->tree_rows.size() * sizeof(int32_t);
+        if (hipMalloc(&p->d_tree_rows, bytes) != hipSuccess) {
+            p->d_tree_rows = nullptr;
+            return fail(DEDISP_ERR_OOM, "hipMalloc tree tables");
+        }
+        if (hipMalloc(&p->d_tree_delay, bytes) != hipSuccess) {
+            p->d_tree_delay = nullptr;
+            return fail(DEDISP_ERR_OOM, "hipMalloc tree tables");
+        }
+        HIP_TRY(hipMemcpy(p->d_tree_rows, p->tree_rows.data(), bytes, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_tree_delay, p->tree_delay.data(), bytes, hipMemcpyHostToDevice));
+    }
+    // the tree kernel reads whole tiles past the last sample
+    const long long pitch1 = xc_pitch(static_cast<long long>(nsamps) + dedisp::tree_tile(nsub) + nsub,
+                                      p->fmt, 0);
+    const long long pitch2 = ((2 * len1 + 64) + 63) / 64 * 64;
+    st = ensure_scratch(p->xc, static_cast<size_t>(pitch1) * p->nchans);
+    if (st != DEDISP_OK) return st;
+    st = ensure_scratch(p->sb_xc2, static_cast<size_t>(pitch2) * p->nchans);
+    if (st != DEDISP_OK) return st;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    // corner turn: every channel keeps its row (killed channels are zeros)
+    BeamDesc d0;
+    std::memset(&d0, 0, sizeof(d0));
+    d0.in0 = static_cast<const uint8_t*>(d_in);
+    d0.n0 = d0.nsamps = static_cast<long long>(nsamps);
+    d0.xc = p->xc.ptr;
+    d0.pitch = pitch1;
+    d0.mask = p->d_mask;
+    d0.nact = p->nchans;
+    d0.pad_row = -1;
+    d0.nchans = p->nchans;
+    d0.row_bytes = p->row_bytes;
+    d0.scrunch = 1;
+    d0.ngroups = 1;
+    d0.out_bytes = 4;
+    hipError_t e = dedisp::launch_unpack(d0, p->nbits, p->fmt, hs);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    // stage 1: the tree's first log2(nsub) steps, 16-bit rows n*nsub + d'
+    e = dedisp::launch_tree(d0, p->fmt, nsub, p->sb_xc2.ptr, pitch2, len1, hs);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    // stage 2: every trial sums, over the sub-bands, its tree row at its delay
+    BeamDesc dg;
+    std::memset(&dg, 0, sizeof(dg));
+    dg.xc = p->sb_xc2.ptr;
+    dg.pitch = pitch2;
+    dg.table = p->d_tree_delay;
+    dg.rowsel = p->d_tree_rows;
+    dg.nact = nsb;
+    dg.nchans = nsb;
+    dg.ndm = dg.ndm_last = static_cast<int>(p->dms.size());
+    dg.ngroups = 1;
+    dg.nout = nout;
+    dg.scrunch = 1;
+    dg.out = d_out;
+    dg.out_bytes = p->out_nbits / 8;
+    dg.out_shift = p->out_shift;
+    dg.out_stride = static_cast<long long>(stride) * (dg.out_bytes == 4 ? 1 : dg.out_bytes);
+    e = dedisp::launch_untiled_xc(dg, dedisp::kFmtHalf, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return DEDISP_OK;
 }
@@ -946,6 +1051,7 @@ dedisp_status dedisp_execute(dedisp_plan p, const void* d_in, size_t nsamps, uin
 {
     if (!p || !d_in || !d_out) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
+    if (p->tree_nsub) return execute_tree(p, d_in, nsamps, d_out, stride, stream);
     if (p->sb_step1) return execute_subband(p, d_in, nsamps, d_out, stride, stream);
     if (!p->groups.empty()) return execute_groups(p, d_in, nsamps, d_out, stride, stream);
     // (an internal scrunch-group plan, run on its own while tuning, sums
@@ -981,6 +1087,26 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
 {
     if (!p || !d_in || !d_out) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
+    if (p->tree_nsub) {
+        // the tree's passes have one shape each: time the transform
+        hipStream_t hs = static_cast<hipStream_t>(stream);
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        dedisp_status rc = dedisp_execute(p, d_in, nsamps, d_out, stride, stream);
+        float ms = 0.f;
+        if (rc == DEDISP_OK) {
+            HIP_TRY(hipEventRecord(e0, hs));
+            rc = dedisp_execute(p, d_in, nsamps, d_out, stride, stream);
+            HIP_TRY(hipEventRecord(e1, hs));
+            HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (best_ms) *best_ms = ms;
+        return rc;
+    }
     if (p->sb_step1) {
         // each pass in turn: time whole transforms over the pass's shapes
         long long len1 = 0, nout = 0;
@@ -1177,8 +1303,8 @@ dedisp_status dedisp_set_scrunching(dedisp_plan p, const int32_t* factors)
     if (!p) return fail(DEDISP_ERR_INVALID_ARG, "NULL plan");
     if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
     if (p->scrunch != 1 || p->internal) return fail(DEDISP_ERR_INVALID_ARG, "not a user plan");
-    if (p->sb_step1 && factors)
-        return fail(DEDISP_ERR_UNSUPPORTED, "time-scrunching and sub-band dedispersion are exclusive");
+    if ((p->sb_step1 || p->tree_nsub) && factors)
+        return fail(DEDISP_ERR_UNSUPPORTED, "time-scrunching excludes sub-band and tree modes");
     const int ndm = static_cast<int>(p->dms.size());
     bool any = false;
     if (factors) {
@@ -1218,6 +1344,8 @@ dedisp_status dedisp_set_scrunching(dedisp_plan p, const int32_t* factors)
         sub->cfg = default_config(sub->fmt);
         sub->killmask = p->killmask;
         sub->active = p->active;
+        sub->out_nbits = p->out_nbits;
+        sub->out_shift = p->out_shift;
         g.sub = sub;
         p->groups.push_back(g);
         std::vector<int32_t> table;
@@ -1246,8 +1374,8 @@ dedisp_status dedisp_set_subband(dedisp_plan p, int nsub, int ngroup)
     if (nsub < 8 || nsub % 8 || p->nchans % nsub)
         return fail(DEDISP_ERR_INVALID_ARG, "nsub must be a multiple of 8 that divides nchans");
     if (ngroup < 1) return fail(DEDISP_ERR_INVALID_ARG, "ngroup must be positive");
-    if (!p->groups.empty())
-        return fail(DEDISP_ERR_UNSUPPORTED, "time-scrunching and sub-band dedispersion are exclusive");
+    if (!p->groups.empty() || p->tree_nsub)
+        return fail(DEDISP_ERR_UNSUPPORTED, "sub-band mode excludes time-scrunching and the tree");
     if (p->row_bytes % 4) return fail(DEDISP_ERR_UNSUPPORTED, "sub-band passes need whole 32-bit words per row");
     const int vsum = (p->nbits == 2 ? 3 : 255) * nsub;      // largest sub-band sum
     if (vsum > 32767) return fail(DEDISP_ERR_UNSUPPORTED, "sub-band sums do not fit 16 bits");
@@ -1315,10 +1443,94 @@ dedisp_status dedisp_set_subband(dedisp_plan p, int nsub, int ngroup)
     return DEDISP_OK;
 }
 
+dedisp_status dedisp_set_tree(dedisp_plan p, int nsub)
+{
+    if (!p) return fail(DEDISP_ERR_INVALID_ARG, "NULL plan");
+    if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
+    if (p->internal || p->scrunch != 1) return fail(DEDISP_ERR_INVALID_ARG, "not a user plan");
+    if (nsub == 0) {
+        destroy_tree(p);
+        return DEDISP_OK;
+    }
+    if (nsub < 8 || nsub > 128 || (nsub & (nsub - 1)) || p->nchans % nsub)
+        return fail(DEDISP_ERR_INVALID_ARG, "nsub must be a power of two in [8, 128] dividing nchans");
+    if (!p->groups.empty() || p->sb_step1)
+        return fail(DEDISP_ERR_UNSUPPORTED, "the tree excludes time-scrunching and sub-band mode");
+    if (p->row_bytes % 4) return fail(DEDISP_ERR_UNSUPPORTED, "tree passes need whole 32-bit words per row");
+    if (!(p->f_top + static_cast<double>(p->nchans) * p->df > 0))
+        return fail(DEDISP_ERR_UNSUPPORTED, "the band edge past the last channel reaches zero frequency");
+    const int nsb = p->nchans / nsub;
+    const int ndm = static_cast<int>(p->dms.size());
+    // Section 3, eq. combining_subbands, in binary64 in this order:
+    // d'_n = round(DM [DeltaT(v_{n+1}) - DeltaT(v_n)]),
+    // dt''_n = round(DM * (sum of those brackets over the sub-bands before n))
+    const double inv_f0_sq = 1.0 / (p->f_top * p->f_top);
+    const double samples_per_unit = kDispersionConstant / p->dt;
+    std::vector<double> step(nsb);
+    for (int n = 0; n < nsb; ++n) {
+        const double fa = p->f_top + static_cast<double>(n * nsub) * p->df;
+        const double fb = p->f_top + static_cast<double>((n + 1) * nsub) * p->df;
+        step[n] = samples_per_unit * (1.0 / (fb * fb) - inv_f0_sq) - samples_per_unit * (1.0 / (fa * fa) - inv_f0_sq);
+    }
+    std::vector<int32_t> rows(static_cast<size_t>(ndm) * nsb), delay(rows.size());
+    int mx = 0;
+    for (int d = 0; d < ndm; ++d) {
+        double acc = 0.0;
+        for (int n = 0; n < nsb; ++n) {
+            const double dp = std::round(p->dms[d] * step[n]);
+            const double dd = std::round(p->dms[d] * acc);
+            if (dp >= static_cast<double>(nsub))
+                return fail(DEDISP_ERR_UNSUPPORTED, "a trial lies beyond the piecewise linear tree's diagonal DM");
+            if (!(dd < 2.0e9)) return fail(DEDISP_ERR_INVALID_ARG, "a delay does not fit in int32");
+            rows[static_cast<size_t>(d) * nsb + n] = n * nsub + static_cast<int32_t>(dp);
+            delay[static_cast<size_t>(d) * nsb + n] = static_cast<int32_t>(dd);
+            mx = std::max(mx, static_cast<int>(dd));
+            acc += step[n];
+        }
+    }
+    destroy_tree(p);
+    p->tree_nsub = nsub;
+    p->tree_maxdelay = mx;
+    p->tree_rows.swap(rows);
+    p->tree_delay.swap(delay);
+    return DEDISP_OK;
+}
+
+dedisp_status dedisp_set_output_format(dedisp_plan p, int nbits, int shift)
+{
+    if (!p) return fail(DEDISP_ERR_INVALID_ARG, "NULL plan");
+    if (p->internal) return fail(DEDISP_ERR_INVALID_ARG, "not a user plan");
+    if (nbits != 8 && nbits != 16 && nbits != 32)
+        return fail(DEDISP_ERR_INVALID_ARG, "output bits must be 8, 16 or 32");
+    if (shift < 0 || shift > 31) return fail(DEDISP_ERR_INVALID_ARG, "shift must be in [0, 31]");
+    p->out_nbits = nbits;
+    p->out_shift = shift;
+    for (auto& g : p->groups) {
+        g.sub->out_nbits = nbits;
+        g.sub->out_shift = shift;
+    }
+    return DEDISP_OK;
+}
+
+dedisp_status dedisp_get_output_format(dedisp_plan p, int* nbits, int* shift)
+{
+    if (!p || !nbits || !shift) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    *nbits = p->out_nbits;
+    *shift = p->out_shift;
+    return DEDISP_OK;
+}
+
 dedisp_status dedisp_get_output_lengths(dedisp_plan p, size_t nsamps, size_t* nout)
 {
     if (!p || !nout) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
+    if (p->tree_nsub) {
+        long long len1 = 0, n = 0;
+        tree_lengths(*p, nsamps, len1, n);
+        if (len1 <= 0 || n <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps too short for the tree passes");
+        for (size_t d = 0; d < p->dms.size(); ++d) nout[d] = static_cast<size_t>(n);
+        return DEDISP_OK;
+    }
     if (p->sb_step1) {
         long long len1 = 0, n = 0;
         subband_lengths(*p, nsamps, len1, n);

@@ -188,7 +188,7 @@ dedisp_status dedisp_batch_create(const dedisp_beam* beams, int nbeams, const ch
         const dedisp_beam& b = beams[i];
         if (!b.plan || !b.d_in || !b.d_out) return fail(DEDISP_ERR_INVALID_ARG, "NULL beam field");
         if (!b.plan->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "beam without DM list");
-        if (!b.plan->groups.empty() || b.plan->sb_step1)
+        if (!b.plan->groups.empty() || b.plan->sb_step1 || b.plan->tree_nsub)
             return fail(DEDISP_ERR_UNSUPPORTED, "batches support the direct transform only");
         if (b.nsamps <= static_cast<size_t>(b.plan->max_delay))
             return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "beam nsamps <= max_delay");

@@ -111,6 +111,8 @@ struct dedisp_plan_s {
     int nbits = 0;
     int fmt = 0;                    // scratch sample format (dedisp::Fmt)
     int scrunch = 1;                // input samples summed per scratch sample
+    int out_nbits = 32;             // output width: 8, 16 or 32 bits
+    int out_shift = 0;              // outputs are min(sum >> out_shift, 2^out_nbits - 1)
     double dt = 0, f_top = 0, df = 0;
     int row_bytes = 0;
     std::vector<double> dms;
@@ -140,6 +142,13 @@ struct dedisp_plan_s {
     // Internal plans of grouped passes: the table holds ngroups blocks of
     // [ndm][nchans]; the last group has ndm_last valid rows; vbound (when
     // set) bounds one scratch sample.
+    // Piecewise linear tree (0 = off): sub-band width, and per (trial,
+    // sub-band) the tree row n*nsub + d'_n(d) and the delay dt''_n(d).
+    int tree_nsub = 0;
+    int tree_maxdelay = 0;
+    std::vector<int32_t> tree_rows, tree_delay;
+    int32_t* d_tree_rows = nullptr;
+    int32_t* d_tree_delay = nullptr;
     bool internal = false;
     int ngroups = 1;
     int ndm_last = 0;

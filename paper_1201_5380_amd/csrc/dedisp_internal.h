@@ -38,6 +38,8 @@ struct BeamDesc {
     const int32_t* chanmap;   // [nchans] scratch row of each channel, -1 = killed (NULL = identity)
     const int32_t* mask;      // [nchans] 0/1 kill mask for the untiled kernel (NULL = all on)
     const int32_t* rowmap;    // [ndm] output row of each DM row (NULL = identity)
+    const int32_t* rowsel;    // untiled scratch pass: [ngroups][ndm][nact] scratch row of each
+                              // term (NULL = term k reads row k)
     int nact;                 // scratch rows the tiled kernel sums (live channels, padded to a multiple of 8)
     int pad_row;              // first of the scratch rows [pad_row, nact) the corner turn zero-fills, or -1
     int nchans;
@@ -54,8 +56,8 @@ struct BeamDesc {
     // the offsets below times g.  ngroups = 1 and offsets 0 otherwise.
     int ngroups;
     int ndm_last;             // DM rows of the last group (the others have ndm)
-    int out_bytes;            // 4: uint32 outputs; 1 or 2: narrow sums into a scratch
-    int pad2_;
+    int out_bytes;            // 4: uint32 outputs; 1 or 2: uint8 / uint16 outputs or narrow sums
+    int out_shift;            // outputs are min(sum >> out_shift, largest value of out_bytes)
     long long g_xc;           // bytes
     long long g_rel;          // elements of rel
     long long g_base;         // elements of base
@@ -85,6 +87,16 @@ constexpr int kMaxLdsBytes = 160 * 1024;
 // Enqueue the corner turn (time-major packed -> channel-major scratch of
 // format fmt in d.xc), summing d.scrunch consecutive samples when above 1.
 hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st);
+
+// Stage 1 of the piecewise linear tree: k = log2(nsub) tree steps (Theta/Phi)
+// within every sub-band of the channel-major scratch d.xc (format fmt, every
+// channel's row kept), written as 16-bit rows n*nsub + d' of out (pitch
+// out_pitch bytes) for t < len1 = nsamps - (nsub - 1).
+hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, uint8_t* out, long long out_pitch,
+                       long long len1, hipStream_t st);
+// Samples per time tile of the tree kernel (the scratch rows need this many
+// samples of margin past nsamps).
+int tree_tile(int nsub);
 
 // Zero `bytes` (a multiple of 16) at base + g*group_stride for g < ngroups.
 hipError_t launch_zero(uint8_t* base, long long group_stride, long long bytes, int ngroups,

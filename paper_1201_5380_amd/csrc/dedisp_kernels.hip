@@ -82,6 +82,15 @@ __device__ __forceinline__ int lane_value(int v, int lane)
     return __builtin_amdgcn_readlane(v, lane);
 }
 
+// An output value at the descriptor's width: shifted right, then saturated.
+__device__ __forceinline__ uint32_t out_value(uint32_t v, int shift, int bytes)
+{
+    v >>= shift;
+    if (bytes == 1) return v < 0xFFu ? v : 0xFFu;
+    if (bytes == 2) return v < 0xFFFFu ? v : 0xFFFFu;
+    return v;
+}
+
 // Address of input row r in the two-segment virtual input.
 __device__ __forceinline__ const uint8_t* row_ptr(const BeamDesc& b, long long r)
 {
@@ -597,7 +606,12 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     const int32_t* rowmap = wave_uniform_ptr(b.rowmap);
     const int ndm_here = group == wave_uniform(b.ngroups) - 1 ? wave_uniform(b.ndm_last) : ndm;
     const int out_bytes = wave_uniform(b.out_bytes);
+    const int out_shift = wave_uniform(b.out_shift);
     const long long g_out = wave_uniform64(b.g_out);
+    // narrow rows take 32-bit stores of 4 bytes or 2 halves when every row
+    // starts 4-byte aligned
+    const bool nvec = ((reinterpret_cast<uintptr_t>(out) & 3) == 0) && ((out_stride & 3) == 0) &&
+                      ((g_out & 3) == 0);
 #pragma unroll
     for (int k = 0; k < DPW; ++k) {
         const int d = block * DB + wave * DPW + k;
@@ -624,7 +638,9 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
 #pragma unroll
                     for (int e = 0; e < SPW; ++e) o[e] = acc[k][j][e];
                 }
-                if (t + SPW <= nout) {
+#pragma unroll
+                for (int e = 0; e < SPW; ++e) o[e] = out_value(o[e], out_shift, out_bytes);
+                if (nvec && t + SPW <= nout) {
                     if (out_bytes == 1) {
 #pragma unroll
                         for (int g4 = 0; g4 < SPW / 4; ++g4)
@@ -664,6 +680,10 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
             } else {
 #pragma unroll
                 for (int e = 0; e < SPW; ++e) o[e] = acc[k][j][e];
+            }
+            if (out_shift) {
+#pragma unroll
+                for (int e = 0; e < SPW; ++e) o[e] >>= out_shift;
             }
 #pragma unroll
             for (int g = 0; g < SPW / VW; ++g) {
@@ -724,10 +744,22 @@ __global__ __launch_bounds__(256) void k_untiled(BeamDesc b)
                     for (int i = 0; i < s; ++i)
                         a[e] += sample_at<NBITS>(b, (t + e + off) * s + i, c);
         }
-        uint32_t* orow = b.out + (size_t)(b.rowmap ? b.rowmap[d] : d) * (size_t)b.out_stride;
+        const int orow_idx = b.rowmap ? b.rowmap[d] : d;
+        if (b.out_bytes == 4) {
+            uint32_t* orow = b.out + (size_t)orow_idx * (size_t)b.out_stride;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-            if (t + e < b.nout) orow[t + e] = a[e];
+            for (int e = 0; e < 4; ++e)
+                if (t + e < b.nout) orow[t + e] = a[e] >> b.out_shift;
+        } else {
+            uint8_t* nrow = reinterpret_cast<uint8_t*>(b.out) + (long long)orow_idx * b.out_stride;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (t + e < b.nout) {
+                    const uint32_t v = out_value(a[e], b.out_shift, b.out_bytes);
+                    if (b.out_bytes == 1) nrow[t + e] = (uint8_t)v;
+                    else reinterpret_cast<uint16_t*>(nrow)[t + e] = (uint16_t)v;
+                }
+        }
     }
 }
 
@@ -753,9 +785,10 @@ __global__ __launch_bounds__(256) void k_untiled_xc(BeamDesc b)
     const uint8_t* xc = b.xc + g * b.g_xc;
     for (int d = blockIdx.y; d < ndm_here; d += gridDim.y) {
         const int32_t* dl = b.table + ((size_t)g * b.ndm + d) * b.nact;
+        const int32_t* rs = b.rowsel ? b.rowsel + ((size_t)g * b.ndm + d) * b.nact : nullptr;
         uint32_t a[4] = {0u, 0u, 0u, 0u};
         for (int k = 0; k < b.nact; ++k) {
-            const uint8_t* row = xc + (long long)k * b.pitch;
+            const uint8_t* row = xc + (long long)(rs ? rs[k] : k) * b.pitch;
             const long long off = dl[k];
 #pragma unroll
             for (int e = 0; e < 4; ++e)
@@ -765,15 +798,92 @@ __global__ __launch_bounds__(256) void k_untiled_xc(BeamDesc b)
             uint32_t* orow = b.out + g * b.g_out + (size_t)d * (size_t)b.out_stride;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (t + e < b.nout) orow[t + e] = a[e];
+                if (t + e < b.nout) orow[t + e] = a[e] >> b.out_shift;
         } else {
             uint8_t* nrow = reinterpret_cast<uint8_t*>(b.out) + g * b.g_out + (long long)d * b.out_stride;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
                 if (t + e < b.nout) {
-                    if (b.out_bytes == 1) nrow[t + e] = (uint8_t)a[e];
-                    else reinterpret_cast<uint16_t*>(nrow)[t + e] = (uint16_t)a[e];
+                    const uint32_t v = out_value(a[e], b.out_shift, b.out_bytes);
+                    if (b.out_bytes == 1) nrow[t + e] = (uint8_t)v;
+                    else reinterpret_cast<uint16_t*>(nrow)[t + e] = (uint16_t)v;
                 }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- tree
+
+// Stage 1 of the piecewise linear tree (Section 3).  Workgroup (tile,
+// sub-band n) loads the sub-band's nsub scratch rows for samples
+// [t0, t0 + T + nsub - 1) into LDS as 16-bit values and applies the tree's
+// steps i = 0 .. k-1 out of place (double buffer):
+//   B[2v][t]   = A[Phi(r, 2v)][t] + A[Phi(r, 2v+1)][t + Theta(i, 2v)]
+//   B[2v+1][t] = A[Phi(r, 2v)][t] + A[Phi(r, 2v+1)][t + Theta(i, 2v+1)]
+// with r = 2^i, Theta(i, v) = ((v mod 2^{i+1}) + 1) / 2 and
+// Phi(r, v) = (v mod 2) r + v/2 + (v/(2r)) r; each step is defined on 2^i
+// fewer samples than the one before.  Row d' of the result is the sub-band at
+// tree DM d', written for t < len1.  Sums stay below 2^16 (nsub codes).
+__host__ __device__ constexpr int tree_tile_len(int nsub) { return 16384 / nsub; }
+
+__device__ __forceinline__ int tree_theta(int i, int v) { return ((v & ((2 << i) - 1)) + 1) >> 1; }
+__device__ __forceinline__ int tree_phi(int r, int v) { return (v & 1) * r + (v >> 1) + (v / (2 * r)) * r; }
+
+template <int FMT, int NSUB>
+__global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long long out_pitch, long long len1)
+{
+    constexpr int T = tree_tile_len(NSUB);
+    constexpr int L = T + NSUB;                    // LDS row length (>= T + NSUB - 1 samples)
+    constexpr int K = NSUB == 8 ? 3 : NSUB == 16 ? 4 : NSUB == 32 ? 5 : NSUB == 64 ? 6 : 7;
+    static_assert((1 << K) == NSUB, "sub-band width must be a power of two");
+    extern __shared__ uint16_t tl[];               // [2][NSUB][L]
+    uint16_t* A = tl;
+    uint16_t* B = tl + NSUB * L;
+    const long long t0 = (long long)blockIdx.x * T;
+    const int n = blockIdx.y;
+    // load: 32-bit words of the channel-major scratch, unpacked to 16 bits
+    constexpr int SPW = fmt_samples_per_word(FMT);
+    constexpr int WPR = L / SPW;                   // words per LDS row
+    static_assert(L % SPW == 0, "whole words per row");
+    for (int it = threadIdx.x; it < NSUB * WPR; it += 256) {
+        const int j = it / WPR, w = it % WPR;
+        const uint8_t* row = b.xc + (long long)(n * NSUB + j) * b.pitch;
+        const uint32_t v = *reinterpret_cast<const uint32_t*>(row + (t0 / SPW + w) * 4);
+        uint16_t* dst = A + j * L + w * SPW;
+#pragma unroll
+        for (int e = 0; e < SPW; ++e) {
+            if constexpr (FMT == kFmtNib) dst[e] = (v >> (4 * e)) & 0xFu;
+            else dst[e] = (v >> (8 * e)) & 0xFFu;
+        }
+    }
+    __syncthreads();
+    int len = L - 1;                               // samples of A in use (T + NSUB - 1)
+#pragma unroll 1
+    for (int i = 0; i < K; ++i) {
+        const int r = 1 << i;
+        const int next = len - r;
+        for (int it = threadIdx.x; it < (NSUB / 2) * next; it += 256) {
+            const int v = it / next, t = it % next;
+            const uint16_t lo = A[tree_phi(r, 2 * v) * L + t];
+            const uint16_t* hi = A + tree_phi(r, 2 * v + 1) * L + t;
+            B[(2 * v) * L + t] = (uint16_t)(lo + hi[tree_theta(i, 2 * v)]);
+            B[(2 * v + 1) * L + t] = (uint16_t)(lo + hi[tree_theta(i, 2 * v + 1)]);
+        }
+        __syncthreads();
+        uint16_t* tmp = A;
+        A = B;
+        B = tmp;
+        len = next;
+    }
+    // store rows n*NSUB + d' (16-bit), samples t0 .. t0 + T - 1 below len1
+    for (int it = threadIdx.x; it < NSUB * (T / 2); it += 256) {
+        const int dp = it / (T / 2), t = 2 * (it % (T / 2));
+        const long long tg = t0 + t;
+        uint16_t* orow = reinterpret_cast<uint16_t*>(out + (long long)(n * NSUB + dp) * out_pitch);
+        if (tg + 1 < len1) {
+            *reinterpret_cast<uint32_t*>(orow + tg) = (uint32_t)A[dp * L + t] | ((uint32_t)A[dp * L + t + 1] << 16);
+        } else if (tg < len1) {
+            orow[tg] = A[dp * L + t];
         }
     }
 }
@@ -995,6 +1105,35 @@ hipError_t launch_untiled_xc(const BeamDesc& d, int fmt, hipStream_t st)
                      : fmt == kFmtHalf ? reinterpret_cast<const void*>(&k_untiled_xc<kFmtHalf>)
                                        : reinterpret_cast<const void*>(&k_untiled_xc<kFmtByte>);
     return hipLaunchKernel(fn, dim3((unsigned)gx, gy, (unsigned)d.ngroups), dim3(256), args, 0, st);
+}
+
+int tree_tile(int nsub) { return tree_tile_len(nsub); }
+
+hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, uint8_t* out, long long out_pitch,
+                       long long len1, hipStream_t st)
+{
+    if (len1 <= 0 || (out_pitch & 3) || (reinterpret_cast<uintptr_t>(out) & 3)) return hipErrorInvalidValue;
+    const long long T = tree_tile_len(nsub);
+    const long long gx = (len1 + T - 1) / T;
+    const long long gy = d.nchans / nsub;
+    if (gx <= 0 || gx > 0x7fffffffLL || gy <= 0 || gy > 65535) return hipErrorInvalidValue;
+    const void* fn = nullptr;
+#define DEDISP_TREE_CASE(F, N) \
+    if (fmt == F && nsub == N) fn = reinterpret_cast<const void*>(&k_tree<F, N>);
+    DEDISP_TREE_CASE(kFmtNib, 8) DEDISP_TREE_CASE(kFmtNib, 16) DEDISP_TREE_CASE(kFmtNib, 32)
+    DEDISP_TREE_CASE(kFmtNib, 64) DEDISP_TREE_CASE(kFmtNib, 128)
+    DEDISP_TREE_CASE(kFmtByte, 8) DEDISP_TREE_CASE(kFmtByte, 16) DEDISP_TREE_CASE(kFmtByte, 32)
+    DEDISP_TREE_CASE(kFmtByte, 64) DEDISP_TREE_CASE(kFmtByte, 128)
+#undef DEDISP_TREE_CASE
+    if (!fn) return hipErrorInvalidValue;
+    const size_t lds = 2ull * nsub * (tree_tile_len(nsub) + nsub) * sizeof(uint16_t);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    BeamDesc a0 = d;
+    uint8_t* a1 = out;
+    long long a2 = out_pitch, a3 = len1;
+    void* args[] = {&a0, &a1, &a2, &a3};
+    return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, lds, st);
 }
 
 hipError_t launch_untiled(const BeamDesc& d, int nbits, hipStream_t st)

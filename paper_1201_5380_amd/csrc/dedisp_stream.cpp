@@ -48,7 +48,7 @@ dedisp_status check_stream(dedisp_stream s)
     if (!s || !s->plan) return fail(DEDISP_ERR_INVALID_ARG, "NULL stream");
     if (!s->plan->has_dms || s->plan->max_delay != s->max_delay)
         return fail(DEDISP_ERR_INVALID_ARG, "the plan's DM list changed after the stream was created");
-    if (!s->plan->groups.empty() || s->plan->sb_step1)
+    if (!s->plan->groups.empty() || s->plan->sb_step1 || s->plan->tree_nsub)
         return fail(DEDISP_ERR_UNSUPPORTED, "streams support the direct transform only");
     return DEDISP_OK;
 }
@@ -133,7 +133,7 @@ dedisp_status dedisp_stream_create(dedisp_plan plan, dedisp_stream* out)
     *out = nullptr;
     if (!plan) return fail(DEDISP_ERR_INVALID_ARG, "plan is NULL");
     if (!plan->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
-    if (!plan->groups.empty() || plan->sb_step1)
+    if (!plan->groups.empty() || plan->sb_step1 || plan->tree_nsub)
         return fail(DEDISP_ERR_UNSUPPORTED, "streams support the direct transform only");
     dedisp_stream s = new (std::nothrow) dedisp_stream_s;
     if (!s) return fail(DEDISP_ERR_OOM, "stream allocation");

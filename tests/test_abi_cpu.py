@@ -281,3 +281,64 @@ def test_subband_validation_precedes_hip(native):
     # a new DM list clears both modes
     plan.set_dm_list(synth.dm_list_linear(32, 100.0))
     assert np.all(plan.output_lengths(5000) == 5000 - plan.max_delay)
+
+
+def test_output_format_validation(native):
+    L = lib()
+    plan = Plan(64, 64e-6, 1500.0, -1.0, 8)
+    nb, sh = ctypes.c_int(), ctypes.c_int()
+    assert L.dedisp_get_output_format(plan.handle, ctypes.byref(nb), ctypes.byref(sh)) == 0
+    assert (nb.value, sh.value) == (32, 0)
+    for bad in ((12, 0), (0, 0), (64, 0), (8, -1), (16, 32)):
+        assert L.dedisp_set_output_format(plan.handle, *bad) == -1, bad
+    plan.set_output_format(8, 3)
+    assert L.dedisp_get_output_format(plan.handle, ctypes.byref(nb), ctypes.byref(sh)) == 0
+    assert (nb.value, sh.value) == (8, 3)
+    import torch
+    assert plan.output_dtype() == torch.uint8
+
+
+# ---------------------------------------------------------------------------
+# piecewise linear tree: host logic against the oracle (no GPU needed)
+# ---------------------------------------------------------------------------
+
+def _tree_diag(nchans, nsub, dt, f0, df):
+    k = 4.148808e3 / dt
+    fb, fa = f0 + nchans * df, f0 + (nchans - nsub) * df
+    return (nsub - 0.5) / (k * (1 / fb ** 2 - 1 / f0 ** 2) - k * (1 / fa ** 2 - 1 / f0 ** 2))
+
+
+@pytest.mark.parametrize("nchans,nbits,nsub", [(1024, 2, 32), (512, 2, 8), (256, 8, 64), (128, 8, 128)])
+def test_tree_output_lengths_match_oracle(native, nchans, nbits, nsub):
+    dt, f0, df = 64e-6, 1581.8, -400.0 / nchans
+    dms = np.linspace(0.0, 0.99 * _tree_diag(nchans, nsub, dt, f0, df), 50)
+    plan = Plan(nchans, dt, f0, df, nbits).set_dm_list(dms).set_tree(nsub)
+    _, dd = oracle.tree_combine_tables(nchans, dt, f0, df, nsub, dms)
+    nsamps = 1 << 18
+    assert np.all(plan.output_lengths(nsamps) == nsamps - (nsub - 1) - dd.max())
+    plan.set_tree(0)
+    assert np.all(plan.output_lengths(nsamps) == nsamps - plan.max_delay)
+
+
+def test_tree_validation_precedes_hip(native):
+    L = lib()
+    nchans, dt, f0, df = 256, 64e-6, 1581.8, -400.0 / 256
+    plan = Plan(nchans, dt, f0, df, 2)
+    assert L.dedisp_set_tree(plan.handle, 16) == -2                        # no DM list
+    diag = _tree_diag(nchans, 16, dt, f0, df)
+    plan.set_dm_list(np.linspace(0, 0.9 * diag, 10))
+    for bad in (4, 12, 256, 3, -16):
+        assert L.dedisp_set_tree(plan.handle, bad) == -1, bad
+    plan.set_dm_list(np.linspace(0, 1.5 * diag, 10))
+    assert L.dedisp_set_tree(plan.handle, 16) == -6                         # beyond the diagonal
+    plan.set_dm_list(np.linspace(0, 0.9 * diag, 10))
+    assert L.dedisp_set_tree(plan.handle, 16) == 0
+    f = np.array([1] * 5 + [2] * 5, np.int32)
+    assert L.dedisp_set_scrunching(plan.handle, f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == -6
+    assert L.dedisp_set_subband(plan.handle, 16, 2) == -6
+    p16 = ctypes.c_void_p(1 << 20)
+    assert L.dedisp_execute(plan.handle, p16, 10, p16, 0, None) == -3
+    h = ctypes.c_void_p()
+    assert L.dedisp_stream_create(plan.handle, ctypes.byref(h)) == -6
+    plan.set_tree(0)
+    assert np.all(plan.output_lengths(5000) == 5000 - plan.max_delay)

@@ -1,0 +1,81 @@
+"""GPU parity of the piecewise linear tree (Section 3) against the oracle, bit for bit.
+
+Stage 1 (the tree's Theta/Phi steps within each sub-band, in LDS) and stage 2
+(the sub-band combination, a gather over tree rows) run on the GPU; the
+oracle performs the same steps on the CPU.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1201_5380_amd import Plan, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _diag(nchans, nsub, dt, f_top, df):
+    k = 4.148808e3 / dt
+    fb = f_top + nchans * df
+    fa = f_top + (nchans - nsub) * df
+    return (nsub - 0.5) / (k * (1 / fb ** 2 - 1 / f_top ** 2) - k * (1 / fa ** 2 - 1 / f_top ** 2))
+
+
+def _run(plan, packed, nsamps, dev):
+    import torch
+    inp = torch.from_numpy(np.ascontiguousarray(packed.reshape(-1))).to(dev)
+    out = plan.execute(inp, nsamps)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("nbits,nchans,nsub,nsamps", [
+    (2, 256, 8, 12011), (2, 512, 32, 20003), (8, 128, 16, 9001), (8, 256, 64, 7777),
+    (2, 1024, 128, 6007)])
+def test_piecewise_tree_bit_exact(native, cuda, nbits, nchans, nsub, nsamps):
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    dms = np.linspace(0.0, 0.99 * _diag(nchans, nsub, dt, f_top, df), 37)
+    rng = np.random.default_rng(nchans + nsub)
+    codes = (rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8) if nbits == 2 else
+             rng.integers(0, 256, size=(nsamps, nchans), dtype=np.uint8))
+    codes[::53] = 3 if nbits == 2 else 255
+    packed = synth.pack(codes, nbits)
+    want = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub)
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms).set_tree(nsub)
+    assert np.all(plan.output_lengths(nsamps) == want.shape[1])
+    got = _run(plan, packed, nsamps, cuda)
+    assert got.shape == want.shape and np.array_equal(got, want)
+
+
+def test_tree_kill_mask_and_reduced_output(native, cuda):
+    import torch
+    nbits, nchans, nsub, nsamps = 2, 512, 16, 15013
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    dms = np.linspace(0.0, 0.99 * _diag(nchans, nsub, dt, f_top, df), 20)
+    rng = np.random.default_rng(4)
+    codes = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+    packed = synth.pack(codes, nbits)
+    mask = (rng.random(nchans) < 0.7).astype(np.int32)
+    want = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub,
+                                            mask=mask)
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms).set_killmask(mask).set_tree(nsub)
+    assert np.array_equal(_run(plan, packed, nsamps, cuda), want)
+    plan.set_output_format(8, 3)
+    inp = torch.from_numpy(packed.reshape(-1)).to(cuda)
+    out = plan.execute(inp, nsamps)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint8), oracle.reduce_output(want, 8, 3))
+
+
+def test_survey_beam_tree_full_size(native, cuda):
+    """The benchmark's survey beam through a 32-channel piecewise tree, for
+    the trials up to the piecewise diagonal, whole against the oracle."""
+    b = synth.survey_beam()
+    diag = _diag(b.nchans, 32, b.dt, b.f_top, b.df)
+    dms = b.dms[b.dms < diag]
+    assert len(dms) >= 30      # the 32-channel piecewise diagonal is ~32.6
+    packed = b.packed()
+    want = oracle.dedisperse_piecewise_tree(packed, b.nsamps, b.nchans, b.nbits, b.dt, b.f_top, b.df,
+                                            dms, 32)
+    plan = Plan(b.nchans, b.dt, b.f_top, b.df, b.nbits).set_dm_list(dms).set_tree(32)
+    got = _run(plan, packed, b.nsamps, cuda)
+    assert np.array_equal(got, want)
