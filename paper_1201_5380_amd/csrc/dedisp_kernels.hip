@@ -778,8 +778,10 @@ __device__ __forceinline__ uint32_t xc_sample(const uint8_t* row, long long t)
 template <int FMT>
 __global__ __launch_bounds__(256) void k_untiled_xc(BeamDesc b)
 {
-    const long long t = ((long long)blockIdx.x * 256 + threadIdx.x) * 4;
-    if (t >= b.nout) return;
+    // outputs base + threadIdx.x + 256*e, e < 4: consecutive lanes read and
+    // write consecutive samples
+    const long long base = (long long)blockIdx.x * 1024 + threadIdx.x;
+    if (base >= b.nout) return;
     const int g = blockIdx.z;
     const int ndm_here = g == b.ngroups - 1 ? b.ndm_last : b.ndm;
     const uint8_t* xc = b.xc + g * b.g_xc;
@@ -792,21 +794,21 @@ __global__ __launch_bounds__(256) void k_untiled_xc(BeamDesc b)
             const long long off = dl[k];
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (t + e < b.nout) a[e] += xc_sample<FMT>(row, t + e + off);
+                if (base + 256 * e < b.nout) a[e] += xc_sample<FMT>(row, base + 256 * e + off);
         }
         if (b.out_bytes == 4) {
             uint32_t* orow = b.out + g * b.g_out + (size_t)d * (size_t)b.out_stride;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (t + e < b.nout) orow[t + e] = a[e] >> b.out_shift;
+                if (base + 256 * e < b.nout) orow[base + 256 * e] = a[e] >> b.out_shift;
         } else {
             uint8_t* nrow = reinterpret_cast<uint8_t*>(b.out) + g * b.g_out + (long long)d * b.out_stride;
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (t + e < b.nout) {
+                if (base + 256 * e < b.nout) {
                     const uint32_t v = out_value(a[e], b.out_shift, b.out_bytes);
-                    if (b.out_bytes == 1) nrow[t + e] = (uint8_t)v;
-                    else reinterpret_cast<uint16_t*>(nrow)[t + e] = (uint16_t)v;
+                    if (b.out_bytes == 1) nrow[base + 256 * e] = (uint8_t)v;
+                    else reinterpret_cast<uint16_t*>(nrow)[base + 256 * e] = (uint16_t)v;
                 }
         }
     }
@@ -824,7 +826,7 @@ __global__ __launch_bounds__(256) void k_untiled_xc(BeamDesc b)
 // Phi(r, v) = (v mod 2) r + v/2 + (v/(2r)) r; each step is defined on 2^i
 // fewer samples than the one before.  Row d' of the result is the sub-band at
 // tree DM d', written for t < len1.  Sums stay below 2^16 (nsub codes).
-__host__ __device__ constexpr int tree_tile_len(int nsub) { return 16384 / nsub; }
+__host__ __device__ constexpr int tree_tile_len(int nsub) { return 8192 / nsub; }
 
 __device__ __forceinline__ int tree_theta(int i, int v) { return ((v & ((2 << i) - 1)) + 1) >> 1; }
 __device__ __forceinline__ int tree_phi(int r, int v) { return (v & 1) * r + (v >> 1) + (v / (2 * r)) * r; }
@@ -862,12 +864,19 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long lon
     for (int i = 0; i < K; ++i) {
         const int r = 1 << i;
         const int next = len - r;
-        for (int it = threadIdx.x; it < (NSUB / 2) * next; it += 256) {
-            const int v = it / next, t = it % next;
-            const uint16_t lo = A[tree_phi(r, 2 * v) * L + t];
-            const uint16_t* hi = A + tree_phi(r, 2 * v + 1) * L + t;
-            B[(2 * v) * L + t] = (uint16_t)(lo + hi[tree_theta(i, 2 * v)]);
-            B[(2 * v + 1) * L + t] = (uint16_t)(lo + hi[tree_theta(i, 2 * v + 1)]);
+        // channel pairs outer (their shuffle and delays are uniform), time
+        // inner with consecutive lanes on consecutive samples
+        for (int v = 0; v < NSUB / 2; ++v) {
+            const uint16_t* lo = A + tree_phi(r, 2 * v) * L;
+            const uint16_t* hi = A + tree_phi(r, 2 * v + 1) * L;
+            const int th0 = tree_theta(i, 2 * v), th1 = tree_theta(i, 2 * v + 1);
+            uint16_t* o0 = B + (2 * v) * L;
+            uint16_t* o1 = B + (2 * v + 1) * L;
+            for (int t = threadIdx.x; t < next; t += 256) {
+                const uint16_t a = lo[t];
+                o0[t] = (uint16_t)(a + hi[t + th0]);
+                o1[t] = (uint16_t)(a + hi[t + th1]);
+            }
         }
         __syncthreads();
         uint16_t* tmp = A;
@@ -917,6 +926,8 @@ __global__ __launch_bounds__(256) void k_zero(uint8_t* base, long long group_str
     X(kFmtNib, 8, 4, 3, 16, 4, 0)          \
     X(kFmtNib, 16, 2, 3, 64, 2, 0)         \
     X(kFmtNib, 16, 1, 5, 64, 2, 0)         \
+    X(kFmtNib, 16, 1, 5, 32, 2, 0)         \
+    X(kFmtNib, 8, 1, 5, 32, 2, 0)          \
     X(kFmtByte, 8, 2, 5, 32, 2, 1)         \
     X(kFmtByte, 8, 2, 3, 16, 4, 1)         \
     X(kFmtByte, 8, 4, 3, 16, 4, 0)         \
@@ -1095,8 +1106,7 @@ hipError_t launch_zero(uint8_t* base, long long group_stride, long long bytes, i
 
 hipError_t launch_untiled_xc(const BeamDesc& d, int fmt, hipStream_t st)
 {
-    const long long nthreads = (d.nout + 3) / 4;
-    const long long gx = (nthreads + 255) / 256;
+    const long long gx = (d.nout + 1023) / 1024;
     if (gx <= 0 || gx > 0x7fffffffLL || d.ngroups < 1 || d.ngroups > 65535) return hipErrorInvalidValue;
     const unsigned gy = (unsigned)(d.ndm < 65535 ? d.ndm : 65535);
     BeamDesc arg = d;
