@@ -157,14 +157,15 @@ def bench_subband(torch, dev, plan, inp, nsamps, steps, direct_ms, nsub=32, ngro
 
 def bench_tree(torch, dev, beam, inp, nsamps, steps, nsub=32):
     """The survey beam through the piecewise linear tree (Section 3) with
-    32-channel sub-bands, for the trials up to the tree's diagonal DM, against
-    the direct transform of the same trials."""
+    32-channel sub-bands, against the direct transform of the same trials:
+    the survey's own trials up to the tree's diagonal DM, and a dense list of
+    1024 trials spread evenly below it (the regime the tree is built for)."""
+    import numpy as np
     from paper_1201_5380_amd import Plan
     k = 4.148808e3 / beam.dt
     fb = beam.f_top + beam.nchans * beam.df
     fa = beam.f_top + (beam.nchans - nsub) * beam.df
     diag = (nsub - 0.5) / (k * (1 / fb ** 2 - 1 / beam.f_top ** 2) - k * (1 / fa ** 2 - 1 / beam.f_top ** 2))
-    dms = beam.dms[beam.dms < diag]
 
     def timed(plan):
         nout = int(plan.output_lengths(nsamps)[0])
@@ -181,14 +182,18 @@ def bench_tree(torch, dev, beam, inp, nsamps, steps, nsub=32):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps, nout
 
-    direct = Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(dms)
-    d_ms, _ = timed(direct)
-    tree = Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(dms).set_tree(nsub)
-    t_ms, nout = timed(tree)
-    return {"workload": f"survey beam, {len(dms)} trials up to the piecewise tree's diagonal "
-                        f"DM {diag:.2f}, sub-bands of {nsub} channels",
-            "ms": t_ms, "nout": nout, "outputs_per_s": len(dms) * nout / (t_ms * 1e-3),
-            "direct_ms_same_trials": d_ms, "speedup_vs_direct": d_ms / t_ms}
+    res = {}
+    for key, dms, what in (("survey_trials", beam.dms[beam.dms < diag], "the survey's trials"),
+                           ("dense_trials", np.linspace(0.0, 0.999 * diag, 1024), "1024 evenly spaced trials")):
+        direct = Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(dms)
+        d_ms, _ = timed(direct)
+        tree = Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(dms).set_tree(nsub)
+        t_ms, nout = timed(tree)
+        res[key] = {"workload": f"survey beam, {what} ({len(dms)}) up to the piecewise tree's diagonal "
+                                f"DM {diag:.2f}, sub-bands of {nsub} channels",
+                    "ms": t_ms, "nout": nout, "outputs_per_s": len(dms) * nout / (t_ms * 1e-3),
+                    "direct_ms_same_trials": d_ms, "speedup_vs_direct": d_ms / t_ms}
+    return res
 
 
 def bench_serve(torch, dev, seconds):

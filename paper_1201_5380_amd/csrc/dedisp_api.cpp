@@ -314,6 +314,17 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
         lp.cc = s.cc;
         lp.rw = window_words(*bt, s);
         lp.lds = s.cc * lp.rw * 4;
+        // Double-buffer the staged chunk (one barrier per chunk instead of
+        // two) when that keeps as many workgroups resident per CU: at most
+        // 16 waves per CU run at the tiled kernels' register counts, so a
+        // CU holds min(16 / waves, LDS / bytes per workgroup) workgroups.
+        {
+            const int by_waves = std::max(1, 16 / s.waves);
+            const int single = std::min(by_waves, dedisp::kMaxLdsBytes / lp.lds);
+            const int twice = std::min(by_waves, dedisp::kMaxLdsBytes / (2 * lp.lds));
+            lp.dbuf = (twice >= 1 && twice >= single) ? 1 : 0;
+        }
+        if (lp.dbuf) lp.lds *= 2;
         lp.nbits = p->nbits;
         lp.flush_every = flush_channels(*p);
         lp.bt = nullptr;
@@ -426,6 +437,7 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
         d.ntiles = static_cast<int>((d.nout + tile_len(lp.shape) - 1) / tile_len(lp.shape));
         d.rw = lp.rw;
         d.flush_every = lp.flush_every;
+        d.dbuf = lp.dbuf;
     }
 }
 
@@ -910,6 +922,7 @@ static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsa
     d1.table = s1->d_table;
     d1.rw = lp1.rw;
     d1.flush_every = lp1.flush_every;
+    d1.dbuf = lp1.dbuf;
     d1.shape = lp1.shape_index;
     d1.scrunch = 1;
     d1.ngroups = nsb;
@@ -943,6 +956,7 @@ static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsa
     d2.table = s2->d_table;
     d2.rw = lp2.rw;
     d2.flush_every = lp2.flush_every;
+    d2.dbuf = lp2.dbuf;
     d2.shape = lp2.shape_index;
     d2.scrunch = 1;
     d2.ngroups = nnom;
@@ -1041,7 +1055,9 @@ static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps
     dg.out_bytes = p->out_nbits / 8;
     dg.out_shift = p->out_shift;
     dg.out_stride = static_cast<long long>(stride) * (dg.out_bytes == 4 ? 1 : dg.out_bytes);
-    e = dedisp::launch_untiled_xc(dg, dedisp::kFmtHalf, hs);
+    // 16-bit partial sums of at most 65535 / (largest row value) terms
+    const int row_max = ((1 << p->nbits) - 1) * p->tree_nsub;
+    e = dedisp::launch_tree_combine(dg, 65535 / row_max, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return DEDISP_OK;
 }

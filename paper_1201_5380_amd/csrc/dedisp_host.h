@@ -46,6 +46,7 @@ struct LaunchPlan {
     Shape shape{};
     int nbits = 0;       // input bit depth (selects the corner-turn kernel)
     int cc = 0, rw = 0, lds = 0, flush_every = 1;
+    int dbuf = 0;        // two LDS chunk buffers (lds counts both)
     BlockTables* bt = nullptr;
 };
 

@@ -58,6 +58,8 @@ struct BeamDesc {
     int ndm_last;             // DM rows of the last group (the others have ndm)
     int out_bytes;            // 4: uint32 outputs; 1 or 2: uint8 / uint16 outputs or narrow sums
     int out_shift;            // outputs are min(sum >> out_shift, largest value of out_bytes)
+    int dbuf;                 // tiled kernel: two LDS chunk buffers (one barrier per chunk)
+    int pad3_;
     long long g_xc;           // bytes
     long long g_rel;          // elements of rel
     long long g_base;         // elements of base
@@ -97,6 +99,14 @@ hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, uint8_t* out, long 
 // Samples per time tile of the tree kernel (the scratch rows need this many
 // samples of margin past nsamps).
 int tree_tile(int nsub);
+
+// Stage 2 of the piecewise linear tree: out[d][t] = sum over the d.nact
+// sub-bands n of S[d.rowsel[d*nact + n]][t + d.table[d*nact + n]] for
+// t < d.nout, S the 16-bit stage-1 rows in d.xc (pitch d.pitch bytes, rows
+// readable 9 samples past the last delayed output).  flush = terms summed in
+// 16-bit lanes between 32-bit flushes (flush * largest row value < 2^16).
+// d.out / out_bytes / out_shift / out_stride as for the other kernels.
+hipError_t launch_tree_combine(const BeamDesc& d, int flush, hipStream_t st);
 
 // Zero `bytes` (a multiple of 16) at base + g*group_stride for g < ngroups.
 hipError_t launch_zero(uint8_t* base, long long group_stride, long long bytes, int ngroups,
