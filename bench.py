@@ -220,9 +220,15 @@ def bench_serve(torch, dev, seconds):
         offs[s] = (o + L) % (1 << 19)
         return pool_np[o:o + L]
 
+    def consume(r):
+        # the consumer takes the result and lets its device memory go
+        r.out = None
+
     def run(open_loop):
         ex = GpuExecutor([plan] * nstreams, device=dev)
-        srv = Server(ex, nstreams, budget_bytes=64 << 30, max_tick=16, max_inflight_ticks=4).start()
+        ex.tune(1 << 18)
+        srv = Server(ex, nstreams, budget_bytes=64 << 30, max_tick=16, max_inflight_ticks=4,
+                     on_done=consume).start()
         reqs = []
         t0 = time.perf_counter()
         for ta, s in zip(t_arr, sids):
@@ -245,11 +251,44 @@ def bench_serve(torch, dev, seconds):
     open_loop = run(True)
     offs[:] = [(s * 7919) % (1 << 19) for s in range(nstreams)]
     lens.update({s: list(synth.stream_chunk_lengths(s, narr)) for s in range(nstreams)})
+    chunk_lens = [int(lens[int(s)][k]) for k, s in enumerate(_per_stream_index(sids))]
     saturated = run(False)
+    saturated["plain_same_chunks_outputs_per_s"] = plain_same_chunks(torch, dev, plan, chunk_lens)
     return {"workload": "32 streams x 2-bit 1024 ch, 1024 DMs in [0, 1000); chunks U[2^14, 2^18] "
                         f"samples, Poisson arrivals at {rate:.1f} chunks/s (4x real time per stream), "
                         "64 GB budget",
             "open_loop": open_loop, "saturated": saturated}
+
+
+def _per_stream_index(sids):
+    """(stream, k) -> k-th chunk of that stream, in arrival order, as stream ids."""
+    seen = {}
+    out = []
+    for s in sids:
+        k = seen.get(int(s), 0)
+        seen[int(s)] = k + 1
+        out.append(k)
+    return out
+
+
+def plain_same_chunks(torch, dev, plan, chunk_lens):
+    """The plain transform over the serving run's chunk lengths, one execute
+    per chunk of L new samples plus max_delay history samples already in HBM,
+    back to back on one stream: the plain form's rate on the serving work."""
+    nmax = max(chunk_lens) + plan.max_delay
+    inp = torch.zeros(nmax * plan.row_bytes, dtype=torch.uint8, device=dev)
+    out = torch.empty((plan.ndm, max(chunk_lens)), dtype=torch.int32, device=dev)
+    plan.tune(inp, out, nmax)
+    for L in chunk_lens[:4]:
+        plan.execute(inp, L + plan.max_delay, out=out, out_row_stride=max(chunk_lens))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for L in chunk_lens:
+        plan.execute(inp, L + plan.max_delay, out=out, out_row_stride=max(chunk_lens))
+    e1.record()
+    torch.cuda.synchronize()
+    return sum(chunk_lens) * plan.ndm / (e0.elapsed_time(e1) * 1e-3)
 
 
 def cpu_baseline(packed, nsamps, nchans, nbits, table, budget_s):

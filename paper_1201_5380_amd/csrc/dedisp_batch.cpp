@@ -1,6 +1,6 @@
 // Batches: several beams -- differing in channel count, bit depth, length,
 // DM list and tile shape -- dedispersed by one multi-beam launch (after one
-// corner-turn kernel per beam), captured once into a HIP graph.  Tile shapes
+// multi-beam corner-turn launch), captured once into a HIP graph.  Tile shapes
 // are chosen per beam by timing the candidates on the beam's own buffers,
 // with results kept in a JSON cache keyed by the beam's shape.
 #include "dedisp_host.h"
@@ -28,42 +28,58 @@ static bool use_persistent_loop()
 
 hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st)
 {
-    for (const Item& it : items)
-        if (it.lp.shape.kind == 0) {
-            hipError_t e = launch_unpack(it.d, it.lp.nbits, it.lp.shape.fmt, st);
+    // corner turns of the tiled beams, up to kMaxBatchDescs per launch
+    {
+        DescBlock ub{};
+        int n = 0;
+        for (const Item& it : items) {
+            if (it.lp.shape.kind != 0) continue;
+            ub.d[n] = it.d;
+            ub.d[n].in_nbits = it.lp.nbits;
+            if (++n == kMaxBatchDescs) {
+                hipError_t e = launch_unpack_multi(ub, n, st);
+                if (e != hipSuccess) return e;
+                n = 0;
+            }
+        }
+        if (n > 0) {
+            hipError_t e = launch_unpack_multi(ub, n, st);
             if (e != hipSuccess) return e;
         }
-    std::vector<Item*> tiled;
-    for (Item& it : items) {
-        if (it.lp.shape.kind == 0) {
-            if (!it.lp.shape.multi) return hipErrorInvalidValue;
-            tiled.push_back(&it);
-        }
     }
-    for (size_t g0 = 0; g0 < tiled.size(); g0 += kMaxBatchDescs) {
-        const size_t g1 = std::min(tiled.size(), g0 + kMaxBatchDescs);
-        DescBlock blk{};
-        long long total = 0;
-        int lds = 0;
-        for (size_t i = g0; i < g1; ++i) {
-            BeamDesc& d = tiled[i]->d;
-            d.work_begin = total;   // a multiple of 8: see the multi-beam kernel
-            total += (static_cast<long long>(d.ntiles) * d.nblocks + 7) / 8 * 8;
-            lds = std::max(lds, tiled[i]->lp.lds);
-            blk.d[i - g0] = d;
+    // multi-beam launches per class, up to kMaxBatchDescs beams each
+    for (int cls = 1; cls <= 2; ++cls) {
+        std::vector<Item*> tiled;
+        for (Item& it : items) {
+            if (it.lp.shape.kind != 0) continue;
+            if (it.lp.shape.multi != 1 && it.lp.shape.multi != 2) return hipErrorInvalidValue;
+            if (it.lp.shape.multi == cls) tiled.push_back(&it);
         }
-        if (total > 0x7fffffffLL) return hipErrorInvalidValue;
-        hipError_t e;
-        if (use_persistent_loop()) {
-            const int maxg = persistent_max_grid(lds);
-            if (maxg <= 0) return hipErrorInvalidValue;
-            const int grid = static_cast<int>(std::min<long long>(total, maxg));
-            e = launch_persistent(blk, static_cast<int>(g1 - g0), static_cast<int>(total), lds,
-                                  grid, st);
-        } else {
-            e = launch_multi(blk, static_cast<int>(g1 - g0), static_cast<int>(total), lds, st);
+        for (size_t g0 = 0; g0 < tiled.size(); g0 += kMaxBatchDescs) {
+            const size_t g1 = std::min(tiled.size(), g0 + kMaxBatchDescs);
+            DescBlock blk{};
+            long long total = 0;
+            int lds = 0;
+            for (size_t i = g0; i < g1; ++i) {
+                BeamDesc& d = tiled[i]->d;
+                d.work_begin = total;   // a multiple of 8: see the multi-beam kernel
+                total += (static_cast<long long>(d.ntiles) * d.nblocks + 7) / 8 * 8;
+                lds = std::max(lds, tiled[i]->lp.lds);
+                blk.d[i - g0] = d;
+            }
+            if (total > 0x7fffffffLL) return hipErrorInvalidValue;
+            hipError_t e;
+            if (cls == 1 && use_persistent_loop()) {
+                const int maxg = persistent_max_grid(lds);
+                if (maxg <= 0) return hipErrorInvalidValue;
+                const int grid = static_cast<int>(std::min<long long>(total, maxg));
+                e = launch_persistent(blk, static_cast<int>(g1 - g0), static_cast<int>(total), lds,
+                                      grid, st);
+            } else {
+                e = launch_multi(blk, static_cast<int>(g1 - g0), static_cast<int>(total), lds, cls, st);
+            }
+            if (e != hipSuccess) return e;
         }
-        if (e != hipSuccess) return e;
     }
     for (const Item& it : items)
         if (it.lp.shape.kind != 0) {

@@ -59,7 +59,7 @@ struct BeamDesc {
     int out_bytes;            // 4: uint32 outputs; 1 or 2: uint8 / uint16 outputs or narrow sums
     int out_shift;            // outputs are min(sum >> out_shift, largest value of out_bytes)
     int dbuf;                 // tiled kernel: two LDS chunk buffers (one barrier per chunk)
-    int pad3_;
+    int in_nbits;             // input bit depth (multi-beam corner turn)
     long long g_xc;           // bytes
     long long g_rel;          // elements of rel
     long long g_base;         // elements of base
@@ -76,7 +76,7 @@ struct Shape {
     int m;          // 32-bit scratch words per lane
     int cc;         // channels staged per chunk
     int pi;         // 16-byte pieces per lane per staged row: row <= 64*pi pieces
-    int multi;      // also compiled into the multi-beam kernels
+    int multi;      // multi-beam kernel class it is also compiled into (0 = none)
 };
 
 // Shapes compiled into the library (index = shape id).
@@ -122,19 +122,26 @@ hipError_t launch_untiled_xc(const BeamDesc& d, int fmt, hipStream_t st);
 
 // Multi-beam launches over up to kMaxBatchDescs beams whose descriptors
 // travel in the kernel arguments (work_begin = prefix sum of ntiles*nblocks,
-// each rounded up to a multiple of 8).  Every
-// beam must use a shape marked multi; the LDS size is the largest any
-// beam needs.
+// each rounded up to a multiple of 8).  Every beam of a launch must use a
+// shape of the launch's multi-beam class (shape.multi): class 1 holds 8-wave
+// shapes, class 2 the 16-wave ones; the LDS size is the largest any beam
+// needs.
 constexpr int kMultiWaves = 8;
+__host__ __device__ constexpr int multi_waves(int cls) { return cls == 2 ? 16 : 8; }
 constexpr int kMaxBatchDescs = 16;
 struct DescBlock {
     BeamDesc d[kMaxBatchDescs];
 };
 static_assert(sizeof(DescBlock) + 16 <= 4096, "multi-beam descriptors must fit the kernel arguments");
-// One workgroup per work item of every beam in one launch.
-hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
+
+// Corner turns (no scrunching) of blk.d[0 .. nbeams) in one launch, each as
+// launch_unpack with d.in_nbits as the bit depth.
+hipError_t launch_unpack_multi(const DescBlock& blk, int nbeams, hipStream_t st);
+// One workgroup per work item of every beam in one launch (cls = the
+// beams' multi-beam class).
+hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int lds_bytes, int cls,
                         hipStream_t st);
-// Grid sized to the machine, workgroups looping over the items.
+// Grid sized to the machine, workgroups looping over the items (class 1).
 hipError_t launch_persistent(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
                              int grid, hipStream_t st);
 int persistent_max_grid(int lds_bytes);

@@ -129,12 +129,11 @@ struct Store {
 // the channel's scratch row (killed channels have none).  Requires
 // row_bytes % 4 == 0 and 4-byte aligned input rows.
 template <int NBITS>
-__global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
+__device__ __forceinline__ void unpack_tile(const BeamDesc& b, long long bx, int by, uint8_t* tile)
 {
     using S = Store<NBITS>;
-    __shared__ __attribute__((aligned(16))) uint8_t tile[kUC * S::kPitch];
-    const long long t0 = (long long)blockIdx.x * kUT;
-    const int c0 = blockIdx.y * kUC;
+    const long long t0 = bx * kUT;
+    const int c0 = by * kUC;
     constexpr int WPR = kUC * NBITS / 32;          // 32-bit words per row segment
     constexpr int CPW = 32 / NBITS;                // channels per word
     // item = (row quad, word): four rows of one word -> CPW channels x 4 times
@@ -200,12 +199,41 @@ __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
         *reinterpret_cast<u32x4*>(b.xc + (long long)row * b.pitch + byte0 + 16 * p) = val;
     }
     // the padding rows (live channels up to a multiple of 8) read as zeros
-    if (b.pad_row >= 0 && blockIdx.y == 0 && threadIdx.x < PPR * (b.nact - b.pad_row)) {
+    if (b.pad_row >= 0 && by == 0 && threadIdx.x < PPR * (b.nact - b.pad_row)) {
         const int r = b.pad_row + threadIdx.x / PPR;
         const int p = threadIdx.x % PPR;
         if (t0 + 16LL * S::kSamplesPerByte * p < b.nsamps)
             *reinterpret_cast<u32x4*>(b.xc + (long long)r * b.pitch + byte0 + 16 * p) =
                 u32x4{0u, 0u, 0u, 0u};
+    }
+}
+
+template <int NBITS>
+__global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t tile[kUC * Store<NBITS>::kPitch];
+    unpack_tile<NBITS>(b, blockIdx.x, blockIdx.y, tile);
+}
+
+// Corner turns of up to kMaxBatchDescs beams in one launch: workgroup i
+// takes unit i of the beams' (time tile, channel tile) units, numbered beam
+// by beam; the beam's input bit depth (b.in_nbits) picks the unpack.
+__global__ __launch_bounds__(256) void k_unpack_multi(DescBlock blk, int nbeams)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t tile[kUC * Store<8>::kPitch];
+    long long id = blockIdx.x;
+    for (int i = 0; i < nbeams; ++i) {
+        const BeamDesc& b = blk.d[i];
+        const long long gx = (b.nsamps + kUT - 1) / kUT;
+        const long long units = gx * ((b.nchans + kUC - 1) / kUC);
+        if (id < units) {
+            const long long bx = id % gx;
+            const int by = (int)(id / gx);
+            if (b.in_nbits == 2) unpack_tile<2>(b, bx, by, tile);
+            else unpack_tile<8>(b, bx, by, tile);
+            return;
+        }
+        id -= units;
     }
 }
 
@@ -1040,8 +1068,8 @@ __global__ __launch_bounds__(256) void k_zero(uint8_t* base, long long group_str
     X(kFmtNib, 8, 2, 5, 32, 2, 0)          \
     X(kFmtNib, 8, 4, 3, 16, 4, 0)          \
     X(kFmtNib, 16, 2, 3, 64, 2, 0)         \
-    X(kFmtNib, 16, 1, 5, 64, 2, 0)         \
-    X(kFmtNib, 16, 1, 5, 32, 2, 0)         \
+    X(kFmtNib, 16, 1, 5, 64, 2, 2)         \
+    X(kFmtNib, 16, 1, 5, 32, 2, 2)         \
     X(kFmtNib, 8, 1, 5, 32, 2, 0)          \
     X(kFmtByte, 8, 2, 5, 32, 2, 1)         \
     X(kFmtByte, 8, 2, 3, 16, 4, 1)         \
@@ -1049,7 +1077,7 @@ __global__ __launch_bounds__(256) void k_zero(uint8_t* base, long long group_str
     X(kFmtByte, 8, 4, 3, 32, 2, 0)         \
     X(kFmtByte, 8, 4, 5, 32, 2, 0)         \
     X(kFmtByte, 8, 2, 5, 64, 2, 0)         \
-    X(kFmtByte, 16, 2, 5, 64, 2, 0)        \
+    X(kFmtByte, 16, 2, 5, 64, 2, 2)        \
     X(kFmtByte, 4, 4, 5, 32, 2, 0)         \
     X(kFmtByteS, 8, 2, 3, 32, 2, 0)        \
     X(kFmtByteS, 8, 2, 3, 16, 4, 0)        \
@@ -1075,14 +1103,14 @@ const ShapeEntry kShapes[] = {
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
-// Multi-beam kernels: the shapes marked multi (all have kMultiWaves
-// waves).
-template <int FMT, int NW, int DPW, int M, int CC, int PM, int MULTI>
+// Multi-beam kernels: class c holds the shapes marked multi = c, all with
+// multi_waves(c) waves.
+template <int CLASS, int FMT, int NW, int DPW, int M, int CC, int PM, int MULTI>
 __device__ __forceinline__ bool run_if(int shape_id, int want, const BeamDesc& b, int tile,
                                        int block, uint32_t* lds)
 {
-    if constexpr (MULTI != 0) {
-        static_assert(NW == kMultiWaves, "multi-beam shapes share one workgroup size");
+    if constexpr (MULTI == CLASS) {
+        static_assert(NW == multi_waves(CLASS), "multi-beam shapes of a class share one workgroup size");
         if (shape_id == want) {
             tile_body<FMT, NW, DPW, M, CC, PM>(b, tile, block, 0, lds);
             return true;
@@ -1097,6 +1125,7 @@ __device__ __forceinline__ bool run_if(int shape_id, int want, const BeamDesc& b
 // applies within each beam: all eight XCDs sweep one beam at a time, each a
 // contiguous range of its (tile, DM block) items, as in a single-beam
 // launch.  Items past ntiles*nblocks are padding and return at once.
+template <int CLASS>
 __device__ __forceinline__ void run_item(const DescBlock& blk, int nbeams, int item, uint32_t* lds)
 {
     int bi = 0;
@@ -1112,7 +1141,7 @@ __device__ __forceinline__ void run_item(const DescBlock& blk, int nbeams, int i
     int id = 0;
     bool done = false;
 #define DEDISP_RUN(FMT, NW, DPW, M, CC, PM, MULTI) \
-    if (!done) done = run_if<FMT, NW, DPW, M, CC, PM, MULTI>(b.shape, id, b, tile, block, lds); \
+    if (!done) done = run_if<CLASS, FMT, NW, DPW, M, CC, PM, MULTI>(b.shape, id, b, tile, block, lds); \
     ++id;
     DEDISP_SHAPES(DEDISP_RUN)
 #undef DEDISP_RUN
@@ -1121,11 +1150,12 @@ __device__ __forceinline__ void run_item(const DescBlock& blk, int nbeams, int i
 
 // Multi-beam launch, one workgroup per work item of every beam (the
 // hardware dispatcher balances the uneven items as workgroups finish).
-__global__ __launch_bounds__(kMultiWaves * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_multi(DescBlock blk, int nbeams,
-                                                                  int total)
+template <int CLASS>
+__global__ __launch_bounds__(multi_waves(CLASS) * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_multi(
+    DescBlock blk, int nbeams, int total)
 {
     extern __shared__ uint32_t lds_dyn[];
-    run_item(blk, nbeams, (int)blockIdx.x, lds_dyn);
+    run_item<CLASS>(blk, nbeams, (int)blockIdx.x, lds_dyn);
 }
 
 // Persistent variant: a grid sized to the machine; workgroup g takes items
@@ -1135,7 +1165,7 @@ __global__ __launch_bounds__(kMultiWaves * 64) void k_persistent(DescBlock blk, 
 {
     extern __shared__ uint32_t lds_dyn[];
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        run_item(blk, nbeams, item, lds_dyn);
+        run_item<1>(blk, nbeams, item, lds_dyn);
         __syncthreads();                     // LDS is reused by the next item
     }
 }
@@ -1180,6 +1210,24 @@ hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st)
     const void* fn = nbits == 2 ? reinterpret_cast<const void*>(&k_unpack<2>)
                                 : reinterpret_cast<const void*>(&k_unpack<8>);
     return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, 0, st);
+}
+
+hipError_t launch_unpack_multi(const DescBlock& blk, int nbeams, hipStream_t st)
+{
+    if (nbeams <= 0 || nbeams > kMaxBatchDescs) return hipErrorInvalidValue;
+    long long units = 0;
+    for (int i = 0; i < nbeams; ++i) {
+        const BeamDesc& b = blk.d[i];
+        if (b.scrunch != 1 || (b.in_nbits != 2 && b.in_nbits != 8) || b.nsamps <= 0 || b.nchans <= 0)
+            return hipErrorInvalidValue;
+        units += ((b.nsamps + kUT - 1) / kUT) * ((b.nchans + kUC - 1) / kUC);
+    }
+    if (units > 0x7fffffffLL) return hipErrorInvalidValue;
+    DescBlock a0 = blk;
+    int a1 = nbeams;
+    void* args[] = {&a0, &a1};
+    return hipLaunchKernel(reinterpret_cast<const void*>(&k_unpack_multi), dim3((unsigned)units), dim3(256),
+                           args, 0, st);
 }
 
 hipError_t launch_tiled(const BeamDesc& d, const Shape& s, int lds_bytes, hipStream_t st)
@@ -1307,19 +1355,20 @@ int persistent_max_grid(int lds_bytes)
     return ncu * per_cu;
 }
 
-hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
+hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int lds_bytes, int cls,
                         hipStream_t st)
 {
-    if (nbeams <= 0 || nbeams > kMaxBatchDescs || total_work <= 0) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_multi),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
+    if (nbeams <= 0 || nbeams > kMaxBatchDescs || total_work <= 0 || (cls != 1 && cls != 2))
+        return hipErrorInvalidValue;
+    const void* fn = cls == 1 ? reinterpret_cast<const void*>(&k_multi<1>)
+                              : reinterpret_cast<const void*>(&k_multi<2>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
     if (e != hipSuccess) return e;
     DescBlock a0 = blk;
     int a1 = nbeams;
     int a2 = total_work;
     void* args[] = {&a0, &a1, &a2};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&k_multi), dim3(total_work),
-                           dim3(kMultiWaves * 64), args, (size_t)lds_bytes, st);
+    return hipLaunchKernel(fn, dim3(total_work), dim3(multi_waves(cls) * 64), args, (size_t)lds_bytes, st);
 }
 
 hipError_t launch_persistent(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,

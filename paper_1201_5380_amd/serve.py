@@ -4,7 +4,7 @@ Requests (one chunk of packed time-major rows of one stream) arrive at any
 time.  A scheduler thread admits them under a device-memory budget, groups
 the admitted head-of-line chunks of distinct streams into a *tick*, copies
 them to the device on a copy stream, and enqueues the tick as one batched
-launch (``dedisp_stream_push_many``: one corner turn per chunk, then a single
+launch (``dedisp_stream_push_many``: one corner-turn launch for all chunks, then a single
 multi-beam kernel over every chunk's tiles) on the compute stream, without
 waiting for earlier ticks: new requests are admitted while others are on the
 GPU and their work overlaps there.  A completion thread waits for each tick's
@@ -18,7 +18,9 @@ requests share its tick.
 
 Latency = completion of the request's outputs on the device minus its
 arrival time (host clock).  Output tensors stay on the device; the caller
-receives them in the finished Request.
+receives them in the finished Request, or in an ``on_done`` callback run by
+the completion thread as each request finishes (a consumer that drops the
+output there lets the device allocator reuse its memory for later ticks).
 """
 from __future__ import annotations
 
@@ -71,6 +73,24 @@ class GpuExecutor:
         self.copy_stream = torch.cuda.Stream(device=self.device)
         self.compute_stream = torch.cuda.Stream(device=self.device)
 
+    def tune(self, nsamps: int, cache_path: str | None = None):
+        """Pick each distinct plan's tile shape by timing the candidates on a
+        zero chunk of `nsamps` rows (the integer sums take the same time
+        whatever the data).  Streams read their plan's shape at every push, so
+        later ticks use the tuned shapes."""
+        torch = self.torch
+        seen = set()
+        for p in self.plans:
+            if id(p) in seen:
+                continue
+            seen.add(id(p))
+            n = max(int(nsamps), p.max_delay + 1)
+            inp = torch.zeros(n * p.row_bytes, dtype=torch.uint8, device=self.device)
+            out = torch.empty((p.ndm, n - p.max_delay), dtype=torch.int32, device=self.device)
+            p.tune(inp, out, n, cache_path=cache_path)
+            del inp, out
+        torch.cuda.synchronize(self.device)
+
     def request_bytes(self, stream_id: int, nsamps: int) -> int:
         p = self.plans[stream_id]
         return nsamps * p.row_bytes + p.ndm * nsamps * 4
@@ -114,8 +134,13 @@ class Server:
     """Admission, per-stream ordering and continuous batching (see module docstring)."""
 
     def __init__(self, executor, nstreams: int, budget_bytes: int, max_tick: int = 16,
-                 max_inflight_ticks: int = 4, admit_timeout_s: float | None = None):
+                 max_inflight_ticks: int = 4, admit_timeout_s: float | None = None,
+                 on_done=None):
         self.ex = executor
+        self.on_done = on_done
+        self._in_callbacks = 0                    # finished ticks whose callbacks still run
+        self._launching = 0                       # ticks taken from the queues, not yet in flight
+        self.callback_errors = []                 # (request, repr of what on_done raised)
         self.nstreams = int(nstreams)
         self.budget = int(budget_bytes)
         self.max_tick = int(max_tick)
@@ -179,7 +204,7 @@ class Server:
         """Wait until every submitted request has finished."""
         t_end = None if timeout is None else time.perf_counter() + timeout
         with self._lock:
-            while any(self.fifo) or self.inflight:
+            while any(self.fifo) or self.inflight or self._launching or self._in_callbacks:
                 left = None if t_end is None else t_end - time.perf_counter()
                 if left is not None and left <= 0:
                     raise TimeoutError("drain timed out")
@@ -232,6 +257,7 @@ class Server:
                 if not tick:
                     self._lock.wait(0.001)
                     continue
+                self._launching += 1
             t_launch = time.perf_counter()
             try:
                 handle = self.ex.launch(tick)
@@ -239,6 +265,7 @@ class Server:
             except Exception as e:                  # the tick fails, its memory is released
                 handle, err = None, e
             with self._lock:
+                self._launching -= 1
                 for r in tick:
                     r.t_launch = t_launch
                 if err is not None:
@@ -270,9 +297,23 @@ class Server:
                     r.t_done = t_done
                     r.status = DONE
                     self.used -= r.nbytes
-                    r.done.set()
                     self.finished.append(r)
+                self._in_callbacks += 1
                 self._lock.notify_all()
+            # outside the lock: the callback may take its time
+            try:
+                for r in tick:
+                    if self.on_done is not None:
+                        try:
+                            self.on_done(r)
+                        except Exception as e:      # a failing consumer must not stop the server
+                            with self._lock:
+                                self.callback_errors.append((r, repr(e)))
+                    r.done.set()
+            finally:
+                with self._lock:
+                    self._in_callbacks -= 1
+                    self._lock.notify_all()
 
     # ------------------------------------------------------------- metrics
     def stats(self):

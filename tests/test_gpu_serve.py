@@ -35,8 +35,9 @@ def test_alone_equals_in_the_mix(native, cuda):
         chunks[sid].append(synth.pack(codes, p.nbits).reshape(L, p.row_bytes))
         order.append((sid, len(chunks[sid]) - 1))
 
-    srv = Server(GpuExecutor(plans), nstreams, budget_bytes=8 << 30, max_tick=4,
-                 max_inflight_ticks=3).start()
+    ex = GpuExecutor(plans)
+    ex.tune(1 << 14)            # tuned shapes, possibly of either multi-beam class
+    srv = Server(ex, nstreams, budget_bytes=8 << 30, max_tick=4, max_inflight_ticks=3).start()
     reqs = {}
     for i, (sid, j) in enumerate(order):
         reqs[(sid, j)] = srv.submit(sid, chunks[sid][j])

@@ -111,18 +111,33 @@ def test_stream_reset_and_invalid_history(native, cuda):
     assert s.state() == (0, 0)
 
 
-def test_push_many_equals_each_stream_alone(native, cuda):
+# 16-wave shapes, compiled into the second multi-beam kernel class
+_WIDE = {2: dict(kind=0, waves=16, dms_per_wave=1, words_per_lane=5, chunk_chans=64),
+         8: dict(kind=0, waves=16, dms_per_wave=2, words_per_lane=5, chunk_chans=64)}
+
+
+@pytest.mark.parametrize("wide", [False, True])
+def test_push_many_equals_each_stream_alone(native, cuda, wide):
+    """Chunks of several streams in one batched launch equal the one-shot
+    transform of each stream; with `wide`, every other stream uses a 16-wave
+    shape, so one tick launches both multi-beam kernel classes."""
     import torch
     specs = [(2, 1024, 32, 1000.0), (8, 512, 20, 300.0), (2, 256, 48, 200.0), (8, 1024, 8, 50.0),
-             (2, 1024, 32, 1000.0)]
+             (2, 1024, 32, 1000.0), (8, 512, 24, 60.0), (8, 256, 16, 40.0)]
     plans, rngs, streams, packs, pos = [], [], [], [], []
     for i, (nb, nc, nd, dmx) in enumerate(specs):
         p, r = _stream_case(nb, nc, nd, dmx, 40 + i)
+        if wide and i % 2 == 0 and p.tile_config()["kind"] == 0:
+            p.set_tile_config(_WIDE[nb])
         plans.append(p)
         streams.append(Stream(p))
         n = 3 * p.max_delay + 9000
         packs.append(synth.pack(_codes(r, n, nc, nb), nb))
         pos.append(0)
+    if wide:
+        # 2- and 8-bit beams on 16-wave shapes beside 8-wave ones
+        waves = [(p.nbits, p.tile_config()["waves"]) for p in plans if p.tile_config()["kind"] == 0]
+        assert {(2, 16), (8, 16), (8, 8)} <= set(waves), waves
     outs = [[] for _ in specs]
     rng = np.random.default_rng(77)
     for step in range(5):

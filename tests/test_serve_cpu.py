@@ -151,3 +151,34 @@ def test_cancel_before_admission_and_failure_releases_memory():
     assert srv.used == 0 and not srv.cancel(a)
     st = srv.stats()
     assert st["failed"] == 1 and st["cancelled"] == 1
+
+
+def test_on_done_sees_every_request_before_drain_returns():
+    """The completion callback runs once per finished request, before the
+    request's done event and before drain() returns; a consumer may drop the
+    output there."""
+    plans = _plans()
+    ex = FakeExecutor(plans, service_s=0.01)
+    seen = []
+
+    def consume(r):
+        assert not r.done.is_set() and r.status == DONE
+        assert (r.out is not None) == (r.n_out > 0)
+        seen.append((r.stream_id, r.seq, r.n_out))
+        r.out = None
+        if r.seq == 1 and r.stream_id == 0:
+            raise RuntimeError("consumer failure")
+
+    srv = Server(ex, len(plans), budget_bytes=10**9, max_tick=2, on_done=consume).start()
+    rng = np.random.default_rng(3)
+    reqs = []
+    for i in range(12):
+        sid = i % len(plans)
+        n = int(rng.integers(20, 60))
+        reqs.append(srv.submit(sid, np.zeros((n, plans[sid].row_bytes), np.uint8)))
+    srv.drain(timeout=30)
+    srv.stop()
+    assert sorted(seen) == sorted((r.stream_id, r.seq, r.n_out) for r in reqs)
+    assert all(r.status == DONE and r.out is None and r.done.is_set() for r in reqs)
+    # a raising consumer is recorded and the server keeps going
+    assert [(r.stream_id, r.seq) for r, _ in srv.callback_errors] == [(0, 1)]
