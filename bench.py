@@ -225,7 +225,7 @@ def bench_serve(torch, dev, seconds):
         r.out = None
 
     def run(open_loop):
-        ex = GpuExecutor([plan] * nstreams, device=dev)
+        ex = GpuExecutor([plan] * nstreams, device=dev, max_chunk=1 << 18)
         ex.tune(1 << 18)
         srv = Server(ex, nstreams, budget_bytes=64 << 30, max_tick=16, max_inflight_ticks=4,
                      on_done=consume).start()

@@ -296,6 +296,14 @@ dedisp_status dedisp_stream_push_many(dedisp_stream* streams, const void* const*
                                       const size_t* out_row_strides, size_t* n_outs, int n,
                                       void* stream);
 
+/* Size the stream's channel-major scratch for pushes of up to max_chunk rows
+ * with the plan's current tile shape (call after tuning the plan).  A push
+ * longer than any seen before otherwise grows the scratch, and freeing the
+ * old one waits for the whole device: in a serving loop that drains the
+ * queued work.  Synchronous; call it before the stream's first push or when
+ * no work of the stream is in flight.  Errors: INVALID_ARG, OOM. */
+dedisp_status dedisp_stream_reserve(dedisp_stream s, size_t max_chunk);
+
 /* Rows currently held as history, and total rows pushed since creation or
  * the last reset / set_history. */
 dedisp_status dedisp_stream_get_state(dedisp_stream s, size_t* history_rows,

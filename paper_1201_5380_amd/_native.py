@@ -76,6 +76,7 @@ SIGNATURES = {
     "dedisp_stream_create": (_i, [_vp, ctypes.POINTER(_vp)]),
     "dedisp_stream_destroy": (None, [_vp]),
     "dedisp_stream_push": (_i, [_vp, _vp, _sz, _vp, _sz, _psz, _vp]),
+    "dedisp_stream_reserve": (_i, [_vp, _sz]),
     "dedisp_stream_push_many": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _psz,
                                      ctypes.POINTER(_vp), _psz, _psz, _i, _vp]),
     "dedisp_stream_get_state": (_i, [_vp, _psz, _pu64]),

@@ -237,6 +237,11 @@ class Stream:
         except Exception:
             pass
 
+    def reserve(self, max_chunk: int):
+        """Size the stream's scratch for pushes of up to max_chunk rows with the
+        plan's current tile shape (synchronous; call after tuning the plan)."""
+        check(lib().dedisp_stream_reserve(self._h, int(max_chunk)), "dedisp_stream_reserve")
+
     def push(self, chunk, out=None, out_row_stride: int = 0, nsamps: int | None = None,
              stream=None):
         """Push a device chunk; returns (n_out, out) where out[:, :n_out] is new output."""

@@ -162,6 +162,24 @@ void dedisp_stream_destroy(dedisp_stream s)
     delete s;
 }
 
+dedisp_status dedisp_stream_reserve(dedisp_stream s, size_t max_chunk)
+{
+    dedisp_status st = check_stream(s);
+    if (st != DEDISP_OK) return st;
+    if (max_chunk == 0 || max_chunk > (1ULL << 40)) return fail(DEDISP_ERR_INVALID_ARG, "bad max_chunk");
+    // the longest push scans max_delay history rows plus the chunk, with the
+    // shape a batched push (multi-beam shapes) or a single push resolves to
+    const long long n = static_cast<long long>(s->max_delay + max_chunk);
+    for (bool multi : {true, false}) {
+        LaunchPlan lp;
+        st = resolve_launch(s->plan, s->plan->cfg, false, lp, multi);
+        if (st != DEDISP_OK) return st;
+        st = ensure_xc(*s->plan, s->xc, n, lp);
+        if (st != DEDISP_OK) return st;
+    }
+    return DEDISP_OK;
+}
+
 dedisp_status dedisp_stream_push(dedisp_stream s, const void* chunk, size_t nsamps,
                                  uint32_t* out, size_t stride, size_t* n_out, void* stream)
 {

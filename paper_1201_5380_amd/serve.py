@@ -63,7 +63,11 @@ class Request:
 class GpuExecutor:
     """Runs ticks on the GPU through the library's streams (one per service stream)."""
 
-    def __init__(self, plans, device="cuda:0"):
+    def __init__(self, plans, device="cuda:0", max_chunk: int | None = None):
+        """max_chunk: longest chunk any request will carry; when given, every
+        stream's scratch is sized for it up front (and again after tune()), so
+        no push has to grow it -- growing frees the old scratch, which waits
+        for the whole device and drains the ticks queued behind it."""
         import torch
         from .api import Stream
         self.torch = torch
@@ -72,6 +76,13 @@ class GpuExecutor:
         self.streams = [Stream(p) for p in self.plans]
         self.copy_stream = torch.cuda.Stream(device=self.device)
         self.compute_stream = torch.cuda.Stream(device=self.device)
+        self.max_chunk = max_chunk
+        self._reserve()
+
+    def _reserve(self):
+        if self.max_chunk:
+            for s in self.streams:
+                s.reserve(self.max_chunk)
 
     def tune(self, nsamps: int, cache_path: str | None = None):
         """Pick each distinct plan's tile shape by timing the candidates on a
@@ -90,6 +101,7 @@ class GpuExecutor:
             p.tune(inp, out, n, cache_path=cache_path)
             del inp, out
         torch.cuda.synchronize(self.device)
+        self._reserve()
 
     def request_bytes(self, stream_id: int, nsamps: int) -> int:
         p = self.plans[stream_id]

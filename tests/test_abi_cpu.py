@@ -132,6 +132,7 @@ def test_stream_and_batch_validation_precedes_hip(native):
     n = ctypes.c_size_t(7)
     assert L.dedisp_stream_push(None, None, 0, None, 0, ctypes.byref(n), None) == -1
     assert L.dedisp_stream_reset(None) == -1
+    assert L.dedisp_stream_reserve(None, 1 << 10) == -1
     from paper_1201_5380_amd._native import BeamStruct
     arr = (BeamStruct * 1)()
     assert L.dedisp_batch_create(arr, 1, None, None, ctypes.byref(out)) == -1   # NULL fields

@@ -35,7 +35,7 @@ def test_alone_equals_in_the_mix(native, cuda):
         chunks[sid].append(synth.pack(codes, p.nbits).reshape(L, p.row_bytes))
         order.append((sid, len(chunks[sid]) - 1))
 
-    ex = GpuExecutor(plans)
+    ex = GpuExecutor(plans, max_chunk=1 << 14)
     ex.tune(1 << 14)            # tuned shapes, possibly of either multi-beam class
     srv = Server(ex, nstreams, budget_bytes=8 << 30, max_tick=4, max_inflight_ticks=3).start()
     reqs = {}
