@@ -28,6 +28,9 @@ if ROOT not in sys.path:
 # MI355X peaks used for the roofline: 256 CUs x 64 int32 lane-adds/clock x
 # 2.4 GHz (one VALU add per lane per clock) and 8 TB/s HBM3E.
 INT_ADD_PEAK_TADDS = 256 * 64 * 2.4e9 / 1e12
+# the sources the tiled kernel is compiled from (their digest keys the
+# committed HBM-traffic counters to the code they were taken on)
+KERNEL_SOURCES = ("dedisp_kernels.hip", "dedisp_device.h")
 HBM_PEAK_GBS = 8000.0
 
 
@@ -194,6 +197,34 @@ def bench_tree(torch, dev, beam, inp, nsamps, steps, nsub=32):
                     "ms": t_ms, "nout": nout, "outputs_per_s": len(dms) * nout / (t_ms * 1e-3),
                     "direct_ms_same_trials": d_ms, "speedup_vs_direct": d_ms / t_ms}
     return res
+
+
+def bench_large(torch, dev, steps):
+    """The large 8-bit beam: 2^20 samples x 4096 channels of 54.6 us,
+    f_top 1500 MHz, df -0.09765625 MHz, 2048 DMs in [0, 2000); input made on
+    the device (seeded rint(N(128, 20)) clipped to [0, 255])."""
+    from paper_1201_5380_amd import Plan, synth
+    nsamps, nchans, ndm = 1 << 20, 4096, 2048
+    plan = Plan(nchans, 54.6e-6, 1500.0, -0.09765625, 8).set_dm_list(synth.dm_list_linear(ndm, 2000.0))
+    inp = synth.device_codes(nsamps, nchans, 8, seed=2, device=dev, sd=20.0).view(-1)
+    nout = nsamps - plan.max_delay
+    out = torch.empty((ndm, nout), dtype=torch.int32, device=dev)
+    plan.tune(inp, out, nsamps)
+    plan.execute(inp, nsamps, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        plan.execute(inp, nsamps, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    adds = ndm * nout * nchans / (ms * 1e-3)
+    return {"workload": "large beam: 8-bit, 4096 ch, 1048576 samples x 54.6 us, 2048 DMs in [0, 2000), "
+                        "f_top 1500 MHz, df -0.09765625 MHz",
+            "ms": ms, "nout": nout, "outputs_per_s": ndm * nout / (ms * 1e-3),
+            "channel_adds_per_s": adds, "alu_frac": adds / (INT_ADD_PEAK_TADDS * 1e12),
+            "tile": plan.tile_config()}
 
 
 def bench_serve(torch, dev, seconds):
@@ -397,8 +428,11 @@ def main():
         try:
             import hashlib
             tj = json.load(open(args.traffic_json))
-            src = os.path.join(ROOT, "paper_1201_5380_amd", "csrc", "dedisp_kernels.hip")
-            sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+            csrc = os.path.join(ROOT, "paper_1201_5380_amd", "csrc")
+            h = hashlib.sha256()
+            for f in KERNEL_SOURCES:
+                h.update(open(os.path.join(csrc, f), "rb").read())
+            sha = h.hexdigest()
             if (tj.get("workload") == beam.name and tj.get("tile") == cfg
                     and tj.get("kernel_source_sha256") == sha):
                 traffic = tj.get("hbm_bytes_per_launch")
@@ -452,6 +486,8 @@ def main():
                                           max(3, args.steps // 2), mean_ms)
         torch.cuda.empty_cache()
         result["tree"] = bench_tree(torch, dev, beam, inp, nsamps, max(3, args.steps // 2))
+        torch.cuda.empty_cache()
+        result["large_beam"] = bench_large(torch, dev, 3)
         torch.cuda.empty_cache()
         result["batched"] = bench_batch(torch, dev, max(3, args.steps // 4))
         torch.cuda.empty_cache()

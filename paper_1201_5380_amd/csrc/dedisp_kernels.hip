@@ -51,64 +51,11 @@
 // Multi-beam kernels (k_multi, k_persistent): one launch over the (beam,
 // time tile, DM block) work items of up to 16 beams that may differ in
 // channel count, bit depth, length, DM list and tile shape.
-#include "dedisp_internal.h"
+#include "dedisp_device.h"
 
 namespace dedisp {
 
 namespace {
-
-__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// Native 4 x 32-bit vector (one 16-byte load or store); unlike HIP's uint4
-// struct it stays in registers when held in arrays.
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ long long wave_uniform64(long long x)
-{
-    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(x & 0xffffffffLL));
-    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(x >> 32));
-    return (long long)(((unsigned long long)hi << 32) | lo);
-}
-
-template <typename T>
-__device__ __forceinline__ T* wave_uniform_ptr(T* p)
-{
-    return reinterpret_cast<T*>(wave_uniform64(reinterpret_cast<long long>(p)));
-}
-
-__device__ __forceinline__ int lane_value(int v, int lane)
-{
-    return __builtin_amdgcn_readlane(v, lane);
-}
-
-// An output value at the descriptor's width: shifted right, then saturated.
-__device__ __forceinline__ uint32_t out_value(uint32_t v, int shift, int bytes)
-{
-    v >>= shift;
-    if (bytes == 1) return v < 0xFFu ? v : 0xFFu;
-    if (bytes == 2) return v < 0xFFFFu ? v : 0xFFFFu;
-    return v;
-}
-
-// Address of input row r in the two-segment virtual input.
-__device__ __forceinline__ const uint8_t* row_ptr(const BeamDesc& b, long long r)
-{
-    return r < b.n0 ? b.in0 + r * (long long)b.row_bytes
-                    : b.in1 + (r - b.n0) * (long long)b.row_bytes;
-}
-
-// Map the hardware workgroup index to a logical one so that the workgroups
-// dispatched to one XCD (round-robin over 8 XCDs) get a contiguous range of
-// logical indices, i.e. all DM blocks of the same few time tiles, which read
-// overlapping input windows through that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int i, int n)
-{
-    constexpr int kXcds = 8;
-    const int per = n / kXcds, rem = n % kXcds;
-    const int x = i % kXcds, k = i / kXcds;
-    return x < rem ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
-}
 
 // ------------------------------------------------------------ corner turn
 
@@ -853,193 +800,6 @@ __global__ __launch_bounds__(256) void k_untiled_xc(BeamDesc b)
     }
 }
 
-// ---------------------------------------------------------------- tree
-
-// Stage 1 of the piecewise linear tree (Section 3).  Workgroup (tile,
-// sub-band n) loads the sub-band's nsub scratch rows for samples
-// [t0, t0 + T + nsub) into LDS as 16-bit values, two per 32-bit word, and
-// applies the tree's steps i = 0 .. k-1 out of place (double buffer):
-//   B[2v][t]   = A[Phi(r, 2v)][t] + A[Phi(r, 2v+1)][t + Theta(i, 2v)]
-//   B[2v+1][t] = A[Phi(r, 2v)][t] + A[Phi(r, 2v+1)][t + Theta(i, 2v+1)]
-// with r = 2^i, Theta(i, v) = ((v mod 2^{i+1}) + 1) / 2 and
-// Phi(r, v) = (v mod 2) r + v/2 + (v/(2r)) r.  Row d' of the result is the
-// sub-band at tree DM d', written for t < len1.  Sums stay below 2^16 (nsub
-// codes), so a 32-bit add sums two samples without a carry between them.
-//
-// Theta(i, 2v+1) = Theta(i, 2v) + 1, so both outputs of a pair read the
-// same three samples of the second row: one aligned word pair q, q+1 and a
-// 16-bit realignment (v_alignbit) give both shifted words.  Every step
-// computes all LW words of every row; words past a step's valid length only
-// ever feed words past the next step's valid length (each step reads at t
-// and above), so the T samples stored at the end are exact.  Rows carry
-// RS >= LW + nsub/4 words so the shifted reads stay inside the row.
-__host__ __device__ constexpr int tree_tile_len(int nsub) { return 8192 / nsub; }
-__host__ __device__ constexpr int tree_row_words(int nsub)
-{
-    return ((tree_tile_len(nsub) + nsub) / 2 + nsub / 4 + 1 + 3) / 4 * 4;
-}
-
-__device__ __forceinline__ int tree_theta(int i, int v) { return ((v & ((2 << i) - 1)) + 1) >> 1; }
-// Phi(2^i, v), with v / 2^{i+1} taken as a shift
-__device__ __forceinline__ int tree_phi(int i, int v) { return ((v & 1) << i) + (v >> 1) + ((v >> (i + 1)) << i); }
-
-template <int FMT, int NSUB>
-__global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long long out_pitch, long long len1)
-{
-    constexpr int T = tree_tile_len(NSUB);
-    constexpr int L = T + NSUB;                    // samples loaded per row (>= T + NSUB - 1)
-    constexpr int LW = L / 2;                      // words computed per row
-    constexpr int RS = tree_row_words(NSUB);       // LDS row stride in words
-    constexpr int K = NSUB == 8 ? 3 : NSUB == 16 ? 4 : NSUB == 32 ? 5 : NSUB == 64 ? 6 : 7;
-    static_assert((1 << K) == NSUB, "sub-band width must be a power of two");
-    static_assert(RS >= LW + NSUB / 4 && RS % 4 == 0, "row stride covers the shifted reads");
-    extern __shared__ __align__(16) uint32_t tw[];             // [2][NSUB][RS]
-    uint32_t* A = tw;
-    uint32_t* B = tw + NSUB * RS;
-    const long long t0 = (long long)blockIdx.x * T;
-    const int n = blockIdx.y;
-    // load: 32-bit scratch words, spread to two 16-bit samples per LDS word
-    constexpr int SPW = fmt_samples_per_word(FMT);
-    constexpr int WPR = L / SPW;                   // scratch words per row
-    static_assert(L % SPW == 0, "whole words per row");
-    // all of a thread's loads are issued before the first LDS store
-    constexpr int NLD = (NSUB * WPR + 255) / 256;
-    uint32_t ld[NLD];
-#pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-        const int it = threadIdx.x + 256 * k;
-        if (it < NSUB * WPR) {
-            const int j = it / WPR, w = it % WPR;
-            const uint8_t* row = b.xc + (long long)(n * NSUB + j) * b.pitch;
-            ld[k] = *reinterpret_cast<const uint32_t*>(row + (t0 / SPW + w) * 4);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < NLD; ++k) {
-        const int it = threadIdx.x + 256 * k;
-        if (it >= NSUB * WPR) break;
-        const int j = it / WPR, w = it % WPR;
-        const uint32_t v = ld[k];
-        uint32_t* dst = A + j * RS + w * (SPW / 2);
-        if constexpr (FMT == kFmtNib) {
-            u32x4 q;
-            q.x = (v & 0xFu) | ((v & 0xF0u) << 12);
-            q.y = ((v >> 8) & 0xFu) | ((v & 0xF000u) << 4);
-            q.z = ((v >> 16) & 0xFu) | ((v >> 4) & 0xF0000u);
-            q.w = ((v >> 24) & 0xFu) | ((v >> 12) & 0xF0000u);
-            *reinterpret_cast<u32x4*>(dst) = q;
-        } else {
-            dst[0] = (v & 0xFFu) | ((v & 0xFF00u) << 8);
-            dst[1] = ((v >> 16) & 0xFFu) | ((v >> 8) & 0xFF0000u);
-        }
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int i = 0; i < K; ++i) {
-        // flattened (pair v, word w): consecutive lanes on consecutive words
-        for (int it = threadIdx.x; it < (NSUB / 2) * LW; it += 256) {
-            const int v = it / LW, w = it - v * LW;
-            const uint32_t* lo = A + tree_phi(i, 2 * v) * RS;
-            const uint32_t* hi = A + tree_phi(i, 2 * v + 1) * RS;
-            const int th = tree_theta(i, 2 * v);
-            const int q = w + (th >> 1);
-            const uint32_t a = lo[w], h0 = hi[q], h1 = hi[q + 1];
-            const uint32_t mid = __builtin_amdgcn_alignbit(h1, h0, 16);
-            B[(2 * v) * RS + w] = a + ((th & 1) ? mid : h0);
-            B[(2 * v + 1) * RS + w] = a + ((th & 1) ? h1 : mid);
-        }
-        __syncthreads();
-        uint32_t* tmp = A;
-        A = B;
-        B = tmp;
-    }
-    // store rows n*NSUB + d', samples t0 .. t0 + T - 1 below len1, 8 per
-    // 16-byte store
-    for (int it = threadIdx.x; it < NSUB * (T / 8); it += 256) {
-        const int dp = it / (T / 8), t = 8 * (it % (T / 8));
-        const long long tg = t0 + t;
-        if (tg >= len1) continue;
-        const u32x4 val = *reinterpret_cast<const u32x4*>(A + dp * RS + t / 2);
-        uint16_t* orow = reinterpret_cast<uint16_t*>(out + (long long)(n * NSUB + dp) * out_pitch);
-        if (tg + 8 <= len1) {
-            *reinterpret_cast<u32x4*>(orow + tg) = val;
-        } else {
-            const uint32_t wv[4] = {val.x, val.y, val.z, val.w};
-            for (int e = 0; tg + e < len1; ++e) orow[tg + e] = (uint16_t)(wv[e >> 1] >> (16 * (e & 1)));
-        }
-    }
-}
-
-// Stage 2 of the piecewise linear tree (Section 3, the piecewise linear
-// combination of sub-bands): out[d][t] = sum over sub-bands n of
-// S[rowsel[d][n]][t + table[d][n]], S the 16-bit stage-1 rows (d.xc, pitch
-// d.pitch bytes).  A lane sums 8 consecutive outputs of one trial: per term
-// five aligned 32-bit words (a 16-byte load and one more) and four 16-bit
-// realignments give the 8 shifted samples as 4 words of two 16-bit lanes,
-// added without a carry between the lanes and moved to 32-bit sums every
-// `flush` terms (flush * largest row value < 2^16).  The shift parity is
-// that of the trial's delay, uniform over the wave.
-//
-// Work items (time tile of 2048 outputs, trial) are ordered tile-major,
-// trial-minor and cut into 8 contiguous ranges, one per XCD (the hardware
-// hands workgroup i to XCD i mod 8): the workgroups in flight on an XCD
-// cover neighbouring trials of one tile, which share most of their tree
-// rows, so the rows stay in that XCD's L2.
-__global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, long long per_xcd)
-{
-    const long long o = (long long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    const long long ndm = b.ndm;
-    if (o >= ndm * ((b.nout + 2047) / 2048)) return;   // no barriers below
-    const int d = (int)(o % ndm);
-    const long long t = (o / ndm) * 2048 + threadIdx.x * 8;
-    if (t >= b.nout) return;
-    const int nsb = b.nact;
-    const int32_t* rows = b.rowsel + (size_t)d * nsb;
-    const int32_t* dly = b.table + (size_t)d * nsb;
-    uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    for (int n0 = 0; n0 < nsb; n0 += flush) {
-        const int n1 = min(nsb, n0 + flush);
-        uint32_t p0 = 0u, p1 = 0u, p2 = 0u, p3 = 0u;
-#pragma unroll 4
-        for (int n = n0; n < n1; ++n) {
-            const long long s = t + dly[n];
-            const uint32_t* w = reinterpret_cast<const uint32_t*>(b.xc + (long long)rows[n] * b.pitch) + (s >> 1);
-            u32x4 v;
-            __builtin_memcpy(&v, w, sizeof(v));
-            const uint32_t v4 = w[4];
-            const int sh = (int)(s & 1) * 16;
-            p0 += __builtin_amdgcn_alignbit(v.y, v.x, sh);
-            p1 += __builtin_amdgcn_alignbit(v.z, v.y, sh);
-            p2 += __builtin_amdgcn_alignbit(v.w, v.z, sh);
-            p3 += __builtin_amdgcn_alignbit(v4, v.w, sh);
-        }
-        acc[0] += p0 & 0xFFFFu; acc[1] += p0 >> 16;
-        acc[2] += p1 & 0xFFFFu; acc[3] += p1 >> 16;
-        acc[4] += p2 & 0xFFFFu; acc[5] += p2 >> 16;
-        acc[6] += p3 & 0xFFFFu; acc[7] += p3 >> 16;
-    }
-    if (b.out_bytes == 4) {
-        uint32_t* orow = b.out + (size_t)d * (size_t)b.out_stride;
-        if (t + 8 <= b.nout) {
-            const u32x4 lo4 = {acc[0] >> b.out_shift, acc[1] >> b.out_shift, acc[2] >> b.out_shift,
-                               acc[3] >> b.out_shift};
-            const u32x4 hi4 = {acc[4] >> b.out_shift, acc[5] >> b.out_shift, acc[6] >> b.out_shift,
-                               acc[7] >> b.out_shift};
-            __builtin_memcpy(orow + t, &lo4, sizeof(lo4));
-            __builtin_memcpy(orow + t + 4, &hi4, sizeof(hi4));
-        } else {
-            for (int e = 0; t + e < b.nout; ++e) orow[t + e] = acc[e] >> b.out_shift;
-        }
-    } else {
-        uint8_t* nrow = reinterpret_cast<uint8_t*>(b.out) + (long long)d * b.out_stride;
-        for (int e = 0; e < 8 && t + e < b.nout; ++e) {
-            const uint32_t v = out_value(acc[e], b.out_shift, b.out_bytes);
-            if (b.out_bytes == 1) nrow[t + e] = (uint8_t)v;
-            else reinterpret_cast<uint16_t*>(nrow)[t + e] = (uint16_t)v;
-        }
-    }
-}
-
 // ---------------------------------------------------------------- zero fill
 
 // Zero [base + g*group_stride, + bytes) for g = blockIdx.y with 16-byte
@@ -1280,51 +1040,6 @@ hipError_t launch_untiled_xc(const BeamDesc& d, int fmt, hipStream_t st)
     return hipLaunchKernel(fn, dim3((unsigned)gx, gy, (unsigned)d.ngroups), dim3(256), args, 0, st);
 }
 
-int tree_tile(int nsub) { return tree_tile_len(nsub); }
-
-hipError_t launch_tree_combine(const BeamDesc& d, int flush, hipStream_t st)
-{
-    if (d.nout <= 0 || d.ndm <= 0 || d.nact <= 0 || flush < 1 || (d.pitch & 3) ||
-        (reinterpret_cast<uintptr_t>(d.xc) & 3) ||
-        (reinterpret_cast<uintptr_t>(d.out) & (d.out_bytes == 4 ? 3 : d.out_bytes - 1)))
-        return hipErrorInvalidValue;
-    const long long items = (long long)d.ndm * ((d.nout + 2047) / 2048);
-    const long long per_xcd = (items + 7) / 8;
-    if (8 * per_xcd > 0x7fffffffLL) return hipErrorInvalidValue;
-    BeamDesc a0 = d;
-    int a1 = flush;
-    long long a2 = per_xcd;
-    void* args[] = {&a0, &a1, &a2};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&k_tree_combine), dim3((unsigned)(8 * per_xcd)),
-                           dim3(256), args, 0, st);
-}
-
-hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, uint8_t* out, long long out_pitch,
-                       long long len1, hipStream_t st)
-{
-    if (len1 <= 0 || (out_pitch & 3) || (reinterpret_cast<uintptr_t>(out) & 3)) return hipErrorInvalidValue;
-    const long long T = tree_tile_len(nsub);
-    const long long gx = (len1 + T - 1) / T;
-    const long long gy = d.nchans / nsub;
-    if (gx <= 0 || gx > 0x7fffffffLL || gy <= 0 || gy > 65535) return hipErrorInvalidValue;
-    const void* fn = nullptr;
-#define DEDISP_TREE_CASE(F, N) \
-    if (fmt == F && nsub == N) fn = reinterpret_cast<const void*>(&k_tree<F, N>);
-    DEDISP_TREE_CASE(kFmtNib, 8) DEDISP_TREE_CASE(kFmtNib, 16) DEDISP_TREE_CASE(kFmtNib, 32)
-    DEDISP_TREE_CASE(kFmtNib, 64) DEDISP_TREE_CASE(kFmtNib, 128)
-    DEDISP_TREE_CASE(kFmtByte, 8) DEDISP_TREE_CASE(kFmtByte, 16) DEDISP_TREE_CASE(kFmtByte, 32)
-    DEDISP_TREE_CASE(kFmtByte, 64) DEDISP_TREE_CASE(kFmtByte, 128)
-#undef DEDISP_TREE_CASE
-    if (!fn) return hipErrorInvalidValue;
-    const size_t lds = 2ull * nsub * tree_row_words(nsub) * sizeof(uint32_t);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    BeamDesc a0 = d;
-    uint8_t* a1 = out;
-    long long a2 = out_pitch, a3 = len1;
-    void* args[] = {&a0, &a1, &a2, &a3};
-    return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, lds, st);
-}
 
 hipError_t launch_untiled(const BeamDesc& d, int nbits, hipStream_t st)
 {
