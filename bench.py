@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--no-systems", action="store_true",
                     help="skip the batched and serving measurements")
     ap.add_argument("--serve-seconds", type=float, default=12.0)
+    ap.add_argument("--legs", default="scrunched,subband,tree,large_beam,batched,serving",
+                    help="comma-separated systems legs to run after the headline transform")
     return ap.parse_args()
 
 
@@ -478,20 +480,19 @@ def main():
     }
     if not args.no_systems:
         del got, out
-        torch.cuda.empty_cache()
-        result["scrunched"] = bench_scrunched(torch, dev, plan, inp, nsamps,
-                                              max(3, args.steps // 2), mean_ms)
-        torch.cuda.empty_cache()
-        result["subband"] = bench_subband(torch, dev, plan, inp, nsamps,
-                                          max(3, args.steps // 2), mean_ms)
-        torch.cuda.empty_cache()
-        result["tree"] = bench_tree(torch, dev, beam, inp, nsamps, max(3, args.steps // 2))
-        torch.cuda.empty_cache()
-        result["large_beam"] = bench_large(torch, dev, 3)
-        torch.cuda.empty_cache()
-        result["batched"] = bench_batch(torch, dev, max(3, args.steps // 4))
-        torch.cuda.empty_cache()
-        result["serving"] = bench_serve(torch, dev, args.serve_seconds)
+        legs = {
+            "scrunched": lambda: bench_scrunched(torch, dev, plan, inp, nsamps, max(3, args.steps // 2), mean_ms),
+            "subband": lambda: bench_subband(torch, dev, plan, inp, nsamps, max(3, args.steps // 2), mean_ms),
+            "tree": lambda: bench_tree(torch, dev, beam, inp, nsamps, max(3, args.steps // 2)),
+            "large_beam": lambda: bench_large(torch, dev, 3),
+            "batched": lambda: bench_batch(torch, dev, max(3, args.steps // 4)),
+            "serving": lambda: bench_serve(torch, dev, args.serve_seconds),
+        }
+        for name in [x for x in args.legs.split(",") if x]:
+            if name not in legs:
+                raise SystemExit(f"unknown leg {name!r}; legs: {', '.join(legs)}")
+            torch.cuda.empty_cache()
+            result[name] = legs[name]()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(packed, nsamps, nchans, beam.nbits, table,
                                               args.cpu_seconds)

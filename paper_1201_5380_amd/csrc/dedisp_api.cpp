@@ -1009,10 +1009,12 @@ static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps
         HIP_TRY(hipMemcpy(p->d_tree_rows, p->tree_rows.data(), bytes, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(p->d_tree_delay, p->tree_delay.data(), bytes, hipMemcpyHostToDevice));
     }
-    // the tree kernel reads whole tiles past the last sample
+    // the tree kernel reads whole tiles past the last sample; tree rows are
+    // bytes while the largest sub-band sum (3 nsub for 2-bit codes) fits
     const long long pitch1 = xc_pitch(static_cast<long long>(nsamps) + dedisp::tree_tile(nsub) + nsub,
                                       p->fmt, 0);
-    const long long pitch2 = ((2 * len1 + 64) + 63) / 64 * 64;
+    const int ob = (p->nbits == 2 && nsub <= 64) ? 1 : 2;
+    const long long pitch2 = ((ob * len1 + 64) + 63) / 64 * 64;
     st = ensure_scratch(p->xc, static_cast<size_t>(pitch1) * p->nchans);
     if (st != DEDISP_OK) return st;
     st = ensure_scratch(p->sb_xc2, static_cast<size_t>(pitch2) * p->nchans);
@@ -1036,7 +1038,7 @@ static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps
     hipError_t e = dedisp::launch_unpack(d0, p->nbits, p->fmt, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     // stage 1: the tree's first log2(nsub) steps, 16-bit rows n*nsub + d'
-    e = dedisp::launch_tree(d0, p->fmt, nsub, p->sb_xc2.ptr, pitch2, len1, hs);
+    e = dedisp::launch_tree(d0, p->fmt, nsub, ob, p->sb_xc2.ptr, pitch2, len1, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     // stage 2: every trial sums, over the sub-bands, its tree row at its delay
     BeamDesc dg;
@@ -1057,7 +1059,7 @@ static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps
     dg.out_stride = static_cast<long long>(stride) * (dg.out_bytes == 4 ? 1 : dg.out_bytes);
     // 16-bit partial sums of at most 65535 / (largest row value) terms
     const int row_max = ((1 << p->nbits) - 1) * p->tree_nsub;
-    e = dedisp::launch_tree_combine(dg, 65535 / row_max, hs);
+    e = dedisp::launch_tree_combine(dg, ob, 65535 / row_max, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return DEDISP_OK;
 }

@@ -92,9 +92,10 @@ hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st);
 
 // Stage 1 of the piecewise linear tree: k = log2(nsub) tree steps (Theta/Phi)
 // within every sub-band of the channel-major scratch d.xc (format fmt, every
-// channel's row kept), written as 16-bit rows n*nsub + d' of out (pitch
-// out_pitch bytes) for t < len1 = nsamps - (nsub - 1).
-hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, uint8_t* out, long long out_pitch,
+// channel's row kept), written as rows n*nsub + d' of out (pitch out_pitch
+// bytes, 16-byte aligned) for t < len1 = nsamps - (nsub - 1), one byte
+// (ob = 1: 2-bit input, nsub <= 64) or 16 bits (ob = 2) per sample.
+hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, uint8_t* out, long long out_pitch,
                        long long len1, hipStream_t st);
 // Samples per time tile of the tree kernel (the scratch rows need this many
 // samples of margin past nsamps).
@@ -102,11 +103,12 @@ int tree_tile(int nsub);
 
 // Stage 2 of the piecewise linear tree: out[d][t] = sum over the d.nact
 // sub-bands n of S[d.rowsel[d*nact + n]][t + d.table[d*nact + n]] for
-// t < d.nout, S the 16-bit stage-1 rows in d.xc (pitch d.pitch bytes, rows
-// readable 9 samples past the last delayed output).  flush = terms summed in
-// 16-bit lanes between 32-bit flushes (flush * largest row value < 2^16).
-// d.out / out_bytes / out_shift / out_stride as for the other kernels.
-hipError_t launch_tree_combine(const BeamDesc& d, int flush, hipStream_t st);
+// t < d.nout, S the stage-1 rows in d.xc (ob bytes per sample, pitch d.pitch
+// bytes, rows readable 20 bytes past the last delayed output).  flush =
+// terms summed in 16-bit lanes between 32-bit flushes (flush * largest row
+// value < 2^16).  d.out / out_bytes / out_shift / out_stride as for the
+// other kernels.
+hipError_t launch_tree_combine(const BeamDesc& d, int ob, int flush, hipStream_t st);
 
 // Zero `bytes` (a multiple of 16) at base + g*group_stride for g < ngroups.
 hipError_t launch_zero(uint8_t* base, long long group_stride, long long bytes, int ngroups,

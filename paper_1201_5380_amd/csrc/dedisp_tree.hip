@@ -37,7 +37,7 @@ __device__ __forceinline__ int tree_theta(int i, int v) { return ((v & ((2 << i)
 // Phi(2^i, v), with v / 2^{i+1} taken as a shift
 __device__ __forceinline__ int tree_phi(int i, int v) { return ((v & 1) << i) + (v >> 1) + ((v >> (i + 1)) << i); }
 
-template <int FMT, int NSUB>
+template <int FMT, int NSUB, int OB>
 __global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long long out_pitch, long long len1)
 {
     constexpr int T = tree_tile_len(NSUB);
@@ -107,8 +107,32 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long lon
         A = B;
         B = tmp;
     }
-    // store rows n*NSUB + d', samples t0 .. t0 + T - 1 below len1, 8 per
-    // 16-byte store
+    // store rows n*NSUB + d', samples t0 .. t0 + T - 1 below len1, as
+    // bytes (OB = 1, values below 256: 16 samples per 16-byte store) or
+    // 16-bit values (8 per store)
+    if constexpr (OB == 1) {
+        static_assert(T % 16 == 0, "whole 16-sample pieces per tile");
+        for (int it = threadIdx.x; it < NSUB * (T / 16); it += 256) {
+            const int dp = it / (T / 16), t = 16 * (it % (T / 16));
+            const long long tg = t0 + t;
+            if (tg >= len1) continue;
+            const u32x4 a = *reinterpret_cast<const u32x4*>(A + dp * RS + t / 2);
+            const u32x4 c = *reinterpret_cast<const u32x4*>(A + dp * RS + t / 2 + 4);
+            // bytes 0 and 2 of each word: samples 2w and 2w+1
+            const u32x4 v = {__builtin_amdgcn_perm(a.y, a.x, 0x06040200u), __builtin_amdgcn_perm(a.w, a.z, 0x06040200u),
+                             __builtin_amdgcn_perm(c.y, c.x, 0x06040200u), __builtin_amdgcn_perm(c.w, c.z, 0x06040200u)};
+            uint8_t* orow = out + (long long)(n * NSUB + dp) * out_pitch;
+            if (tg + 16 <= len1) {
+                *reinterpret_cast<u32x4*>(orow + tg) = v;
+            } else {
+                const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int e = 0; e < 16; ++e)
+                    if (tg + e < len1) orow[tg + e] = (uint8_t)(wv[e >> 2] >> (8 * (e & 3)));
+            }
+        }
+        return;
+    }
     for (int it = threadIdx.x; it < NSUB * (T / 8); it += 256) {
         const int dp = it / (T / 8), t = 8 * (it % (T / 8));
         const long long tg = t0 + t;
@@ -119,74 +143,36 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long lon
             *reinterpret_cast<u32x4*>(orow + tg) = val;
         } else {
             const uint32_t wv[4] = {val.x, val.y, val.z, val.w};
-            for (int e = 0; tg + e < len1; ++e) orow[tg + e] = (uint16_t)(wv[e >> 1] >> (16 * (e & 1)));
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (tg + e < len1) orow[tg + e] = (uint16_t)(wv[e >> 1] >> (16 * (e & 1)));
         }
     }
 }
 
-// Stage 2 of the piecewise linear tree (Section 3, the piecewise linear
-// combination of sub-bands): out[d][t] = sum over sub-bands n of
-// S[rowsel[d][n]][t + table[d][n]], S the 16-bit stage-1 rows (d.xc, pitch
-// d.pitch bytes).  A lane sums 8 consecutive outputs of one trial: per term
-// five aligned 32-bit words (a 16-byte load and one more) and four 16-bit
-// realignments give the 8 shifted samples as 4 words of two 16-bit lanes,
-// added without a carry between the lanes and moved to 32-bit sums every
-// `flush` terms (flush * largest row value < 2^16).  The shift parity is
-// that of the trial's delay, uniform over the wave.
-//
-// Work items (time tile of 2048 outputs, trial) are ordered tile-major,
-// trial-minor and cut into 8 contiguous ranges, one per XCD (the hardware
-// hands workgroup i to XCD i mod 8): the workgroups in flight on an XCD
-// cover neighbouring trials of one tile, which share most of their tree
-// rows, so the rows stay in that XCD's L2.
-__global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, long long per_xcd)
+// N consecutive outputs t .. t+N-1 of trial d at the descriptor's width.
+template <int N>
+__device__ __forceinline__ void tree_store(const BeamDesc& b, int d, long long t, const uint32_t (&acc)[N])
 {
-    const long long o = (long long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    const long long ndm = b.ndm;
-    if (o >= ndm * ((b.nout + 2047) / 2048)) return;   // no barriers below
-    const int d = (int)(o % ndm);
-    const long long t = (o / ndm) * 2048 + threadIdx.x * 8;
-    if (t >= b.nout) return;
-    const int nsb = b.nact;
-    const int32_t* rows = b.rowsel + (size_t)d * nsb;
-    const int32_t* dly = b.table + (size_t)d * nsb;
-    uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    for (int n0 = 0; n0 < nsb; n0 += flush) {
-        const int n1 = min(nsb, n0 + flush);
-        uint32_t p0 = 0u, p1 = 0u, p2 = 0u, p3 = 0u;
-#pragma unroll 4
-        for (int n = n0; n < n1; ++n) {
-            const long long s = t + dly[n];
-            const uint32_t* w = reinterpret_cast<const uint32_t*>(b.xc + (long long)rows[n] * b.pitch) + (s >> 1);
-            u32x4 v;
-            __builtin_memcpy(&v, w, sizeof(v));
-            const uint32_t v4 = w[4];
-            const int sh = (int)(s & 1) * 16;
-            p0 += __builtin_amdgcn_alignbit(v.y, v.x, sh);
-            p1 += __builtin_amdgcn_alignbit(v.z, v.y, sh);
-            p2 += __builtin_amdgcn_alignbit(v.w, v.z, sh);
-            p3 += __builtin_amdgcn_alignbit(v4, v.w, sh);
-        }
-        acc[0] += p0 & 0xFFFFu; acc[1] += p0 >> 16;
-        acc[2] += p1 & 0xFFFFu; acc[3] += p1 >> 16;
-        acc[4] += p2 & 0xFFFFu; acc[5] += p2 >> 16;
-        acc[6] += p3 & 0xFFFFu; acc[7] += p3 >> 16;
-    }
     if (b.out_bytes == 4) {
         uint32_t* orow = b.out + (size_t)d * (size_t)b.out_stride;
-        if (t + 8 <= b.nout) {
-            const u32x4 lo4 = {acc[0] >> b.out_shift, acc[1] >> b.out_shift, acc[2] >> b.out_shift,
-                               acc[3] >> b.out_shift};
-            const u32x4 hi4 = {acc[4] >> b.out_shift, acc[5] >> b.out_shift, acc[6] >> b.out_shift,
-                               acc[7] >> b.out_shift};
-            __builtin_memcpy(orow + t, &lo4, sizeof(lo4));
-            __builtin_memcpy(orow + t + 4, &hi4, sizeof(hi4));
+        if (t + N <= b.nout) {
+#pragma unroll
+            for (int q = 0; q < N / 4; ++q) {
+                const u32x4 v = {acc[4 * q] >> b.out_shift, acc[4 * q + 1] >> b.out_shift,
+                                 acc[4 * q + 2] >> b.out_shift, acc[4 * q + 3] >> b.out_shift};
+                __builtin_memcpy(orow + t + 4 * q, &v, sizeof(v));
+            }
         } else {
-            for (int e = 0; t + e < b.nout; ++e) orow[t + e] = acc[e] >> b.out_shift;
+#pragma unroll
+            for (int e = 0; e < N; ++e)
+                if (t + e < b.nout) orow[t + e] = acc[e] >> b.out_shift;
         }
     } else {
         uint8_t* nrow = reinterpret_cast<uint8_t*>(b.out) + (long long)d * b.out_stride;
-        for (int e = 0; e < 8 && t + e < b.nout; ++e) {
+#pragma unroll
+        for (int e = 0; e < N; ++e) {
+            if (t + e >= b.nout) continue;
             const uint32_t v = out_value(acc[e], b.out_shift, b.out_bytes);
             if (b.out_bytes == 1) nrow[t + e] = (uint8_t)v;
             else reinterpret_cast<uint16_t*>(nrow)[t + e] = (uint16_t)v;
@@ -194,42 +180,120 @@ __global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, lon
     }
 }
 
+// Stage 2 of the piecewise linear tree (Section 3, the piecewise linear
+// combination of sub-bands): out[d][t] = sum over sub-bands n of
+// S[rowsel[d][n]][t + table[d][n]], S the stage-1 rows (d.xc, pitch d.pitch
+// bytes) of 16-bit values (OB = 2) or bytes (OB = 1).  A lane sums L = 8
+// (16-bit) or 16 (byte) consecutive outputs of one trial: per term five
+// aligned 32-bit words (a 16-byte load and one more) and four realignments
+// (v_alignbit by the delay's offset within a word) give the L shifted
+// samples; they are added in 16-bit lanes without a carry between lanes and
+// moved to 32-bit sums every `flush` terms (flush * largest row value
+// < 2^16).  The realignment is uniform over the wave (t is a multiple of
+// the samples per word).
+//
+// Work items (time tile of 256 L outputs, trial) are ordered tile-major,
+// trial-minor and cut into 8 contiguous ranges, one per XCD (the hardware
+// hands workgroup i to XCD i mod 8): the workgroups in flight on an XCD
+// cover neighbouring trials of one tile, which share most of their tree
+// rows, so the rows stay in that XCD's L2.
+template <int OB>
+__global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, long long per_xcd)
+{
+    constexpr int L = OB == 2 ? 8 : 16;           // outputs per lane
+    constexpr int SPW = 4 / OB;                   // samples per 32-bit word
+    const long long o = (long long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const long long ndm = b.ndm;
+    if (o >= ndm * ((b.nout + 256 * L - 1) / (256 * L))) return;   // no barriers below
+    const int d = (int)(o % ndm);
+    const long long t = (o / ndm) * (256 * L) + threadIdx.x * L;
+    if (t >= b.nout) return;
+    const int nsb = b.nact;
+    const int32_t* rows = b.rowsel + (size_t)d * nsb;
+    const int32_t* dly = b.table + (size_t)d * nsb;
+    uint32_t acc[L];
+#pragma unroll
+    for (int e = 0; e < L; ++e) acc[e] = 0u;
+    for (int n0 = 0; n0 < nsb; n0 += flush) {
+        const int n1 = min(nsb, n0 + flush);
+        // OB = 2: p[k] = samples (2k, 2k+1); OB = 1: p[k] = (4k, 4k+2),
+        // q[k] = (4k+1, 4k+3), each pair in the two 16-bit lanes
+        uint32_t p[4] = {0u, 0u, 0u, 0u}, q[4] = {0u, 0u, 0u, 0u};
+#pragma unroll 4
+        for (int n = n0; n < n1; ++n) {
+            const long long s = t + dly[n];
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(b.xc + (long long)rows[n] * b.pitch) + s / SPW;
+            u32x4 v;
+            __builtin_memcpy(&v, w, sizeof(v));
+            const uint32_t v4 = w[4];
+            const int sh = (int)(s % SPW) * (32 / SPW);
+            const uint32_t x[4] = {__builtin_amdgcn_alignbit(v.y, v.x, sh), __builtin_amdgcn_alignbit(v.z, v.y, sh),
+                                   __builtin_amdgcn_alignbit(v.w, v.z, sh), __builtin_amdgcn_alignbit(v4, v.w, sh)};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if constexpr (OB == 2) {
+                    p[k] += x[k];
+                } else {
+                    p[k] += x[k] & 0x00FF00FFu;
+                    q[k] += (x[k] >> 8) & 0x00FF00FFu;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if constexpr (OB == 2) {
+                acc[2 * k] += p[k] & 0xFFFFu;
+                acc[2 * k + 1] += p[k] >> 16;
+            } else {
+                acc[4 * k] += p[k] & 0xFFFFu;
+                acc[4 * k + 1] += q[k] & 0xFFFFu;
+                acc[4 * k + 2] += p[k] >> 16;
+                acc[4 * k + 3] += q[k] >> 16;
+            }
+        }
+    }
+    tree_store<L>(b, d, t, acc);
+}
+
 }  // namespace
 
 int tree_tile(int nsub) { return tree_tile_len(nsub); }
 
-hipError_t launch_tree_combine(const BeamDesc& d, int flush, hipStream_t st)
+hipError_t launch_tree_combine(const BeamDesc& d, int ob, int flush, hipStream_t st)
 {
-    if (d.nout <= 0 || d.ndm <= 0 || d.nact <= 0 || flush < 1 || (d.pitch & 3) ||
+    if (d.nout <= 0 || d.ndm <= 0 || d.nact <= 0 || flush < 1 || (d.pitch & 3) || (ob != 1 && ob != 2) ||
         (reinterpret_cast<uintptr_t>(d.xc) & 3) ||
         (reinterpret_cast<uintptr_t>(d.out) & (d.out_bytes == 4 ? 3 : d.out_bytes - 1)))
         return hipErrorInvalidValue;
-    const long long items = (long long)d.ndm * ((d.nout + 2047) / 2048);
+    const long long per_item = ob == 2 ? 2048 : 4096;
+    const long long items = (long long)d.ndm * ((d.nout + per_item - 1) / per_item);
     const long long per_xcd = (items + 7) / 8;
     if (8 * per_xcd > 0x7fffffffLL) return hipErrorInvalidValue;
     BeamDesc a0 = d;
     int a1 = flush;
     long long a2 = per_xcd;
     void* args[] = {&a0, &a1, &a2};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&k_tree_combine), dim3((unsigned)(8 * per_xcd)),
-                           dim3(256), args, 0, st);
+    const void* fn = ob == 2 ? reinterpret_cast<const void*>(&k_tree_combine<2>)
+                             : reinterpret_cast<const void*>(&k_tree_combine<1>);
+    return hipLaunchKernel(fn, dim3((unsigned)(8 * per_xcd)), dim3(256), args, 0, st);
 }
 
-hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, uint8_t* out, long long out_pitch,
+hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, uint8_t* out, long long out_pitch,
                        long long len1, hipStream_t st)
 {
-    if (len1 <= 0 || (out_pitch & 3) || (reinterpret_cast<uintptr_t>(out) & 3)) return hipErrorInvalidValue;
+    if (len1 <= 0 || (out_pitch & 15) || (reinterpret_cast<uintptr_t>(out) & 15)) return hipErrorInvalidValue;
     const long long T = tree_tile_len(nsub);
     const long long gx = (len1 + T - 1) / T;
     const long long gy = d.nchans / nsub;
     if (gx <= 0 || gx > 0x7fffffffLL || gy <= 0 || gy > 65535) return hipErrorInvalidValue;
     const void* fn = nullptr;
-#define DEDISP_TREE_CASE(F, N) \
-    if (fmt == F && nsub == N) fn = reinterpret_cast<const void*>(&k_tree<F, N>);
-    DEDISP_TREE_CASE(kFmtNib, 8) DEDISP_TREE_CASE(kFmtNib, 16) DEDISP_TREE_CASE(kFmtNib, 32)
-    DEDISP_TREE_CASE(kFmtNib, 64) DEDISP_TREE_CASE(kFmtNib, 128)
-    DEDISP_TREE_CASE(kFmtByte, 8) DEDISP_TREE_CASE(kFmtByte, 16) DEDISP_TREE_CASE(kFmtByte, 32)
-    DEDISP_TREE_CASE(kFmtByte, 64) DEDISP_TREE_CASE(kFmtByte, 128)
+    // byte rows hold 2-bit sub-band sums up to nsub = 64 (3 * 64 < 256)
+#define DEDISP_TREE_CASE(F, N, O) \
+    if (fmt == F && nsub == N && ob == O) fn = reinterpret_cast<const void*>(&k_tree<F, N, O>);
+    DEDISP_TREE_CASE(kFmtNib, 8, 1) DEDISP_TREE_CASE(kFmtNib, 16, 1) DEDISP_TREE_CASE(kFmtNib, 32, 1)
+    DEDISP_TREE_CASE(kFmtNib, 64, 1) DEDISP_TREE_CASE(kFmtNib, 128, 2)
+    DEDISP_TREE_CASE(kFmtByte, 8, 2) DEDISP_TREE_CASE(kFmtByte, 16, 2) DEDISP_TREE_CASE(kFmtByte, 32, 2)
+    DEDISP_TREE_CASE(kFmtByte, 64, 2) DEDISP_TREE_CASE(kFmtByte, 128, 2)
 #undef DEDISP_TREE_CASE
     if (!fn) return hipErrorInvalidValue;
     const size_t lds = 2ull * nsub * tree_row_words(nsub) * sizeof(uint32_t);
