@@ -74,7 +74,14 @@ def _load():
                                                _i32p, _i32p]
     lib.oracle_tree_combine.argtypes = [_u32p, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _i32p,
                                         _i32p, ctypes.c_int, ctypes.c_int64, _u32p]
+    lib.oracle_tree_imposed.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, _u32p, _i32p]
+    lib.oracle_tree_dm_tables.argtypes = lib.oracle_tree_combine_tables.argtypes
+    lib.oracle_tree_combine_passes.argtypes = [_u32p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                               ctypes.c_int, _i32p, _i32p, ctypes.c_int, ctypes.c_int64,
+                                               _u32p]
     for f in ("oracle_tree", "oracle_tree_combine_tables", "oracle_tree_combine",
+              "oracle_tree_imposed", "oracle_tree_dm_tables", "oracle_tree_combine_passes",
               "oracle_reduce_output", "oracle_subband_lengths", "oracle_subband_step1", "oracle_subband_step2",
               "oracle_dedisperse_scrunched_points", "oracle_partial_delay", "oracle_delay_table", "oracle_dedisperse",
               "oracle_dedisperse_points", "oracle_max_threads", "oracle_diagonal_dm",
@@ -360,6 +367,35 @@ def tree(packed, nsamps, nchans, nbits, k, mask=None):
     return out
 
 
+def tree_imposed(packed, nsamps, nchans, nbits, k, slope, mask=None):
+    """Stage 1 with an imposed delay of `slope` samples per channel within every block
+    of 2^k channels (Section 3, computing larger DMs): uint32
+    [nchans][nsamps - (slope + 1)(2^k - 1)]."""
+    packed = np.ascontiguousarray(packed, dtype=np.uint8).reshape(-1)
+    if packed.size < int(nsamps) * nchans * nbits // 8:
+        raise OracleError("input too short")
+    n_out = int(nsamps) - (int(slope) + 1) * ((1 << int(k)) - 1)
+    if n_out <= 0:
+        raise OracleError("too few samples")
+    out = np.zeros((nchans, n_out), dtype=np.uint32)
+    m, mp = _mask_arg(mask, nchans)
+    _check(_load().oracle_tree_imposed(_ptr(packed, _u8p), int(nsamps), nchans, nbits, int(k),
+                                       int(slope), _ptr(out, _u32p), mp), "tree_imposed")
+    return out
+
+
+def tree_dm_tables(nchans, dt, f_top, df, nsub, dms):
+    """(d'_n(d), dt''_n(d)) as int32 [ndm][nchans / nsub] each, d' unrestricted."""
+    dms = np.ascontiguousarray(dms, dtype=np.float64)
+    nsb = nchans // nsub
+    dp = np.zeros((len(dms), nsb), dtype=np.int32)
+    dd = np.zeros((len(dms), nsb), dtype=np.int32)
+    _check(_load().oracle_tree_dm_tables(nchans, dt, f_top, df, int(nsub), _ptr(dms, _f64p),
+                                         len(dms), _ptr(dp, _i32p), _ptr(dd, _i32p)),
+           "tree_dm_tables")
+    return dp, dd
+
+
 def tree_combine_tables(nchans, dt, f_top, df, nsub, dms):
     """(d'_n(d), dt''_n(d)) as int32 [ndm][nchans / nsub] each."""
     dms = np.ascontiguousarray(dms, dtype=np.float64)
@@ -374,18 +410,30 @@ def tree_combine_tables(nchans, dt, f_top, df, nsub, dms):
 
 def dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub, mask=None):
     """Piecewise linear tree (Section 3): stage 1 = log2(nsub) tree steps, stage 2 = the
-    sub-band combination.  uint32 [ndm][nout]."""
+    sub-band combination.  Trials past the piecewise diagonal use further passes with an
+    imposed delay (pass p: p samples per channel within each sub-band), sub-band n of
+    trial d taking pass d'_n(d) // nsub.  uint32 [ndm][nout], nout = nsamps -
+    (P + 1)(nsub - 1) - max dt'' with P the largest pass."""
     k = int(nsub).bit_length() - 1
     if (1 << k) != int(nsub):
         raise OracleError("nsub must be a power of two")
-    S = tree(packed, nsamps, nchans, nbits, k, mask=mask)
-    len1 = S.shape[1]
-    dp, dd = tree_combine_tables(nchans, dt, f_top, df, nsub, dms)
+    dp, dd = tree_dm_tables(nchans, dt, f_top, df, nsub, dms)
+    npass = int(dp.max()) // int(nsub) + 1
+    len1 = int(nsamps) - npass * (int(nsub) - 1)
     nout = len1 - int(dd.max())
-    if nout <= 0:
+    if len1 <= 0 or nout <= 0:
         raise OracleError("too few samples")
     out = np.zeros((len(dms), nout), dtype=np.uint32)
-    _check(_load().oracle_tree_combine(_ptr(S, _u32p), nchans, len1, int(nsub), _ptr(dp, _i32p),
-                                       _ptr(dd, _i32p), len(dms), nout, _ptr(out, _u32p)),
-           "tree_combine")
+    if npass == 1:
+        S = tree(packed, nsamps, nchans, nbits, k, mask=mask)
+        _check(_load().oracle_tree_combine(_ptr(S, _u32p), nchans, len1, int(nsub), _ptr(dp, _i32p),
+                                           _ptr(dd, _i32p), len(dms), nout, _ptr(out, _u32p)),
+               "tree_combine")
+        return out
+    S = np.zeros((npass, nchans, len1), dtype=np.uint32)
+    for p in range(npass):
+        S[p] = tree_imposed(packed, nsamps, nchans, nbits, k, p, mask=mask)[:, :len1]
+    _check(_load().oracle_tree_combine_passes(_ptr(S, _u32p), npass, nchans, len1, int(nsub),
+                                              _ptr(dp, _i32p), _ptr(dd, _i32p), len(dms), nout,
+                                              _ptr(out, _u32p)), "tree_combine_passes")
     return out

@@ -460,14 +460,18 @@ static int oracle_tree_phi(int r, int v) { return (v % 2) * r + v / 2 + (v / (2 
 
 /* k steps of the tree over every channel (nchans a multiple of 2^k), with an
  * optional 0/1 kill mask applied to the input: out [nchans][nsamps - (2^k - 1)]. */
-int oracle_tree(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k,
-                uint32_t* out, const int32_t* mask)
+/* The k tree steps on the channel-major input, channel v read
+ * slope * (v mod 2^k) samples later (slope = 0: the input as it is). */
+static int tree_steps(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k, int slope,
+                      uint32_t* out, const int32_t* mask)
 {
-    if (!in || !out || k < 0 || k > 20 || nchans <= 0 || nchans % (1 << k)) return ORACLE_BAD_ARG;
+    if (!in || !out || k < 0 || k > 20 || nchans <= 0 || nchans % (1 << k) || slope < 0) return ORACLE_BAD_ARG;
     if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
-    const int64_t n_out = nsamps - ((1 << k) - 1);
+    const int B = 1 << k;
+    const int64_t ns = nsamps - (int64_t)slope * (B - 1);   /* samples every channel has */
+    const int64_t n_out = ns - (B - 1);
     if (n_out <= 0) return ORACLE_TOO_FEW_SAMPLES;
-    const size_t cells = (size_t)nchans * (size_t)nsamps;
+    const size_t cells = (size_t)nchans * (size_t)ns;
     uint32_t* a = (uint32_t*)malloc(cells * sizeof(uint32_t));
     uint32_t* b = (uint32_t*)malloc(cells * sizeof(uint32_t));
     if (!a || !b) {
@@ -475,20 +479,22 @@ int oracle_tree(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k,
         free(b);
         return ORACLE_BAD_ARG;
     }
-    /* A^0 = the input, channel-major */
-    for (int v = 0; v < nchans; ++v)
-        for (int64_t t = 0; t < nsamps; ++t)
-            a[(size_t)v * nsamps + t] = (mask ? (uint32_t)mask[v] : 1u) * oracle_sample(in, nchans, nbits, t, v);
-    int64_t len = nsamps;
+    /* A^0 = the input, channel-major, with the imposed delay */
+    for (int v = 0; v < nchans; ++v) {
+        const int64_t shift = (int64_t)slope * (v % B);
+        for (int64_t t = 0; t < ns; ++t)
+            a[(size_t)v * ns + t] = (mask ? (uint32_t)mask[v] : 1u) * oracle_sample(in, nchans, nbits, t + shift, v);
+    }
+    int64_t len = ns;
     for (int i = 0; i < k; ++i) {
         const int r = 1 << i;
         const int64_t next = len - r;       /* largest Theta(i, .) is 2^i */
         for (int v = 0; v < nchans / 2; ++v) {
-            const uint32_t* lo = a + (size_t)oracle_tree_phi(r, 2 * v) * nsamps;
-            const uint32_t* hi = a + (size_t)oracle_tree_phi(r, 2 * v + 1) * nsamps;
+            const uint32_t* lo = a + (size_t)oracle_tree_phi(r, 2 * v) * ns;
+            const uint32_t* hi = a + (size_t)oracle_tree_phi(r, 2 * v + 1) * ns;
             const int th0 = oracle_tree_theta(i, 2 * v), th1 = oracle_tree_theta(i, 2 * v + 1);
-            uint32_t* o0 = b + (size_t)(2 * v) * nsamps;
-            uint32_t* o1 = b + (size_t)(2 * v + 1) * nsamps;
+            uint32_t* o0 = b + (size_t)(2 * v) * ns;
+            uint32_t* o1 = b + (size_t)(2 * v + 1) * ns;
             for (int64_t t = 0; t < next; ++t) {
                 o0[t] = lo[t] + hi[t + th0];
                 o1[t] = lo[t] + hi[t + th1];
@@ -501,10 +507,29 @@ int oracle_tree(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k,
     }
     for (int v = 0; v < nchans; ++v)
         for (int64_t t = 0; t < n_out; ++t)
-            out[(size_t)v * n_out + t] = a[(size_t)v * nsamps + t];
+            out[(size_t)v * n_out + t] = a[(size_t)v * ns + t];
     free(a);
     free(b);
     return ORACLE_OK;
+}
+
+int oracle_tree(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k,
+                uint32_t* out, const int32_t* mask)
+{
+    return tree_steps(in, nsamps, nchans, nbits, k, 0, out, mask);
+}
+
+/* Stage 1 for DMs beyond the piecewise diagonal (Section 3, computing larger
+ * DMs): a time delay is imposed across each block of 2^k channels before the
+ * tree steps -- channel v is read slope * (v mod 2^k) samples later, a
+ * diagonal of `slope` samples per channel -- so tree row d' of a block then
+ * covers a trail of slope * 2^k + d' samples from the block's first channel
+ * to the next block's.  Output [nchans][nsamps - (slope + 1)(2^k - 1)];
+ * slope 0 is oracle_tree. */
+int oracle_tree_imposed(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k, int slope,
+                        uint32_t* out, const int32_t* mask)
+{
+    return tree_steps(in, nsamps, nchans, nbits, k, slope, out, mask);
 }
 
 /* Stage 2 of the piecewise linear tree (Section 3, eq. combining_subbands):
@@ -517,10 +542,11 @@ int oracle_tree(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k,
  * channel), both evaluated in binary64 in this order, and
  *   D[d][t] = sum over n of S[n*nsub + d'_n(d)][t + dt''_n(d)]
  * for t < len1 - (largest dt''), S being the k-step tree output of length
- * len1.  Every d'_n(d) must be below nsub (DMs up to the piecewise diagonal);
- * the tables dprime and dpp [ndm][nsb] are returned for inspection. */
-int oracle_tree_combine_tables(int nchans, double dt, double f_top, double df, int nsub,
-                               const double* dms, int ndm, int32_t* dprime, int32_t* dpp)
+ * len1 (oracle_tree_combine).  This function returns the tables dprime and
+ * dpp [ndm][nsb]; d'_n(d) may reach nsub and beyond (DMs past the piecewise
+ * diagonal, which oracle_tree_combine_passes serves). */
+int oracle_tree_dm_tables(int nchans, double dt, double f_top, double df, int nsub,
+                          const double* dms, int ndm, int32_t* dprime, int32_t* dpp)
 {
     if (!dms || !dprime || !dpp || nsub <= 0 || nchans % nsub) return ORACLE_BAD_ARG;
     if (oracle_check_params(nchans, dt, f_top, df, 8) != ORACLE_OK) return ORACLE_BAD_ARG;
@@ -536,12 +562,24 @@ int oracle_tree_combine_tables(int nchans, double dt, double f_top, double df, i
             const double step = scale * (1.0 / (fb * fb) - inv_top2) - scale * (1.0 / (fa * fa) - inv_top2);
             const double dp = round(dms[d] * step);
             const double dd = round(dms[d] * acc);
-            if (!(dp >= 0.0) || dp >= (double)nsub || !(dd >= 0.0) || dd > 2.0e9) return ORACLE_BAD_ARG;
+            if (!(dp >= 0.0) || dp > 2.0e9 || !(dd >= 0.0) || dd > 2.0e9) return ORACLE_BAD_ARG;
             dprime[(size_t)d * nsb + n] = (int32_t)dp;
             dpp[(size_t)d * nsb + n] = (int32_t)dd;
             acc += step;
         }
     }
+    return ORACLE_OK;
+}
+
+/* The same tables for DMs up to the piecewise diagonal: every d'_n(d) must be
+ * below nsub. */
+int oracle_tree_combine_tables(int nchans, double dt, double f_top, double df, int nsub,
+                               const double* dms, int ndm, int32_t* dprime, int32_t* dpp)
+{
+    const int rc = oracle_tree_dm_tables(nchans, dt, f_top, df, nsub, dms, ndm, dprime, dpp);
+    if (rc != ORACLE_OK) return rc;
+    for (size_t i = 0; i < (size_t)ndm * (size_t)(nchans / nsub); ++i)
+        if (dprime[i] >= nsub) return ORACLE_BAD_ARG;
     return ORACLE_OK;
 }
 
@@ -563,6 +601,40 @@ int oracle_tree_combine(const uint32_t* S, int nchans, int64_t len1, int nsub,
             for (int n = 0; n < nsb; ++n) {
                 const int32_t dp = dprime[(size_t)d * nsb + n];
                 sum += S[((size_t)n * nsub + dp) * (size_t)len1 + (size_t)(t + dpp[(size_t)d * nsb + n])];
+            }
+            row[t] = sum;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* Stage 2 over several passes (Section 3, computing larger DMs): S holds
+ * npass stage-1 outputs [npass][nchans][len1], pass p taken with an imposed
+ * slope of p samples per channel (oracle_tree_imposed, truncated to len1).
+ * Sub-band n of trial d reads pass p = d'_n(d) / nsub at row
+ * n*nsub + d'_n(d) mod nsub, placed at dt''_n(d) as before:
+ *   D[d][t] = sum over n of S[p][n*nsub + d'_n(d) - p*nsub][t + dt''_n(d)]. */
+int oracle_tree_combine_passes(const uint32_t* S, int npass, int nchans, int64_t len1, int nsub,
+                               const int32_t* dprime, const int32_t* dpp, int ndm, int64_t nout,
+                               uint32_t* out)
+{
+    if (!S || !dprime || !dpp || !out || npass <= 0 || nsub <= 0 || nchans % nsub || nout <= 0)
+        return ORACLE_BAD_ARG;
+    const int nsb = nchans / nsub;
+    for (int d = 0; d < ndm; ++d)
+        for (int n = 0; n < nsb; ++n)
+            if (nout + dpp[(size_t)d * nsb + n] > len1 || dprime[(size_t)d * nsb + n] / nsub >= npass)
+                return ORACLE_BAD_ARG;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int d = 0; d < ndm; ++d) {
+        uint32_t* row = out + (size_t)d * (size_t)nout;
+        for (int64_t t = 0; t < nout; ++t) {
+            uint32_t sum = 0;
+            for (int n = 0; n < nsb; ++n) {
+                const int32_t dp = dprime[(size_t)d * nsb + n];
+                const int p = dp / nsub;
+                const size_t r = (size_t)p * nchans + (size_t)n * nsub + (size_t)(dp % nsub);
+                sum += S[r * (size_t)len1 + (size_t)(t + dpp[(size_t)d * nsb + n])];
             }
             row[t] = sum;
         }

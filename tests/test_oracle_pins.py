@@ -807,3 +807,116 @@ def test_piecewise_tree_reductions_and_error_bound():
                                            prm["df"], dms[:4] * 0.2, nchans)
     for d in range(4):
         assert dd1[d, 0] == 0 and np.array_equal(one[d], full[dp1[d, 0], : one.shape[1]])
+
+
+# ---------------------------------------------------------------- tree past the diagonal
+
+def test_imposed_tree_slope_zero_is_the_tree():
+    """With no imposed delay the pass is the basic tree, bit for bit."""
+    rng = np.random.default_rng(31)
+    nchans, nsamps = 32, 300
+    codes = rng.integers(0, 256, size=(nsamps, nchans), dtype=np.uint8)
+    for k in (1, 3, 5):
+        assert np.array_equal(oracle.tree_imposed(codes, nsamps, nchans, 8, k, 0),
+                              oracle.tree(codes, nsamps, nchans, 8, k))
+
+
+@pytest.mark.parametrize("k,slope", [(1, 1), (2, 3), (3, 1), (3, 2), (4, 5)])
+def test_imposed_tree_is_a_direct_sum_along_shifted_staircases(k, slope):
+    """Row d' of a block under an imposed slope sums channel j of the block at
+    slope*j + (the basic tree's staircase delay from the index recursion):
+    scattered from every input sample (push brute force), so a wrong sign,
+    a shift applied to the wrong channel or a slope not relative to the
+    block's first channel fails."""
+    B = 1 << k
+    nchans, nsamps = 2 * B, 40 + (slope + 2) * B
+    rng = np.random.default_rng(100 + 10 * k + slope)
+    codes = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+    got = oracle.tree_imposed(synth.pack(codes, 2), nsamps, nchans, 2, k, slope)
+    assert got.shape == (nchans, nsamps - (slope + 1) * (B - 1))
+    rec = _tree_delay_recursion(k)
+    j = np.arange(B)
+    table = np.zeros((nchans, nchans), dtype=np.int64)         # [row][channel]
+    for row in range(nchans):
+        blk, dprime = divmod(row, B)
+        table[row] = -10 ** 6                                   # channels outside the block
+        table[row, blk * B:(blk + 1) * B] = slope * j + rec[dprime]
+    # channels outside a row's block contribute nothing: drop them by zeroing
+    # their codes per row
+    for row in range(nchans):
+        blk = row // B
+        sub = np.zeros_like(codes)
+        sub[:, blk * B:(blk + 1) * B] = codes[:, blk * B:(blk + 1) * B]
+        tab = np.where(table[row] < 0, 0, table[row])[None, :]
+        want = _push_brute_force(sub.astype(np.int64), tab)[0]
+        assert np.array_equal(got[row].astype(np.int64), want[: got.shape[1]]), row
+
+
+def _beyond_case(nsub, factor, ndm=20):
+    nchans = 64
+    prm = dict(dt=64e-6, f_top=1581.8, df=-400.0 / nchans)
+    fb = prm["f_top"] + nchans * prm["df"]
+    fa = prm["f_top"] + (nchans - nsub) * prm["df"]
+    kk = 4.148808e3 / prm["dt"]
+    diag = (nsub - 0.5) / (kk * (1 / fb ** 2 - 1 / prm["f_top"] ** 2) - kk * (1 / fa ** 2 - 1 / prm["f_top"] ** 2))
+    return nchans, prm, diag, np.linspace(0.0, factor * diag, ndm)
+
+
+def test_piecewise_tree_beyond_the_diagonal_is_the_composed_direct_sum():
+    """Trials up to 3.5x the piecewise diagonal: each sub-band takes pass
+    p = d'_n // nsub and row d'_n mod nsub, so the output is the direct sum at
+    E[d][c] = dt''_n(d) + p j + staircase(d'_n mod nsub, j) (c = n nsub + j);
+    E stays within Appendix A's trail error of the exact delays plus the
+    roundings and one sample of staircase slope."""
+    nsub, nsamps = 16, 2600
+    nchans, prm, diag, dms = _beyond_case(nsub, 3.5)
+    rng = np.random.default_rng(17)
+    codes = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+    packed = synth.pack(codes, 2)
+    out = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, 2, prm["dt"], prm["f_top"],
+                                           prm["df"], dms, nsub)
+    dp, dd = oracle.tree_dm_tables(nchans, prm["dt"], prm["f_top"], prm["df"], nsub, dms)
+    assert dp.max() >= 3 * nsub                                 # four passes in use
+    npass = int(dp.max()) // nsub + 1
+    assert out.shape[1] == nsamps - npass * (nsub - 1) - int(dd.max())
+    rec = _tree_delay_recursion(int(nsub).bit_length() - 1)
+    E = np.zeros((len(dms), nchans), dtype=np.int64)
+    for d in range(len(dms)):
+        for c in range(nchans):
+            n, j = divmod(c, nsub)
+            p, row = divmod(int(dp[d, n]), nsub)
+            E[d, c] = dd[d, n] + p * j + rec[row, j]
+    bf = _push_brute_force(codes.astype(np.int64), E)
+    assert np.array_equal(out.astype(np.int64), bf[:, : out.shape[1]])
+    tab, _ = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], dms)
+    lam = -prm["df"] / prm["f_top"] * nchans
+    k = int(nsub).bit_length() - 1
+    for d in range(len(dms)):
+        t_tree = 0.75 * dms[d] * 4.148808e3 / prm["f_top"] ** 2 * (nsub / nchans) ** 2 \
+            * lam ** 2 / (1 - lam) ** 4 / prm["dt"]
+        bound = t_tree + 0.5 * k + 0.5 + 0.5 + 1.0
+        assert np.abs(E[d] - tab[d]).max() <= bound, (d, np.abs(E[d] - tab[d]).max(), bound)
+    # below the diagonal it is the single-pass tree
+    lo = dms < diag * 0.999
+    base = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, 2, prm["dt"], prm["f_top"],
+                                            prm["df"], dms[lo], nsub)
+    m = min(base.shape[1], out.shape[1])
+    assert np.array_equal(base[:, :m], out[lo][:, :m])
+
+
+def test_piecewise_tree_finds_a_pulse_beyond_the_diagonal():
+    """A pulse dispersed at the exact delays of a trial at ~2.6x the diagonal,
+    on a flat background, peaks at that trial and time."""
+    nsub, nsamps = 16, 3000
+    nchans, prm, diag, dms = _beyond_case(nsub, 3.0, ndm=40)
+    tab, _ = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], dms)
+    d0, t0 = 35, 700
+    codes = np.ones((nsamps, nchans), dtype=np.uint8)
+    for c in range(nchans):
+        codes[t0 + tab[d0, c], c] = 3
+    out = oracle.dedisperse_piecewise_tree(synth.pack(codes, 2), nsamps, nchans, 2, prm["dt"],
+                                           prm["f_top"], prm["df"], dms, nsub).astype(np.int64)
+    win = out[:, t0 - 40:t0 + 41]
+    d, t = np.unravel_index(int(win.argmax()), win.shape)
+    assert dms[d0] > 2.5 * diag
+    assert abs(d - d0) <= 1 and abs(t - 40) <= 1, (d, t)
