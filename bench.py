@@ -163,8 +163,10 @@ def bench_subband(torch, dev, plan, inp, nsamps, steps, direct_ms, nsub=32, ngro
 def bench_tree(torch, dev, beam, inp, nsamps, steps, nsub=32):
     """The survey beam through the piecewise linear tree (Section 3) with
     32-channel sub-bands, against the direct transform of the same trials:
-    the survey's own trials up to the tree's diagonal DM, and a dense list of
-    1024 trials spread evenly below it (the regime the tree is built for)."""
+    the survey's own trials up to the tree's diagonal DM, a dense list of
+    1024 trials spread evenly below it (the regime the tree is built for),
+    4096 trials up to 4x the diagonal (four stage-1 passes) and all of the
+    survey's trials (up to ~31x the diagonal)."""
     import numpy as np
     from paper_1201_5380_amd import Plan
     k = 4.148808e3 / beam.dt
@@ -189,13 +191,16 @@ def bench_tree(torch, dev, beam, inp, nsamps, steps, nsub=32):
 
     res = {}
     for key, dms, what in (("survey_trials", beam.dms[beam.dms < diag], "the survey's trials"),
-                           ("dense_trials", np.linspace(0.0, 0.999 * diag, 1024), "1024 evenly spaced trials")):
+                           ("dense_trials", np.linspace(0.0, 0.999 * diag, 1024), "1024 evenly spaced trials"),
+                           ("dense_beyond", np.linspace(0.0, 4.0 * diag, 4096, endpoint=False),
+                            "4096 evenly spaced trials (4 passes)"),
+                           ("survey_all", beam.dms, "all of the survey's trials (31 passes)")):
         direct = Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(dms)
         d_ms, _ = timed(direct)
         tree = Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(dms).set_tree(nsub)
         t_ms, nout = timed(tree)
-        res[key] = {"workload": f"survey beam, {what} ({len(dms)}) up to the piecewise tree's diagonal "
-                                f"DM {diag:.2f}, sub-bands of {nsub} channels",
+        res[key] = {"workload": f"survey beam, {what} ({len(dms)}) up to DM {float(dms.max()):.2f} "
+                                f"(piecewise diagonal {diag:.2f}), sub-bands of {nsub} channels",
                     "ms": t_ms, "nout": nout, "outputs_per_s": len(dms) * nout / (t_ms * 1e-3),
                     "direct_ms_same_trials": d_ms, "speedup_vs_direct": d_ms / t_ms}
     return res

@@ -179,8 +179,13 @@ dedisp_status dedisp_get_output_lengths(dedisp_plan plan, size_t nsamps, size_t*
  * evaluated in binary64 in that order.  An approximation of the direct
  * transform whose error Appendix A bounds.  Outputs exist for
  * t < nsamps - (nsub - 1) - (largest dt''); dedisp_get_output_lengths gives
- * it.  Every trial must keep d'_n(d) < nsub (DMs up to the piecewise
- * diagonal), else UNSUPPORTED.  nsub = 0 switches the mode off; a new DM
+ * it.  Trials past the piecewise diagonal (d'_n(d) >= nsub) use further
+ * passes of stage 1 over the data with a delay of p samples per channel
+ * imposed within each sub-band (Section 3, computing larger DMs): sub-band n
+ * of trial d reads pass p = d'_n(d) / nsub at tree DM d'_n(d) mod nsub, and
+ * outputs then exist for t < nsamps - (P + 1)(nsub - 1) - (largest dt''),
+ * P the largest pass.  Stage 1 runs once per (sub-band, pass) pair in use
+ * (at most 65535 pairs, else UNSUPPORTED).  nsub = 0 switches the mode off; a new DM
  * list does too.  Excludes time-scrunching and sub-band mode; streams and
  * batches reject such a plan.  Needs 4-byte aligned input rows and a band
  * whose edge past the last channel is above zero frequency.

@@ -515,14 +515,17 @@ void write_cache(const char* path, const std::map<std::string, std::vector<doubl
 
 void destroy_tree(dedisp_plan p)
 {
-    if (p->d_tree_rows || p->d_tree_delay) (void)hipDeviceSynchronize();
+    if (p->d_tree_rows || p->d_tree_delay || p->d_tree_pairs) (void)hipDeviceSynchronize();
     if (p->d_tree_rows) (void)hipFree(p->d_tree_rows);
     if (p->d_tree_delay) (void)hipFree(p->d_tree_delay);
-    p->d_tree_rows = p->d_tree_delay = nullptr;
+    if (p->d_tree_pairs) (void)hipFree(p->d_tree_pairs);
+    p->d_tree_rows = p->d_tree_delay = p->d_tree_pairs = nullptr;
     p->tree_rows.clear();
     p->tree_delay.clear();
+    p->tree_pairs.clear();
     p->tree_nsub = 0;
     p->tree_maxdelay = 0;
+    p->tree_npass = 0;
 }
 
 void destroy_subband(dedisp_plan p)
@@ -978,7 +981,8 @@ static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsa
 // Piecewise linear tree: stage-1 length and outputs for nsamps input rows.
 static void tree_lengths(const dedisp_plan_s& p, size_t nsamps, long long& len1, long long& nout)
 {
-    len1 = static_cast<long long>(nsamps) - (p.tree_nsub - 1);
+    // pass p reads p (nsub - 1) samples further, and its tree another nsub - 1
+    len1 = static_cast<long long>(nsamps) - static_cast<long long>(p.tree_npass) * (p.tree_nsub - 1);
     nout = len1 - p.tree_maxdelay;
 }
 
@@ -1009,15 +1013,27 @@ static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps
         HIP_TRY(hipMemcpy(p->d_tree_rows, p->tree_rows.data(), bytes, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(p->d_tree_delay, p->tree_delay.data(), bytes, hipMemcpyHostToDevice));
     }
-    // the tree kernel reads whole tiles past the last sample; tree rows are
-    // bytes while the largest sub-band sum (3 nsub for 2-bit codes) fits
-    const long long pitch1 = xc_pitch(static_cast<long long>(nsamps) + dedisp::tree_tile(nsub) + nsub,
+    if (!p->d_tree_pairs) {
+        const size_t bytes = p->tree_pairs.size() * sizeof(int32_t);
+        if (hipMalloc(&p->d_tree_pairs, bytes) != hipSuccess) {
+            p->d_tree_pairs = nullptr;
+            return fail(DEDISP_ERR_OOM, "hipMalloc tree tables");
+        }
+        HIP_TRY(hipMemcpy(p->d_tree_pairs, p->tree_pairs.data(), bytes, hipMemcpyHostToDevice));
+    }
+    const int npairs = static_cast<int>(p->tree_pairs.size() / 2);
+    // the tree kernel reads whole tiles (and one more word) past the last
+    // sample, up to (npass - 1)(nsub - 1) samples further under an imposed
+    // delay; tree rows are bytes while the largest sub-band sum (3 nsub for
+    // 2-bit codes) fits
+    const long long pitch1 = xc_pitch(static_cast<long long>(nsamps) + dedisp::tree_tile(nsub) + nsub +
+                                          static_cast<long long>(p->tree_npass - 1) * (nsub - 1) + 8,
                                       p->fmt, 0);
     const int ob = (p->nbits == 2 && nsub <= 64) ? 1 : 2;
     const long long pitch2 = ((ob * len1 + 64) + 63) / 64 * 64;
     st = ensure_scratch(p->xc, static_cast<size_t>(pitch1) * p->nchans);
     if (st != DEDISP_OK) return st;
-    st = ensure_scratch(p->sb_xc2, static_cast<size_t>(pitch2) * p->nchans);
+    st = ensure_scratch(p->sb_xc2, static_cast<size_t>(pitch2) * npairs * nsub);
     if (st != DEDISP_OK) return st;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     // corner turn: every channel keeps its row (killed channels are zeros)
@@ -1038,7 +1054,7 @@ static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps
     hipError_t e = dedisp::launch_unpack(d0, p->nbits, p->fmt, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     // stage 1: the tree's first log2(nsub) steps, 16-bit rows n*nsub + d'
-    e = dedisp::launch_tree(d0, p->fmt, nsub, ob, p->sb_xc2.ptr, pitch2, len1, hs);
+    e = dedisp::launch_tree(d0, p->fmt, nsub, ob, p->d_tree_pairs, npairs, p->sb_xc2.ptr, pitch2, len1, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     // stage 2: every trial sums, over the sub-bands, its tree row at its delay
     BeamDesc dg;
@@ -1490,25 +1506,49 @@ dedisp_status dedisp_set_tree(dedisp_plan p, int nsub)
         const double fb = p->f_top + static_cast<double>((n + 1) * nsub) * p->df;
         step[n] = samples_per_unit * (1.0 / (fb * fb) - inv_f0_sq) - samples_per_unit * (1.0 / (fa * fa) - inv_f0_sq);
     }
-    std::vector<int32_t> rows(static_cast<size_t>(ndm) * nsb), delay(rows.size());
-    int mx = 0;
+    // past the diagonal (Section 3, computing larger DMs): sub-band n of
+    // trial d reads stage-1 pass p = d' / nsub (a delay of p samples per
+    // channel imposed within the sub-band) at tree DM d' mod nsub
+    std::vector<int32_t> dprime(static_cast<size_t>(ndm) * nsb), delay(dprime.size());
+    int mx = 0, maxpass = 0;
     for (int d = 0; d < ndm; ++d) {
         double acc = 0.0;
         for (int n = 0; n < nsb; ++n) {
             const double dp = std::round(p->dms[d] * step[n]);
             const double dd = std::round(p->dms[d] * acc);
-            if (dp >= static_cast<double>(nsub))
-                return fail(DEDISP_ERR_UNSUPPORTED, "a trial lies beyond the piecewise linear tree's diagonal DM");
-            if (!(dd < 2.0e9)) return fail(DEDISP_ERR_INVALID_ARG, "a delay does not fit in int32");
-            rows[static_cast<size_t>(d) * nsb + n] = n * nsub + static_cast<int32_t>(dp);
+            if (!(dd < 2.0e9) || !(dp < 2.0e9)) return fail(DEDISP_ERR_INVALID_ARG, "a delay does not fit in int32");
+            dprime[static_cast<size_t>(d) * nsb + n] = static_cast<int32_t>(dp);
             delay[static_cast<size_t>(d) * nsb + n] = static_cast<int32_t>(dd);
             mx = std::max(mx, static_cast<int>(dd));
+            maxpass = std::max(maxpass, static_cast<int>(dp) / nsub);
             acc += step[n];
         }
+    }
+    // the (sub-band, pass) pairs in use, sub-band major
+    std::vector<int32_t> pair_of(static_cast<size_t>(nsb) * (maxpass + 1), -1);
+    for (size_t i = 0; i < dprime.size(); ++i)
+        pair_of[(i % nsb) * (maxpass + 1) + dprime[i] / nsub] = 0;
+    std::vector<int32_t> pairs;
+    for (int n = 0; n < nsb; ++n)
+        for (int q = 0; q <= maxpass; ++q) {
+            int32_t& y = pair_of[static_cast<size_t>(n) * (maxpass + 1) + q];
+            if (y < 0) continue;
+            y = static_cast<int32_t>(pairs.size() / 2);
+            pairs.push_back(n);
+            pairs.push_back(q);
+        }
+    if (pairs.size() / 2 > 65535)
+        return fail(DEDISP_ERR_UNSUPPORTED, "more than 65535 (sub-band, pass) pairs for the tree's stage 1");
+    std::vector<int32_t> rows(dprime.size());
+    for (size_t i = 0; i < dprime.size(); ++i) {
+        const int n = static_cast<int>(i % nsb), q = dprime[i] / nsub;
+        rows[i] = pair_of[static_cast<size_t>(n) * (maxpass + 1) + q] * nsub + dprime[i] % nsub;
     }
     destroy_tree(p);
     p->tree_nsub = nsub;
     p->tree_maxdelay = mx;
+    p->tree_npass = maxpass + 1;
+    p->tree_pairs.swap(pairs);
     p->tree_rows.swap(rows);
     p->tree_delay.swap(delay);
     return DEDISP_OK;

@@ -143,13 +143,18 @@ struct dedisp_plan_s {
     // Internal plans of grouped passes: the table holds ngroups blocks of
     // [ndm][nchans]; the last group has ndm_last valid rows; vbound (when
     // set) bounds one scratch sample.
-    // Piecewise linear tree (0 = off): sub-band width, and per (trial,
-    // sub-band) the tree row n*nsub + d'_n(d) and the delay dt''_n(d).
+    // Piecewise linear tree (0 = off): sub-band width; the (sub-band, pass)
+    // pairs stage 1 computes, pair y's rows at y*nsub .. y*nsub + nsub - 1;
+    // per (trial, sub-band) the stage-1 row of d'_n(d) and the delay
+    // dt''_n(d); passes in use = largest pass + 1.
     int tree_nsub = 0;
     int tree_maxdelay = 0;
+    int tree_npass = 0;
+    std::vector<int32_t> tree_pairs;        // [npairs][2] = (sub-band, pass)
     std::vector<int32_t> tree_rows, tree_delay;
     int32_t* d_tree_rows = nullptr;
     int32_t* d_tree_delay = nullptr;
+    int32_t* d_tree_pairs = nullptr;
     bool internal = false;
     int ngroups = 1;
     int ndm_last = 0;

@@ -91,12 +91,15 @@ constexpr int kMaxLdsBytes = 160 * 1024;
 hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st);
 
 // Stage 1 of the piecewise linear tree: k = log2(nsub) tree steps (Theta/Phi)
-// within every sub-band of the channel-major scratch d.xc (format fmt, every
-// channel's row kept), written as rows n*nsub + d' of out (pitch out_pitch
-// bytes, 16-byte aligned) for t < len1 = nsamps - (nsub - 1), one byte
-// (ob = 1: 2-bit input, nsub <= 64) or 16 bits (ob = 2) per sample.
-hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, uint8_t* out, long long out_pitch,
-                       long long len1, hipStream_t st);
+// for each of the npairs (sub-band n, pass p) pairs in pairs[2y], pairs[2y+1]
+// (device memory), over the channel-major scratch d.xc (format fmt, every
+// channel's row kept) with channel j of the sub-band read p*j samples later;
+// pair y's tree DM d' is written as row y*nsub + d' of out (pitch out_pitch
+// bytes, 16-byte aligned) for t < len1, one byte (ob = 1: 2-bit input,
+// nsub <= 64) or 16 bits (ob = 2) per sample.  The scratch rows must hold
+// len1 + tile + nsub + (largest p)(nsub - 1) + 8 samples.
+hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, const int32_t* pairs, int npairs,
+                       uint8_t* out, long long out_pitch, long long len1, hipStream_t st);
 // Samples per time tile of the tree kernel (the scratch rows need this many
 // samples of margin past nsamps).
 int tree_tile(int nsub);

@@ -38,7 +38,8 @@ __device__ __forceinline__ int tree_theta(int i, int v) { return ((v & ((2 << i)
 __device__ __forceinline__ int tree_phi(int i, int v) { return ((v & 1) << i) + (v >> 1) + ((v >> (i + 1)) << i); }
 
 template <int FMT, int NSUB, int OB>
-__global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long long out_pitch, long long len1)
+__global__ __launch_bounds__(256) void k_tree(BeamDesc b, const int32_t* pairs, uint8_t* out, long long out_pitch,
+                                              long long len1)
 {
     constexpr int T = tree_tile_len(NSUB);
     constexpr int L = T + NSUB;                    // samples loaded per row (>= T + NSUB - 1)
@@ -51,8 +52,11 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long lon
     uint32_t* A = tw;
     uint32_t* B = tw + NSUB * RS;
     const long long t0 = (long long)blockIdx.x * T;
-    const int n = blockIdx.y;
-    // load: 32-bit scratch words, spread to two 16-bit samples per LDS word
+    const int y = blockIdx.y;
+    const int n = pairs[2 * y], pass = pairs[2 * y + 1];
+    // load: 32-bit scratch words, spread to two 16-bit samples per LDS word;
+    // channel j of the sub-band starts pass*j samples later (the imposed
+    // delay), realigned from two consecutive words
     constexpr int SPW = fmt_samples_per_word(FMT);
     constexpr int WPR = L / SPW;                   // scratch words per row
     static_assert(L % SPW == 0, "whole words per row");
@@ -64,8 +68,11 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long lon
         const int it = threadIdx.x + 256 * k;
         if (it < NSUB * WPR) {
             const int j = it / WPR, w = it % WPR;
-            const uint8_t* row = b.xc + (long long)(n * NSUB + j) * b.pitch;
-            ld[k] = *reinterpret_cast<const uint32_t*>(row + (t0 / SPW + w) * 4);
+            const int shift = pass * j;
+            const uint32_t* row = reinterpret_cast<const uint32_t*>(b.xc + (long long)(n * NSUB + j) * b.pitch);
+            u32x2 v;
+            __builtin_memcpy(&v, row + t0 / SPW + shift / SPW + w, sizeof(v));
+            ld[k] = __builtin_amdgcn_alignbit(v.y, v.x, (shift % SPW) * (32 / SPW));
         }
     }
 #pragma unroll
@@ -121,7 +128,7 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long lon
             // bytes 0 and 2 of each word: samples 2w and 2w+1
             const u32x4 v = {__builtin_amdgcn_perm(a.y, a.x, 0x06040200u), __builtin_amdgcn_perm(a.w, a.z, 0x06040200u),
                              __builtin_amdgcn_perm(c.y, c.x, 0x06040200u), __builtin_amdgcn_perm(c.w, c.z, 0x06040200u)};
-            uint8_t* orow = out + (long long)(n * NSUB + dp) * out_pitch;
+            uint8_t* orow = out + (long long)(y * NSUB + dp) * out_pitch;
             if (tg + 16 <= len1) {
                 *reinterpret_cast<u32x4*>(orow + tg) = v;
             } else {
@@ -138,7 +145,7 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, uint8_t* out, long lon
         const long long tg = t0 + t;
         if (tg >= len1) continue;
         const u32x4 val = *reinterpret_cast<const u32x4*>(A + dp * RS + t / 2);
-        uint16_t* orow = reinterpret_cast<uint16_t*>(out + (long long)(n * NSUB + dp) * out_pitch);
+        uint16_t* orow = reinterpret_cast<uint16_t*>(out + (long long)(y * NSUB + dp) * out_pitch);
         if (tg + 8 <= len1) {
             *reinterpret_cast<u32x4*>(orow + tg) = val;
         } else {
@@ -278,13 +285,15 @@ hipError_t launch_tree_combine(const BeamDesc& d, int ob, int flush, hipStream_t
     return hipLaunchKernel(fn, dim3((unsigned)(8 * per_xcd)), dim3(256), args, 0, st);
 }
 
-hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, uint8_t* out, long long out_pitch,
-                       long long len1, hipStream_t st)
+hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, const int32_t* pairs, int npairs,
+                       uint8_t* out, long long out_pitch, long long len1, hipStream_t st)
 {
-    if (len1 <= 0 || (out_pitch & 15) || (reinterpret_cast<uintptr_t>(out) & 15)) return hipErrorInvalidValue;
+    if (len1 <= 0 || (out_pitch & 15) || (reinterpret_cast<uintptr_t>(out) & 15) || !pairs ||
+        (d.pitch & 3))
+        return hipErrorInvalidValue;
     const long long T = tree_tile_len(nsub);
     const long long gx = (len1 + T - 1) / T;
-    const long long gy = d.nchans / nsub;
+    const long long gy = npairs;
     if (gx <= 0 || gx > 0x7fffffffLL || gy <= 0 || gy > 65535) return hipErrorInvalidValue;
     const void* fn = nullptr;
     // byte rows hold 2-bit sub-band sums up to nsub = 64 (3 * 64 < 256)
@@ -300,9 +309,10 @@ hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, uint8_t* ou
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     BeamDesc a0 = d;
-    uint8_t* a1 = out;
-    long long a2 = out_pitch, a3 = len1;
-    void* args[] = {&a0, &a1, &a2, &a3};
+    const int32_t* a1 = pairs;
+    uint8_t* a2 = out;
+    long long a3 = out_pitch, a4 = len1;
+    void* args[] = {&a0, &a1, &a2, &a3, &a4};
     return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, lds, st);
 }
 

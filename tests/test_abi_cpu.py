@@ -309,14 +309,20 @@ def _tree_diag(nchans, nsub, dt, f0, df):
     return (nsub - 0.5) / (k * (1 / fb ** 2 - 1 / f0 ** 2) - k * (1 / fa ** 2 - 1 / f0 ** 2))
 
 
-@pytest.mark.parametrize("nchans,nbits,nsub", [(1024, 2, 32), (512, 2, 8), (256, 8, 64), (128, 8, 128)])
-def test_tree_output_lengths_match_oracle(native, nchans, nbits, nsub):
+@pytest.mark.parametrize("nchans,nbits,nsub,reach", [(1024, 2, 32, 0.99), (512, 2, 8, 0.99),
+                                                     (256, 8, 64, 0.99), (128, 8, 128, 0.99),
+                                                     (1024, 2, 32, 30.0), (256, 8, 16, 4.5)])
+def test_tree_output_lengths_match_oracle(native, nchans, nbits, nsub, reach):
+    """Outputs exist for t < nsamps - (P + 1)(nsub - 1) - max dt'', P the largest
+    pass (0 up to the diagonal), as the oracle's tables give."""
     dt, f0, df = 64e-6, 1581.8, -400.0 / nchans
-    dms = np.linspace(0.0, 0.99 * _tree_diag(nchans, nsub, dt, f0, df), 50)
+    dms = np.linspace(0.0, reach * _tree_diag(nchans, nsub, dt, f0, df), 50)
     plan = Plan(nchans, dt, f0, df, nbits).set_dm_list(dms).set_tree(nsub)
-    _, dd = oracle.tree_combine_tables(nchans, dt, f0, df, nsub, dms)
+    dp, dd = oracle.tree_dm_tables(nchans, dt, f0, df, nsub, dms)
+    npass = int(dp.max()) // nsub + 1
+    assert (npass == 1) == (reach < 1)
     nsamps = 1 << 18
-    assert np.all(plan.output_lengths(nsamps) == nsamps - (nsub - 1) - dd.max())
+    assert np.all(plan.output_lengths(nsamps) == nsamps - npass * (nsub - 1) - dd.max())
     plan.set_tree(0)
     assert np.all(plan.output_lengths(nsamps) == nsamps - plan.max_delay)
 
@@ -331,7 +337,7 @@ def test_tree_validation_precedes_hip(native):
     for bad in (4, 12, 256, 3, -16):
         assert L.dedisp_set_tree(plan.handle, bad) == -1, bad
     plan.set_dm_list(np.linspace(0, 1.5 * diag, 10))
-    assert L.dedisp_set_tree(plan.handle, 16) == -6                         # beyond the diagonal
+    assert L.dedisp_set_tree(plan.handle, 16) == 0                          # a second pass
     plan.set_dm_list(np.linspace(0, 0.9 * diag, 10))
     assert L.dedisp_set_tree(plan.handle, 16) == 0
     f = np.array([1] * 5 + [2] * 5, np.int32)

@@ -1,8 +1,9 @@
 """GPU parity of the piecewise linear tree (Section 3) against the oracle, bit for bit.
 
-Stage 1 (the tree's Theta/Phi steps within each sub-band, in LDS) and stage 2
-(the sub-band combination, a gather over tree rows) run on the GPU; the
-oracle performs the same steps on the CPU.
+Stage 1 (the tree's Theta/Phi steps within each sub-band, in LDS, once per
+pass for trials past the diagonal) and stage 2 (the sub-band combination, a
+gather over tree rows) run on the GPU; the oracle performs the same steps on
+the CPU.
 """
 import numpy as np
 import pytest
@@ -38,6 +39,29 @@ def test_piecewise_tree_bit_exact(native, cuda, nbits, nchans, nsub, nsamps):
     codes = (rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8) if nbits == 2 else
              rng.integers(0, 256, size=(nsamps, nchans), dtype=np.uint8))
     codes[::53] = 3 if nbits == 2 else 255
+    packed = synth.pack(codes, nbits)
+    want = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub)
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms).set_tree(nsub)
+    assert np.all(plan.output_lengths(nsamps) == want.shape[1])
+    got = _run(plan, packed, nsamps, cuda)
+    assert got.shape == want.shape and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("nbits,nchans,nsub,nsamps,reach,ndm", [
+    (2, 256, 16, 30011, 6.0, 41), (2, 512, 32, 24007, 3.2, 33), (8, 128, 8, 20021, 9.0, 29),
+    (8, 256, 64, 16001, 2.5, 17), (2, 256, 128, 14003, 1.8, 13)])
+def test_piecewise_tree_beyond_the_diagonal_bit_exact(native, cuda, nbits, nchans, nsub, nsamps, reach, ndm):
+    """Trials up to `reach` times the piecewise diagonal: stage 1 runs once per
+    (sub-band, pass) pair in use, each pass with its imposed delay, and each
+    sub-band of a trial reads the pass its own d' falls in."""
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    dms = np.linspace(0.0, reach * _diag(nchans, nsub, dt, f_top, df), ndm)
+    dp, _ = oracle.tree_dm_tables(nchans, dt, f_top, df, nsub, dms)
+    assert dp.max() >= nsub                                   # more than one pass
+    rng = np.random.default_rng(nchans * 3 + nsub)
+    codes = (rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8) if nbits == 2 else
+             rng.integers(0, 256, size=(nsamps, nchans), dtype=np.uint8))
+    codes[::41] = 3 if nbits == 2 else 255
     packed = synth.pack(codes, nbits)
     want = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub)
     plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms).set_tree(nsub)
