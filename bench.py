@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--no-systems", action="store_true",
                     help="skip the batched and serving measurements")
     ap.add_argument("--serve-seconds", type=float, default=12.0)
-    ap.add_argument("--legs", default="scrunched,subband,tree,large_beam,batched,serving",
+    ap.add_argument("--legs", default="scrunched,subband,tree,large_beam,tiny,batched,serving",
                     help="comma-separated systems legs to run after the headline transform")
     return ap.parse_args()
 
@@ -204,6 +204,63 @@ def bench_tree(torch, dev, beam, inp, nsamps, steps, nsub=32):
                     "ms": t_ms, "nout": nout, "outputs_per_s": len(dms) * nout / (t_ms * 1e-3),
                     "direct_ms_same_trials": d_ms, "speedup_vs_direct": d_ms / t_ms}
     return res
+
+
+def copy_times(torch, dev, packed, out, ms_per_step):
+    """Host-to-device copy of the survey input and device-to-host copy of its
+    outputs, from and to pinned host memory (the transform itself takes its
+    input already in HBM), and the outputs/s a caller handing over host
+    buffers would see with copies and transform in sequence."""
+    host_in = torch.from_numpy(packed.reshape(-1)).pin_memory()
+    dev_in = torch.empty_like(host_in, device=dev)
+    host_out = torch.empty(out.shape, dtype=out.dtype).pin_memory()
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    h2d = timed(lambda: dev_in.copy_(host_in, non_blocking=True))
+    d2h = timed(lambda: host_out.copy_(out, non_blocking=True))
+    n_in, n_out = host_in.numel(), out.numel() * 4
+    return {"h2d_ms": h2d, "h2d_GBs": n_in / (h2d * 1e-3) / 1e9, "d2h_ms": d2h,
+            "d2h_GBs": n_out / (d2h * 1e-3) / 1e9,
+            "pcie_inclusive_outputs_per_s": out.numel() / ((h2d + ms_per_step + d2h) * 1e-3)}
+
+
+def bench_tiny(torch, dev, reps=200):
+    """The tiny 8-bit case: 4096 samples x 64 channels of 64 us, f_top 1500 MHz,
+    df -1 MHz, 32 DMs in [0, 100) (launch-bound; a parity case, reported but
+    not the roofline's workload)."""
+    from paper_1201_5380_amd import Plan, synth
+    b = synth.tiny_beam()
+    plan = Plan(b.nchans, b.dt, b.f_top, b.df, b.nbits).set_dm_list(b.dms)
+    b.inject(lambda i: plan.delay_table()[i])
+    nsamps = b.nsamps
+    inp = torch.from_numpy(np.ascontiguousarray(b.packed()).reshape(-1)).to(dev)
+    nout = nsamps - plan.max_delay
+    out = torch.empty((plan.ndm, nout), dtype=torch.int32, device=dev)
+    plan.tune(inp, out, nsamps)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for _ in range(5):
+        plan.execute(inp, nsamps, out=out)
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record()
+        plan.execute(inp, nsamps, out=out)
+        e1.record()
+    torch.cuda.synchronize()
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    return {"workload": "tiny beam: 8-bit, 64 ch, 4096 samples x 64 us, 32 DMs in [0, 100), "
+                        "f_top 1500 MHz, df -1 MHz",
+            "median_ms": float(np.median(ms)), "p95_ms": float(np.percentile(ms, 95)),
+            "outputs_per_s": plan.ndm * nout / (float(np.median(ms)) * 1e-3), "tile": plan.tile_config()}
 
 
 def bench_large(torch, dev, steps):
@@ -412,6 +469,8 @@ def main():
     wall = time.perf_counter() - w0
     kern_ms = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
 
+    copies = copy_times(torch, dev, packed, out, ms_per_step=float(np.mean(kern_ms)))
+
     # sanity: every injected pulse peaks at its trial and time
     got = out.cpu().numpy().view(np.uint32)
     pulses_ok = True
@@ -481,6 +540,7 @@ def main():
         "hbm_algorithmic_GBs": alg_bytes / (mean_ms * 1e-3) / 1e9,
         "pulses_recovered": bool(pulses_ok),
         "tune_best_ms": tune_ms,
+        "copies": copies,
         "device": torch.cuda.get_device_name(0),
     }
     if not args.no_systems:
@@ -490,6 +550,7 @@ def main():
             "subband": lambda: bench_subband(torch, dev, plan, inp, nsamps, max(3, args.steps // 2), mean_ms),
             "tree": lambda: bench_tree(torch, dev, beam, inp, nsamps, max(3, args.steps // 2)),
             "large_beam": lambda: bench_large(torch, dev, 3),
+            "tiny": lambda: bench_tiny(torch, dev),
             "batched": lambda: bench_batch(torch, dev, max(3, args.steps // 4)),
             "serving": lambda: bench_serve(torch, dev, args.serve_seconds),
         }
