@@ -77,11 +77,14 @@ def _load():
     lib.oracle_tree_imposed.argtypes = [_u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, _u32p, _i32p]
     lib.oracle_tree_dm_tables.argtypes = lib.oracle_tree_combine_tables.argtypes
+    lib.oracle_tree_imposed_values.argtypes = [_u32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_int, _u32p, _i32p]
     lib.oracle_tree_combine_passes.argtypes = [_u32p, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
                                                ctypes.c_int, _i32p, _i32p, ctypes.c_int, ctypes.c_int64,
                                                _u32p]
     for f in ("oracle_tree", "oracle_tree_combine_tables", "oracle_tree_combine",
               "oracle_tree_imposed", "oracle_tree_dm_tables", "oracle_tree_combine_passes",
+              "oracle_tree_imposed_values",
               "oracle_reduce_output", "oracle_subband_lengths", "oracle_subband_step1", "oracle_subband_step2",
               "oracle_dedisperse_scrunched_points", "oracle_partial_delay", "oracle_delay_table", "oracle_dedisperse",
               "oracle_dedisperse_points", "oracle_max_threads", "oracle_diagonal_dm",
@@ -384,6 +387,21 @@ def tree_imposed(packed, nsamps, nchans, nbits, k, slope, mask=None):
     return out
 
 
+def tree_imposed_values(x, k, slope, mask=None):
+    """tree_imposed over unpacked time-major values x [nsamps][nchans] (e.g. scrunched
+    samples): uint32 [nchans][nsamps - (slope + 1)(2^k - 1)]."""
+    x = np.ascontiguousarray(x, dtype=np.uint32)
+    nsamps, nchans = x.shape
+    n_out = nsamps - (int(slope) + 1) * ((1 << int(k)) - 1)
+    if n_out <= 0:
+        raise OracleError("too few samples")
+    out = np.zeros((nchans, n_out), dtype=np.uint32)
+    m, mp = _mask_arg(mask, nchans)
+    _check(_load().oracle_tree_imposed_values(_ptr(x, _u32p), nsamps, nchans, int(k), int(slope),
+                                              _ptr(out, _u32p), mp), "tree_imposed_values")
+    return out
+
+
 def tree_dm_tables(nchans, dt, f_top, df, nsub, dms):
     """(d'_n(d), dt''_n(d)) as int32 [ndm][nchans / nsub] each, d' unrestricted."""
     dms = np.ascontiguousarray(dms, dtype=np.float64)
@@ -408,12 +426,8 @@ def tree_combine_tables(nchans, dt, f_top, df, nsub, dms):
     return dp, dd
 
 
-def dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub, mask=None):
-    """Piecewise linear tree (Section 3): stage 1 = log2(nsub) tree steps, stage 2 = the
-    sub-band combination.  Trials past the piecewise diagonal use further passes with an
-    imposed delay (pass p: p samples per channel within each sub-band), sub-band n of
-    trial d taking pass d'_n(d) // nsub.  uint32 [ndm][nout], nout = nsamps -
-    (P + 1)(nsub - 1) - max dt'' with P the largest pass."""
+def _piecewise_tree(stage1, nsamps, nchans, dt, f_top, df, dms, nsub):
+    """Stage 2 over the passes stage1(p) -> [nchans][>= len1] returns."""
     k = int(nsub).bit_length() - 1
     if (1 << k) != int(nsub):
         raise OracleError("nsub must be a power of two")
@@ -425,15 +439,51 @@ def dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms,
         raise OracleError("too few samples")
     out = np.zeros((len(dms), nout), dtype=np.uint32)
     if npass == 1:
-        S = tree(packed, nsamps, nchans, nbits, k, mask=mask)
+        S = np.ascontiguousarray(stage1(0)[:, :len1])
         _check(_load().oracle_tree_combine(_ptr(S, _u32p), nchans, len1, int(nsub), _ptr(dp, _i32p),
                                            _ptr(dd, _i32p), len(dms), nout, _ptr(out, _u32p)),
                "tree_combine")
         return out
     S = np.zeros((npass, nchans, len1), dtype=np.uint32)
     for p in range(npass):
-        S[p] = tree_imposed(packed, nsamps, nchans, nbits, k, p, mask=mask)[:, :len1]
+        S[p] = stage1(p)[:, :len1]
     _check(_load().oracle_tree_combine_passes(_ptr(S, _u32p), npass, nchans, len1, int(nsub),
                                               _ptr(dp, _i32p), _ptr(dd, _i32p), len(dms), nout,
                                               _ptr(out, _u32p)), "tree_combine_passes")
     return out
+
+
+def dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub, mask=None):
+    """Piecewise linear tree (Section 3): stage 1 = log2(nsub) tree steps, stage 2 = the
+    sub-band combination.  Trials past the piecewise diagonal use further passes with an
+    imposed delay (pass p: p samples per channel within each sub-band), sub-band n of
+    trial d taking pass d'_n(d) // nsub.  uint32 [ndm][nout], nout = nsamps -
+    (P + 1)(nsub - 1) - max dt'' with P the largest pass."""
+    k = int(nsub).bit_length() - 1
+    if int(nsub) != 1 << k:
+        raise OracleError("nsub must be a power of two")
+    return _piecewise_tree(lambda p: (tree(packed, nsamps, nchans, nbits, k, mask=mask) if p == 0 else
+                                      tree_imposed(packed, nsamps, nchans, nbits, k, p, mask=mask)),
+                           nsamps, nchans, dt, f_top, df, dms, nsub)
+
+
+def dedisperse_piecewise_tree_scrunched(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub,
+                                       factors, mask=None):
+    """The tree on time-scrunched data (Section 3, computing larger DMs with
+    time-scrunching): the trials of scrunch factor s go through the piecewise tree
+    (with its passes) over the s-sample sums (scrunch) at resolution s*dt.  Returns a
+    list of uint32 rows, trial d's of length nsamps // s - (P_s + 1)(nsub - 1) -
+    max dt''_s over its group."""
+    dms = np.asarray(dms, dtype=np.float64)
+    factors = np.asarray(factors)
+    k = int(nsub).bit_length() - 1
+    rows = [None] * len(dms)
+    for s in sorted(set(int(f) for f in factors)):
+        idx = np.nonzero(factors == s)[0]
+        x = scrunch(packed, nsamps, nchans, nbits, s)
+        n = x.shape[0]
+        got = _piecewise_tree(lambda p: tree_imposed_values(x, k, p, mask=mask), n, nchans, dt * s,
+                              f_top, df, dms[idx], nsub)
+        for j, d in enumerate(idx):
+            rows[d] = got[j]
+    return rows

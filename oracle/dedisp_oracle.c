@@ -460,13 +460,16 @@ static int oracle_tree_phi(int r, int v) { return (v % 2) * r + v / 2 + (v / (2 
 
 /* k steps of the tree over every channel (nchans a multiple of 2^k), with an
  * optional 0/1 kill mask applied to the input: out [nchans][nsamps - (2^k - 1)]. */
-/* The k tree steps on the channel-major input, channel v read
- * slope * (v mod 2^k) samples later (slope = 0: the input as it is). */
-static int tree_steps(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k, int slope,
-                      uint32_t* out, const int32_t* mask)
+/* The k tree steps on the channel-major input -- packed codes `in` of nbits
+ * bits, or (in = NULL) unpacked time-major values `vals` [nsamps][nchans] --
+ * with channel v read slope * (v mod 2^k) samples later (slope = 0: the input
+ * as it is). */
+static int tree_steps(const uint8_t* in, const uint32_t* vals, int64_t nsamps, int nchans, int nbits,
+                      int k, int slope, uint32_t* out, const int32_t* mask)
 {
-    if (!in || !out || k < 0 || k > 20 || nchans <= 0 || nchans % (1 << k) || slope < 0) return ORACLE_BAD_ARG;
-    if (nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
+    if ((!in && !vals) || !out || k < 0 || k > 20 || nchans <= 0 || nchans % (1 << k) || slope < 0)
+        return ORACLE_BAD_ARG;
+    if (in && nbits != 2 && nbits != 8) return ORACLE_BAD_ARG;
     const int B = 1 << k;
     const int64_t ns = nsamps - (int64_t)slope * (B - 1);   /* samples every channel has */
     const int64_t n_out = ns - (B - 1);
@@ -482,8 +485,11 @@ static int tree_steps(const uint8_t* in, int64_t nsamps, int nchans, int nbits, 
     /* A^0 = the input, channel-major, with the imposed delay */
     for (int v = 0; v < nchans; ++v) {
         const int64_t shift = (int64_t)slope * (v % B);
-        for (int64_t t = 0; t < ns; ++t)
-            a[(size_t)v * ns + t] = (mask ? (uint32_t)mask[v] : 1u) * oracle_sample(in, nchans, nbits, t + shift, v);
+        for (int64_t t = 0; t < ns; ++t) {
+            const uint32_t x = in ? oracle_sample(in, nchans, nbits, t + shift, v)
+                                  : vals[(size_t)(t + shift) * (size_t)nchans + (size_t)v];
+            a[(size_t)v * ns + t] = (mask ? (uint32_t)mask[v] : 1u) * x;
+        }
     }
     int64_t len = ns;
     for (int i = 0; i < k; ++i) {
@@ -516,7 +522,7 @@ static int tree_steps(const uint8_t* in, int64_t nsamps, int nchans, int nbits, 
 int oracle_tree(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k,
                 uint32_t* out, const int32_t* mask)
 {
-    return tree_steps(in, nsamps, nchans, nbits, k, 0, out, mask);
+    return tree_steps(in, NULL, nsamps, nchans, nbits, k, 0, out, mask);
 }
 
 /* Stage 1 for DMs beyond the piecewise diagonal (Section 3, computing larger
@@ -529,7 +535,16 @@ int oracle_tree(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k,
 int oracle_tree_imposed(const uint8_t* in, int64_t nsamps, int nchans, int nbits, int k, int slope,
                         uint32_t* out, const int32_t* mask)
 {
-    return tree_steps(in, nsamps, nchans, nbits, k, slope, out, mask);
+    return tree_steps(in, NULL, nsamps, nchans, nbits, k, slope, out, mask);
+}
+
+/* The same pass over unpacked time-major values x [nsamps][nchans] (such as
+ * the scrunched samples of oracle_scrunch: the paper applies the tree to
+ * scrunched data for the larger DMs in the same way). */
+int oracle_tree_imposed_values(const uint32_t* x, int64_t nsamps, int nchans, int k, int slope,
+                               uint32_t* out, const int32_t* mask)
+{
+    return tree_steps(NULL, x, nsamps, nchans, 0, k, slope, out, mask);
 }
 
 /* Stage 2 of the piecewise linear tree (Section 3, eq. combining_subbands):

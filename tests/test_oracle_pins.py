@@ -920,3 +920,86 @@ def test_piecewise_tree_finds_a_pulse_beyond_the_diagonal():
     d, t = np.unravel_index(int(win.argmax()), win.shape)
     assert dms[d0] > 2.5 * diag
     assert abs(d - d0) <= 1 and abs(t - 40) <= 1, (d, t)
+
+
+# ---------------------------------------------------------------- tree on scrunched data
+
+def test_tree_over_values_equals_tree_over_codes():
+    """The values path of the tree (for scrunched samples) on the unpacked codes
+    is the packed-code path, for both bit depths and with an imposed slope."""
+    rng = np.random.default_rng(41)
+    nchans, nsamps = 32, 260
+    for nbits, hi in ((2, 4), (8, 256)):
+        codes = rng.integers(0, hi, size=(nsamps, nchans), dtype=np.uint8)
+        packed = synth.pack(codes, nbits)
+        mask = (rng.random(nchans) < 0.8).astype(np.int32)
+        for k, slope in ((2, 0), (3, 2), (4, 1)):
+            assert np.array_equal(oracle.tree_imposed_values(codes.astype(np.uint32), k, slope, mask=mask),
+                                  oracle.tree_imposed(packed, nsamps, nchans, nbits, k, slope, mask=mask))
+
+
+def test_scrunched_tree_with_unit_factors_is_the_tree():
+    nsub, nsamps = 16, 2200
+    nchans, prm, diag, dms = _beyond_case(nsub, 2.5, ndm=12)
+    rng = np.random.default_rng(43)
+    packed = synth.pack(rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8), 2)
+    rows = oracle.dedisperse_piecewise_tree_scrunched(packed, nsamps, nchans, 2, prm["dt"], prm["f_top"],
+                                                      prm["df"], dms, nsub, np.ones(len(dms), int))
+    want = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, 2, prm["dt"], prm["f_top"],
+                                            prm["df"], dms, nsub)
+    assert np.array_equal(np.stack(rows), want)
+
+
+def test_scrunched_tree_is_the_composed_sum_over_scrunched_samples():
+    """Each factor group is the direct sum, over the group's s-sample sums
+    (reshape-summed here, not through the oracle's scrunch), at the composed
+    delays of its tables at s*dt; the group's rows have the group's length."""
+    nsub, nsamps = 16, 4000
+    nchans, prm, diag, dms = _beyond_case(nsub, 7.0, ndm=16)
+    factors = np.array([1 if dm < 2 * diag else 2 if dm < 4 * diag else 4 for dm in dms])
+    rng = np.random.default_rng(47)
+    codes = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+    rows = oracle.dedisperse_piecewise_tree_scrunched(synth.pack(codes, 2), nsamps, nchans, 2, prm["dt"],
+                                                      prm["f_top"], prm["df"], dms, nsub, factors)
+    rec = _tree_delay_recursion(int(nsub).bit_length() - 1)
+    for s in (1, 2, 4):
+        idx = np.nonzero(factors == s)[0]
+        assert idx.size
+        n = nsamps // s
+        x = codes[: n * s].astype(np.int64).reshape(n, s, nchans).sum(axis=1)
+        dp, dd = oracle.tree_dm_tables(nchans, prm["dt"] * s, prm["f_top"], prm["df"], nsub, dms[idx])
+        E = np.zeros((len(idx), nchans), dtype=np.int64)
+        for a in range(len(idx)):
+            for c in range(nchans):
+                nb, j = divmod(c, nsub)
+                p, row = divmod(int(dp[a, nb]), nsub)
+                E[a, c] = dd[a, nb] + p * j + rec[row, j]
+        bf = _push_brute_force(x, E)
+        npass = int(dp.max()) // nsub + 1
+        L = n - npass * (nsub - 1) - int(dd.max())
+        for a, d in enumerate(idx):
+            assert rows[d].shape == (L,)
+            assert np.array_equal(rows[d].astype(np.int64), bf[a, :L]), (s, d)
+
+
+def test_scrunched_tree_finds_a_pulse_at_six_times_the_diagonal():
+    """A pulse at the exact delays of a trial near 6x the diagonal, its trail
+    two samples wide (so the 4-sample sums keep it whole), peaks at that
+    trial and at t0 / 4 in the factor-4 group."""
+    nsub, nsamps = 16, 6000
+    nchans, prm, diag, dms = _beyond_case(nsub, 7.0, ndm=48)
+    factors = np.array([1 if dm < 2 * diag else 2 if dm < 4 * diag else 4 for dm in dms])
+    tab, _ = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], dms)
+    d0 = int(np.argmin(np.abs(dms - 6.0 * diag)))
+    t0 = 1600
+    codes = np.ones((nsamps, nchans), dtype=np.uint8)
+    for c in range(nchans):
+        codes[t0 + tab[d0, c]: t0 + tab[d0, c] + 2, c] = 3
+    rows = oracle.dedisperse_piecewise_tree_scrunched(synth.pack(codes, 2), nsamps, nchans, 2, prm["dt"],
+                                                      prm["f_top"], prm["df"], dms, nsub, factors)
+    idx = np.nonzero(factors == 4)[0]
+    L = min(rows[d].shape[0] for d in idx)
+    win = np.stack([rows[d][t0 // 4 - 30:t0 // 4 + 31] for d in idx]).astype(np.int64)
+    a, t = np.unravel_index(int(win.argmax()), win.shape)
+    assert factors[d0] == 4 and L > t0 // 4 + 31
+    assert abs(idx[a] - d0) <= 1 and abs(t - 30) <= 1, (idx[a], d0, t)
