@@ -155,8 +155,10 @@ dedisp_status dedisp_default_scrunch_factors(dedisp_plan plan, int max_factor, i
  * trials sharing its factor) outputs at resolution s*dt.  Setting a new DM
  * list switches scrunching off; the delay table and max_delay queries keep
  * describing the full-resolution list.  Streams and batches reject a plan
- * with scrunching on (UNSUPPORTED).  Work enqueued with the plan must have
- * finished.  Errors: INVALID_ARG, NO_DM_LIST, OOM. */
+ * with scrunching on (UNSUPPORTED).  Set it before dedisp_set_tree (each
+ * factor group then runs the tree); while the tree is on any call, and with
+ * sub-band mode on a call with factors, is UNSUPPORTED.  Work enqueued with the plan must have finished.
+ * Errors: INVALID_ARG, NO_DM_LIST, OOM, UNSUPPORTED. */
 dedisp_status dedisp_set_scrunching(dedisp_plan plan, const int32_t* factors);
 
 /* Valid outputs of every row for an input of nsamps rows, written to host
@@ -185,9 +187,14 @@ dedisp_status dedisp_get_output_lengths(dedisp_plan plan, size_t nsamps, size_t*
  * of trial d reads pass p = d'_n(d) / nsub at tree DM d'_n(d) mod nsub, and
  * outputs then exist for t < nsamps - (P + 1)(nsub - 1) - (largest dt''),
  * P the largest pass.  Stage 1 runs once per (sub-band, pass) pair in use
- * (at most 65535 pairs, else UNSUPPORTED).  nsub = 0 switches the mode off; a new DM
- * list does too.  Excludes time-scrunching and sub-band mode; streams and
- * batches reject such a plan.  Needs 4-byte aligned input rows and a band
+ * (at most 65535 pairs, else UNSUPPORTED).  With time-scrunching set first
+ * (dedisp_set_scrunching; setting it afterwards is UNSUPPORTED), every scrunch
+ * group runs its own tree over its s-sample sums at resolution s*dt, as the
+ * paper combines the two for large DMs; its rows' lengths then follow from
+ * nsamps / s, and a group whose sub-band sums can exceed 16 bits (largest
+ * s-sample sum times nsub above 65535) makes the call UNSUPPORTED.
+ * nsub = 0 switches the mode off; a new DM list does too.  Excludes sub-band
+ * mode; streams and batches reject such a plan.  Needs 4-byte aligned input rows and a band
  * whose edge past the last channel is above zero frequency.
  * Errors: INVALID_ARG, NO_DM_LIST, UNSUPPORTED. */
 dedisp_status dedisp_set_tree(dedisp_plan plan, int nsub);

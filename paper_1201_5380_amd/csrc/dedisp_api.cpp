@@ -526,6 +526,8 @@ void destroy_tree(dedisp_plan p)
     p->tree_nsub = 0;
     p->tree_maxdelay = 0;
     p->tree_npass = 0;
+    for (auto& g : p->groups)
+        if (g.sub && g.sub->tree_nsub) destroy_tree(g.sub);
 }
 
 void destroy_subband(dedisp_plan p)
@@ -981,25 +983,18 @@ static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsa
 // Piecewise linear tree: stage-1 length and outputs for nsamps input rows.
 static void tree_lengths(const dedisp_plan_s& p, size_t nsamps, long long& len1, long long& nout)
 {
-    // pass p reads p (nsub - 1) samples further, and its tree another nsub - 1
-    len1 = static_cast<long long>(nsamps) - static_cast<long long>(p.tree_npass) * (p.tree_nsub - 1);
+    // on the plan's (scrunched) samples: pass p reads p (nsub - 1) samples
+    // further, and its tree another nsub - 1
+    len1 = static_cast<long long>(nsamps) / p.scrunch - static_cast<long long>(p.tree_npass) * (p.tree_nsub - 1);
     nout = len1 - p.tree_maxdelay;
 }
 
-static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps, uint32_t* d_out,
-                                  size_t stride, void* stream)
+// The plan whose rows a tree run covers: the plan itself, or each scrunch
+// group's plan (rows placed through the group's row map).
+static dedisp_status tree_upload(dedisp_plan p)
 {
-    if (nsamps > (1ULL << 40)) return fail(DEDISP_ERR_INVALID_ARG, "nsamps too large");
-    long long len1 = 0, nout = 0;
-    tree_lengths(*p, nsamps, len1, nout);
-    if (len1 <= 0 || nout <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps too short for the tree passes");
-    if (stride == 0) stride = static_cast<size_t>(nout);
-    if (stride < static_cast<size_t>(nout)) return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < nout");
-    if (reinterpret_cast<uintptr_t>(d_in) & 3)
-        return fail(DEDISP_ERR_INVALID_ARG, "tree passes need 4-byte aligned input");
     dedisp_status st = ensure_device_table(p);
     if (st != DEDISP_OK) return st;
-    const int nsub = p->tree_nsub, nsb = p->nchans / nsub;
     if (!p->d_tree_rows) {
         const size_t bytes = p->tree_rows.size() * sizeof(int32_t);
         if (hipMalloc(&p->d_tree_rows, bytes) != hipSuccess) {
@@ -1021,22 +1016,40 @@ static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps
         }
         HIP_TRY(hipMemcpy(p->d_tree_pairs, p->tree_pairs.data(), bytes, hipMemcpyHostToDevice));
     }
+    return DEDISP_OK;
+}
+
+// Tree rows are bytes while the largest sub-band sum fits (3 nsub for 2-bit
+// codes up to nsub = 64, small scrunched sums), else 16 bits.
+static int tree_row_bytes(const dedisp_plan_s& p)
+{
+    return static_cast<long long>(p.value_bound()) * p.tree_nsub <= 255 ? 1 : 2;
+}
+
+// Enqueue one plan's tree: corner turn (scrunching for a group's plan),
+// stage 1 per (sub-band, pass) pair, stage 2 into d_out rows (through rowmap
+// when set).  Lengths, strides and tables are checked by the caller.
+static dedisp_status run_tree(dedisp_plan p, const void* d_in, size_t nsamps, uint32_t* d_out,
+                              size_t stride, const int32_t* rowmap, hipStream_t hs)
+{
+    long long len1 = 0, nout = 0;
+    tree_lengths(*p, nsamps, len1, nout);
+    const int nsub = p->tree_nsub, nsb = p->nchans / nsub;
     const int npairs = static_cast<int>(p->tree_pairs.size() / 2);
+    const long long ns = static_cast<long long>(nsamps) / p->scrunch;
     // the tree kernel reads whole tiles (and one more word) past the last
     // sample, up to (npass - 1)(nsub - 1) samples further under an imposed
-    // delay; tree rows are bytes while the largest sub-band sum (3 nsub for
-    // 2-bit codes) fits
-    const long long pitch1 = xc_pitch(static_cast<long long>(nsamps) + dedisp::tree_tile(nsub) + nsub +
+    // delay
+    const long long pitch1 = xc_pitch(ns + dedisp::tree_tile(nsub) + nsub +
                                           static_cast<long long>(p->tree_npass - 1) * (nsub - 1) + 8,
                                       p->fmt, 0);
-    const int ob = (p->nbits == 2 && nsub <= 64) ? 1 : 2;
+    const int ob = tree_row_bytes(*p);
     const long long pitch2 = ((ob * len1 + 64) + 63) / 64 * 64;
-    st = ensure_scratch(p->xc, static_cast<size_t>(pitch1) * p->nchans);
+    dedisp_status st = ensure_scratch(p->xc, static_cast<size_t>(pitch1) * p->nchans);
     if (st != DEDISP_OK) return st;
     st = ensure_scratch(p->sb_xc2, static_cast<size_t>(pitch2) * npairs * nsub);
     if (st != DEDISP_OK) return st;
-    hipStream_t hs = static_cast<hipStream_t>(stream);
-    // corner turn: every channel keeps its row (killed channels are zeros)
+    // corner turn: every channel keeps its row (stage 1 reads killed ones as zeros)
     BeamDesc d0;
     std::memset(&d0, 0, sizeof(d0));
     d0.in0 = static_cast<const uint8_t*>(d_in);
@@ -1048,12 +1061,11 @@ static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps
     d0.pad_row = -1;
     d0.nchans = p->nchans;
     d0.row_bytes = p->row_bytes;
-    d0.scrunch = 1;
+    d0.scrunch = p->scrunch;
     d0.ngroups = 1;
     d0.out_bytes = 4;
     hipError_t e = dedisp::launch_unpack(d0, p->nbits, p->fmt, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    // stage 1: the tree's first log2(nsub) steps, 16-bit rows n*nsub + d'
     e = dedisp::launch_tree(d0, p->fmt, nsub, ob, p->d_tree_pairs, npairs, p->sb_xc2.ptr, pitch2, len1, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     // stage 2: every trial sums, over the sub-bands, its tree row at its delay
@@ -1063,6 +1075,7 @@ static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps
     dg.pitch = pitch2;
     dg.table = p->d_tree_delay;
     dg.rowsel = p->d_tree_rows;
+    dg.rowmap = rowmap;
     dg.nact = nsb;
     dg.nchans = nsb;
     dg.ndm = dg.ndm_last = static_cast<int>(p->dms.size());
@@ -1074,9 +1087,54 @@ static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps
     dg.out_shift = p->out_shift;
     dg.out_stride = static_cast<long long>(stride) * (dg.out_bytes == 4 ? 1 : dg.out_bytes);
     // 16-bit partial sums of at most 65535 / (largest row value) terms
-    const int row_max = ((1 << p->nbits) - 1) * p->tree_nsub;
+    const int row_max = p->value_bound() * nsub;
     e = dedisp::launch_tree_combine(dg, ob, 65535 / row_max, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return DEDISP_OK;
+}
+
+static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps, uint32_t* d_out,
+                                  size_t stride, void* stream)
+{
+    if (nsamps > (1ULL << 40)) return fail(DEDISP_ERR_INVALID_ARG, "nsamps too large");
+    if (reinterpret_cast<uintptr_t>(d_in) & 3)
+        return fail(DEDISP_ERR_INVALID_ARG, "tree passes need 4-byte aligned input");
+    // the plans that run: this one, or every scrunch group's (Section 3's
+    // tree on time-scrunched data); validate them all before any launch
+    std::vector<std::pair<dedisp_plan, const int32_t*>> runs;
+    if (p->groups.empty()) {
+        runs.emplace_back(p, nullptr);
+    } else {
+        for (auto& g : p->groups) {
+            if (!g.d_rows) {
+                const size_t bytes = g.rows.size() * sizeof(int32_t);
+                if (hipMalloc(&g.d_rows, bytes) != hipSuccess) {
+                    g.d_rows = nullptr;
+                    return fail(DEDISP_ERR_OOM, "hipMalloc scrunch row map");
+                }
+                HIP_TRY(hipMemcpy(g.d_rows, g.rows.data(), bytes, hipMemcpyHostToDevice));
+            }
+            runs.emplace_back(g.sub, g.d_rows);
+        }
+    }
+    long long width = 0;
+    for (auto& r : runs) {
+        long long len1 = 0, nout = 0;
+        tree_lengths(*r.first, nsamps, len1, nout);
+        if (len1 <= 0 || nout <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps too short for the tree passes");
+        width = std::max(width, nout);
+    }
+    if (stride == 0) stride = static_cast<size_t>(width);
+    if (stride < static_cast<size_t>(width)) return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < nout");
+    for (auto& r : runs) {
+        dedisp_status st = tree_upload(r.first);
+        if (st != DEDISP_OK) return st;
+    }
+    for (auto& r : runs) {
+        dedisp_status st = run_tree(r.first, d_in, nsamps, d_out, stride, r.second,
+                                    static_cast<hipStream_t>(stream));
+        if (st != DEDISP_OK) return st;
+    }
     return DEDISP_OK;
 }
 
@@ -1337,8 +1395,9 @@ dedisp_status dedisp_set_scrunching(dedisp_plan p, const int32_t* factors)
     if (!p) return fail(DEDISP_ERR_INVALID_ARG, "NULL plan");
     if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
     if (p->scrunch != 1 || p->internal) return fail(DEDISP_ERR_INVALID_ARG, "not a user plan");
-    if ((p->sb_step1 || p->tree_nsub) && factors)
-        return fail(DEDISP_ERR_UNSUPPORTED, "time-scrunching excludes sub-band and tree modes");
+    if (p->sb_step1 && factors) return fail(DEDISP_ERR_UNSUPPORTED, "time-scrunching excludes sub-band mode");
+    // the tree is built on the scrunch groups: switch it off before changing them
+    if (p->tree_nsub) return fail(DEDISP_ERR_UNSUPPORTED, "set time-scrunching before the tree");
     const int ndm = static_cast<int>(p->dms.size());
     bool any = false;
     if (factors) {
@@ -1477,6 +1536,73 @@ dedisp_status dedisp_set_subband(dedisp_plan p, int nsub, int ngroup)
     return DEDISP_OK;
 }
 
+// Tables of the piecewise tree with sub-bands of nsub channels for plan q's
+// trials, at q's resolution (dt, or s*dt for a scrunch group's plan).
+static dedisp_status build_tree(dedisp_plan q, int nsub)
+{
+    const int nsb = q->nchans / nsub;
+    const int ndm = static_cast<int>(q->dms.size());
+    // Section 3, eq. combining_subbands, in binary64 in this order:
+    // d'_n = round(DM [DeltaT(v_{n+1}) - DeltaT(v_n)]),
+    // dt''_n = round(DM * (sum of those brackets over the sub-bands before n))
+    const double inv_f0_sq = 1.0 / (q->f_top * q->f_top);
+    const double samples_per_unit = kDispersionConstant / q->dt;
+    std::vector<double> step(nsb);
+    for (int n = 0; n < nsb; ++n) {
+        const double fa = q->f_top + static_cast<double>(n * nsub) * q->df;
+        const double fb = q->f_top + static_cast<double>((n + 1) * nsub) * q->df;
+        step[n] = samples_per_unit * (1.0 / (fb * fb) - inv_f0_sq) - samples_per_unit * (1.0 / (fa * fa) - inv_f0_sq);
+    }
+    // past the diagonal (Section 3, computing larger DMs): sub-band n of
+    // trial d reads stage-1 pass p = d' / nsub (a delay of p samples per
+    // channel imposed within the sub-band) at tree DM d' mod nsub
+    std::vector<int32_t> dprime(static_cast<size_t>(ndm) * nsb), delay(dprime.size());
+    int mx = 0, maxpass = 0;
+    for (int d = 0; d < ndm; ++d) {
+        double acc = 0.0;
+        for (int n = 0; n < nsb; ++n) {
+            const double dp = std::round(q->dms[d] * step[n]);
+            const double dd = std::round(q->dms[d] * acc);
+            if (!(dd < 2.0e9) || !(dp < 2.0e9)) return fail(DEDISP_ERR_INVALID_ARG, "a delay does not fit in int32");
+            dprime[static_cast<size_t>(d) * nsb + n] = static_cast<int32_t>(dp);
+            delay[static_cast<size_t>(d) * nsb + n] = static_cast<int32_t>(dd);
+            mx = std::max(mx, static_cast<int>(dd));
+            maxpass = std::max(maxpass, static_cast<int>(dp) / nsub);
+            acc += step[n];
+        }
+    }
+    if (maxpass >= 65535)
+        return fail(DEDISP_ERR_UNSUPPORTED, "more than 65535 (sub-band, pass) pairs for the tree's stage 1");
+    // the (sub-band, pass) pairs in use, sub-band major
+    std::vector<int32_t> pair_of(static_cast<size_t>(nsb) * (maxpass + 1), -1);
+    for (size_t i = 0; i < dprime.size(); ++i)
+        pair_of[(i % nsb) * (maxpass + 1) + dprime[i] / nsub] = 0;
+    std::vector<int32_t> pairs;
+    for (int n = 0; n < nsb; ++n)
+        for (int ps = 0; ps <= maxpass; ++ps) {
+            int32_t& y = pair_of[static_cast<size_t>(n) * (maxpass + 1) + ps];
+            if (y < 0) continue;
+            y = static_cast<int32_t>(pairs.size() / 2);
+            pairs.push_back(n);
+            pairs.push_back(ps);
+        }
+    if (pairs.size() / 2 > 65535)
+        return fail(DEDISP_ERR_UNSUPPORTED, "more than 65535 (sub-band, pass) pairs for the tree's stage 1");
+    std::vector<int32_t> rows(dprime.size());
+    for (size_t i = 0; i < dprime.size(); ++i) {
+        const int n = static_cast<int>(i % nsb), ps = dprime[i] / nsub;
+        rows[i] = pair_of[static_cast<size_t>(n) * (maxpass + 1) + ps] * nsub + dprime[i] % nsub;
+    }
+    destroy_tree(q);
+    q->tree_nsub = nsub;
+    q->tree_maxdelay = mx;
+    q->tree_npass = maxpass + 1;
+    q->tree_pairs.swap(pairs);
+    q->tree_rows.swap(rows);
+    q->tree_delay.swap(delay);
+    return DEDISP_OK;
+}
+
 dedisp_status dedisp_set_tree(dedisp_plan p, int nsub)
 {
     if (!p) return fail(DEDISP_ERR_INVALID_ARG, "NULL plan");
@@ -1488,69 +1614,25 @@ dedisp_status dedisp_set_tree(dedisp_plan p, int nsub)
     }
     if (nsub < 8 || nsub > 128 || (nsub & (nsub - 1)) || p->nchans % nsub)
         return fail(DEDISP_ERR_INVALID_ARG, "nsub must be a power of two in [8, 128] dividing nchans");
-    if (!p->groups.empty() || p->sb_step1)
-        return fail(DEDISP_ERR_UNSUPPORTED, "the tree excludes time-scrunching and sub-band mode");
+    if (p->sb_step1) return fail(DEDISP_ERR_UNSUPPORTED, "the tree excludes sub-band mode");
     if (p->row_bytes % 4) return fail(DEDISP_ERR_UNSUPPORTED, "tree passes need whole 32-bit words per row");
     if (!(p->f_top + static_cast<double>(p->nchans) * p->df > 0))
         return fail(DEDISP_ERR_UNSUPPORTED, "the band edge past the last channel reaches zero frequency");
-    const int nsb = p->nchans / nsub;
-    const int ndm = static_cast<int>(p->dms.size());
-    // Section 3, eq. combining_subbands, in binary64 in this order:
-    // d'_n = round(DM [DeltaT(v_{n+1}) - DeltaT(v_n)]),
-    // dt''_n = round(DM * (sum of those brackets over the sub-bands before n))
-    const double inv_f0_sq = 1.0 / (p->f_top * p->f_top);
-    const double samples_per_unit = kDispersionConstant / p->dt;
-    std::vector<double> step(nsb);
-    for (int n = 0; n < nsb; ++n) {
-        const double fa = p->f_top + static_cast<double>(n * nsub) * p->df;
-        const double fb = p->f_top + static_cast<double>((n + 1) * nsub) * p->df;
-        step[n] = samples_per_unit * (1.0 / (fb * fb) - inv_f0_sq) - samples_per_unit * (1.0 / (fa * fa) - inv_f0_sq);
-    }
-    // past the diagonal (Section 3, computing larger DMs): sub-band n of
-    // trial d reads stage-1 pass p = d' / nsub (a delay of p samples per
-    // channel imposed within the sub-band) at tree DM d' mod nsub
-    std::vector<int32_t> dprime(static_cast<size_t>(ndm) * nsb), delay(dprime.size());
-    int mx = 0, maxpass = 0;
-    for (int d = 0; d < ndm; ++d) {
-        double acc = 0.0;
-        for (int n = 0; n < nsb; ++n) {
-            const double dp = std::round(p->dms[d] * step[n]);
-            const double dd = std::round(p->dms[d] * acc);
-            if (!(dd < 2.0e9) || !(dp < 2.0e9)) return fail(DEDISP_ERR_INVALID_ARG, "a delay does not fit in int32");
-            dprime[static_cast<size_t>(d) * nsb + n] = static_cast<int32_t>(dp);
-            delay[static_cast<size_t>(d) * nsb + n] = static_cast<int32_t>(dd);
-            mx = std::max(mx, static_cast<int>(dd));
-            maxpass = std::max(maxpass, static_cast<int>(dp) / nsub);
-            acc += step[n];
-        }
-    }
-    // the (sub-band, pass) pairs in use, sub-band major
-    std::vector<int32_t> pair_of(static_cast<size_t>(nsb) * (maxpass + 1), -1);
-    for (size_t i = 0; i < dprime.size(); ++i)
-        pair_of[(i % nsb) * (maxpass + 1) + dprime[i] / nsub] = 0;
-    std::vector<int32_t> pairs;
-    for (int n = 0; n < nsb; ++n)
-        for (int q = 0; q <= maxpass; ++q) {
-            int32_t& y = pair_of[static_cast<size_t>(n) * (maxpass + 1) + q];
-            if (y < 0) continue;
-            y = static_cast<int32_t>(pairs.size() / 2);
-            pairs.push_back(n);
-            pairs.push_back(q);
-        }
-    if (pairs.size() / 2 > 65535)
-        return fail(DEDISP_ERR_UNSUPPORTED, "more than 65535 (sub-band, pass) pairs for the tree's stage 1");
-    std::vector<int32_t> rows(dprime.size());
-    for (size_t i = 0; i < dprime.size(); ++i) {
-        const int n = static_cast<int>(i % nsb), q = dprime[i] / nsub;
-        rows[i] = pair_of[static_cast<size_t>(n) * (maxpass + 1) + q] * nsub + dprime[i] % nsub;
-    }
+    if (p->groups.empty()) return build_tree(p, nsub);
+    // time-scrunched trials: one tree per scrunch group over its s-sample
+    // sums, whose sub-band sums must stay below 2^16
+    for (const auto& g : p->groups)
+        if (static_cast<long long>(g.sub->value_bound()) * nsub > 65535)
+            return fail(DEDISP_ERR_UNSUPPORTED, "a scrunch group's sub-band sums exceed 16 bits");
     destroy_tree(p);
+    for (auto& g : p->groups) {
+        dedisp_status st = build_tree(g.sub, nsub);
+        if (st != DEDISP_OK) {
+            destroy_tree(p);
+            return st;
+        }
+    }
     p->tree_nsub = nsub;
-    p->tree_maxdelay = mx;
-    p->tree_npass = maxpass + 1;
-    p->tree_pairs.swap(pairs);
-    p->tree_rows.swap(rows);
-    p->tree_delay.swap(delay);
     return DEDISP_OK;
 }
 
@@ -1582,11 +1664,20 @@ dedisp_status dedisp_get_output_lengths(dedisp_plan p, size_t nsamps, size_t* no
 {
     if (!p || !nout) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
-    if (p->tree_nsub) {
+    if (p->tree_nsub && p->groups.empty()) {
         long long len1 = 0, n = 0;
         tree_lengths(*p, nsamps, len1, n);
         if (len1 <= 0 || n <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps too short for the tree passes");
         for (size_t d = 0; d < p->dms.size(); ++d) nout[d] = static_cast<size_t>(n);
+        return DEDISP_OK;
+    }
+    if (p->tree_nsub) {
+        for (const auto& g : p->groups) {
+            long long len1 = 0, n = 0;
+            tree_lengths(*g.sub, nsamps, len1, n);
+            if (len1 <= 0 || n <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps too short for the tree passes");
+            for (int32_t r : g.rows) nout[r] = static_cast<size_t>(n);
+        }
         return DEDISP_OK;
     }
     if (p->sb_step1) {

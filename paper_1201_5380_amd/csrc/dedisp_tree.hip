@@ -10,8 +10,11 @@ namespace {
 // ---------------------------------------------------------------- tree
 
 // Stage 1 of the piecewise linear tree (Section 3).  Workgroup (tile,
-// sub-band n) loads the sub-band's nsub scratch rows for samples
-// [t0, t0 + T + nsub) into LDS as 16-bit values, two per 32-bit word, and
+// (sub-band n, pass p) pair) loads the sub-band's nsub scratch rows -- any
+// scratch format: 2-bit nibbles, bytes, scrunched byte or 16-bit sums; row j
+// read p*j samples later (the pass's imposed delay), killed channels as
+// zeros -- for samples [t0, t0 + T + nsub) into LDS as 16-bit values, two
+// per 32-bit word, and
 // applies the tree's steps i = 0 .. k-1 out of place (double buffer):
 //   B[2v][t]   = A[Phi(r, 2v)][t] + A[Phi(r, 2v+1)][t + Theta(i, 2v)]
 //   B[2v+1][t] = A[Phi(r, 2v)][t] + A[Phi(r, 2v+1)][t + Theta(i, 2v+1)]
@@ -73,6 +76,8 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, const int32_t* pairs, 
             u32x2 v;
             __builtin_memcpy(&v, row + t0 / SPW + shift / SPW + w, sizeof(v));
             ld[k] = __builtin_amdgcn_alignbit(v.y, v.x, (shift % SPW) * (32 / SPW));
+            // killed channels read as zeros (a scrunching corner turn keeps their rows)
+            if (b.mask && b.mask[n * NSUB + j] == 0) ld[k] = 0u;
         }
     }
 #pragma unroll
@@ -82,7 +87,9 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, const int32_t* pairs, 
         const int j = it / WPR, w = it % WPR;
         const uint32_t v = ld[k];
         uint32_t* dst = A + j * RS + w * (SPW / 2);
-        if constexpr (FMT == kFmtNib) {
+        if constexpr (FMT == kFmtHalf) {
+            dst[0] = v;                            // already two 16-bit samples
+        } else if constexpr (FMT == kFmtNib) {
             u32x4 q;
             q.x = (v & 0xFu) | ((v & 0xF0u) << 12);
             q.y = ((v >> 8) & 0xFu) | ((v & 0xF000u) << 4);
@@ -161,6 +168,7 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, const int32_t* pairs, 
 template <int N>
 __device__ __forceinline__ void tree_store(const BeamDesc& b, int d, long long t, const uint32_t (&acc)[N])
 {
+    if (b.rowmap) d = b.rowmap[d];               // the trial's row of the whole output
     if (b.out_bytes == 4) {
         uint32_t* orow = b.out + (size_t)d * (size_t)b.out_stride;
         if (t + N <= b.nout) {
@@ -296,13 +304,19 @@ hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, const int32
     const long long gy = npairs;
     if (gx <= 0 || gx > 0x7fffffffLL || gy <= 0 || gy > 65535) return hipErrorInvalidValue;
     const void* fn = nullptr;
-    // byte rows hold 2-bit sub-band sums up to nsub = 64 (3 * 64 < 256)
+    // byte rows hold sub-band sums below 256: 2-bit codes up to nsub = 64,
+    // small scrunched sums (byte format) for narrow sub-bands
 #define DEDISP_TREE_CASE(F, N, O) \
     if (fmt == F && nsub == N && ob == O) fn = reinterpret_cast<const void*>(&k_tree<F, N, O>);
     DEDISP_TREE_CASE(kFmtNib, 8, 1) DEDISP_TREE_CASE(kFmtNib, 16, 1) DEDISP_TREE_CASE(kFmtNib, 32, 1)
     DEDISP_TREE_CASE(kFmtNib, 64, 1) DEDISP_TREE_CASE(kFmtNib, 128, 2)
     DEDISP_TREE_CASE(kFmtByte, 8, 2) DEDISP_TREE_CASE(kFmtByte, 16, 2) DEDISP_TREE_CASE(kFmtByte, 32, 2)
     DEDISP_TREE_CASE(kFmtByte, 64, 2) DEDISP_TREE_CASE(kFmtByte, 128, 2)
+    DEDISP_TREE_CASE(kFmtByteS, 8, 1) DEDISP_TREE_CASE(kFmtByteS, 16, 1) DEDISP_TREE_CASE(kFmtByteS, 32, 1)
+    DEDISP_TREE_CASE(kFmtByteS, 8, 2) DEDISP_TREE_CASE(kFmtByteS, 16, 2) DEDISP_TREE_CASE(kFmtByteS, 32, 2)
+    DEDISP_TREE_CASE(kFmtByteS, 64, 2) DEDISP_TREE_CASE(kFmtByteS, 128, 2)
+    DEDISP_TREE_CASE(kFmtHalf, 8, 2) DEDISP_TREE_CASE(kFmtHalf, 16, 2) DEDISP_TREE_CASE(kFmtHalf, 32, 2)
+    DEDISP_TREE_CASE(kFmtHalf, 64, 2) DEDISP_TREE_CASE(kFmtHalf, 128, 2)
 #undef DEDISP_TREE_CASE
     if (!fn) return hipErrorInvalidValue;
     const size_t lds = 2ull * nsub * tree_row_words(nsub) * sizeof(uint32_t);

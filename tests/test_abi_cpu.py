@@ -327,6 +327,42 @@ def test_tree_output_lengths_match_oracle(native, nchans, nbits, nsub, reach):
     assert np.all(plan.output_lengths(nsamps) == nsamps - plan.max_delay)
 
 
+@pytest.mark.parametrize("nbits,nsub,maxf", [(2, 32, 64), (2, 16, 8), (8, 16, 4)])
+def test_scrunched_tree_output_lengths_match_oracle(native, nbits, nsub, maxf):
+    """Scrunching then the tree: row d has nsamps // s - (P_s + 1)(nsub - 1) - max dt''_s
+    outputs, from its factor group's tables at s*dt."""
+    nchans, dt, f0, df = 1024, 64e-6, 1581.8, -0.390625
+    dms = synth.dm_list_linear(300, 1000.0)
+    plan = Plan(nchans, dt, f0, df, nbits).set_dm_list(dms)
+    factors = plan.default_scrunch_factors(maxf)
+    plan.set_scrunching(factors).set_tree(nsub)
+    nsamps = 1 << 18
+    want = np.zeros(len(dms), dtype=np.int64)
+    for s in sorted(set(factors.tolist())):
+        idx = np.nonzero(factors == s)[0]
+        dp, dd = oracle.tree_dm_tables(nchans, dt * s, f0, df, nsub, dms[idx])
+        want[idx] = nsamps // s - (int(dp.max()) // nsub + 1) * (nsub - 1) - int(dd.max())
+    assert np.array_equal(plan.output_lengths(nsamps), want)
+    assert plan.nout(nsamps) == want.max()
+
+
+def test_scrunched_tree_validation(native):
+    L = lib()
+    nchans, dt, f0, df = 1024, 64e-6, 1581.8, -0.390625
+    dms = synth.dm_list_linear(64, 1000.0)
+    plan = Plan(nchans, dt, f0, df, 8).set_dm_list(dms)
+    plan.set_scrunching(plan.default_scrunch_factors(16))
+    assert L.dedisp_set_tree(plan.handle, 32) == -6         # 255 * 16 * 32 > 65535
+    assert L.dedisp_set_tree(plan.handle, 8) == 0           # 255 * 16 * 8 fits
+    f = plan.default_scrunch_factors(16).astype(np.int32)
+    assert L.dedisp_set_scrunching(plan.handle, f.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))) == -6
+    assert L.dedisp_set_scrunching(plan.handle, None) == -6            # the tree sits on the groups
+    assert plan.output_lengths(1 << 18).min() > 0
+    plan.set_tree(0)
+    plan.set_scrunching(None)
+    assert np.all(plan.output_lengths(1 << 18) == (1 << 18) - plan.max_delay)
+
+
 def test_tree_validation_precedes_hip(native):
     L = lib()
     nchans, dt, f0, df = 256, 64e-6, 1581.8, -400.0 / 256

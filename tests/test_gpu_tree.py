@@ -103,3 +103,35 @@ def test_survey_beam_tree_full_size(native, cuda):
     plan = Plan(b.nchans, b.dt, b.f_top, b.df, b.nbits).set_dm_list(dms).set_tree(32)
     got = _run(plan, packed, b.nsamps, cuda)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("nbits,nchans,nsub,nsamps,maxf,ndm,dm_max,masked", [
+    (2, 256, 16, 60013, 32, 40, 1000.0, False),
+    (2, 512, 32, 40009, 8, 30, 600.0, True),
+    (8, 128, 8, 30011, 4, 60, 40.0, False)])
+def test_scrunched_tree_bit_exact(native, cuda, nbits, nchans, nsub, nsamps, maxf, ndm, dm_max, masked):
+    """Time-scrunching then the tree: every factor group runs the corner turn
+    with s-sample sums (nibble, byte-sum or 16-bit scratch), its own tree
+    passes and the combine into its rows of the output."""
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    dms = synth.dm_list_linear(ndm, dm_max)
+    rng = np.random.default_rng(nchans + 7 * nsub + nbits)
+    codes = (rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8) if nbits == 2 else
+             rng.integers(0, 256, size=(nsamps, nchans), dtype=np.uint8))
+    codes[::37] = 3 if nbits == 2 else 255
+    packed = synth.pack(codes, nbits)
+    mask = (rng.random(nchans) < 0.8).astype(np.int32) if masked else None
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms)
+    if masked:
+        plan.set_killmask(mask)
+    factors = plan.default_scrunch_factors(maxf)
+    assert len(set(factors.tolist())) >= 3
+    plan.set_scrunching(factors).set_tree(nsub)
+    want = oracle.dedisperse_piecewise_tree_scrunched(packed, nsamps, nchans, nbits, dt, f_top, df, dms,
+                                                      nsub, factors, mask=mask)
+    lens = plan.output_lengths(nsamps)
+    assert [len(r) for r in want] == lens.tolist()
+    got = _run(plan, packed, nsamps, cuda)
+    assert got.shape == (ndm, lens.max())
+    for d in range(ndm):
+        assert np.array_equal(got[d, : lens[d]], want[d]), (d, factors[d])
