@@ -102,19 +102,27 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, const int32_t* pairs, 
         }
     }
     __syncthreads();
+    // each pair v of output rows has a team of TPP threads; team lane l takes
+    // words l, l + TPP, ... of the row (consecutive lanes on consecutive
+    // words), so the pair's rows and shift are computed once per step
+    constexpr int TPP = 256 / (NSUB / 2);
+    constexpr int WPT = (LW + TPP - 1) / TPP;      // words per thread
+    const int v = threadIdx.x / TPP, l = threadIdx.x % TPP;
 #pragma unroll 1
     for (int i = 0; i < K; ++i) {
-        // flattened (pair v, word w): consecutive lanes on consecutive words
-        for (int it = threadIdx.x; it < (NSUB / 2) * LW; it += 256) {
-            const int v = it / LW, w = it - v * LW;
-            const uint32_t* lo = A + tree_phi(i, 2 * v) * RS;
-            const uint32_t* hi = A + tree_phi(i, 2 * v + 1) * RS;
-            const int th = tree_theta(i, 2 * v);
-            const int q = w + (th >> 1);
-            const uint32_t a = lo[w], h0 = hi[q], h1 = hi[q + 1];
+        const uint32_t* lo = A + tree_phi(i, 2 * v) * RS + l;
+        const int th = tree_theta(i, 2 * v);
+        const uint32_t* hi = A + tree_phi(i, 2 * v + 1) * RS + (th >> 1) + l;
+        uint32_t* o0 = B + (2 * v) * RS + l;
+        uint32_t* o1 = B + (2 * v + 1) * RS + l;
+        const bool odd = (th & 1) != 0;
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+            if (LW % TPP != 0 && k == WPT - 1 && l + TPP * k >= LW) break;
+            const uint32_t a = lo[TPP * k], h0 = hi[TPP * k], h1 = hi[TPP * k + 1];
             const uint32_t mid = __builtin_amdgcn_alignbit(h1, h0, 16);
-            B[(2 * v) * RS + w] = a + ((th & 1) ? mid : h0);
-            B[(2 * v + 1) * RS + w] = a + ((th & 1) ? h1 : mid);
+            o0[TPP * k] = a + (odd ? mid : h0);
+            o1[TPP * k] = a + (odd ? h1 : mid);
         }
         __syncthreads();
         uint32_t* tmp = A;
