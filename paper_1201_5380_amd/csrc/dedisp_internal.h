@@ -89,6 +89,9 @@ constexpr int kMaxLdsBytes = 160 * 1024;
 // Enqueue the corner turn (time-major packed -> channel-major scratch of
 // format fmt in d.xc), summing d.scrunch consecutive samples when above 1.
 hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st);
+// The scrunching corner turn alone (d.scrunch > 1; fmt = kFmtByteS for 2-bit
+// s <= 8, else kFmtHalf).
+hipError_t launch_scrunch(const BeamDesc& d, int nbits, int fmt, hipStream_t st);
 
 // Stage 1 of the piecewise linear tree: k = log2(nsub) tree steps (Theta/Phi)
 // for each of the npairs (sub-band n, pass p) pairs in pairs[2y], pairs[2y+1]

@@ -184,85 +184,6 @@ __global__ __launch_bounds__(256) void k_unpack_multi(DescBlock blk, int nbeams)
     }
 }
 
-// ------------------------------------------------------------ scrunching corner turn
-
-// Time-scrunching corner turn (Section 2.1): scratch sample t' of a live
-// channel is the sum of input samples s*t' .. s*t'+s-1 (s = b.scrunch),
-// written channel-major as one byte (OB = 1) or one 16-bit word (OB = 2)
-// per scrunched sample.  A workgroup covers SC channels (32 input words of a
-// row) and ST scrunched samples; lanes 0..31 of a wave read consecutive
-// words of one row.  Requires row_bytes % 4 == 0, 4-byte aligned rows and
-// 3*s (2-bit) or 255*s (8-bit) below the format's value bound.
-template <int NBITS, int OB>
-__global__ __launch_bounds__(256) void k_scrunch(BeamDesc b)
-{
-    constexpr int SC = NBITS == 2 ? 512 : 128;     // channels per workgroup
-    constexpr int ST = NBITS == 2 ? 32 : 64;       // scrunched samples per workgroup
-    constexpr int RB = ST * OB;                    // tile bytes per channel row
-    constexpr int LP = RB + 16;                    // LDS row pitch in bytes
-    static_assert(NBITS == 2 || OB == 2, "8-bit sums need 16 bits");
-    __shared__ __attribute__((aligned(16))) uint8_t tile[SC * LP];
-    const int s = b.scrunch;
-    const long long ns = b.nsamps / s;             // whole scrunched samples
-    const long long tp0 = (long long)blockIdx.x * ST;
-    const int c0 = blockIdx.y * SC;
-    const int w = threadIdx.x & 31;                // input word within the row segment
-    const int cw = c0 + w * (32 / NBITS);          // first channel of that word
-    auto put = [&](int ch, int q, uint32_t v) {
-        if constexpr (OB == 1) tile[(size_t)ch * LP + q] = (uint8_t)v;
-        else reinterpret_cast<uint16_t*>(tile + (size_t)ch * LP)[q] = (uint16_t)v;
-    };
-    for (int q = threadIdx.x >> 5; q < ST; q += 8) {
-        const long long tp = tp0 + q;
-        const bool live = tp < ns && cw < b.nchans;
-        if constexpr (NBITS == 8) {
-            uint32_t lo = 0u, hi = 0u;             // 16-bit lanes: channels (0, 2) and (1, 3) of the word
-            if (live)
-                for (int i = 0; i < s; ++i) {
-                    const uint32_t v = *reinterpret_cast<const uint32_t*>(row_ptr(b, tp * s + i) + cw);
-                    lo += v & 0x00FF00FFu;
-                    hi += (v >> 8) & 0x00FF00FFu;
-                }
-            put(4 * w + 0, q, lo & 0xFFFFu);
-            put(4 * w + 1, q, hi & 0xFFFFu);
-            put(4 * w + 2, q, lo >> 16);
-            put(4 * w + 3, q, hi >> 16);
-        } else {
-            uint32_t g[4] = {0u, 0u, 0u, 0u};      // byte k of g[j]: channel 4k + j of the word
-            if (live)
-                for (int i = 0; i < s; ++i) {
-                    const uint32_t v = *reinterpret_cast<const uint32_t*>(row_ptr(b, tp * s + i) + cw / 4);
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) g[j] += (v >> (2 * j)) & 0x03030303u;
-                }
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) put(16 * w + 4 * k + j, q, (g[j] >> (8 * k)) & 0xFFu);
-        }
-    }
-    __syncthreads();
-    // 16-byte pieces to each live channel's scratch row; samples past the
-    // last whole scrunched sample hold zeros
-    constexpr int PPR = RB / 16;
-    const long long byte0 = tp0 * OB;
-    for (int it = threadIdx.x; it < SC * PPR; it += 256) {
-        const int c = it / PPR;
-        const int p = it % PPR;
-        if (c0 + c >= b.nchans) continue;
-        const int row = b.chanmap ? b.chanmap[c0 + c] : c0 + c;
-        if (row < 0) continue;
-        *reinterpret_cast<u32x4*>(b.xc + (long long)row * b.pitch + byte0 + 16 * p) =
-            *reinterpret_cast<const u32x4*>(tile + (size_t)c * LP + 16 * p);
-    }
-    if (b.pad_row >= 0 && blockIdx.y == 0 && threadIdx.x < PPR * (b.nact - b.pad_row)) {
-        const int r = b.pad_row + threadIdx.x / PPR;
-        const int p = threadIdx.x % PPR;
-        *reinterpret_cast<u32x4*>(b.xc + (long long)r * b.pitch + byte0 + 16 * p) =
-            u32x4{0u, 0u, 0u, 0u};
-    }
-}
-
 // ------------------------------------------------------------ tiled sum
 
 // One (time tile, DM block) work item.
@@ -950,19 +871,7 @@ hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st)
 {
     BeamDesc arg = d;
     void* args[] = {&arg};
-    if (d.scrunch > 1) {
-        const long long sc = nbits == 2 ? 512 : 128, stl = nbits == 2 ? 32 : 64;
-        const long long ns = d.nsamps / d.scrunch;
-        const long long gx = (ns + stl - 1) / stl;
-        const long long gy = (d.nchans + sc - 1) / sc;
-        if (gx <= 0 || gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidValue;
-        const void* fn = nullptr;
-        if (nbits == 2 && fmt == kFmtByteS) fn = reinterpret_cast<const void*>(&k_scrunch<2, 1>);
-        else if (nbits == 2 && fmt == kFmtHalf) fn = reinterpret_cast<const void*>(&k_scrunch<2, 2>);
-        else if (nbits == 8 && fmt == kFmtHalf) fn = reinterpret_cast<const void*>(&k_scrunch<8, 2>);
-        if (!fn) return hipErrorInvalidValue;
-        return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, 0, st);
-    }
+    if (d.scrunch > 1) return launch_scrunch(d, nbits, fmt, st);
     const long long gx = (d.nsamps + kUT - 1) / kUT;
     const long long gy = (d.nchans + kUC - 1) / kUC;
     if (gx <= 0 || gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidValue;
