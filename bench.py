@@ -135,29 +135,41 @@ def bench_scrunched(torch, dev, plan, inp, nsamps, steps, direct_ms):
             "speedup_vs_direct": direct_ms / ms}
 
 
-def bench_subband(torch, dev, plan, inp, nsamps, steps, direct_ms, nsub=32, ngroup=32):
+def bench_subband(torch, dev, plan, inp, nsamps, steps, direct_ms, nsub=32, ngroup=32,
+                  sweep=((16, 16), (64, 32), (64, 64))):
     """The survey beam with sub-band dedispersion (Section 4): 32-channel
     sub-bands, 32 trials per nominal DM (the balanced choice N'_DM = N'_nu),
-    each pass tuned; the same input as the direct transform."""
-    plan.set_subband(nsub, ngroup)
-    nout = int(plan.output_lengths(nsamps)[0])
-    out = torch.empty((plan.ndm, nout), dtype=torch.int32, device=dev)
-    tune_ms = plan.tune(inp, out, nsamps)
-    for _ in range(2):
-        plan.execute(inp, nsamps, out=out)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(steps):
-        plan.execute(inp, nsamps, out=out)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    plan.set_subband(0, 0)
-    return {"workload": f"survey beam, sub-bands of {nsub} channels, {ngroup} trials per nominal DM",
-            "ms": ms, "tune_ms": tune_ms, "nout": nout,
-            "outputs_per_s": plan.ndm * nout / (ms * 1e-3),
-            "speedup_vs_direct": direct_ms / ms}
+    each pass tuned; the same input as the direct transform.  `sweep` times
+    other (sub-band width, trials per nominal DM) pairs: wider sub-bands and
+    more trials per nominal DM do less work and smear more (Appendix B)."""
+    def timed(ns, ng):
+        plan.set_subband(ns, ng)
+        nout = int(plan.output_lengths(nsamps)[0])
+        out = torch.empty((plan.ndm, nout), dtype=torch.int32, device=dev)
+        tune_ms = plan.tune(inp, out, nsamps)
+        for _ in range(2):
+            plan.execute(inp, nsamps, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            plan.execute(inp, nsamps, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        plan.set_subband(0, 0)
+        del out
+        return e0.elapsed_time(e1) / steps, tune_ms, nout
+
+    ms, tune_ms, nout = timed(nsub, ngroup)
+    res = {"workload": f"survey beam, sub-bands of {nsub} channels, {ngroup} trials per nominal DM",
+           "ms": ms, "tune_ms": tune_ms, "nout": nout,
+           "outputs_per_s": plan.ndm * nout / (ms * 1e-3),
+           "speedup_vs_direct": direct_ms / ms, "sweep": []}
+    for ns, ng in sweep:
+        m, _, n = timed(ns, ng)
+        res["sweep"].append({"nsub": ns, "trials_per_nominal_dm": ng, "ms": m,
+                             "speedup_vs_direct": direct_ms / m})
+    return res
 
 
 def bench_tree(torch, dev, beam, inp, nsamps, steps, nsub=32):
