@@ -767,6 +767,8 @@ __global__ __launch_bounds__(256) void k_zero(uint8_t* base, long long group_str
     X(kFmtHalf, 8, 2, 3, 32, 2, 0)         \
     X(kFmtHalf, 8, 2, 3, 16, 4, 0)         \
     X(kFmtHalf, 16, 1, 5, 64, 2, 0)        \
+    X(kFmtHalf, 16, 2, 3, 32, 2, 0)        \
+    X(kFmtHalf, 8, 4, 3, 32, 2, 0)         \
     X(kFmtHalf, 8, 2, 5, 32, 2, 0)
 
 struct ShapeEntry {
