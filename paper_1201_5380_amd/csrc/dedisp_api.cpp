@@ -515,11 +515,24 @@ void write_cache(const char* path, const std::map<std::string, std::vector<doubl
 
 void destroy_tree(dedisp_plan p)
 {
-    if (p->d_tree_rows || p->d_tree_delay || p->d_tree_pairs) (void)hipDeviceSynchronize();
+    if (p->d_tree_rows || p->d_tree_delay || p->d_tree_pairs || p->d_tree_stage || p->d_tree_sblocks ||
+        p->d_tree_off || p->d_tree_gtrials)
+        (void)hipDeviceSynchronize();
     if (p->d_tree_rows) (void)hipFree(p->d_tree_rows);
     if (p->d_tree_delay) (void)hipFree(p->d_tree_delay);
     if (p->d_tree_pairs) (void)hipFree(p->d_tree_pairs);
+    if (p->d_tree_stage) (void)hipFree(p->d_tree_stage);
+    if (p->d_tree_sblocks) (void)hipFree(p->d_tree_sblocks);
+    if (p->d_tree_off) (void)hipFree(p->d_tree_off);
+    if (p->d_tree_gtrials) (void)hipFree(p->d_tree_gtrials);
     p->d_tree_rows = p->d_tree_delay = p->d_tree_pairs = nullptr;
+    p->d_tree_stage = nullptr;
+    p->d_tree_sblocks = p->d_tree_off = p->d_tree_gtrials = nullptr;
+    p->tree_stage.clear();
+    p->tree_sblocks.clear();
+    p->tree_off.clear();
+    p->tree_gtrials.clear();
+    p->tree_lds = 0;
     p->tree_rows.clear();
     p->tree_delay.clear();
     p->tree_pairs.clear();
@@ -1016,7 +1029,26 @@ static dedisp_status tree_upload(dedisp_plan p)
         }
         HIP_TRY(hipMemcpy(p->d_tree_pairs, p->tree_pairs.data(), bytes, hipMemcpyHostToDevice));
     }
-    return DEDISP_OK;
+    auto upload = [](void** dst, const void* src, size_t bytes) -> dedisp_status {
+        if (*dst || bytes == 0) return DEDISP_OK;
+        if (hipMalloc(dst, bytes) != hipSuccess) {
+            *dst = nullptr;
+            return fail(DEDISP_ERR_OOM, "hipMalloc tree tables");
+        }
+        HIP_TRY(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+        return DEDISP_OK;
+    };
+    dedisp_status s2 = upload(reinterpret_cast<void**>(&p->d_tree_stage), p->tree_stage.data(),
+                              p->tree_stage.size() * sizeof(dedisp::TreeStage));
+    if (s2 == DEDISP_OK)
+        s2 = upload(reinterpret_cast<void**>(&p->d_tree_sblocks), p->tree_sblocks.data(),
+                    p->tree_sblocks.size() * sizeof(int32_t));
+    if (s2 == DEDISP_OK)
+        s2 = upload(reinterpret_cast<void**>(&p->d_tree_off), p->tree_off.data(), p->tree_off.size() * sizeof(int32_t));
+    if (s2 == DEDISP_OK)
+        s2 = upload(reinterpret_cast<void**>(&p->d_tree_gtrials), p->tree_gtrials.data(),
+                    p->tree_gtrials.size() * sizeof(int32_t));
+    return s2;
 }
 
 // Tree rows are bytes while the largest sub-band sum fits (3 nsub for 2-bit
@@ -1088,7 +1120,18 @@ static dedisp_status run_tree(dedisp_plan p, const void* d_in, size_t nsamps, ui
     dg.out_stride = static_cast<long long>(stride) * (dg.out_bytes == 4 ? 1 : dg.out_bytes);
     // 16-bit partial sums of at most 65535 / (largest row value) terms
     const int row_max = p->value_bound() * nsub;
-    e = dedisp::launch_tree_combine(dg, ob, 65535 / row_max, hs);
+    const int flush = 65535 / row_max;
+    if (!p->tree_sblocks.empty()) {
+        // the staged trial blocks through LDS, the rest gathered
+        e = dedisp::launch_tree_combine_lds(dg, p->d_tree_sblocks, static_cast<int>(p->tree_sblocks.size()),
+                                            p->d_tree_stage, p->d_tree_off, p->tree_lds, flush, hs);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        if (!p->tree_gtrials.empty())
+            e = dedisp::launch_tree_combine(dg, ob, flush, p->d_tree_gtrials,
+                                            static_cast<int>(p->tree_gtrials.size()), hs);
+    } else {
+        e = dedisp::launch_tree_combine(dg, ob, flush, nullptr, 0, hs);
+    }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return DEDISP_OK;
 }
@@ -1593,6 +1636,56 @@ static dedisp_status build_tree(dedisp_plan q, int nsub)
         const int n = static_cast<int>(i % nsb), ps = dprime[i] / nsub;
         rows[i] = pair_of[static_cast<size_t>(n) * (maxpass + 1) + ps] * nsub + dprime[i] % nsub;
     }
+    // LDS staging of stage 2 (byte rows only): per block of kTreeBlock
+    // consecutive trials and sub-band, the rows the block uses and its delay
+    // window; a block whose rows exceed kTreeLdsDwords is gathered instead
+    constexpr int TB = dedisp::kTreeBlock, TT = dedisp::kTreeTile;
+    constexpr long long kTreeLdsDwords = 16 * 1024;          // 64 KB: two workgroups per CU
+    std::vector<dedisp::TreeStage> stage;
+    std::vector<int32_t> sblocks, off, gtrials;
+    int lds_max = 0;
+    // (the kernel keeps a trial's offsets in two registers: up to 128 sub-bands)
+    if (static_cast<long long>(q->value_bound()) * nsub <= 255 && nsb <= 128) {
+        off.assign(static_cast<size_t>(ndm) * nsb, 0);
+        std::vector<dedisp::TreeStage> st(nsb);
+        for (int b = 0; b * TB < ndm; ++b) {
+            const int d0 = b * TB, d1 = std::min(ndm, d0 + TB);
+            long long lds = 0;
+            for (int n = 0; n < nsb; ++n) {
+                int lo = 0x7fffffff, hi = -1, dmin = 0x7fffffff, dmax = -1;
+                for (int d = d0; d < d1; ++d) {
+                    const size_t i = static_cast<size_t>(d) * nsb + n;
+                    lo = std::min(lo, rows[i]);
+                    hi = std::max(hi, rows[i]);
+                    dmin = std::min(dmin, delay[i]);
+                    dmax = std::max(dmax, delay[i]);
+                }
+                dedisp::TreeStage& g = st[n];
+                g = dedisp::TreeStage{};
+                g.lo = lo;
+                g.span = hi - lo + 1;
+                g.dmin4 = dmin & ~3;
+                // the window covers the tile, the block's delay spread and the
+                // second dword each lane reads past its four outputs
+                g.wdw = (TT + (dmax - g.dmin4) + 8 + 3) / 4;
+                g.lds = static_cast<int>(std::min<long long>(lds, 0x7fffffff));
+                lds += static_cast<long long>(g.span) * g.wdw;
+            }
+            if (lds > kTreeLdsDwords) {
+                for (int d = d0; d < d1; ++d) gtrials.push_back(d);
+                continue;
+            }
+            for (int n = 0; n < nsb; ++n)
+                for (int d = d0; d < d1; ++d) {
+                    const size_t i = static_cast<size_t>(d) * nsb + n;
+                    const dedisp::TreeStage& g = st[n];
+                    off[i] = 4 * (g.lds + (rows[i] - g.lo) * g.wdw) + (delay[i] - g.dmin4);
+                }
+            sblocks.push_back(b);
+            stage.insert(stage.end(), st.begin(), st.end());
+            lds_max = std::max(lds_max, static_cast<int>(lds));
+        }
+    }
     destroy_tree(q);
     q->tree_nsub = nsub;
     q->tree_maxdelay = mx;
@@ -1600,6 +1693,13 @@ static dedisp_status build_tree(dedisp_plan q, int nsub)
     q->tree_pairs.swap(pairs);
     q->tree_rows.swap(rows);
     q->tree_delay.swap(delay);
+    if (!sblocks.empty()) {
+        q->tree_stage.swap(stage);
+        q->tree_sblocks.swap(sblocks);
+        q->tree_off.swap(off);
+        q->tree_gtrials.swap(gtrials);
+        q->tree_lds = lds_max;
+    }
     return DEDISP_OK;
 }
 

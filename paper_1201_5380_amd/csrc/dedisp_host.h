@@ -155,6 +155,16 @@ struct dedisp_plan_s {
     int32_t* d_tree_rows = nullptr;
     int32_t* d_tree_delay = nullptr;
     int32_t* d_tree_pairs = nullptr;
+    // LDS-staged stage 2 (byte rows): staged trial blocks with their tables,
+    // per (trial, sub-band) LDS byte offsets, and the trials of the blocks
+    // whose rows do not fit (gathered from global memory instead)
+    std::vector<dedisp::TreeStage> tree_stage;
+    std::vector<int32_t> tree_sblocks, tree_off, tree_gtrials;
+    int tree_lds = 0;                       // dwords per workgroup
+    dedisp::TreeStage* d_tree_stage = nullptr;
+    int32_t* d_tree_sblocks = nullptr;
+    int32_t* d_tree_off = nullptr;
+    int32_t* d_tree_gtrials = nullptr;
     bool internal = false;
     int ngroups = 1;
     int ndm_last = 0;

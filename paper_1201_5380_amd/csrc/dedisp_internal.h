@@ -114,7 +114,26 @@ int tree_tile(int nsub);
 // terms summed in 16-bit lanes between 32-bit flushes (flush * largest row
 // value < 2^16).  d.out / out_bytes / out_shift / out_stride as for the
 // other kernels.
-hipError_t launch_tree_combine(const BeamDesc& d, int ob, int flush, hipStream_t st);
+// trials (device, ntrials entries) restricts it to those trials (NULL: all).
+hipError_t launch_tree_combine(const BeamDesc& d, int ob, int flush, const int32_t* trials, int ntrials,
+                               hipStream_t st);
+
+// Stage 2 with LDS staging, byte rows only: for the nblocks trial blocks
+// blocks[] (block k = trials k*kTreeBlock .. +kTreeBlock-1), a workgroup
+// stages, per sub-band n, rows stage[.][n].lo .. + span over a window of wdw
+// dwords starting at sample t0 + dmin4 (a multiple of 4) at LDS dword lds,
+// then every trial d of the block sums, over n, the bytes at LDS byte
+// off[d][n] + (t - t0) for its outputs t of the time tile [t0, t0 +
+// kTreeTile).  lds_dwords = LDS per workgroup; at most 128 sub-bands.  d as
+// for launch_tree_combine.
+constexpr int kTreeBlock = 32;
+constexpr int kTreeTile = 512;
+struct TreeStage {
+    int lo, span, dmin4, wdw, lds;
+    int pad_[3];
+};
+hipError_t launch_tree_combine_lds(const BeamDesc& d, const int32_t* blocks, int nblocks, const TreeStage* stage,
+                                   const int32_t* off, int lds_dwords, int flush, hipStream_t st);
 
 // Zero `bytes` (a multiple of 16) at base + g*group_stride for g < ngroups.
 hipError_t launch_zero(uint8_t* base, long long group_stride, long long bytes, int ngroups,

@@ -221,19 +221,30 @@ __device__ __forceinline__ void tree_store(const BeamDesc& b, int d, long long t
 // cover neighbouring trials of one tile, which share most of their tree
 // rows, so the rows stay in that XCD's L2.
 template <int OB>
-__global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, long long per_xcd)
+__global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, long long per_xcd,
+                                                      const int32_t* trials, int ntr)
 {
     constexpr int L = OB == 2 ? 8 : 16;           // outputs per lane
     constexpr int SPW = 4 / OB;                   // samples per 32-bit word
     const long long o = (long long)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    const long long ndm = b.ndm;
+    const long long ndm = trials ? ntr : b.ndm;   // the trials this launch covers
     if (o >= ndm * ((b.nout + 256 * L - 1) / (256 * L))) return;   // no barriers below
-    const int d = (int)(o % ndm);
-    const long long t = (o / ndm) * (256 * L) + threadIdx.x * L;
-    if (t >= b.nout) return;
+    const int d = trials ? trials[o % ndm] : (int)(o % ndm);
+    const long long t_out = (o / ndm) * (256 * L) + threadIdx.x * L;
+    // every lane stays to the end (the tables below are broadcast from all
+    // lanes' registers); lanes past the last output read from sample 0 and
+    // store nothing
+    const bool live = t_out < b.nout;
+    const long long t = live ? t_out : 0;
     const int nsb = b.nact;
     const int32_t* rows = b.rowsel + (size_t)d * nsb;
     const int32_t* dly = b.table + (size_t)d * nsb;
+    // up to 128 sub-bands: the trial's rows and delays sit in registers (lane
+    // n holds sub-band n's and n + 64's) and are broadcast per term
+    const int lane = threadIdx.x & 63;
+    const bool in_regs = nsb <= 128;
+    const int r_lo = in_regs && lane < nsb ? rows[lane] : 0, r_hi = in_regs && lane + 64 < nsb ? rows[lane + 64] : 0;
+    const int d_lo = in_regs && lane < nsb ? dly[lane] : 0, d_hi = in_regs && lane + 64 < nsb ? dly[lane + 64] : 0;
     uint32_t acc[L];
 #pragma unroll
     for (int e = 0; e < L; ++e) acc[e] = 0u;
@@ -242,10 +253,11 @@ __global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, lon
         // OB = 2: p[k] = samples (2k, 2k+1); OB = 1: p[k] = (4k, 4k+2),
         // q[k] = (4k+1, 4k+3), each pair in the two 16-bit lanes
         uint32_t p[4] = {0u, 0u, 0u, 0u}, q[4] = {0u, 0u, 0u, 0u};
-#pragma unroll 4
         for (int n = n0; n < n1; ++n) {
-            const long long s = t + dly[n];
-            const uint32_t* w = reinterpret_cast<const uint32_t*>(b.xc + (long long)rows[n] * b.pitch) + s / SPW;
+            const int rn = in_regs ? __builtin_amdgcn_readlane(n < 64 ? r_lo : r_hi, n & 63) : rows[n];
+            const int dn = in_regs ? __builtin_amdgcn_readlane(n < 64 ? d_lo : d_hi, n & 63) : dly[n];
+            const long long s = t + dn;
+            const uint32_t* w = reinterpret_cast<const uint32_t*>(b.xc + (long long)rn * b.pitch) + s / SPW;
             u32x4 v;
             __builtin_memcpy(&v, w, sizeof(v));
             const uint32_t v4 = w[4];
@@ -275,27 +287,156 @@ __global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, lon
             }
         }
     }
-    tree_store<L>(b, d, t, acc);
+    if (live) tree_store<L>(b, d, t, acc);
+}
+
+// Stage 2 with LDS staging (byte rows).  Consecutive trials of a sorted,
+// dense DM list use nearly the same tree rows (d'_n changes slowly with DM)
+// at nearly the same delays, so a workgroup stages, for its time tile and
+// block of kTreeBlock trials, each sub-band's rows the block uses over the
+// block's delay window once, and every trial then reads its terms from LDS:
+// lane l takes outputs t0 + 256 j + 4 l .. +3 (j < kTreeTile / 256), one realigned dword
+// (two consecutive LDS dwords, consecutive lanes on consecutive dwords) per
+// four outputs, summed as byte pairs in 16-bit lanes.
+__global__ __launch_bounds__(256) void k_tree_combine_lds(BeamDesc b, const int32_t* blocks, const TreeStage* stage,
+                                                          const int32_t* off, int flush)
+{
+    extern __shared__ uint32_t sl[];
+    constexpr int TT = kTreeTile, TB = kTreeBlock;
+    constexpr int J = TT / 256;                    // groups of four outputs per lane
+    static_assert(TT % 256 == 0, "whole groups per lane");
+    const long long t0 = (long long)blockIdx.x * TT;
+    const int blk = blocks[blockIdx.y];
+    const int nsb = b.nact;
+    const TreeStage* st = stage + (size_t)blockIdx.y * nsb;
+    const long long pitch_dw = b.pitch / 4;
+    auto fetch = [&](const TreeStage& g, int i) -> uint32_t {
+        const int r = i / g.wdw, c = i - r * g.wdw;
+        const long long col = (t0 + g.dmin4) / 4 + c;   // dword column in the row
+        const uint32_t* row = reinterpret_cast<const uint32_t*>(b.xc + (long long)(g.lo + r) * b.pitch);
+        return col < pitch_dw ? row[col] : 0u;
+    };
+    // staging: four sub-bands at a time, up to two dwords of each per thread,
+    // all eight loads in flight before the LDS stores
+    for (int n0 = 0; n0 < nsb; n0 += 4) {
+        uint32_t v[4][2];
+        int at[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                at[u][k] = -1;
+                v[u][k] = 0u;
+                if (n0 + u < nsb) {
+                    const TreeStage g = st[n0 + u];
+                    const int i = threadIdx.x + 256 * k;
+                    if (i < g.span * g.wdw) {
+                        v[u][k] = fetch(g, i);
+                        at[u][k] = g.lds + i;
+                    }
+                }
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (at[u][k] >= 0) sl[at[u][k]] = v[u][k];
+    }
+    // wider rows (more than 512 dwords of a sub-band)
+    for (int n = 0; n < nsb; ++n) {
+        const TreeStage g = st[n];
+        for (int i = 512 + threadIdx.x; i < g.span * g.wdw; i += 256) sl[g.lds + i] = fetch(g, i);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = wave; k < TB; k += 4) {
+        const int d = blk * TB + k;
+        if (d >= b.ndm) break;                     // no barriers below
+        // the trial's LDS offsets, lane n holding sub-band n's (and n + 64's),
+        // broadcast per term with v_readlane
+        const int32_t* od = off + (size_t)d * nsb;
+        const int o_lo = lane < nsb ? od[lane] : 0;
+        const int o_hi = lane + 64 < nsb ? od[lane + 64] : 0;
+        uint32_t acc[4 * J];
+#pragma unroll
+        for (int e = 0; e < 4 * J; ++e) acc[e] = 0u;
+        for (int n0 = 0; n0 < nsb; n0 += flush) {
+            const int n1 = min(nsb, n0 + flush);
+            uint32_t p[J], q[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) p[j] = q[j] = 0u;
+            for (int n = n0; n < n1; ++n) {
+                const int o = __builtin_amdgcn_readlane(n < 64 ? o_lo : o_hi, n & 63);
+                const uint32_t* src = sl + (o >> 2) + lane;
+                const int sh = (o & 3) * 8;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const uint32_t x = __builtin_amdgcn_alignbit(src[64 * j + 1], src[64 * j], sh);
+                    p[j] += x & 0x00FF00FFu;          // bytes 0, 2: outputs 4l, 4l+2
+                    q[j] += (x >> 8) & 0x00FF00FFu;   // bytes 1, 3: outputs 4l+1, 4l+3
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                acc[4 * j] += p[j] & 0xFFFFu;
+                acc[4 * j + 1] += q[j] & 0xFFFFu;
+                acc[4 * j + 2] += p[j] >> 16;
+                acc[4 * j + 3] += q[j] >> 16;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t a4[4] = {acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]};
+            tree_store<4>(b, d, t0 + 256 * j + 4 * lane, a4);
+        }
+    }
 }
 
 }  // namespace
 
 int tree_tile(int nsub) { return tree_tile_len(nsub); }
 
-hipError_t launch_tree_combine(const BeamDesc& d, int ob, int flush, hipStream_t st)
+hipError_t launch_tree_combine_lds(const BeamDesc& d, const int32_t* blocks, int nblocks, const TreeStage* stage,
+                                   const int32_t* off, int lds_dwords, int flush, hipStream_t st)
+{
+    if (d.nout <= 0 || d.ndm <= 0 || d.nact <= 0 || d.nact > 128 || nblocks <= 0 || nblocks > 65535 || flush < 1 ||
+        lds_dwords <= 0 || (size_t)lds_dwords * 4 > (size_t)kMaxLdsBytes || (d.pitch & 3) ||
+        (reinterpret_cast<uintptr_t>(d.xc) & 3) ||
+        (reinterpret_cast<uintptr_t>(d.out) & (d.out_bytes == 4 ? 3 : d.out_bytes - 1)))
+        return hipErrorInvalidValue;
+    const long long gx = (d.nout + kTreeTile - 1) / kTreeTile;
+    if (gx > 0x7fffffffLL) return hipErrorInvalidValue;
+    const void* fn = reinterpret_cast<const void*>(&k_tree_combine_lds);
+    const size_t lds = (size_t)lds_dwords * 4;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    BeamDesc a0 = d;
+    const int32_t* a1 = blocks;
+    const TreeStage* a2 = stage;
+    const int32_t* a3 = off;
+    int a4 = flush;
+    void* args[] = {&a0, &a1, &a2, &a3, &a4};
+    return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)nblocks), dim3(256), args, lds, st);
+}
+
+hipError_t launch_tree_combine(const BeamDesc& d, int ob, int flush, const int32_t* trials, int ntrials,
+                               hipStream_t st)
 {
     if (d.nout <= 0 || d.ndm <= 0 || d.nact <= 0 || flush < 1 || (d.pitch & 3) || (ob != 1 && ob != 2) ||
         (reinterpret_cast<uintptr_t>(d.xc) & 3) ||
         (reinterpret_cast<uintptr_t>(d.out) & (d.out_bytes == 4 ? 3 : d.out_bytes - 1)))
         return hipErrorInvalidValue;
     const long long per_item = ob == 2 ? 2048 : 4096;
-    const long long items = (long long)d.ndm * ((d.nout + per_item - 1) / per_item);
+    if (trials && ntrials <= 0) return hipErrorInvalidValue;
+    const long long items = (long long)(trials ? ntrials : d.ndm) * ((d.nout + per_item - 1) / per_item);
     const long long per_xcd = (items + 7) / 8;
     if (8 * per_xcd > 0x7fffffffLL) return hipErrorInvalidValue;
     BeamDesc a0 = d;
     int a1 = flush;
     long long a2 = per_xcd;
-    void* args[] = {&a0, &a1, &a2};
+    const int32_t* a3 = trials;
+    int a4 = ntrials;
+    void* args[] = {&a0, &a1, &a2, &a3, &a4};
     const void* fn = ob == 2 ? reinterpret_cast<const void*>(&k_tree_combine<2>)
                              : reinterpret_cast<const void*>(&k_tree_combine<1>);
     return hipLaunchKernel(fn, dim3((unsigned)(8 * per_xcd)), dim3(256), args, 0, st);

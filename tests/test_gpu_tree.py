@@ -31,7 +31,7 @@ def _run(plan, packed, nsamps, dev):
 
 @pytest.mark.parametrize("nbits,nchans,nsub,nsamps", [
     (2, 256, 8, 12011), (2, 512, 32, 20003), (8, 128, 16, 9001), (8, 256, 64, 7777),
-    (2, 1024, 128, 6007)])
+    (2, 1024, 128, 6007), (2, 2048, 8, 5003)])
 def test_piecewise_tree_bit_exact(native, cuda, nbits, nchans, nsub, nsamps):
     dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
     dms = np.linspace(0.0, 0.99 * _diag(nchans, nsub, dt, f_top, df), 37)
@@ -135,3 +135,29 @@ def test_scrunched_tree_bit_exact(native, cuda, nbits, nchans, nsub, nsamps, max
     assert got.shape == (ndm, lens.max())
     for d in range(ndm):
         assert np.array_equal(got[d, : lens[d]], want[d]), (d, factors[d])
+
+
+def test_tree_staged_and_gathered_blocks_in_one_transform(native, cuda):
+    """Stage 2 stages a block of consecutive trials in LDS when the rows it
+    uses fit and gathers the block from global memory otherwise: 64 dense,
+    sorted trials (two staged blocks) followed by 32 trials in shuffled order
+    across twice the diagonal (a block whose rows do not fit), with a kill
+    mask and 16-bit outputs, bit for bit against the oracle."""
+    import torch
+    nbits, nchans, nsub, nsamps = 2, 1024, 32, 40009
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    diag = _diag(nchans, nsub, dt, f_top, df)
+    rng = np.random.default_rng(12)
+    dms = np.concatenate([np.linspace(3.0, 3.0 + 0.05 * 63, 64), rng.permutation(np.linspace(0.0, 2.0 * diag, 32))])
+    codes = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+    codes[::29] = 3
+    packed = synth.pack(codes, nbits)
+    mask = (rng.random(nchans) < 0.9).astype(np.int32)
+    want = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub, mask=mask)
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms).set_killmask(mask).set_tree(nsub)
+    assert np.array_equal(_run(plan, packed, nsamps, cuda), want)
+    plan.set_output_format(16, 0)
+    inp = torch.from_numpy(packed.reshape(-1)).to(cuda)
+    out = plan.execute(inp, nsamps)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint16), oracle.reduce_output(want, 16, 0))
