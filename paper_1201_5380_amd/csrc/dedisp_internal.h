@@ -103,7 +103,7 @@ hipError_t launch_scrunch(const BeamDesc& d, int nbits, int fmt, hipStream_t st)
 // len1 + tile + nsub + (largest p)(nsub - 1) + 8 samples.
 hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, const int32_t* pairs, int npairs,
                        uint8_t* out, long long out_pitch, long long len1, hipStream_t st);
-// Samples per time tile of the tree kernel (the scratch rows need this many
+// Samples per time tile of the longest stage-1 tile (the scratch rows need this many
 // samples of margin past nsamps).
 int tree_tile(int nsub);
 

@@ -20,8 +20,9 @@ namespace {
 //   B[2v+1][t] = A[Phi(r, 2v)][t] + A[Phi(r, 2v+1)][t + Theta(i, 2v+1)]
 // with r = 2^i, Theta(i, v) = ((v mod 2^{i+1}) + 1) / 2 and
 // Phi(r, v) = (v mod 2) r + v/2 + (v/(2r)) r.  Row d' of the result is the
-// sub-band at tree DM d', written for t < len1.  Sums stay below 2^16 (nsub
-// codes), so a 32-bit add sums two samples without a carry between them.
+// sub-band at tree DM d', written as 16-bit values for t < len1 (byte rows
+// take k_tree_b below).  Sums stay below 2^16 (nsub codes), so a 32-bit add
+// sums two samples without a carry between them.
 //
 // Theta(i, 2v+1) = Theta(i, 2v) + 1, so both outputs of a pair read the
 // same three samples of the second row: one aligned word pair q, q+1 and a
@@ -40,7 +41,7 @@ __device__ __forceinline__ int tree_theta(int i, int v) { return ((v & ((2 << i)
 // Phi(2^i, v), with v / 2^{i+1} taken as a shift
 __device__ __forceinline__ int tree_phi(int i, int v) { return ((v & 1) << i) + (v >> 1) + ((v >> (i + 1)) << i); }
 
-template <int FMT, int NSUB, int OB>
+template <int FMT, int NSUB>
 __global__ __launch_bounds__(256) void k_tree(BeamDesc b, const int32_t* pairs, uint8_t* out, long long out_pitch,
                                               long long len1)
 {
@@ -63,30 +64,40 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, const int32_t* pairs, 
     constexpr int SPW = fmt_samples_per_word(FMT);
     constexpr int WPR = L / SPW;                   // scratch words per row
     static_assert(L % SPW == 0, "whole words per row");
-    // all of a thread's loads are issued before the first LDS store
+    // every load (and kill-mask flag) is issued before the first
+    // realignment, so a thread waits for global memory once; a thread's last
+    // index may run past the rows (clamped: loaded, not stored)
     constexpr int NLD = (NSUB * WPR + 255) / 256;
-    uint32_t ld[NLD];
+    int jj[NLD], ww[NLD], keep[NLD];
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
         const int it = threadIdx.x + 256 * k;
-        if (it < NSUB * WPR) {
-            const int j = it / WPR, w = it % WPR;
-            const int shift = pass * j;
-            const uint32_t* row = reinterpret_cast<const uint32_t*>(b.xc + (long long)(n * NSUB + j) * b.pitch);
-            u32x2 v;
-            __builtin_memcpy(&v, row + t0 / SPW + shift / SPW + w, sizeof(v));
-            ld[k] = __builtin_amdgcn_alignbit(v.y, v.x, (shift % SPW) * (32 / SPW));
-            // killed channels read as zeros (a scrunching corner turn keeps their rows)
-            if (b.mask && b.mask[n * NSUB + j] == 0) ld[k] = 0u;
-        }
+        const int ic = it < NSUB * WPR ? it : NSUB * WPR - 1;
+        jj[k] = ic / WPR;
+        ww[k] = ic % WPR;
+    }
+    if (b.mask) {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) keep[k] = b.mask[n * NSUB + jj[k]];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) keep[k] = 1;
+    }
+    u32x2 raw[NLD];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const uint32_t* row = reinterpret_cast<const uint32_t*>(b.xc + (long long)(n * NSUB + jj[k]) * b.pitch);
+        __builtin_memcpy(&raw[k], row + t0 / SPW + (pass * jj[k]) / SPW + ww[k], sizeof(u32x2));
     }
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
         const int it = threadIdx.x + 256 * k;
         if (it >= NSUB * WPR) break;
-        const int j = it / WPR, w = it % WPR;
-        const uint32_t v = ld[k];
-        uint32_t* dst = A + j * RS + w * (SPW / 2);
+        const int shift = pass * jj[k];
+        // killed channels read as zeros (a scrunching corner turn keeps their rows)
+        const uint32_t v = __builtin_amdgcn_alignbit(raw[k].y, raw[k].x, (shift % SPW) * (32 / SPW)) &
+                           (0u - (uint32_t)(keep[k] != 0));
+        uint32_t* dst = A + jj[k] * RS + ww[k] * (SPW / 2);
         if constexpr (FMT == kFmtHalf) {
             dst[0] = v;                            // already two 16-bit samples
         } else if constexpr (FMT == kFmtNib) {
@@ -108,7 +119,9 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, const int32_t* pairs, 
     constexpr int TPP = 256 / (NSUB / 2);
     constexpr int WPT = (LW + TPP - 1) / TPP;      // words per thread
     const int v = threadIdx.x / TPP, l = threadIdx.x % TPP;
-#pragma unroll 1
+    // unrolled: each step's Theta/Phi masks and buffer offsets are
+    // constants; a step issues all of a thread's LDS reads before its writes
+#pragma unroll
     for (int i = 0; i < K; ++i) {
         const uint32_t* lo = A + tree_phi(i, 2 * v) * RS + l;
         const int th = tree_theta(i, 2 * v);
@@ -116,45 +129,28 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, const int32_t* pairs, 
         uint32_t* o0 = B + (2 * v) * RS + l;
         uint32_t* o1 = B + (2 * v + 1) * RS + l;
         const bool odd = (th & 1) != 0;
+        uint32_t ra[WPT], r0[WPT], r1[WPT];
 #pragma unroll
         for (int k = 0; k < WPT; ++k) {
             if (LW % TPP != 0 && k == WPT - 1 && l + TPP * k >= LW) break;
-            const uint32_t a = lo[TPP * k], h0 = hi[TPP * k], h1 = hi[TPP * k + 1];
-            const uint32_t mid = __builtin_amdgcn_alignbit(h1, h0, 16);
-            o0[TPP * k] = a + (odd ? mid : h0);
-            o1[TPP * k] = a + (odd ? h1 : mid);
+            ra[k] = lo[TPP * k];
+            r0[k] = hi[TPP * k];
+            r1[k] = hi[TPP * k + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < WPT; ++k) {
+            if (LW % TPP != 0 && k == WPT - 1 && l + TPP * k >= LW) break;
+            const uint32_t mid = __builtin_amdgcn_alignbit(r1[k], r0[k], 16);
+            o0[TPP * k] = ra[k] + (odd ? mid : r0[k]);
+            o1[TPP * k] = ra[k] + (odd ? r1[k] : mid);
         }
         __syncthreads();
         uint32_t* tmp = A;
         A = B;
         B = tmp;
     }
-    // store rows n*NSUB + d', samples t0 .. t0 + T - 1 below len1, as
-    // bytes (OB = 1, values below 256: 16 samples per 16-byte store) or
-    // 16-bit values (8 per store)
-    if constexpr (OB == 1) {
-        static_assert(T % 16 == 0, "whole 16-sample pieces per tile");
-        for (int it = threadIdx.x; it < NSUB * (T / 16); it += 256) {
-            const int dp = it / (T / 16), t = 16 * (it % (T / 16));
-            const long long tg = t0 + t;
-            if (tg >= len1) continue;
-            const u32x4 a = *reinterpret_cast<const u32x4*>(A + dp * RS + t / 2);
-            const u32x4 c = *reinterpret_cast<const u32x4*>(A + dp * RS + t / 2 + 4);
-            // bytes 0 and 2 of each word: samples 2w and 2w+1
-            const u32x4 v = {__builtin_amdgcn_perm(a.y, a.x, 0x06040200u), __builtin_amdgcn_perm(a.w, a.z, 0x06040200u),
-                             __builtin_amdgcn_perm(c.y, c.x, 0x06040200u), __builtin_amdgcn_perm(c.w, c.z, 0x06040200u)};
-            uint8_t* orow = out + (long long)(y * NSUB + dp) * out_pitch;
-            if (tg + 16 <= len1) {
-                *reinterpret_cast<u32x4*>(orow + tg) = v;
-            } else {
-                const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int e = 0; e < 16; ++e)
-                    if (tg + e < len1) orow[tg + e] = (uint8_t)(wv[e >> 2] >> (8 * (e & 3)));
-            }
-        }
-        return;
-    }
+    // store rows n*NSUB + d', samples t0 .. t0 + T - 1 below len1, eight
+    // 16-bit values per 16-byte store
     for (int it = threadIdx.x; it < NSUB * (T / 8); it += 256) {
         const int dp = it / (T / 8), t = 8 * (it % (T / 8));
         const long long tg = t0 + t;
@@ -168,6 +164,158 @@ __global__ __launch_bounds__(256) void k_tree(BeamDesc b, const int32_t* pairs, 
 #pragma unroll
             for (int e = 0; e < 8; ++e)
                 if (tg + e < len1) orow[tg + e] = (uint16_t)(wv[e >> 1] >> (16 * (e & 1)));
+        }
+    }
+}
+
+// Stage 1 for byte rows (every sub-band sum below 256: 2-bit codes up to
+// nsub = 64, small scrunched sums): the same steps as k_tree on byte lanes,
+// four samples per 32-bit LDS word, so a step moves half the LDS bytes per
+// sample of the 16-bit form.  512 threads per workgroup in teams of
+// TPP >= 32 threads, each team taking one output pair (two for nsub = 64)
+// and WPT consecutive-word columns of its rows, so every half-wave reads 32
+// consecutive words (no bank conflicts); a step issues all of a thread's
+// LDS reads before its first write.
+// Theta(i, 2v+1) = Theta(i, 2v) + 1: with s = Theta mod 4, the words of the
+// second row shifted by s and s + 1 samples are bytes s .. s+3 and
+// s+1 .. s+4 of the aligned pair (h0, h1), one v_perm each.  Byte sums never
+// carry into the next lane (values below 256).
+constexpr int kTreeBThreads = 512;
+// LW words (4 LW samples) computed per row
+__host__ __device__ constexpr int tree_b_words(int nsub) { return 4096 / nsub > 128 ? 4096 / nsub : 128; }
+// T samples per tile: the 4 LW loaded samples less at least nsub of halo
+__host__ __device__ constexpr int tree_tile_len_b(int nsub) { return 4 * tree_b_words(nsub) - (nsub > 16 ? nsub : 16); }
+__host__ __device__ constexpr int tree_row_words_b(int nsub) { return (tree_b_words(nsub) + nsub / 8 + 1 + 3) / 4 * 4; }
+
+template <int FMT, int NSUB>
+__global__ __launch_bounds__(kTreeBThreads) void k_tree_b(BeamDesc b, const int32_t* pairs, uint8_t* out,
+                                                          long long out_pitch, long long len1)
+{
+    static_assert(FMT == kFmtNib || FMT == kFmtByteS, "byte lanes hold 2-bit codes or small byte sums");
+    constexpr int NT = kTreeBThreads;
+    constexpr int LW = tree_b_words(NSUB);         // words computed per row
+    constexpr int L = 4 * LW;                      // samples loaded per row
+    constexpr int T = tree_tile_len_b(NSUB);       // samples stored per row
+    constexpr int RS = tree_row_words_b(NSUB);     // LDS row stride in words
+    constexpr int K = NSUB == 8 ? 3 : NSUB == 16 ? 4 : NSUB == 32 ? 5 : 6;
+    static_assert((1 << K) == NSUB && NSUB <= 64, "sub-band width must be a power of two up to 64");
+    static_assert(L >= T + NSUB - 1 && L % 8 == 0 && T % 16 == 0, "halo, whole scratch words, 16-sample stores");
+    // Theta <= NSUB / 2 samples: reads reach word LW - 1 + NSUB / 8 + 1
+    static_assert(RS >= LW + NSUB / 8 + 1 && RS % 4 == 0, "row stride covers the shifted reads");
+    extern __shared__ __align__(16) uint32_t tw[];             // [2][NSUB][RS]
+    uint32_t* A = tw;
+    uint32_t* B = tw + NSUB * RS;
+    const long long t0 = (long long)blockIdx.x * T;
+    const int y = blockIdx.y;
+    const int n = pairs[2 * y], pass = pairs[2 * y + 1];
+    // load: channel j of the sub-band starts pass*j samples later (the
+    // imposed delay), realigned from two consecutive scratch words.  Thread
+    // x takes word w = x mod WPR of rows j = x / WPR + JS k; every load (and
+    // kill-mask flag) is issued before the first realignment, so a thread
+    // waits for global memory once
+    constexpr int SPW = fmt_samples_per_word(FMT);   // 8 (nibbles) or 4 (bytes)
+    constexpr int WPR = L / SPW;
+    static_assert(NT % WPR == 0 && (NSUB * WPR) % NT == 0, "whole rows per thread block pass");
+    constexpr int JS = NT / WPR;                   // rows per pass over the threads
+    constexpr int NLD = NSUB * WPR / NT;           // loads per thread
+    const int w = threadIdx.x % WPR, j0 = threadIdx.x / WPR;
+    int keep[NLD];
+    if (b.mask) {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) keep[k] = b.mask[n * NSUB + j0 + JS * k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) keep[k] = 1;
+    }
+    const uint8_t* row0 = b.xc + (long long)(n * NSUB + j0) * b.pitch + (t0 / SPW + w) * 4;
+    u32x2 raw[NLD];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int shift = pass * (j0 + JS * k);
+        __builtin_memcpy(&raw[k], row0 + (long long)(JS * k) * b.pitch + (shift / SPW) * 4, sizeof(u32x2));
+    }
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+        const int shift = pass * (j0 + JS * k);
+        // killed channels read as zeros (a scrunching corner turn keeps their rows)
+        const uint32_t v = __builtin_amdgcn_alignbit(raw[k].y, raw[k].x, (shift % SPW) * (32 / SPW)) &
+                           (0u - (uint32_t)(keep[k] != 0));
+        uint32_t* dst = A + (j0 + JS * k) * RS + w * (SPW / 4);
+        if constexpr (FMT == kFmtNib) {
+            // nibble i (sample i) to byte i of two words: even samples from
+            // the low nibbles, odd ones from the high nibbles, interleaved
+            const uint32_t ev = v & 0x0F0F0F0Fu, od = (v >> 4) & 0x0F0F0F0Fu;
+            u32x2 q;
+            q.x = __builtin_amdgcn_perm(od, ev, 0x05010400u);
+            q.y = __builtin_amdgcn_perm(od, ev, 0x07030602u);
+            *reinterpret_cast<u32x2*>(dst) = q;
+        } else {
+            dst[0] = v;                            // already four byte samples
+        }
+    }
+    __syncthreads();
+    // output pairs v = team + NTEAM q (q < PPT) of a team of TPP threads;
+    // team lane l takes words l, l + TPP, ... of the rows
+    constexpr int TPP = NT / (NSUB / 2) > 32 ? NT / (NSUB / 2) : 32;
+    constexpr int NTEAM = NT / TPP;
+    constexpr int PPT = (NSUB / 2) / NTEAM;        // output pairs per team
+    constexpr int WPT = LW / TPP;                  // words per thread and row
+    static_assert(NTEAM * PPT == NSUB / 2 && TPP * WPT == LW, "whole teams and team passes");
+    const int team = threadIdx.x / TPP, l = threadIdx.x % TPP;
+    // unrolled: each step's Theta/Phi masks and buffer offsets are constants
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        uint32_t a[PPT][WPT], h0[PPT][WPT], h1[PPT][WPT], sel0[PPT];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int v = team + NTEAM * q;
+            const int th = tree_theta(i, 2 * v);
+            const uint32_t* lo = A + tree_phi(i, 2 * v) * RS + l;
+            const uint32_t* hi = A + tree_phi(i, 2 * v + 1) * RS + (th >> 2) + l;
+            // v_perm selector: bytes s .. s+3 of (h0 = bytes 0-3, h1 = 4-7)
+            sel0[q] = 0x03020100u + (uint32_t)(th & 3) * 0x01010101u;
+#pragma unroll
+            for (int k = 0; k < WPT; ++k) {
+                a[q][k] = lo[TPP * k];
+                h0[q][k] = hi[TPP * k];
+                h1[q][k] = hi[TPP * k + 1];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            uint32_t* o0 = B + (2 * (team + NTEAM * q)) * RS + l;
+            const uint32_t sel1 = sel0[q] + 0x01010101u;   // bytes s+1 .. s+4
+#pragma unroll
+            for (int k = 0; k < WPT; ++k) {
+                o0[TPP * k] = a[q][k] + __builtin_amdgcn_perm(h1[q][k], h0[q][k], sel0[q]);
+                o0[RS + TPP * k] = a[q][k] + __builtin_amdgcn_perm(h1[q][k], h0[q][k], sel1);
+            }
+        }
+        __syncthreads();
+        uint32_t* tmp = A;
+        A = B;
+        B = tmp;
+    }
+    // store rows n*NSUB + d', samples t0 .. t0 + T - 1 below len1, 16 per
+    // 16-byte store
+    constexpr int PR = T / 16;                     // pieces per row
+    uint8_t* obase = out + (long long)y * NSUB * out_pitch + t0;
+    const long long rem = len1 - t0;               // samples of this tile below len1
+#pragma unroll
+    for (int m = 0; m < (NSUB * PR + NT - 1) / NT; ++m) {
+        const int it = threadIdx.x + NT * m;
+        if ((NSUB * PR) % NT != 0 && it >= NSUB * PR) break;
+        const int dp = it / PR, t = 16 * (it - dp * PR);
+        if (t >= rem) continue;
+        const u32x4 val = *reinterpret_cast<const u32x4*>(A + dp * RS + t / 4);
+        uint8_t* o = obase + (long long)dp * out_pitch + t;
+        if (t + 16 <= rem) {
+            *reinterpret_cast<u32x4*>(o) = val;
+        } else {
+            const uint32_t wv[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if (t + e < rem) o[e] = (uint8_t)(wv[e >> 2] >> (8 * (e & 3)));
         }
     }
 }
@@ -394,7 +542,7 @@ __global__ __launch_bounds__(256) void k_tree_combine_lds(BeamDesc b, const int3
 
 }  // namespace
 
-int tree_tile(int nsub) { return tree_tile_len(nsub); }
+int tree_tile(int nsub) { return tree_tile_len_b(nsub) > tree_tile_len(nsub) ? tree_tile_len_b(nsub) : tree_tile_len(nsub); }
 
 hipError_t launch_tree_combine_lds(const BeamDesc& d, const int32_t* blocks, int nblocks, const TreeStage* stage,
                                    const int32_t* off, int lds_dwords, int flush, hipStream_t st)
@@ -448,27 +596,31 @@ hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, const int32
     if (len1 <= 0 || (out_pitch & 15) || (reinterpret_cast<uintptr_t>(out) & 15) || !pairs ||
         (d.pitch & 3))
         return hipErrorInvalidValue;
-    const long long T = tree_tile_len(nsub);
+    const long long T = ob == 1 ? tree_tile_len_b(nsub) : tree_tile_len(nsub);
     const long long gx = (len1 + T - 1) / T;
     const long long gy = npairs;
     if (gx <= 0 || gx > 0x7fffffffLL || gy <= 0 || gy > 65535) return hipErrorInvalidValue;
     const void* fn = nullptr;
-    // byte rows hold sub-band sums below 256: 2-bit codes up to nsub = 64,
-    // small scrunched sums (byte format) for narrow sub-bands
-#define DEDISP_TREE_CASE(F, N, O) \
-    if (fmt == F && nsub == N && ob == O) fn = reinterpret_cast<const void*>(&k_tree<F, N, O>);
-    DEDISP_TREE_CASE(kFmtNib, 8, 1) DEDISP_TREE_CASE(kFmtNib, 16, 1) DEDISP_TREE_CASE(kFmtNib, 32, 1)
-    DEDISP_TREE_CASE(kFmtNib, 64, 1) DEDISP_TREE_CASE(kFmtNib, 128, 2)
-    DEDISP_TREE_CASE(kFmtByte, 8, 2) DEDISP_TREE_CASE(kFmtByte, 16, 2) DEDISP_TREE_CASE(kFmtByte, 32, 2)
-    DEDISP_TREE_CASE(kFmtByte, 64, 2) DEDISP_TREE_CASE(kFmtByte, 128, 2)
-    DEDISP_TREE_CASE(kFmtByteS, 8, 1) DEDISP_TREE_CASE(kFmtByteS, 16, 1) DEDISP_TREE_CASE(kFmtByteS, 32, 1)
-    DEDISP_TREE_CASE(kFmtByteS, 8, 2) DEDISP_TREE_CASE(kFmtByteS, 16, 2) DEDISP_TREE_CASE(kFmtByteS, 32, 2)
-    DEDISP_TREE_CASE(kFmtByteS, 64, 2) DEDISP_TREE_CASE(kFmtByteS, 128, 2)
-    DEDISP_TREE_CASE(kFmtHalf, 8, 2) DEDISP_TREE_CASE(kFmtHalf, 16, 2) DEDISP_TREE_CASE(kFmtHalf, 32, 2)
-    DEDISP_TREE_CASE(kFmtHalf, 64, 2) DEDISP_TREE_CASE(kFmtHalf, 128, 2)
+    // byte rows (byte lanes in LDS) hold sub-band sums below 256: 2-bit
+    // codes up to nsub = 64, small scrunched sums (byte format) for narrow
+    // sub-bands; 16-bit rows everything else
+#define DEDISP_TREE_B(F, N) \
+    if (fmt == F && nsub == N && ob == 1) fn = reinterpret_cast<const void*>(&k_tree_b<F, N>);
+#define DEDISP_TREE_CASE(F, N) \
+    if (fmt == F && nsub == N && ob == 2) fn = reinterpret_cast<const void*>(&k_tree<F, N>);
+    DEDISP_TREE_B(kFmtNib, 8) DEDISP_TREE_B(kFmtNib, 16) DEDISP_TREE_B(kFmtNib, 32) DEDISP_TREE_B(kFmtNib, 64)
+    DEDISP_TREE_B(kFmtByteS, 8) DEDISP_TREE_B(kFmtByteS, 16) DEDISP_TREE_B(kFmtByteS, 32)
+    DEDISP_TREE_CASE(kFmtNib, 128)
+    DEDISP_TREE_CASE(kFmtByte, 8) DEDISP_TREE_CASE(kFmtByte, 16) DEDISP_TREE_CASE(kFmtByte, 32)
+    DEDISP_TREE_CASE(kFmtByte, 64) DEDISP_TREE_CASE(kFmtByte, 128)
+    DEDISP_TREE_CASE(kFmtByteS, 8) DEDISP_TREE_CASE(kFmtByteS, 16) DEDISP_TREE_CASE(kFmtByteS, 32)
+    DEDISP_TREE_CASE(kFmtByteS, 64) DEDISP_TREE_CASE(kFmtByteS, 128)
+    DEDISP_TREE_CASE(kFmtHalf, 8) DEDISP_TREE_CASE(kFmtHalf, 16) DEDISP_TREE_CASE(kFmtHalf, 32)
+    DEDISP_TREE_CASE(kFmtHalf, 64) DEDISP_TREE_CASE(kFmtHalf, 128)
+#undef DEDISP_TREE_B
 #undef DEDISP_TREE_CASE
     if (!fn) return hipErrorInvalidValue;
-    const size_t lds = 2ull * nsub * tree_row_words(nsub) * sizeof(uint32_t);
+    const size_t lds = 2ull * nsub * (ob == 1 ? tree_row_words_b(nsub) : tree_row_words(nsub)) * sizeof(uint32_t);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     BeamDesc a0 = d;
@@ -476,7 +628,7 @@ hipError_t launch_tree(const BeamDesc& d, int fmt, int nsub, int ob, const int32
     uint8_t* a2 = out;
     long long a3 = out_pitch, a4 = len1;
     void* args[] = {&a0, &a1, &a2, &a3, &a4};
-    return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, lds, st);
+    return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(ob == 1 ? kTreeBThreads : 256), args, lds, st);
 }
 
 }  // namespace dedisp

@@ -31,7 +31,7 @@ def _run(plan, packed, nsamps, dev):
 
 @pytest.mark.parametrize("nbits,nchans,nsub,nsamps", [
     (2, 256, 8, 12011), (2, 512, 32, 20003), (8, 128, 16, 9001), (8, 256, 64, 7777),
-    (2, 1024, 128, 6007), (2, 2048, 8, 5003)])
+    (2, 1024, 128, 6007), (2, 2048, 8, 5003), (2, 512, 64, 9013), (2, 128, 16, 1500)])
 def test_piecewise_tree_bit_exact(native, cuda, nbits, nchans, nsub, nsamps):
     dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
     dms = np.linspace(0.0, 0.99 * _diag(nchans, nsub, dt, f_top, df), 37)
@@ -108,6 +108,7 @@ def test_survey_beam_tree_full_size(native, cuda):
 @pytest.mark.parametrize("nbits,nchans,nsub,nsamps,maxf,ndm,dm_max,masked", [
     (2, 256, 16, 60013, 32, 40, 1000.0, False),
     (2, 512, 32, 40009, 8, 30, 600.0, True),
+    (2, 128, 8, 70001, 8, 50, 150.0, True),
     (8, 128, 8, 30011, 4, 60, 40.0, False)])
 def test_scrunched_tree_bit_exact(native, cuda, nbits, nchans, nsub, nsamps, maxf, ndm, dm_max, masked):
     """Time-scrunching then the tree: every factor group runs the corner turn
