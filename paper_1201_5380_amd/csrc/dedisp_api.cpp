@@ -1124,7 +1124,7 @@ static dedisp_status run_tree(dedisp_plan p, const void* d_in, size_t nsamps, ui
     if (!p->tree_sblocks.empty()) {
         // the staged trial blocks through LDS, the rest gathered
         e = dedisp::launch_tree_combine_lds(dg, p->d_tree_sblocks, static_cast<int>(p->tree_sblocks.size()),
-                                            p->d_tree_stage, p->d_tree_off, p->tree_lds, flush, hs);
+                                            p->d_tree_stage, p->d_tree_off, p->tree_lds, hs);
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         if (!p->tree_gtrials.empty())
             e = dedisp::launch_tree_combine(dg, ob, flush, p->d_tree_gtrials,
@@ -1668,6 +1668,7 @@ static dedisp_status build_tree(dedisp_plan q, int nsub)
                 // the window covers the tile, the block's delay spread and the
                 // second dword each lane reads past its four outputs
                 g.wdw = (TT + (dmax - g.dmin4) + 8 + 3) / 4;
+                g.rcp = static_cast<uint32_t>(((1ull << 32) + g.wdw - 1) / g.wdw);
                 g.lds = static_cast<int>(std::min<long long>(lds, 0x7fffffff));
                 lds += static_cast<long long>(g.span) * g.wdw;
             }

@@ -125,15 +125,16 @@ hipError_t launch_tree_combine(const BeamDesc& d, int ob, int flush, const int32
 // then every trial d of the block sums, over n, the bytes at LDS byte
 // off[d][n] + (t - t0) for its outputs t of the time tile [t0, t0 +
 // kTreeTile).  lds_dwords = LDS per workgroup; at most 128 sub-bands.  d as
-// for launch_tree_combine.
+// for launch_tree_combine (32-bit sums: no flush interval).
 constexpr int kTreeBlock = 32;
 constexpr int kTreeTile = 512;
 struct TreeStage {
     int lo, span, dmin4, wdw, lds;
-    int pad_[3];
+    uint32_t rcp;          // ceil(2^32 / wdw): i / wdw = umulhi(i, rcp) for i < 2^16
+    int pad_[2];
 };
 hipError_t launch_tree_combine_lds(const BeamDesc& d, const int32_t* blocks, int nblocks, const TreeStage* stage,
-                                   const int32_t* off, int lds_dwords, int flush, hipStream_t st);
+                                   const int32_t* off, int lds_dwords, hipStream_t st);
 
 // Zero `bytes` (a multiple of 16) at base + g*group_stride for g < ngroups.
 hipError_t launch_zero(uint8_t* base, long long group_stride, long long bytes, int ngroups,

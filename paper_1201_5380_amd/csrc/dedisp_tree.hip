@@ -1,6 +1,8 @@
 // Piecewise linear tree dedispersion (Section 3): stage 1 applies the
 // tree's steps within every sub-band of the channel-major scratch, stage 2
 // combines one tree row per sub-band for every trial.
+#include <type_traits>
+
 #include "dedisp_device.h"
 
 namespace dedisp {
@@ -356,12 +358,13 @@ __device__ __forceinline__ void tree_store(const BeamDesc& b, int d, long long t
 // S[rowsel[d][n]][t + table[d][n]], S the stage-1 rows (d.xc, pitch d.pitch
 // bytes) of 16-bit values (OB = 2) or bytes (OB = 1).  A lane sums L = 8
 // (16-bit) or 16 (byte) consecutive outputs of one trial: per term five
-// aligned 32-bit words (a 16-byte load and one more) and four realignments
-// (v_alignbit by the delay's offset within a word) give the L shifted
-// samples; they are added in 16-bit lanes without a carry between lanes and
-// moved to 32-bit sums every `flush` terms (flush * largest row value
-// < 2^16).  The realignment is uniform over the wave (t is a multiple of
-// the samples per word).
+// aligned 32-bit words (a 16-byte load and one more, four terms' loads in
+// flight at a time) give the L shifted samples through four realignments
+// (v_alignbit by the delay's offset within a word) for 16-bit rows, or
+// eight v_perm byte-pair picks for byte rows; they are added in 16-bit
+// lanes without a carry between lanes and moved to 32-bit sums every
+// `flush` terms (flush * largest row value < 2^16).  The realignment is
+// uniform over the wave (t is a multiple of the samples per word).
 //
 // Work items (time tile of 256 L outputs, trial) are ordered tile-major,
 // trial-minor and cut into 8 contiguous ranges, one per XCD (the hardware
@@ -401,24 +404,45 @@ __global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, lon
         // OB = 2: p[k] = samples (2k, 2k+1); OB = 1: p[k] = (4k, 4k+2),
         // q[k] = (4k+1, 4k+3), each pair in the two 16-bit lanes
         uint32_t p[4] = {0u, 0u, 0u, 0u}, q[4] = {0u, 0u, 0u, 0u};
-        for (int n = n0; n < n1; ++n) {
-            const int rn = in_regs ? __builtin_amdgcn_readlane(n < 64 ? r_lo : r_hi, n & 63) : rows[n];
-            const int dn = in_regs ? __builtin_amdgcn_readlane(n < 64 ? d_lo : d_hi, n & 63) : dly[n];
-            const long long s = t + dn;
-            const uint32_t* w = reinterpret_cast<const uint32_t*>(b.xc + (long long)rn * b.pitch) + s / SPW;
-            u32x4 v;
-            __builtin_memcpy(&v, w, sizeof(v));
-            const uint32_t v4 = w[4];
-            const int sh = (int)(s % SPW) * (32 / SPW);
-            const uint32_t x[4] = {__builtin_amdgcn_alignbit(v.y, v.x, sh), __builtin_amdgcn_alignbit(v.z, v.y, sh),
-                                   __builtin_amdgcn_alignbit(v.w, v.z, sh), __builtin_amdgcn_alignbit(v4, v.w, sh)};
+        // U terms at a time: the group's loads are all issued before the
+        // first add
+        constexpr int U = 4;
+        for (int n = n0; n < n1; n += U) {
+            uint32_t w[U][5];
+            int sh[U];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+            for (int u = 0; u < U; ++u) {
+                const int m = n + u < n1 ? n + u : n;   // past the range: repeat n, not added
+                const int rn = in_regs ? __builtin_amdgcn_readlane(m < 64 ? r_lo : r_hi, m & 63) : rows[m];
+                const int dn = in_regs ? __builtin_amdgcn_readlane(m < 64 ? d_lo : d_hi, m & 63) : dly[m];
+                const long long s = t + dn;
+                const uint32_t* src = reinterpret_cast<const uint32_t*>(b.xc + (long long)rn * b.pitch) + s / SPW;
+                u32x4 v;
+                __builtin_memcpy(&v, src, sizeof(v));
+                w[u][0] = v.x;
+                w[u][1] = v.y;
+                w[u][2] = v.z;
+                w[u][3] = v.w;
+                w[u][4] = src[4];
+                sh[u] = (int)(s % SPW);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (n + u >= n1) break;
                 if constexpr (OB == 2) {
-                    p[k] += x[k];
+                    // 16-bit rows: realign by 0 or 16 bits, add both lanes
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) p[k] += __builtin_amdgcn_alignbit(w[u][k + 1], w[u][k], 16 * sh[u]);
                 } else {
-                    p[k] += x[k] & 0x00FF00FFu;
-                    q[k] += (x[k] >> 8) & 0x00FF00FFu;
+                    // byte rows: one v_perm of the aligned pair picks bytes
+                    // s, s+2 into p's 16-bit lanes, another s+1, s+3 into q's
+                    const uint32_t sa = 0x0C020C00u + (uint32_t)sh[u] * 0x00010001u;
+                    const uint32_t sb = sa + 0x00010001u;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        p[k] += __builtin_amdgcn_perm(w[u][k + 1], w[u][k], sa);
+                        q[k] += __builtin_amdgcn_perm(w[u][k + 1], w[u][k], sb);
+                    }
                 }
             }
         }
@@ -445,9 +469,9 @@ __global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, lon
 // block's delay window once, and every trial then reads its terms from LDS:
 // lane l takes outputs t0 + 256 j + 4 l .. +3 (j < kTreeTile / 256), one realigned dword
 // (two consecutive LDS dwords, consecutive lanes on consecutive dwords) per
-// four outputs, summed as byte pairs in 16-bit lanes.
+// four outputs, added as byte pairs in 16-bit lanes.
 __global__ __launch_bounds__(256) void k_tree_combine_lds(BeamDesc b, const int32_t* blocks, const TreeStage* stage,
-                                                          const int32_t* off, int flush)
+                                                          const int32_t* off)
 {
     extern __shared__ uint32_t sl[];
     constexpr int TT = kTreeTile, TB = kTreeBlock;
@@ -458,37 +482,40 @@ __global__ __launch_bounds__(256) void k_tree_combine_lds(BeamDesc b, const int3
     const int nsb = b.nact;
     const TreeStage* st = stage + (size_t)blockIdx.y * nsb;
     const long long pitch_dw = b.pitch / 4;
+    // staged dword i of a sub-band is row r = i / wdw, column c; i stays
+    // below 2^14 (the LDS budget), where the rounded-up reciprocal gives the
+    // exact quotient
     auto fetch = [&](const TreeStage& g, int i) -> uint32_t {
-        const int r = i / g.wdw, c = i - r * g.wdw;
+        const int r = (int)__umulhi((uint32_t)i, g.rcp), c = i - r * g.wdw;
         const long long col = (t0 + g.dmin4) / 4 + c;   // dword column in the row
         const uint32_t* row = reinterpret_cast<const uint32_t*>(b.xc + (long long)(g.lo + r) * b.pitch);
         return col < pitch_dw ? row[col] : 0u;
     };
-    // staging: four sub-bands at a time, up to two dwords of each per thread,
-    // all eight loads in flight before the LDS stores
-    for (int n0 = 0; n0 < nsb; n0 += 4) {
-        uint32_t v[4][2];
-        int at[4][2];
+    // staging: sixteen sub-bands at a time, up to two dwords of each per
+    // thread, all of a batch's loads in flight before its LDS stores
+    constexpr int SB = 16;
+    for (int n0 = 0; n0 < nsb; n0 += SB) {
+        uint32_t v[SB][2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < SB; ++u)
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                at[u][k] = -1;
                 v[u][k] = 0u;
                 if (n0 + u < nsb) {
                     const TreeStage g = st[n0 + u];
                     const int i = threadIdx.x + 256 * k;
-                    if (i < g.span * g.wdw) {
-                        v[u][k] = fetch(g, i);
-                        at[u][k] = g.lds + i;
-                    }
+                    if (i < g.span * g.wdw) v[u][k] = fetch(g, i);
                 }
             }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < SB; ++u)
 #pragma unroll
             for (int k = 0; k < 2; ++k)
-                if (at[u][k] >= 0) sl[at[u][k]] = v[u][k];
+                if (n0 + u < nsb) {
+                    const TreeStage g = st[n0 + u];
+                    const int i = threadIdx.x + 256 * k;
+                    if (i < g.span * g.wdw) sl[g.lds + i] = v[u][k];
+                }
     }
     // wider rows (more than 512 dwords of a sub-band)
     for (int n = 0; n < nsb; ++n) {
@@ -505,36 +532,60 @@ __global__ __launch_bounds__(256) void k_tree_combine_lds(BeamDesc b, const int3
         const int32_t* od = off + (size_t)d * nsb;
         const int o_lo = lane < nsb ? od[lane] : 0;
         const int o_hi = lane + 64 < nsb ? od[lane + 64] : 0;
-        uint32_t acc[4 * J];
+        // the four bytes at LDS byte offset o + 4 (64 j + lane) are outputs
+        // 256 j + 4 lane .. +3; one v_perm of the aligned dword pair picks
+        // bytes s, s+2 (s = o mod 4) into the 16-bit lanes of p[j], another
+        // bytes s+1, s+3 into q[j].  At most 128 terms of byte values: the
+        // 16-bit lanes never carry (128 * 255 < 2^16).
+        uint32_t p[J], q[J];
 #pragma unroll
-        for (int e = 0; e < 4 * J; ++e) acc[e] = 0u;
-        for (int n0 = 0; n0 < nsb; n0 += flush) {
-            const int n1 = min(nsb, n0 + flush);
-            uint32_t p[J], q[J];
+        for (int j = 0; j < J; ++j) p[j] = q[j] = 0u;
+        // C terms at a time (offsets o[0 .. C-1]): every LDS read of the
+        // group is issued before the first add
+        auto terms = [&](auto cnt, const int* o) {
+            constexpr int C = decltype(cnt)::value;
+            uint32_t w[C][J][2];
 #pragma unroll
-            for (int j = 0; j < J; ++j) p[j] = q[j] = 0u;
-            for (int n = n0; n < n1; ++n) {
-                const int o = __builtin_amdgcn_readlane(n < 64 ? o_lo : o_hi, n & 63);
-                const uint32_t* src = sl + (o >> 2) + lane;
-                const int sh = (o & 3) * 8;
+            for (int u = 0; u < C; ++u) {
+                const uint32_t* src = sl + (o[u] >> 2) + lane;
 #pragma unroll
                 for (int j = 0; j < J; ++j) {
-                    const uint32_t x = __builtin_amdgcn_alignbit(src[64 * j + 1], src[64 * j], sh);
-                    p[j] += x & 0x00FF00FFu;          // bytes 0, 2: outputs 4l, 4l+2
-                    q[j] += (x >> 8) & 0x00FF00FFu;   // bytes 1, 3: outputs 4l+1, 4l+3
+                    w[u][j][0] = src[64 * j];
+                    w[u][j][1] = src[64 * j + 1];
                 }
             }
 #pragma unroll
-            for (int j = 0; j < J; ++j) {
-                acc[4 * j] += p[j] & 0xFFFFu;
-                acc[4 * j + 1] += q[j] & 0xFFFFu;
-                acc[4 * j + 2] += p[j] >> 16;
-                acc[4 * j + 3] += q[j] >> 16;
+            for (int u = 0; u < C; ++u) {
+                // selectors: bytes (s, zero, s+2, zero) and (s+1, zero, s+3, zero)
+                const uint32_t sa = 0x0C020C00u + (uint32_t)(o[u] & 3) * 0x00010001u;
+                const uint32_t sb = sa + 0x00010001u;
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    p[j] += __builtin_amdgcn_perm(w[u][j][1], w[u][j][0], sa);
+                    q[j] += __builtin_amdgcn_perm(w[u][j][1], w[u][j][0], sb);
+                }
             }
-        }
+        };
+        // sub-bands n0 .. n1-1, offsets in lanes n - base of reg
+        auto range = [&](int reg, int base, int n0, int n1) {
+            constexpr int U = 4;
+            int n = n0;
+            for (; n + U <= n1; n += U) {
+                int o[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) o[u] = __builtin_amdgcn_readlane(reg, n - base + u);
+                terms(std::integral_constant<int, U>(), o);
+            }
+            for (; n < n1; ++n) {
+                const int o[1] = {__builtin_amdgcn_readlane(reg, n - base)};
+                terms(std::integral_constant<int, 1>(), o);
+            }
+        };
+        range(o_lo, 0, 0, nsb < 64 ? nsb : 64);
+        if (nsb > 64) range(o_hi, 64, 64, nsb);
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            const uint32_t a4[4] = {acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]};
+            const uint32_t a4[4] = {p[j] & 0xFFFFu, q[j] & 0xFFFFu, p[j] >> 16, q[j] >> 16};
             tree_store<4>(b, d, t0 + 256 * j + 4 * lane, a4);
         }
     }
@@ -545,9 +596,9 @@ __global__ __launch_bounds__(256) void k_tree_combine_lds(BeamDesc b, const int3
 int tree_tile(int nsub) { return tree_tile_len_b(nsub) > tree_tile_len(nsub) ? tree_tile_len_b(nsub) : tree_tile_len(nsub); }
 
 hipError_t launch_tree_combine_lds(const BeamDesc& d, const int32_t* blocks, int nblocks, const TreeStage* stage,
-                                   const int32_t* off, int lds_dwords, int flush, hipStream_t st)
+                                   const int32_t* off, int lds_dwords, hipStream_t st)
 {
-    if (d.nout <= 0 || d.ndm <= 0 || d.nact <= 0 || d.nact > 128 || nblocks <= 0 || nblocks > 65535 || flush < 1 ||
+    if (d.nout <= 0 || d.ndm <= 0 || d.nact <= 0 || d.nact > 128 || nblocks <= 0 || nblocks > 65535 ||
         lds_dwords <= 0 || (size_t)lds_dwords * 4 > (size_t)kMaxLdsBytes || (d.pitch & 3) ||
         (reinterpret_cast<uintptr_t>(d.xc) & 3) ||
         (reinterpret_cast<uintptr_t>(d.out) & (d.out_bytes == 4 ? 3 : d.out_bytes - 1)))
@@ -562,8 +613,7 @@ hipError_t launch_tree_combine_lds(const BeamDesc& d, const int32_t* blocks, int
     const int32_t* a1 = blocks;
     const TreeStage* a2 = stage;
     const int32_t* a3 = off;
-    int a4 = flush;
-    void* args[] = {&a0, &a1, &a2, &a3, &a4};
+    void* args[] = {&a0, &a1, &a2, &a3};
     return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)nblocks), dim3(256), args, lds, st);
 }
 
