@@ -270,6 +270,9 @@ dedisp_status dedisp_get_tile_config(dedisp_plan plan, dedisp_tile_config* cfg);
  * (the output is overwritten with a valid result), keep the fastest on the
  * plan, and if `cache_path` is not NULL read/update a JSON cache keyed by
  * (nbits, nchans, ndm, max_delay, nsamps bucket).  Synchronises `stream`.
+ * In sub-band mode each pass is tuned in turn, and where the sub-band sums
+ * fit a byte both widths of the intermediate sums (bytes, 16-bit values)
+ * are timed and the faster kept.
  * `best_ms` (nullable) receives the best time of one call. */
 dedisp_status dedisp_tune(dedisp_plan plan, const void* d_in, size_t nsamps,
                           uint32_t* d_out, size_t out_row_stride, void* stream,

@@ -65,6 +65,19 @@ void free_device(dedisp_plan p)
     p->d_mask = nullptr;
 }
 
+// Drop the cached DM-block tables (their window bases are aligned to the
+// scratch format's 16-byte pieces) before a plan's format changes.
+void drop_block_tables(dedisp_plan p)
+{
+    if (p->blocks.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto& kv : p->blocks) {
+        if (kv.second.d_rel) (void)hipFree(kv.second.d_rel);
+        if (kv.second.d_base) (void)hipFree(kv.second.d_base);
+    }
+    p->blocks.clear();
+}
+
 bool is_finite(double x) { return std::isfinite(x); }
 
 // Section 2.1: DeltaT(nu) = (k_DM/dtau) (1/(nu0 + nu dnu)^2 - 1/nu0^2) and
@@ -1243,7 +1256,9 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
         return rc;
     }
     if (p->sb_step1) {
-        // each pass in turn: time whole transforms over the pass's shapes
+        // each pass in turn: time whole transforms over the pass's shapes;
+        // where the sub-band sums fit a byte, for both intermediate widths
+        // (bytes read as 8-bit codes, 16-bit values), keeping the faster
         long long len1 = 0, nout = 0;
         subband_lengths(*p, nsamps, len1, nout);
         if (len1 <= 0 || nout <= 0) return fail(DEDISP_ERR_TOO_FEW_SAMPLES, "nsamps too short for the sub-band passes");
@@ -1251,52 +1266,82 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
         hipEvent_t e0, e1;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
-        float best_total = 0.f;
-        for (dedisp_plan q : {p->sb_step1, p->sb_step2}) {
-            float best = 1e30f;
-            dedisp_tile_config best_cfg = q->cfg;
-            for (int i = 0; i < dedisp::shape_count(); ++i) {
-                const Shape& s = dedisp::shape_at(i);
-                if (s.kind != 0 || !shape_matches(s, *q)) continue;
-                dedisp_tile_config c{};
-                c.kind = 0;
-                c.waves = s.waves;
-                c.dms_per_wave = s.dpw;
-                c.words_per_lane = s.m;
-                c.chunk_chans = s.cc;
-                LaunchPlan probe;
-                if (resolve_launch(q, c, false, probe) != DEDISP_OK || probe.shape_index != i) continue;
-                const dedisp_tile_config saved = q->cfg;
-                q->cfg = c;
-                dedisp_status rc = dedisp_execute(p, d_in, nsamps, d_out, stride, stream);
-                float ms = 0.f;
-                if (rc == DEDISP_OK) {
-                    HIP_TRY(hipEventRecord(e0, hs));
-                    for (int r = 0; r < 3 && rc == DEDISP_OK; ++r)
-                        rc = dedisp_execute(p, d_in, nsamps, d_out, stride, stream);
-                    HIP_TRY(hipEventRecord(e1, hs));
-                    HIP_TRY(hipEventSynchronize(e1));
-                    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                    ms /= 3;
+        dedisp_plan s1 = p->sb_step1, s2 = p->sb_step2;
+        auto tune_passes = [&](float& total) -> dedisp_status {
+            total = 0.f;
+            for (dedisp_plan q : {s1, s2}) {
+                float best = 1e30f;
+                dedisp_tile_config best_cfg = q->cfg;
+                for (int i = 0; i < dedisp::shape_count(); ++i) {
+                    const Shape& s = dedisp::shape_at(i);
+                    if (s.kind != 0 || !shape_matches(s, *q)) continue;
+                    dedisp_tile_config c{};
+                    c.kind = 0;
+                    c.waves = s.waves;
+                    c.dms_per_wave = s.dpw;
+                    c.words_per_lane = s.m;
+                    c.chunk_chans = s.cc;
+                    LaunchPlan probe;
+                    if (resolve_launch(q, c, false, probe) != DEDISP_OK || probe.shape_index != i) continue;
+                    const dedisp_tile_config saved = q->cfg;
+                    q->cfg = c;
+                    dedisp_status rc = dedisp_execute(p, d_in, nsamps, d_out, stride, stream);
+                    float ms = 0.f;
+                    if (rc == DEDISP_OK) {
+                        HIP_TRY(hipEventRecord(e0, hs));
+                        for (int r = 0; r < 3 && rc == DEDISP_OK; ++r)
+                            rc = dedisp_execute(p, d_in, nsamps, d_out, stride, stream);
+                        HIP_TRY(hipEventRecord(e1, hs));
+                        HIP_TRY(hipEventSynchronize(e1));
+                        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                        ms /= 3;
+                    }
+                    q->cfg = saved;
+                    if (rc != DEDISP_OK) return rc;
+                    if (ms < best) {
+                        best = ms;
+                        best_cfg = c;
+                    }
                 }
-                q->cfg = saved;
-                if (rc != DEDISP_OK) {
-                    (void)hipEventDestroy(e0);
-                    (void)hipEventDestroy(e1);
-                    return rc;
-                }
-                if (ms < best) {
-                    best = ms;
-                    best_cfg = c;
-                }
+                q->cfg = best_cfg;
+                // each timing is a whole transform: the last pass's best is
+                // the tuned transform's time
+                if (best < 1e29f) total = best;
             }
-            q->cfg = best_cfg;
-            // each timing is a whole transform: the last pass's best is the
-            // tuned transform's time
-            if (best < 1e29f) best_total = best;
+            return DEDISP_OK;
+        };
+        std::vector<int> fmts{s2->fmt};
+        if (s2->fmt == dedisp::kFmtByte) fmts.push_back(kFmtHalf);
+        else if (s2->fmt == kFmtHalf && s2->vbound <= 255) fmts.push_back(dedisp::kFmtByte);
+        float best_total = 0.f;
+        int best_fmt = s2->fmt;
+        dedisp_tile_config best1 = s1->cfg, best2 = s2->cfg;
+        dedisp_status rc = DEDISP_OK;
+        for (size_t k = 0; k < fmts.size() && rc == DEDISP_OK; ++k) {
+            if (k > 0) {
+                drop_block_tables(s2);
+                s2->fmt = fmts[k];
+                s1->cfg = default_config(s1->fmt);
+                s2->cfg = default_config(s2->fmt);
+            }
+            float total = 0.f;
+            rc = tune_passes(total);
+            if (rc == DEDISP_OK && (k == 0 || total < best_total)) {
+                best_total = total;
+                best_fmt = s2->fmt;
+                best1 = s1->cfg;
+                best2 = s2->cfg;
+            }
         }
+        if (s2->fmt != best_fmt) {
+            drop_block_tables(s2);
+            s2->fmt = best_fmt;
+        }
+        s1->cfg = best1;
+        s2->cfg = best2;
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        if (rc != DEDISP_OK) return rc;
         if (best_ms) *best_ms = best_total;
         return DEDISP_OK;
     }
@@ -1554,7 +1599,16 @@ dedisp_status dedisp_set_subband(dedisp_plan p, int nsub, int ngroup)
     // (padded with zero rows to a multiple of 8), delays of each sub-band's
     // first channel
     s2->nchans = nsb_p;
-    s2->fmt = vsum <= 24 ? kFmtByteS : kFmtHalf;
+    // intermediate sums: byte lanes with periodic flushes while a flush
+    // comes at most every 6 channels (1.5 + 8/6 VALU per channel and 4
+    // samples); else bytes spread to 16-bit lanes (the 8-bit code path: 3
+    // VALU, exact up to 255) or 16-bit values (also 3 VALU, twice the bytes
+    // through HBM and LDS).  The 8-bit shapes fill with 32 or more sub-bands
+    // and trials per nominal DM, so bytes are the default there; the tuner
+    // times both widths wherever sums fit a byte
+    s2->fmt = vsum <= 42                               ? kFmtByteS
+              : vsum <= 255 && nsb >= 32 && ngroup >= 32 ? dedisp::kFmtByte
+                                                         : kFmtHalf;
     s2->vbound = vsum;
     s2->ngroups = nnom;
     s2->dms.assign(ngroup, 0.0);

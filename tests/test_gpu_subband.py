@@ -1,8 +1,8 @@
 """GPU parity of sub-band dedispersion (Section 4) against the oracle, bit for bit.
 
 The library runs the corner turn, then step 1 (every sub-band at every
-nominal DM, one grouped launch of the tiled kernel writing 8- or 16-bit sums
-into an intermediate scratch) and step 2 (every nominal DM's trials over the
+nominal DM, one grouped launch of the tiled kernel writing byte or 16-bit
+sums into an intermediate scratch) and step 2 (every nominal DM's trials over the
 sub-band series, a second grouped launch).  Outputs are compared whole with
 the oracle's two-step definition.
 """
@@ -37,8 +37,10 @@ def _codes(rng, nsamps, nchans, nbits):
 
 
 @pytest.mark.parametrize("nbits,nchans,nsub,ngroup,ndm,nsamps", [
-    (2, 256, 8, 8, 70, 20011),      # 8-bit intermediate sums (at most 24)
-    (2, 256, 32, 16, 64, 16003),    # 16-bit intermediate sums
+    (2, 256, 8, 8, 70, 20011),      # byte-lane intermediate sums (at most 24)
+    (2, 256, 32, 16, 64, 16003),    # byte intermediate sums (at most 96) read as 8-bit codes
+    (2, 256, 16, 8, 48, 14009),     # byte intermediate sums (at most 48) read as 8-bit codes
+    (2, 512, 128, 8, 40, 16007),    # 16-bit intermediate sums (at most 384)
     (8, 128, 16, 5, 43, 15007),     # 8-bit codes: 16-bit sums, last group short
     (2, 192, 8, 4, 33, 17001),      # 24 sub-bands: zero padding rows in step 2
 ])
@@ -115,3 +117,30 @@ def test_survey_beam_subband_full_size(native, cuda):
     torch.cuda.synchronize()
     got = out.cpu().numpy().view(np.uint32)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("nchans,nsub,ngroup,ndm", [(512, 32, 8, 40), (1024, 32, 32, 96)])
+def test_subband_tuned_intermediate_width_bit_exact(native, cuda, nchans, nsub, ngroup, ndm):
+    """2-bit codes in 32-channel sub-bands give sums up to 96: the tuner times
+    both intermediate widths (bytes read as 8-bit codes, 16-bit values) and
+    keeps the faster, starting from 16-bit sums (16 sub-bands, 8 trials per
+    nominal DM) or from bytes (32 and 32).  The transform matches the oracle
+    before and after tuning."""
+    import torch
+    nbits, nsamps = 2, 24007
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    dms = synth.dm_list_linear(ndm, 400.0)
+    rng = np.random.default_rng(nchans + ngroup)
+    packed = synth.pack(_codes(rng, nsamps, nchans, nbits), nbits)
+    want = oracle.dedisperse_subband(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub, ngroup)
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms)
+    plan.set_subband(nsub, ngroup)
+    nout = want.shape[1]
+    width = nout + 3
+    assert np.array_equal(_run(plan, packed, nsamps, cuda, width)[:, :nout], want)
+    inp = torch.from_numpy(np.ascontiguousarray(packed.reshape(-1))).to(cuda)
+    out = torch.empty((plan.ndm, width), dtype=torch.int32, device=cuda)
+    assert plan.tune(inp, out, nsamps, out_row_stride=width) > 0
+    got = _run(plan, packed, nsamps, cuda, width)
+    assert np.array_equal(got[:, :nout], want)
+    assert np.all(got[:, nout:] == SENTINEL)
