@@ -608,12 +608,15 @@ double diagonal_dm(const dedisp_plan_s& p)
 }
 
 // Scratch format of a scrunch group: sums of up to 8 two-bit codes stay in
-// byte lanes (four samples per add); larger sums, and every 8-bit sum, in
-// 16-bit lanes.
+// byte lanes (four samples per add, flushed at least every 10 channels);
+// larger two-bit sums (at most 3*64 = 192) are bytes read through the 8-bit
+// code path (one v_perm spreads two bytes into 16-bit lanes), the same VALU
+// per sample as 16-bit scratch with half the bytes; 8-bit sums take 16 bits.
 int scrunch_format(int nbits, int s)
 {
     if (s == 1) return nbits == 2 ? kFmtNib : kFmtByte;
-    return (nbits == 2 && s <= 8) ? kFmtByteS : kFmtHalf;
+    if (nbits == 2) return s <= 8 ? kFmtByteS : kFmtByte;
+    return kFmtHalf;
 }
 
 constexpr int kMaxScrunch = 64;

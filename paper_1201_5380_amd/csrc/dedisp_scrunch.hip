@@ -149,7 +149,9 @@ hipError_t launch_scrunch(const BeamDesc& d, int nbits, int fmt, hipStream_t st)
     const long long gy = (d.nchans + sc - 1) / sc;
     if (gx <= 0 || gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidValue;
     const void* fn = nullptr;
-    if (nbits == 2 && fmt == kFmtByteS) fn = reinterpret_cast<const void*>(&k_scrunch<2, 1>);
+    // 2-bit sums as bytes: byte-lane (s <= 8) or 8-bit-code (s <= 85) scratch
+    if (nbits == 2 && (fmt == kFmtByteS || fmt == kFmtByte) && 3 * d.scrunch <= 255)
+        fn = reinterpret_cast<const void*>(&k_scrunch<2, 1>);
     else if (nbits == 2 && fmt == kFmtHalf) fn = reinterpret_cast<const void*>(&k_scrunch<2, 2>);
     else if (nbits == 8 && fmt == kFmtHalf) fn = reinterpret_cast<const void*>(&k_scrunch<8, 2>);
     if (!fn) return hipErrorInvalidValue;
