@@ -162,3 +162,23 @@ def test_tree_staged_and_gathered_blocks_in_one_transform(native, cuda):
     out = plan.execute(inp, nsamps)
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy().view(np.uint16), oracle.reduce_output(want, 16, 0))
+
+
+def test_tree_more_than_64_sub_bands_staged_and_gathered(native, cuda):
+    """80 sub-bands of 8 channels: each trial's offsets of sub-bands 64 .. 79
+    sit in the second register of both combine kernels.  64 dense, sorted
+    trials (two blocks whose rows fit LDS: staged) and 24 trials in shuffled
+    order across twice the diagonal (gathered), bit for bit against the
+    oracle."""
+    nbits, nchans, nsub, nsamps = 2, 640, 8, 30011
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    diag = _diag(nchans, nsub, dt, f_top, df)
+    rng = np.random.default_rng(80)
+    dms = np.concatenate([3.0 + 0.05 * np.arange(64), rng.permutation(np.linspace(0.0, 2.0 * diag, 24))])
+    codes = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+    codes[::31] = 3
+    packed = synth.pack(codes, nbits)
+    want = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub)
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms).set_tree(nsub)
+    assert np.all(plan.output_lengths(nsamps) == want.shape[1])
+    assert np.array_equal(_run(plan, packed, nsamps, cuda), want)
