@@ -21,8 +21,10 @@ against things other than itself:
   closed form, every factor group against the push brute force at s times
   the sampling time, DM 0 against the s-sums of the plain channel sum, the
   impulse response, and time-shift equivariance by whole scrunched samples;
-* sub-band dedispersion (Section 4): the two-step result against the push
-  brute force at the composed delays it takes each sample at, the two
+* sub-band dedispersion (Section 4): the whole result, its length included,
+  against two chained calls of the direct oracle (one per sub-band, then one
+  per nominal DM over the miniature filterbank), the two-step result against
+  the push brute force at the composed delays it takes each sample at, the two
   reductions to the direct transform (one trial per nominal DM, one channel
   per sub-band), the delay error within Appendix B's smearing bound (and
   zero at nominal trials), the kill mask, and a pulse on a nominal trial's
@@ -34,7 +36,8 @@ against things other than itself:
   full-band tree against the push brute force at those delays (DM 0 = the
   channel sum); the piecewise linear tree against the brute force at its
   composed delays, within Appendix A's bound, and with one sub-band reducing
-  to picking a tree row;
+  to picking a tree row; its length from the shapes of its stage-1 passes
+  and a direct transform per trial over the rows it combines;
 * the reduced output bit depth by its invariants.
 """
 from fractions import Fraction
@@ -586,6 +589,54 @@ def test_subband_is_direct_sum_at_composed_delays(nbits, nsub, ngroup):
     assert np.array_equal(got.astype(np.int64), bf[:, :nout])
 
 
+def _sub_packed(codes, nbits, c0, c1):
+    """The packed input of channels [c0, c1) alone (a filterbank of its own)."""
+    return synth.pack(np.ascontiguousarray(codes[:, c0:c1]), nbits)
+
+
+@pytest.mark.parametrize("nbits,nsub,ngroup", [(2, 8, 4), (8, 16, 5), (2, 32, 8), (8, 4, 3), (2, 16, 1)])
+def test_subband_is_two_chained_direct_transforms(nbits, nsub, ngroup):
+    """Section 4 builds the sub-band method from two calls of the direct
+    routine.  Step 1: each sub-band alone is a filterbank of nsub channels,
+    dedispersed by the direct oracle at every nominal DM with the delays
+    relative to the sub-band's first channel.  Step 2: for each nominal DM, the
+    sub-band series form a miniature filterbank of nsb channels, dedispersed by
+    the direct oracle at the trials of its group with the delay of each
+    sub-band's first channel.  Every direct call keeps only its fully covered
+    outputs; series of different lengths are cut to the shortest before they
+    are stacked, and the rows of different groups likewise.  The whole result,
+    its length included, must be the sub-band oracle's."""
+    codes, prm, dms = _subband_case(300 + nsub + ngroup, nbits)
+    nsamps, nchans = codes.shape
+    nsb = nchans // nsub
+    tab, _ = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], dms)
+    nom = dms[::ngroup]
+    tnom, _ = oracle.delay_table(nchans, prm["dt"], prm["f_top"], prm["df"], nom)
+    # step 1: one direct transform per sub-band, rows = nominal DMs
+    series = []
+    for n in range(nsb):
+        c0 = n * nsub
+        rel = np.ascontiguousarray(tnom[:, c0:c0 + nsub] - tnom[:, c0:c0 + 1])
+        series.append(oracle.dedisperse(_sub_packed(codes, nbits, c0, c0 + nsub), nsamps, nsub,
+                                        nbits, rel))
+    len1 = min(s.shape[1] for s in series)
+    # step 2: one direct transform per nominal DM over its miniature filterbank
+    rows = []
+    for m in range(len(nom)):
+        x = np.stack([series[n][m, :len1] for n in range(nsb)], axis=1)   # [len1][nsb]
+        trials = list(range(m * ngroup, min((m + 1) * ngroup, len(dms))))
+        t2 = np.ascontiguousarray(tab[trials][:, ::nsub])
+        rows.append(oracle.dedisperse_values(x, t2))
+    nout = min(r.shape[1] for r in rows)
+    want = np.concatenate([r[:, :nout] for r in rows], axis=0)
+    got = oracle.dedisperse_subband(synth.pack(codes, nbits), nsamps, nchans, nbits, prm["dt"],
+                                    prm["f_top"], prm["df"], dms, nsub, ngroup)
+    assert got.shape == want.shape == (len(dms), nout)
+    assert np.array_equal(got, want)
+    # the lengths the oracle reports are those of the chained calls
+    assert oracle.subband_lengths(nsamps, nchans, nsub, tnom, tab) == (len1, nout)
+
+
 @pytest.mark.parametrize("nbits", [2, 8])
 def test_subband_reduces_to_direct(nbits):
     """One trial per group (every trial its own nominal DM) or one channel per
@@ -902,6 +953,39 @@ def test_piecewise_tree_beyond_the_diagonal_is_the_composed_direct_sum():
                                             prm["df"], dms[lo], nsub)
     m = min(base.shape[1], out.shape[1])
     assert np.array_equal(base[:, :m], out[lo][:, :m])
+
+
+@pytest.mark.parametrize("nsub,factor", [(16, 3.5), (8, 0.9), (32, 2.2)])
+def test_piecewise_tree_length_from_its_passes(nsub, factor):
+    """The tree's output length follows from its parts, not from a formula:
+    stage 1 is the set of passes tree_imposed(p) for p up to the largest pass a
+    trial uses (each pass's shape is pinned against the push brute force);
+    stage 2 (eq. combining_subbands) is, per trial, a direct transform of the
+    miniature filterbank of the rows it takes, one per sub-band, cut to the
+    shortest pass, whose fully covered outputs end at the trial's largest
+    dt''.  The rows of all trials share the shortest such length."""
+    nsamps = 2600
+    nchans, prm, diag, dms = _beyond_case(nsub, factor, ndm=14)
+    rng = np.random.default_rng(61 + nsub)
+    codes = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+    packed = synth.pack(codes, 2)
+    k = int(nsub).bit_length() - 1
+    dp, dd = oracle.tree_dm_tables(nchans, prm["dt"], prm["f_top"], prm["df"], nsub, dms)
+    used = sorted(set(int(v) // nsub for v in dp.reshape(-1)))
+    passes = {p: (oracle.tree(packed, nsamps, nchans, 2, k) if p == 0 else
+                  oracle.tree_imposed(packed, nsamps, nchans, 2, k, p)) for p in range(max(used) + 1)}
+    len1 = min(passes[p].shape[1] for p in passes)
+    rows = []
+    for d in range(len(dms)):
+        x = np.stack([passes[int(dp[d, n]) // nsub][n * nsub + int(dp[d, n]) % nsub, :len1]
+                      for n in range(nchans // nsub)], axis=1)             # [len1][nsb]
+        rows.append(oracle.dedisperse_values(x, dd[d:d + 1]))
+    nout = min(r.shape[1] for r in rows)
+    want = np.concatenate([r[:, :nout] for r in rows], axis=0)
+    got = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, 2, prm["dt"], prm["f_top"],
+                                           prm["df"], dms, nsub)
+    assert got.shape == want.shape == (len(dms), nout)
+    assert np.array_equal(got, want)
 
 
 def test_piecewise_tree_finds_a_pulse_beyond_the_diagonal():
