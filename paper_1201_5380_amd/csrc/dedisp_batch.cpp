@@ -6,7 +6,6 @@
 #include "dedisp_host.h"
 
 #include <algorithm>
-#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -17,14 +16,6 @@ using namespace dedisp::host;
 
 namespace dedisp {
 namespace host {
-
-// DEDISP_PERSISTENT_LOOP=1 selects the looping persistent kernel instead of
-// the one-workgroup-per-item multi-beam kernel (for comparison).
-static bool use_persistent_loop()
-{
-    const char* v = std::getenv("DEDISP_PERSISTENT_LOOP");
-    return v && v[0] == '1';
-}
 
 hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st)
 {
@@ -68,16 +59,7 @@ hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st)
                 blk.d[i - g0] = d;
             }
             if (total > 0x7fffffffLL) return hipErrorInvalidValue;
-            hipError_t e;
-            if (cls == 1 && use_persistent_loop()) {
-                const int maxg = persistent_max_grid(lds);
-                if (maxg <= 0) return hipErrorInvalidValue;
-                const int grid = static_cast<int>(std::min<long long>(total, maxg));
-                e = launch_persistent(blk, static_cast<int>(g1 - g0), static_cast<int>(total), lds,
-                                      grid, st);
-            } else {
-                e = launch_multi(blk, static_cast<int>(g1 - g0), static_cast<int>(total), lds, cls, st);
-            }
+            hipError_t e = launch_multi(blk, static_cast<int>(g1 - g0), static_cast<int>(total), lds, cls, st);
             if (e != hipSuccess) return e;
         }
     }

@@ -169,9 +169,5 @@ hipError_t launch_unpack_multi(const DescBlock& blk, int nbeams, hipStream_t st)
 // beams' multi-beam class).
 hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int lds_bytes, int cls,
                         hipStream_t st);
-// Grid sized to the machine, workgroups looping over the items (class 1).
-hipError_t launch_persistent(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
-                             int grid, hipStream_t st);
-int persistent_max_grid(int lds_bytes);
 
 }  // namespace dedisp

@@ -48,7 +48,7 @@
 // packed input directly.  Used when a DM block's delay spread is too large
 // for LDS (e.g. a DM list with huge gaps) or the input is misaligned.
 //
-// Multi-beam kernels (k_multi, k_persistent): one launch over the (beam,
+// Multi-beam kernel (k_multi): one launch over the (beam,
 // time tile, DM block) work items of up to 16 beams that may differ in
 // channel count, bit depth, length, DM list and tile shape.
 #include "dedisp_device.h"
@@ -841,18 +841,6 @@ __global__ __launch_bounds__(multi_waves(CLASS) * 64) __attribute__((amdgpu_wave
     run_item<CLASS>(blk, nbeams, (int)blockIdx.x, lds_dyn);
 }
 
-// Persistent variant: a grid sized to the machine; workgroup g takes items
-// g, g + grid, ...
-__global__ __launch_bounds__(kMultiWaves * 64) void k_persistent(DescBlock blk, int nbeams,
-                                                                       int total)
-{
-    extern __shared__ uint32_t lds_dyn[];
-    for (int item = blockIdx.x; item < total; item += gridDim.x) {
-        run_item<1>(blk, nbeams, item, lds_dyn);
-        __syncthreads();                     // LDS is reused by the next item
-    }
-}
-
 bool g_attr_done[kNumShapes + 1] = {};
 
 hipError_t ensure_lds_attr(int idx, const void* fn)
@@ -965,22 +953,6 @@ hipError_t launch_untiled(const BeamDesc& d, int nbits, hipStream_t st)
     return hipLaunchKernel(fn, dim3((unsigned)gx, gy), dim3(256), args, 0, st);
 }
 
-int persistent_max_grid(int lds_bytes)
-{
-    int dev = 0, ncu = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return 0;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persistent),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&k_persistent), kMultiWaves * 64,
-            (size_t)lds_bytes) != hipSuccess)
-        return 0;
-    if (per_cu < 1) per_cu = 1;
-    return ncu * per_cu;
-}
-
 hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int lds_bytes, int cls,
                         hipStream_t st)
 {
@@ -995,23 +967,6 @@ hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int ld
     int a2 = total_work;
     void* args[] = {&a0, &a1, &a2};
     return hipLaunchKernel(fn, dim3(total_work), dim3(multi_waves(cls) * 64), args, (size_t)lds_bytes, st);
-}
-
-hipError_t launch_persistent(const DescBlock& blk, int nbeams, int total_work, int lds_bytes,
-                             int grid, hipStream_t st)
-{
-    if (grid <= 0 || nbeams <= 0 || nbeams > kMaxBatchDescs || total_work <= 0)
-        return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_persistent),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       kMaxLdsBytes);
-    if (e != hipSuccess) return e;
-    DescBlock a0 = blk;
-    int a1 = nbeams;
-    int a2 = total_work;
-    void* args[] = {&a0, &a1, &a2};
-    return hipLaunchKernel(reinterpret_cast<const void*>(&k_persistent), dim3(grid),
-                           dim3(kMultiWaves * 64), args, (size_t)lds_bytes, st);
 }
 
 }  // namespace dedisp

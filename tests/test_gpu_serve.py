@@ -1,7 +1,7 @@
 """The streaming service on the GPU: every request's output is bit-identical
 whether its stream runs alone (one push per chunk, nothing else on the
 device) or in the mix (continuous batching with other streams' chunks in the
-same persistent launches); one stream is also checked against the oracle."""
+same multi-beam launches); one stream is also checked against the oracle."""
 import time
 
 import numpy as np
