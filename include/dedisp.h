@@ -319,6 +319,14 @@ dedisp_status dedisp_stream_push_many(dedisp_stream* streams, const void* const*
  * no work of the stream is in flight.  Errors: INVALID_ARG, OOM. */
 dedisp_status dedisp_stream_reserve(dedisp_stream s, size_t max_chunk);
 
+/* Device memory the stream holds between pushes (the benchmark spec serving form:
+ * admission by HBM budget): its two history buffers of max(1, max_delay)
+ * packed rows each plus its channel-major scratch as currently sized
+ * (dedisp_stream_reserve sizes it for the longest chunk).  The chunk and the
+ * outputs of a push are the caller's and are not counted.  Host-only; errors:
+ * INVALID_ARG (NULL argument). */
+dedisp_status dedisp_stream_get_device_bytes(dedisp_stream s, size_t* bytes);
+
 /* Rows currently held as history, and total rows pushed since creation or
  * the last reset / set_history. */
 dedisp_status dedisp_stream_get_state(dedisp_stream s, size_t* history_rows,

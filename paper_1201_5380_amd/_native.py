@@ -80,6 +80,7 @@ SIGNATURES = {
     "dedisp_stream_push_many": (_i, [ctypes.POINTER(_vp), ctypes.POINTER(_vp), _psz,
                                      ctypes.POINTER(_vp), _psz, _psz, _i, _vp]),
     "dedisp_stream_get_state": (_i, [_vp, _psz, _pu64]),
+    "dedisp_stream_get_device_bytes": (_i, [_vp, _psz]),
     "dedisp_stream_get_history": (_i, [_vp, _vp, _psz]),
     "dedisp_stream_set_history": (_i, [_vp, _vp, _sz, _u64]),
     "dedisp_stream_reset": (_i, [_vp]),

@@ -254,6 +254,13 @@ class Stream:
                                        _stream_handle(stream)), "dedisp_stream_push")
         return int(n_out.value), out
 
+    def device_bytes(self) -> int:
+        """Device memory the stream holds between pushes: history + scratch."""
+        n = ctypes.c_size_t()
+        check(lib().dedisp_stream_get_device_bytes(self._h, ctypes.byref(n)),
+              "dedisp_stream_get_device_bytes")
+        return int(n.value)
+
     def state(self):
         h = ctypes.c_size_t()
         t = ctypes.c_uint64()

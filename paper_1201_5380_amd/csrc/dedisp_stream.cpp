@@ -232,6 +232,14 @@ dedisp_status dedisp_stream_push_many(dedisp_stream* streams, const void* const*
     return DEDISP_OK;
 }
 
+dedisp_status dedisp_stream_get_device_bytes(dedisp_stream s, size_t* bytes)
+{
+    if (!s || !bytes) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
+    const size_t hist = std::max<size_t>(1, static_cast<size_t>(s->max_delay)) * s->row_bytes;
+    *bytes = 2 * hist + s->xc.bytes;
+    return DEDISP_OK;
+}
+
 dedisp_status dedisp_stream_get_state(dedisp_stream s, size_t* history_rows, uint64_t* total_rows)
 {
     if (!s || !history_rows || !total_rows) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");

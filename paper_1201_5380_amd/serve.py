@@ -104,8 +104,14 @@ class GpuExecutor:
         self._reserve()
 
     def request_bytes(self, stream_id: int, nsamps: int) -> int:
+        """Device bytes a request holds while admitted: its chunk and its outputs."""
         p = self.plans[stream_id]
         return nsamps * p.row_bytes + p.ndm * nsamps * 4
+
+    def resident_bytes(self) -> int:
+        """Device bytes held whatever is admitted: every stream's history and
+        channel-major scratch (as reserved for max_chunk)."""
+        return sum(s.device_bytes() for s in self.streams)
 
     def launch(self, reqs):
         """Enqueue one tick; returns an object whose wait() blocks until it is done."""
@@ -154,7 +160,13 @@ class Server:
         self._launching = 0                       # ticks taken from the queues, not yet in flight
         self.callback_errors = []                 # (request, repr of what on_done raised)
         self.nstreams = int(nstreams)
-        self.budget = int(budget_bytes)
+        # The budget bounds all device memory of the service: what the streams
+        # hold between requests (history and scratch) is charged up front, the
+        # rest is shared by the admitted requests.
+        self.total_budget = int(budget_bytes)
+        self.resident = 0
+        self.budget = 0
+        self._charge_resident()
         self.max_tick = int(max_tick)
         self.max_inflight = int(max_inflight_ticks)
         self.admit_timeout = admit_timeout_s
@@ -169,6 +181,14 @@ class Server:
         self._lock = threading.Condition()
         self._stop = False
         self._threads = []
+
+    def _charge_resident(self):
+        res = getattr(self.ex, "resident_bytes", None)
+        self.resident = int(res()) if res is not None else 0
+        self.budget = self.total_budget - self.resident
+        if self.budget <= 0:
+            raise ValueError(f"the streams' resident device memory ({self.resident} bytes) "
+                             f"leaves nothing of the {self.total_budget}-byte budget")
 
     # -------------------------------------------------------------- client
     def submit(self, stream_id: int, data: np.ndarray, seq: int | None = None,
@@ -206,6 +226,9 @@ class Server:
             return False
 
     def start(self):
+        # the executor may have re-reserved its streams' scratch (tuning)
+        with self._lock:
+            self._charge_resident()
         self._threads = [threading.Thread(target=self._schedule, daemon=True),
                          threading.Thread(target=self._complete, daemon=True)]
         for t in self._threads:
@@ -342,4 +365,7 @@ class Server:
             "latency_p99_s": float(np.percentile(lat, 99)),
             "latency_max_s": float(lat.max()),
             "peak_budget_bytes": self.peak_used,
+            "resident_bytes": self.resident,
+            "peak_device_bytes": self.resident + self.peak_used,
+            "budget_bytes": self.total_budget,
         }

@@ -120,6 +120,44 @@ def test_budget_never_exceeded_and_requests_wait():
     assert srv.used == 0
 
 
+class ResidentExecutor(FakeExecutor):
+    """A fake executor whose streams hold device memory between requests."""
+
+    def __init__(self, plans, resident, **kw):
+        super().__init__(plans, **kw)
+        self.resident = resident
+
+    def resident_bytes(self):
+        return self.resident
+
+
+def test_budget_counts_the_streams_resident_memory():
+    """History and scratch the streams hold are charged before any request:
+    with them, only one request fits where two would fit without."""
+    plans = _plans()
+    ex = ResidentExecutor(plans, resident=0, service_s=0.02)
+    one = ex.request_bytes(0, 100)
+    resident = one // 2
+    ex.resident = resident
+    srv = Server(ex, len(plans), budget_bytes=2 * one + 1, max_tick=4).start()
+    assert srv.budget == 2 * one + 1 - resident
+    data = np.zeros((100, plans[0].row_bytes), np.uint8)
+    reqs = [srv.submit(0, data) for _ in range(2)] + [srv.submit(1, np.zeros((100, plans[1].row_bytes), np.uint8))]
+    srv.drain(timeout=30)
+    srv.stop()
+    assert all(r.status == DONE for r in reqs)
+    st = srv.stats()
+    assert st["resident_bytes"] == resident
+    assert st["peak_device_bytes"] == resident + srv.peak_used <= 2 * one + 1
+    # two requests of stream 0 never ran side by side: one plus the resident bytes fill the budget
+    assert srv.peak_used < 2 * one
+    # a chunk that fits the whole budget but not what the streams leave is rejected
+    srv2 = Server(ResidentExecutor(plans, resident=one), len(plans), budget_bytes=2 * one - 1)
+    assert srv2.submit(0, data).status == REJECTED
+    with pytest.raises(ValueError):
+        Server(ResidentExecutor(plans, resident=10**6), len(plans), budget_bytes=10**6)
+
+
 def test_rejections():
     plans = _plans()
     srv = Server(FakeExecutor(plans), len(plans), budget_bytes=10**6)
