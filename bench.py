@@ -25,30 +25,119 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X peaks used for the roofline: 256 CUs x 64 int32 lane-adds/clock x
-# 2.4 GHz (one VALU add per lane per clock) and 8 TB/s HBM3E.
-INT_ADD_PEAK_TADDS = 256 * 64 * 2.4e9 / 1e12
-# the sources the tiled kernel is compiled from (their digest keys the
-# committed HBM-traffic counters to the code they were taken on)
-KERNEL_SOURCES = ("dedisp_kernels.hip", "dedisp_device.h")
+# MI355X peaks used for the roofline.  VALU: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 39.32 T 32-bit lane operations/s (a wave64 instruction occupies a
+# SIMD for 4 cycles).  The sums are exact integer adds in packed lanes
+# (Section 2.3, bit-level parallelism): a 32-bit lane operation can add at
+# most eight 2-bit codes (4-bit lanes) or two 8-bit codes (16-bit lanes), so
+# the ALU roofline in channel-adds/s is 8x (2-bit) or 2x (8-bit) the lane-op
+# rate.  HBM3E: 8 TB/s.
+VALU_LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
+SIMDS = 256 * 4
+XCDS = 8
+ADDS_PER_LANE_OP = {2: 8, 8: 2}
 HBM_PEAK_GBS = 8000.0
+# the sources the tiled kernel is compiled from (their digest keys the
+# committed counters to the code they were taken on)
+KERNEL_SOURCES = ("dedisp_kernels.hip", "dedisp_device.h")
+
+
+def alu_peak_tadds(nbits):
+    return ADDS_PER_LANE_OP[nbits] * VALU_LANE_OPS_PER_S / 1e12
+
+
+def kernel_source_sha():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1201_5380_amd", "csrc")
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def counters_for(path, workload, tile):
+    """The committed rocprofv3 counter entry for this workload and tile shape,
+    if it was taken on the current kernel sources (else None)."""
+    try:
+        entries = json.load(open(path)).get("entries", [])
+    except (OSError, ValueError):
+        return None
+    sha = kernel_source_sha()
+    for e in entries:
+        if e.get("workload") == workload and e.get("tile") == tile and e.get("kernel_source_sha256") == sha:
+            return e
+    return None
+
+
+def roofline_block(nbits, adds, kernel_ms, ctr):
+    """Roofline of the dominant kernel: achieved channel-adds/s against the ALU
+    peak of the lanes the adds run in; HBM bytes and VALU issue from counters."""
+    achieved = adds / (kernel_ms * 1e-3) / 1e12
+    peak = alu_peak_tadds(nbits)
+    blk = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tadd/s",
+           "frac": achieved / peak, "traffic": None, "valu_issue": None, "lds_busy": None,
+           "counters_kernel_us": None}
+    if ctr:
+        blk["traffic"] = ctr.get("hbm_bytes_per_launch")
+        cyc = ctr.get("grbm_gui_active")             # summed over the XCDs
+        if cyc:
+            per_xcd = cyc / XCDS
+            blk["valu_issue"] = ctr["sq_insts_valu"] * 4 / (SIMDS * per_xcd)
+            if ctr.get("sq_lds_idx_active"):
+                blk["lds_busy"] = ctr["sq_lds_idx_active"] / (per_xcd * 256)   # per CU cycle
+            blk["counters_kernel_us"] = per_xcd / 2.4e3
+        blk["counters_kernel"] = ctr.get("kernel")
+    return blk
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cpus": os.cpu_count()}
+
+
+def gpu_info(torch):
+    prop = torch.cuda.get_device_properties(0)
+    info = {"name": prop.name, "arch": getattr(prop, "gcnArchName", None),
+            "compute_units": prop.multi_processor_count, "sclk_mhz": None}
+    # current shader clock from the driver's DPM table, where readable
+    import glob
+    for f in glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"):
+        try:
+            for line in open(f):
+                if line.strip().endswith("*"):
+                    info["sclk_mhz"] = line.split(":")[1].strip().rstrip("*").strip()
+        except OSError:
+            continue
+        if info["sclk_mhz"]:
+            break
+    return info
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    # the paper's protocol (Section 5.2): repeated runs, median and 5th/95th percentiles
+    ap.add_argument("--steps", type=int, default=101)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nsamps", type=int, default=1 << 19)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile shape")
     ap.add_argument("--tile", default=None,
                     help="waves,dms_per_wave,words_per_lane,chunk_chans: use this shape, no tuning")
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--large-tile", default=None,
+                    help="waves,dms_per_wave,words_per_lane,chunk_chans for the large beam: no tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget for the oracle baseline")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"),
-                    help="HBM bytes per launch measured by rocprofv3 counters, if present")
+    ap.add_argument("--counters-json", default=os.path.join(ROOT, "profiles", "counters.json"),
+                    help="rocprofv3 counters per launch (HBM bytes, VALU instructions), if present")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-systems", action="store_true",
@@ -68,7 +157,7 @@ def bench_batch(torch, dev, steps):
         plan = Plan(prm["nchans"], prm["dt"], prm["f_top"], prm["df"], prm["nbits"]).set_dm_list(
             synth.dm_list_linear(prm["ndm"], prm["dm_max"]))
         n = prm["nsamps"]
-        inp = synth.device_codes(n, prm["nchans"], prm["nbits"], seed=b, device=dev)
+        inp = torch.from_numpy(synth.batch_beam(b).packed().reshape(-1)).to(dev)
         out = torch.empty((plan.ndm, n - plan.max_delay), dtype=torch.int32, device=dev)
         beams.append((plan, inp, n, out, 0))
         outputs += plan.ndm * (n - plan.max_delay)
@@ -292,32 +381,47 @@ def bench_tiny(torch, dev, reps=200):
             "outputs_per_s": plan.ndm * nout / (float(np.median(ms)) * 1e-3), "tile": plan.tile_config()}
 
 
-def bench_large(torch, dev, steps):
+def bench_large(torch, dev, steps, counters_json, tile=None):
     """The large 8-bit beam: 2^20 samples x 4096 channels of 54.6 us,
-    f_top 1500 MHz, df -0.09765625 MHz, 2048 DMs in [0, 2000); input made on
-    the device (seeded rint(N(128, 20)) clipped to [0, 255])."""
+    f_top 1500 MHz, df -0.09765625 MHz, 2048 DMs in [0, 2000); seeded
+    rint(N(128, 20)) noise clipped to [0, 255] made on the host."""
     from paper_1201_5380_amd import Plan, synth
-    nsamps, nchans, ndm = 1 << 20, 4096, 2048
-    plan = Plan(nchans, 54.6e-6, 1500.0, -0.09765625, 8).set_dm_list(synth.dm_list_linear(ndm, 2000.0))
-    inp = synth.device_codes(nsamps, nchans, 8, seed=2, device=dev, sd=20.0).view(-1)
+    t0 = time.perf_counter()
+    b = synth.large_beam()
+    packed = b.packed()
+    sha = synth.sha256(packed)
+    gen_s = time.perf_counter() - t0
+    nsamps, nchans, ndm = b.nsamps, b.nchans, len(b.dms)
+    plan = Plan(nchans, b.dt, b.f_top, b.df, 8).set_dm_list(b.dms)
+    inp = torch.from_numpy(packed.reshape(-1)).to(dev)
+    del b, packed
     nout = nsamps - plan.max_delay
     out = torch.empty((ndm, nout), dtype=torch.int32, device=dev)
-    plan.tune(inp, out, nsamps)
+    if tile:
+        w, dpw, m, cc = (int(x) for x in tile.split(","))
+        plan.set_tile_config(dict(kind=0, waves=w, dms_per_wave=dpw, words_per_lane=m, chunk_chans=cc))
+    else:
+        plan.tune(inp, out, nsamps)
     plan.execute(inp, nsamps, out=out)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
-    e0.record()
-    for _ in range(steps):
-        plan.execute(inp, nsamps, out=out)
-    e1.record()
+    for e0, e1 in ev:
+        e0.record(stream)
+        plan.execute(inp, nsamps, out=out, stream=stream)
+        e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
-    adds = ndm * nout * nchans / (ms * 1e-3)
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    med = float(np.median(ms))
+    adds = ndm * nout * nchans
+    cfg = plan.tile_config()
     return {"workload": "large beam: 8-bit, 4096 ch, 1048576 samples x 54.6 us, 2048 DMs in [0, 2000), "
                         "f_top 1500 MHz, df -0.09765625 MHz",
-            "ms": ms, "nout": nout, "outputs_per_s": ndm * nout / (ms * 1e-3),
-            "channel_adds_per_s": adds, "alu_frac": adds / (INT_ADD_PEAK_TADDS * 1e12),
-            "tile": plan.tile_config()}
+            "ms": med, "ms_p5": float(np.percentile(ms, 5)), "ms_p95": float(np.percentile(ms, 95)),
+            "runs": steps, "nout": nout, "outputs_per_s": ndm * nout / (med * 1e-3),
+            "channel_adds_per_s": adds / (med * 1e-3),
+            "roofline": roofline_block(8, adds, med, counters_for(counters_json, "large-8bit-4096ch", cfg)),
+            "input_sha256": sha, "input_gen_s": gen_s, "tile": cfg}
 
 
 def bench_serve(torch, dev, seconds):
@@ -375,7 +479,7 @@ def bench_serve(torch, dev, seconds):
     open_loop = run(True)
     offs[:] = [(s * 7919) % (1 << 19) for s in range(nstreams)]
     lens.update({s: list(synth.stream_chunk_lengths(s, narr)) for s in range(nstreams)})
-    chunk_lens = [int(lens[int(s)][k]) for k, s in enumerate(_per_stream_index(sids))]
+    chunk_lens = [int(lens[int(s)][k]) for s, k in zip(sids, _per_stream_index(sids))]
     saturated = run(False)
     saturated["plain_same_chunks_outputs_per_s"] = plain_same_chunks(torch, dev, plan, chunk_lens)
     return {"workload": "32 streams x 2-bit 1024 ch, 1024 DMs in [0, 1000); chunks U[2^14, 2^18] "
@@ -432,6 +536,7 @@ def cpu_baseline(packed, nsamps, nchans, nbits, table, budget_s):
     oracle.dedisperse(packed, nsamps, nchans, nbits, table[:k], max_delay=mx)
     dt = time.perf_counter() - t0
     return {"value": k * nout / dt, "unit": "outputs/s", "cores": threads, "kind": "oracle",
+            "cpu_model": host_info()["cpu_model"],
             "sample": f"first {k} of {ndm} DM rows x all {nout} output samples "
                       f"({k * nout * nchans:.3g} channel-adds) in {dt:.2f} s",
             "adds_per_s": k * nout * nchans / dt}
@@ -513,26 +618,12 @@ def main():
     adds = outputs * nchans
     mean_ms = float(kern_ms.mean())
     ms_per_step = wall * 1e3 / args.steps
-    achieved_tadds = adds / (mean_ms * 1e-3) / 1e12
     alg_bytes = nsamps * nchans * beam.nbits // 8 + 4 * outputs + 4 * ndm * nchans
-    # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE /
-    # WRITE_SIZE counters (profiles/traffic.json), only while the kernel source
-    # and the tile shape are the ones the counters were taken on.
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            import hashlib
-            tj = json.load(open(args.traffic_json))
-            csrc = os.path.join(ROOT, "paper_1201_5380_amd", "csrc")
-            h = hashlib.sha256()
-            for f in KERNEL_SOURCES:
-                h.update(open(os.path.join(csrc, f), "rb").read())
-            sha = h.hexdigest()
-            if (tj.get("workload") == beam.name and tj.get("tile") == cfg
-                    and tj.get("kernel_source_sha256") == sha):
-                traffic = tj.get("hbm_bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
+    # counters of the dominant kernel (HBM bytes from rocprofv3 FETCH_SIZE /
+    # WRITE_SIZE, VALU issue from SQ_INSTS_VALU and GRBM_GUI_ACTIVE), only while
+    # the kernel source and the tile shape are the ones they were taken on
+    ctr = counters_for(args.counters_json, beam.name, cfg)
+    med_ms = float(np.median(kern_ms))
 
     result = {
         "metric": "dedispersed outputs/s (DM x sample)",
@@ -553,34 +644,31 @@ def main():
             "nsamps": nsamps, "nchans": nchans, "nbits": beam.nbits, "ndm": ndm,
             "max_delay": mx, "nout": nout, "tile": cfg,
         },
-        "kernel_ms": {"mean": mean_ms, "median": float(np.median(kern_ms)),
+        "kernel_ms": {"runs": args.steps, "mean": mean_ms, "median": med_ms,
                       "p5": float(np.percentile(kern_ms, 5)),
                       "p95": float(np.percentile(kern_ms, 95))},
-        "channel_adds_per_s": adds / (mean_ms * 1e-3),
-        "realtime_factor": nsamps * beam.dt / (mean_ms * 1e-3),
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved_tadds,
-            "peak": INT_ADD_PEAK_TADDS,
-            "unit": "Tadd/s",
-            "frac": achieved_tadds / INT_ADD_PEAK_TADDS,
-            "traffic": traffic,
-        },
+        "channel_adds_per_s": adds / (med_ms * 1e-3),
+        "realtime_factor": nsamps * beam.dt / (med_ms * 1e-3),
+        "roofline": roofline_block(beam.nbits, adds, mean_ms, ctr),
         "hbm_algorithmic_GBs": alg_bytes / (mean_ms * 1e-3) / 1e9,
+        "hbm_algorithmic_bytes": alg_bytes,
         "pulses_recovered": bool(pulses_ok),
         "tune_best_ms": tune_ms,
         "copies": copies,
-        "device": torch.cuda.get_device_name(0),
+        "input_sha256": synth.sha256(packed),
+        "gpu": gpu_info(torch),
+        "host": host_info(),
     }
     if not args.no_systems:
         del got, out
+        leg_steps = min(20, max(3, args.steps // 2))
         legs = {
-            "scrunched": lambda: bench_scrunched(torch, dev, plan, inp, nsamps, max(3, args.steps // 2), mean_ms),
-            "subband": lambda: bench_subband(torch, dev, plan, inp, nsamps, max(3, args.steps // 2), mean_ms),
-            "tree": lambda: bench_tree(torch, dev, beam, inp, nsamps, max(3, args.steps // 2)),
-            "large_beam": lambda: bench_large(torch, dev, 3),
+            "scrunched": lambda: bench_scrunched(torch, dev, plan, inp, nsamps, leg_steps, mean_ms),
+            "subband": lambda: bench_subband(torch, dev, plan, inp, nsamps, leg_steps, mean_ms),
+            "tree": lambda: bench_tree(torch, dev, beam, inp, nsamps, leg_steps),
+            "large_beam": lambda: bench_large(torch, dev, 11, args.counters_json, args.large_tile),
             "tiny": lambda: bench_tiny(torch, dev),
-            "batched": lambda: bench_batch(torch, dev, max(3, args.steps // 4)),
+            "batched": lambda: bench_batch(torch, dev, max(3, leg_steps // 2)),
             "serving": lambda: bench_serve(torch, dev, args.serve_seconds),
         }
         for name in [x for x in args.legs.split(",") if x]:

@@ -16,11 +16,16 @@ is the top of the band (frequency ``f_top``); channel ``c`` is at
 
 Random streams are numpy ``default_rng(seed)`` (PCG64), drawn in row blocks of
 ``BLOCK_ROWS`` rows so that arbitrarily large inputs can be produced with
-bounded host memory; the block size is part of the recipe.
+bounded host memory; the block size is part of the recipe.  The large beam and
+the batched beams draw every block from a generator of its own,
+``default_rng([*key, block])``, so their blocks are made on several host
+threads at once.
 """
 from __future__ import annotations
 
 import hashlib
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -64,6 +69,46 @@ def eight_bit_noise(rng: np.random.Generator, nsamps: int, nchans: int,
         np.rint(z, out=z)
         np.clip(z, 0.0, 255.0, out=z)
         out[r0:r1] = z.astype(np.uint8)
+    return out
+
+
+def _two_bit_block(rng: np.random.Generator, out: np.ndarray) -> None:
+    t1, t2, t3 = _TWO_BIT_THRESHOLDS
+    u = rng.integers(0, 100, size=out.shape, dtype=np.uint8)
+    np.greater_equal(u, t1, out=out, casting="unsafe")
+    out += (u >= t2)
+    out += (u >= t3)
+
+
+def _eight_bit_block(rng: np.random.Generator, out: np.ndarray, mean: float, sd: float) -> None:
+    z = rng.standard_normal(size=out.shape, dtype=np.float32)
+    z *= np.float32(sd)
+    z += np.float32(mean)
+    np.rint(z, out=z)
+    np.clip(z, 0.0, 255.0, out=z)
+    out[...] = z.astype(np.uint8)
+
+
+def blockwise_codes(key, nsamps: int, nchans: int, nbits: int, mean: float = 128.0,
+                    sd: float = 16.0, threads: int | None = None) -> np.ndarray:
+    """Codes uint8 [nsamps][nchans]: block b (rows b*BLOCK_ROWS ...) drawn from
+    ``default_rng([*key, b])`` -- 2-bit levels as in ``two_bit_codes``, or
+    8-bit ``rint(mean + sd * z)`` clipped to [0, 255] -- on several threads."""
+    key = [int(k) for k in (key if isinstance(key, (list, tuple)) else [key])]
+    out = np.empty((nsamps, nchans), dtype=np.uint8)
+    nblk = (nsamps + BLOCK_ROWS - 1) // BLOCK_ROWS
+
+    def one(b):
+        rng = np.random.default_rng(key + [b])
+        blk = out[b * BLOCK_ROWS:min(nsamps, (b + 1) * BLOCK_ROWS)]
+        if nbits == 2:
+            _two_bit_block(rng, blk)
+        else:
+            _eight_bit_block(rng, blk, mean, sd)
+
+    n = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=max(1, n)) as ex:
+        list(ex.map(one, range(nblk)))
     return out
 
 
@@ -180,9 +225,10 @@ def survey_beam(seed: int = 1, nsamps: int = 1 << 19, nchans: int = 1024,
 
 
 def large_beam(seed: int = 2, nsamps: int = 1 << 20, nchans: int = 4096, ndm: int = 2048) -> Beam:
-    """8-bit, 4096 channels, dt 54.6 us, f_top 1500 MHz, df -0.09765625 MHz, DMs in [0, 2000)."""
-    rng = np.random.default_rng(seed)
-    codes = eight_bit_noise(rng, nsamps, nchans, 128.0, 20.0)
+    """8-bit, 4096 channels, dt 54.6 us, f_top 1500 MHz, df -0.09765625 MHz, DMs in [0, 2000).
+
+    Noise rint(N(128, 20)) clipped to [0, 255], block b from default_rng([seed, b])."""
+    codes = blockwise_codes([seed], nsamps, nchans, 8, 128.0, 20.0)
     return Beam(f"large-8bit-{nchans}ch", nchans, 8, 54.6e-6, 1500.0, -400.0 / nchans,
                 dm_list_linear(ndm, 2000.0 * ndm / 2048.0), codes, [])
 
@@ -205,41 +251,13 @@ def batch_beam_params(b: int) -> dict:
 
 
 def batch_beam(b: int, nsamps: int | None = None) -> Beam:
+    """Beam ``b`` of the batched workload: block k of its codes from
+    default_rng([b, 11, k]); 8-bit noise N(128, 16) or 2-bit levels."""
     p = batch_beam_params(b)
     n = p["nsamps"] if nsamps is None else int(nsamps)
-    rng = np.random.default_rng([p["seed"], 11])
-    if p["nbits"] == 8:
-        codes = eight_bit_noise(rng, n, p["nchans"], 128.0, 16.0)
-    else:
-        codes = two_bit_codes(rng, n, p["nchans"])
+    codes = blockwise_codes([p["seed"], 11], n, p["nchans"], p["nbits"], 128.0, 16.0)
     return Beam(f"batch-{b}", p["nchans"], p["nbits"], p["dt"], p["f_top"], p["df"],
                 dm_list_linear(p["ndm"], p["dm_max"]), codes, [])
-
-
-def device_codes(nsamps: int, nchans: int, nbits: int, seed: int, device="cuda",
-                 sd: float = 16.0):
-    """Seeded packed input made on the device with torch's generator (for sizes
-    where numpy generation would dominate a run): 2-bit level codes with
-    probabilities .16/.34/.34/.16 packed four per byte, or 8-bit
-    rint(N(128, sd)) clipped to [0, 255].  Returns a uint8 tensor
-    [nsamps][nchans*nbits/8]."""
-    import torch
-    gen = torch.Generator(device=device)
-    gen.manual_seed(int(seed))
-    if nbits == 2:
-        u = torch.randint(0, 100, (nsamps, nchans), generator=gen, device=device,
-                          dtype=torch.int16)
-        c = (u >= 16).to(torch.uint8) + (u >= 50).to(torch.uint8) + (u >= 84).to(torch.uint8)
-        del u
-        c = c.view(nsamps, nchans // 4, 4)
-        return (c[..., 0] | (c[..., 1] << 2) | (c[..., 2] << 4) | (c[..., 3] << 6)).contiguous()
-    out = torch.empty((nsamps, nchans), dtype=torch.uint8, device=device)
-    step = max(1, (1 << 26) // nchans)
-    for r0 in range(0, nsamps, step):
-        r1 = min(nsamps, r0 + step)
-        z = torch.randn((r1 - r0, nchans), generator=gen, device=device) * float(sd) + 128.0
-        out[r0:r1] = z.round_().clamp_(0, 255).to(torch.uint8)
-    return out
 
 
 def stream_chunk_lengths(stream: int, nchunks: int, lo: int = 1 << 14, hi: int = 1 << 18) -> np.ndarray:

@@ -163,24 +163,6 @@ def test_push_many_equals_each_stream_alone(native, cuda, wide):
         assert np.array_equal(got, want), specs[i]
 
 
-def _batch_beams(dev, nsamps_cap):
-    beams, refs = [], []
-    for b in range(13):
-        prm = synth.batch_beam_params(b)
-        n = min(prm["nsamps"], nsamps_cap)
-        beam = synth.batch_beam(b, nsamps=n)
-        plan = Plan(beam.nchans, beam.dt, beam.f_top, beam.df, beam.nbits).set_dm_list(beam.dms)
-        if n <= plan.max_delay:
-            n = plan.max_delay + 3000
-            beam = synth.batch_beam(b, nsamps=n)
-        packed = beam.packed()
-        import torch
-        out = torch.full((plan.ndm, n - plan.max_delay), -1, dtype=torch.int32, device=dev)
-        beams.append((plan, _gpu(packed, dev), n, out, 0))
-        refs.append((packed, plan))
-    return beams, refs
-
-
 def test_batch_small_every_beam_and_replay(native, cuda, tmp_path):
     """13 beams of the batched workload, shortened so the oracle runs whole.
 
@@ -223,25 +205,6 @@ def test_batch_small_every_beam_and_replay(native, cuda, tmp_path):
     assert len(json.load(open(cache))) >= 1
     Batch(beams, tune_cache_path=cache).execute()
     torch.cuda.synchronize()
-
-
-def test_batch_full_size_sampled(native, cuda):
-    """The 13-beam batched workload at full size: sampled outputs of every beam."""
-    import torch
-    beams, refs = _batch_beams(cuda, 1 << 19)
-    batch = Batch(beams)
-    batch.execute()
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(123)
-    for (plan, _, n, out, _), (packed, _) in zip(beams, refs):
-        nout = n - plan.max_delay
-        d = rng.integers(0, plan.ndm, size=300)
-        t = rng.integers(0, nout, size=300)
-        d = np.concatenate([d, [plan.ndm - 1, 0]])
-        t = np.concatenate([t, [nout - 1, nout - 1]])
-        want = oracle.dedisperse_points(packed, n, plan.nchans, plan.nbits, plan.delay_table(), d, t)
-        got = out[torch.from_numpy(d).to(cuda), torch.from_numpy(t).to(cuda)]
-        assert np.array_equal(_np(got), want), (plan.nchans, plan.nbits, n)
 
 
 def test_stream_with_kill_mask(native, cuda):
