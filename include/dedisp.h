@@ -84,8 +84,12 @@ const char* dedisp_last_error(void);
 dedisp_status dedisp_plan_create(dedisp_plan* out, int nchans, double dt_s,
                                  double f_top_mhz, double df_mhz, int nbits);
 
-/* Release a plan and its device tables (NULL is ignored).  Work already
- * enqueued that uses the plan must have finished. */
+/* Release a plan and its device tables (NULL is ignored).  Waits, on the
+ * host, for the work enqueued with the plan (its executes and the stream
+ * pushes and batch launches that read its tables) before freeing; other work
+ * on the device is not waited for by the library (the HIP runtime's free may
+ * still synchronise the device).  Streams and batches using the plan must
+ * be destroyed first. */
 void dedisp_plan_destroy(dedisp_plan plan);
 
 /* Set the trial DMs (the DM(d) array of Section 2.1), `ndm` values in
@@ -100,7 +104,8 @@ dedisp_status dedisp_set_dm_list(dedisp_plan plan, const double* dms, int ndm);
  * copied; entries other than 0/1 are INVALID_ARG.  The delay table, max_delay
  * and the output range do not change.  Killed channels cost nothing in the
  * tiled kernel: the corner turn leaves them out of the channel-major
- * scratch.  Work enqueued with the plan must have finished. */
+ * scratch.  Waits for the plan's own enqueued work before it drops the
+ * device tables. */
 dedisp_status dedisp_set_killmask(dedisp_plan plan, const int32_t* mask);
 
 /* Plan queries (host-only).  NO_DM_LIST before dedisp_set_dm_list for the
@@ -157,7 +162,8 @@ dedisp_status dedisp_default_scrunch_factors(dedisp_plan plan, int max_factor, i
  * describing the full-resolution list.  Streams and batches reject a plan
  * with scrunching on (UNSUPPORTED).  Set it before dedisp_set_tree (each
  * factor group then runs the tree); while the tree is on any call, and with
- * sub-band mode on a call with factors, is UNSUPPORTED.  Work enqueued with the plan must have finished.
+ * sub-band mode on a call with factors, is UNSUPPORTED.  Waits for the plan's own enqueued work
+ * before it replaces device tables.
  * Errors: INVALID_ARG, NO_DM_LIST, OOM, UNSUPPORTED. */
 dedisp_status dedisp_set_scrunching(dedisp_plan plan, const int32_t* factors);
 
@@ -231,7 +237,7 @@ dedisp_status dedisp_get_output_format(dedisp_plan plan, int* nbits, int* shift)
  * data); ngroup >= 1; (0, 0) switches sub-band mode off.  Setting a new DM
  * list switches it off; it excludes time-scrunching (UNSUPPORTED) and
  * streams and batches reject such a plan.  Needs 4-byte aligned input rows.
- * Work enqueued with the plan must have finished.
+ * Waits for the plan's own enqueued work before it replaces device tables.
  * Errors: INVALID_ARG, NO_DM_LIST, UNSUPPORTED, OOM. */
 dedisp_status dedisp_set_subband(dedisp_plan plan, int nsub, int ngroup);
 
@@ -239,16 +245,24 @@ dedisp_status dedisp_set_subband(dedisp_plan plan, int nsub, int ngroup);
 
 /* Shape of the LDS-tiled kernel: `waves` wavefronts per workgroup share one
  * staged time tile; each wave sums `dms_per_wave` neighbouring trial DMs;
- * each lane owns 4*`words_per_lane` consecutive output samples (so a tile is
- * 256*words_per_lane samples long); `chunk_chans` channels are staged in LDS
- * at a time.  kind = 0 is the LDS-tiled kernel, kind = 1 the untiled
- * fallback (no LDS; used automatically when a tile would not fit). */
+ * each lane owns `words_per_lane` consecutive 32-bit words of the
+ * channel-major scratch, i.e. words_per_lane times the samples a word holds
+ * (`sample_format`: 0 = 2-bit codes as nibbles, 8 per word; 1 = bytes, 4;
+ * 2 = small byte sums, 4; 3 = 16-bit sums, 2; 4 = 2-bit codes as two bit
+ * planes, 32 per word of each plane), so a tile is 64 lanes times that;
+ * `chunk_chans` channels are staged in LDS at a time.  kind = 0 is the
+ * LDS-tiled kernel, kind = 1 the untiled fallback (no LDS; used
+ * automatically when a tile would not fit).  The plan's bit depth and
+ * channel count fix the scratch format (2-bit codes are bit planes up to
+ * 1365 channels, nibbles beyond); `sample_format` is reported by the getters
+ * and ignored by dedisp_set_tile_config. */
 typedef struct {
     int kind;
     int waves;
     int dms_per_wave;
     int words_per_lane;
     int chunk_chans;
+    int sample_format;
 } dedisp_tile_config;
 
 /* Number of tile shapes compiled into this library, and the i-th one. */
@@ -314,9 +328,9 @@ dedisp_status dedisp_stream_push_many(dedisp_stream* streams, const void* const*
 /* Size the stream's channel-major scratch for pushes of up to max_chunk rows
  * with the plan's current tile shape (call after tuning the plan).  A push
  * longer than any seen before otherwise grows the scratch, and freeing the
- * old one waits for the whole device: in a serving loop that drains the
- * queued work.  Synchronous; call it before the stream's first push or when
- * no work of the stream is in flight.  Errors: INVALID_ARG, OOM. */
+ * old one waits for this stream's queued pushes (and the HIP runtime's free
+ * may synchronise the device): in a serving loop that stalls the tick.
+ * Synchronous.  Errors: INVALID_ARG, OOM. */
 dedisp_status dedisp_stream_reserve(dedisp_stream s, size_t max_chunk);
 
 /* Device memory the stream holds between pushes (the benchmark spec serving form:
@@ -332,7 +346,9 @@ dedisp_status dedisp_stream_get_device_bytes(dedisp_stream s, size_t* bytes);
 dedisp_status dedisp_stream_get_state(dedisp_stream s, size_t* history_rows,
                                       uint64_t* total_rows);
 
-/* Checkpoint / restore of the history (synchronous host copies).
+/* Checkpoint / restore of the history (synchronous host copies, after this
+ * stream's own pushes, on the stream they last ran on; other streams keep
+ * running).
  * get: host_buf of at least history_rows * row_bytes bytes; *nsamps receives
  * history_rows.  set: replaces the history with nsamps <= max_delay rows
  * (the stream then behaves as if exactly those rows had been pushed, with

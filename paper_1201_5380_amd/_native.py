@@ -34,7 +34,7 @@ _pf32 = ctypes.POINTER(ctypes.c_float)
 
 class TileConfig(ctypes.Structure):
     _fields_ = [("kind", _i), ("waves", _i), ("dms_per_wave", _i),
-                ("words_per_lane", _i), ("chunk_chans", _i)]
+                ("words_per_lane", _i), ("chunk_chans", _i), ("sample_format", _i)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

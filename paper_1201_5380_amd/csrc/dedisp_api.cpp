@@ -48,9 +48,45 @@ constexpr double kDispersionConstant = 4.148808e3;
 
 void destroy_groups(dedisp_plan p);
 
+InFlight::~InFlight()
+{
+    for (auto& e : ev) (void)hipEventDestroy(e.second);
+}
+
+void InFlight::record(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    hipEvent_t e = nullptr;
+    for (auto& x : ev)
+        if (x.first == s) e = x.second;
+    if (!e) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            // cannot track this stream: fall back to waiting for the device
+            last = s;
+            any = true;
+            ev.clear();
+            return;
+        }
+        ev.emplace_back(s, e);
+    }
+    if (hipEventRecord(e, s) != hipSuccess) ev.clear();
+    last = s;
+    any = true;
+}
+
+void InFlight::wait()
+{
+    if (!any) return;
+    bool ok = !ev.empty();
+    for (auto& x : ev)
+        if (hipEventSynchronize(x.second) != hipSuccess) ok = false;
+    if (!ok) (void)hipDeviceSynchronize();
+}
+
 void free_device(dedisp_plan p)
 {
-    if (p->d_table || !p->blocks.empty()) (void)hipDeviceSynchronize();
+    if (p->d_table || !p->blocks.empty()) p->inflight.wait();
     if (p->d_table) (void)hipFree(p->d_table);
     p->d_table = nullptr;
     for (auto& kv : p->blocks) {
@@ -70,7 +106,7 @@ void free_device(dedisp_plan p)
 void drop_block_tables(dedisp_plan p)
 {
     if (p->blocks.empty()) return;
-    (void)hipDeviceSynchronize();
+    p->inflight.wait();
     for (auto& kv : p->blocks) {
         if (kv.second.d_rel) (void)hipFree(kv.second.d_rel);
         if (kv.second.d_base) (void)hipFree(kv.second.d_base);
@@ -262,11 +298,20 @@ int window_words(const BlockTables& bt, const Shape& s)
     return ((bt.relmax / dedisp::fmt_samples_per_word(s.fmt) + 64 * s.m + 1) + 3) & ~3;
 }
 
+// LDS bytes of one staged chunk: bit-plane shapes stage both planes of
+// every channel in rows of a fixed length.
+int chunk_lds_bytes(const Shape& s, int rw)
+{
+    if (s.fmt == dedisp::kFmtPlane) return s.cc * 2 * dedisp::kPlaneRowWords * 4;
+    return s.cc * rw * 4;
+}
+
 bool shape_fits(const BlockTables& bt, const Shape& s)
 {
     const int rw = window_words(bt, s);
+    if (s.fmt == dedisp::kFmtPlane && rw > dedisp::kPlaneRowWords) return false;
     return bt.relmax < 0x10000 && (rw >> 2) <= 64 * s.pi &&
-           static_cast<long long>(s.cc) * rw * 4 <= dedisp::kMaxLdsBytes;
+           static_cast<long long>(chunk_lds_bytes(s, rw)) <= dedisp::kMaxLdsBytes;
 }
 
 // The tiled path reads input rows as 32-bit words and keeps unscrunched
@@ -274,7 +319,8 @@ bool shape_fits(const BlockTables& bt, const Shape& s)
 bool tiled_supported(const dedisp_plan_s& p)
 {
     return (p.internal || p.row_bytes % 4 == 0) && p.nact() >= 1 &&
-           (p.fmt != kFmtNib || p.nact_padded() <= 21845);
+           (p.fmt != kFmtNib || p.nact_padded() <= 21845) &&
+           (p.fmt != dedisp::kFmtPlane || (p.nact_padded() <= dedisp::kPlaneMaxChans && p.ngroups == 1));
 }
 
 // Channels summed into the packed lanes of the small-value formats between
@@ -326,7 +372,7 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
         lp.shape = s;
         lp.cc = s.cc;
         lp.rw = window_words(*bt, s);
-        lp.lds = s.cc * lp.rw * 4;
+        lp.lds = chunk_lds_bytes(s, lp.rw);
         // Double-buffer the staged chunk (one barrier per chunk instead of
         // two) when that keeps as many workgroups resident per CU: at most
         // 16 waves per CU run at the tiled kernels' register counts, so a
@@ -387,7 +433,8 @@ long long xc_pitch(long long nsamps, int fmt, int rw)
 void free_scratch(Scratch& x)
 {
     if (x.ptr) {
-        (void)hipDeviceSynchronize();
+        if (x.owner) x.owner->wait();
+        else (void)hipDeviceSynchronize();
         (void)hipFree(x.ptr);
     }
     x.ptr = nullptr;
@@ -410,7 +457,8 @@ dedisp_status ensure_xc(const dedisp_plan_s& p, Scratch& x, long long nsamps, co
 {
     if (lp.shape.kind != 0) return DEDISP_OK;
     const long long ns = nsamps / p.scrunch;
-    return ensure_scratch(x, static_cast<size_t>(xc_pitch(ns, lp.shape.fmt, lp.rw)) * p.nact_padded());
+    return ensure_scratch(x, static_cast<size_t>(xc_pitch(ns, lp.shape.fmt, lp.rw)) * p.nact_padded() *
+                                 dedisp::fmt_rows(lp.shape.fmt));
 }
 
 void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n0,
@@ -443,6 +491,7 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
     d.shape = lp.shape_index;
     if (lp.shape.kind == 0) {
         d.xc = xc;
+        d.xc_fmt = lp.shape.fmt;
         d.pitch = xc_pitch(nsamps / p->scrunch, lp.shape.fmt, lp.rw);
         d.rel = lp.bt->d_rel;
         d.base = lp.bt->d_base;
@@ -530,7 +579,7 @@ void destroy_tree(dedisp_plan p)
 {
     if (p->d_tree_rows || p->d_tree_delay || p->d_tree_pairs || p->d_tree_stage || p->d_tree_sblocks ||
         p->d_tree_off || p->d_tree_gtrials)
-        (void)hipDeviceSynchronize();
+        p->inflight.wait();
     if (p->d_tree_rows) (void)hipFree(p->d_tree_rows);
     if (p->d_tree_delay) (void)hipFree(p->d_tree_delay);
     if (p->d_tree_pairs) (void)hipFree(p->d_tree_pairs);
@@ -558,7 +607,7 @@ void destroy_tree(dedisp_plan p)
 
 void destroy_subband(dedisp_plan p)
 {
-    if (p->sb_step1 || p->sb_step2) (void)hipDeviceSynchronize();
+    if (p->sb_step1 || p->sb_step2) p->inflight.wait();   // the passes' tables serve p's executes
     dedisp_plan_destroy(p->sb_step1);
     dedisp_plan_destroy(p->sb_step2);
     p->sb_step1 = p->sb_step2 = nullptr;
@@ -583,7 +632,7 @@ dedisp_plan new_internal(const dedisp_plan_s& p)
 
 void destroy_groups(dedisp_plan p)
 {
-    if (!p->groups.empty()) (void)hipDeviceSynchronize();
+    if (!p->groups.empty()) p->inflight.wait();   // the groups' tables serve p's executes
     for (auto& g : p->groups) {
         if (g.d_rows) (void)hipFree(g.d_rows);
         dedisp_plan_destroy(g.sub);
@@ -607,14 +656,24 @@ double diagonal_dm(const dedisp_plan_s& p)
     return 1.0 / (dTb - dTa);
 }
 
+// Scratch format of the direct transform at full resolution: 2-bit codes as
+// bit planes while every sum fits the planes' levels, else as nibbles; 8-bit
+// codes as bytes.
+int direct_format(int nbits, int nchans)
+{
+    if (nbits != 2) return kFmtByte;
+    const int u = dedisp::fmt_chan_unit(dedisp::kFmtPlane);
+    return (nchans + u - 1) / u * u <= dedisp::kPlaneMaxChans ? dedisp::kFmtPlane : kFmtNib;
+}
+
 // Scratch format of a scrunch group: sums of up to 8 two-bit codes stay in
 // byte lanes (four samples per add, flushed at least every 10 channels);
 // larger two-bit sums (at most 3*64 = 192) are bytes read through the 8-bit
 // code path (one v_perm spreads two bytes into 16-bit lanes), the same VALU
 // per sample as 16-bit scratch with half the bytes; 8-bit sums take 16 bits.
-int scrunch_format(int nbits, int s)
+int scrunch_format(int nbits, int nchans, int s)
 {
-    if (s == 1) return nbits == 2 ? kFmtNib : kFmtByte;
+    if (s == 1) return direct_format(nbits, nchans);
     if (nbits == 2) return s <= 8 ? kFmtByteS : kFmtByte;
     return kFmtHalf;
 }
@@ -675,7 +734,7 @@ dedisp_status dedisp_plan_create(dedisp_plan* out, int nchans, double dt_s, doub
     p->f_top = f_top_mhz;
     p->df = df_mhz;
     p->row_bytes = nchans * nbits / 8;
-    p->fmt = nbits == 2 ? kFmtNib : kFmtByte;
+    p->fmt = direct_format(nbits, nchans);
     p->cfg = default_config(p->fmt);
     *out = p;
     return DEDISP_OK;
@@ -788,6 +847,7 @@ dedisp_status dedisp_tile_config_get(int i, dedisp_tile_config* c)
     c->dms_per_wave = s.dpw;
     c->words_per_lane = s.m;
     c->chunk_chans = s.cc;
+    c->sample_format = s.kind == 0 ? s.fmt : -1;
     return DEDISP_OK;
 }
 
@@ -815,6 +875,7 @@ dedisp_status dedisp_get_tile_config(dedisp_plan p, dedisp_tile_config* c)
     c->dms_per_wave = lp.shape.dpw;
     c->words_per_lane = lp.shape.m;
     c->chunk_chans = lp.cc;
+    c->sample_format = lp.shape.kind == 0 ? lp.shape.fmt : -1;
     return DEDISP_OK;
 }
 
@@ -847,7 +908,7 @@ static dedisp_status execute_groups(dedisp_plan p, const void* d_in, size_t nsam
         if (lps[i].shape.kind == 0) {
             const long long ns = static_cast<long long>(nsamps) / sub->scrunch;
             need = std::max(need, static_cast<size_t>(xc_pitch(ns, lps[i].shape.fmt, lps[i].rw)) *
-                                      sub->nact_padded());
+                                      sub->nact_padded() * dedisp::fmt_rows(lps[i].shape.fmt));
         }
         ScrunchGroup& g = p->groups[i];
         if (!g.d_rows) {
@@ -903,7 +964,7 @@ static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsa
     if (st != DEDISP_OK) return st;
     const int nsub = p->sb_nsub, ngroup = p->sb_ngroup;
     const int nsb = p->nchans / nsub, nsb_p = s2->nchans, nnom = s1->ndm_last;
-    const long long pitch1 = xc_pitch(static_cast<long long>(nsamps), p->fmt, lp1.rw);
+    const long long pitch1 = xc_pitch(static_cast<long long>(nsamps), s1->fmt, lp1.rw);
     const long long pitch2 = xc_pitch(len1, s2->fmt, lp2.rw);
     st = ensure_scratch(p->xc, static_cast<size_t>(pitch1) * p->nchans);
     if (st != DEDISP_OK) return st;
@@ -926,7 +987,7 @@ static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsa
     d0.scrunch = 1;
     d0.ngroups = 1;
     d0.out_bytes = 4;
-    hipError_t e = dedisp::launch_unpack(d0, p->nbits, p->fmt, hs);
+    hipError_t e = dedisp::launch_unpack(d0, p->nbits, s1->fmt, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     if (nsb_p > nsb) {
         e = dedisp::launch_zero(p->sb_xc2.ptr + static_cast<long long>(nsb) * pitch2,
@@ -1088,9 +1149,11 @@ static dedisp_status run_tree(dedisp_plan p, const void* d_in, size_t nsamps, ui
     // the tree kernel reads whole tiles (and one more word) past the last
     // sample, up to (npass - 1)(nsub - 1) samples further under an imposed
     // delay
+    // stage 1 reads one row per channel: 2-bit codes as nibbles
+    const int tfmt = p->fmt == dedisp::kFmtPlane ? kFmtNib : p->fmt;
     const long long pitch1 = xc_pitch(ns + dedisp::tree_tile(nsub) + nsub +
                                           static_cast<long long>(p->tree_npass - 1) * (nsub - 1) + 8,
-                                      p->fmt, 0);
+                                      tfmt, 0);
     const int ob = tree_row_bytes(*p);
     const long long pitch2 = ((ob * len1 + 64) + 63) / 64 * 64;
     dedisp_status st = ensure_scratch(p->xc, static_cast<size_t>(pitch1) * p->nchans);
@@ -1112,9 +1175,9 @@ static dedisp_status run_tree(dedisp_plan p, const void* d_in, size_t nsamps, ui
     d0.scrunch = p->scrunch;
     d0.ngroups = 1;
     d0.out_bytes = 4;
-    hipError_t e = dedisp::launch_unpack(d0, p->nbits, p->fmt, hs);
+    hipError_t e = dedisp::launch_unpack(d0, p->nbits, tfmt, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    e = dedisp::launch_tree(d0, p->fmt, nsub, ob, p->d_tree_pairs, npairs, p->sb_xc2.ptr, pitch2, len1, hs);
+    e = dedisp::launch_tree(d0, tfmt, nsub, ob, p->d_tree_pairs, npairs, p->sb_xc2.ptr, pitch2, len1, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     // stage 2: every trial sums, over the sub-bands, its tree row at its delay
     BeamDesc dg;
@@ -1202,9 +1265,13 @@ dedisp_status dedisp_execute(dedisp_plan p, const void* d_in, size_t nsamps, uin
 {
     if (!p || !d_in || !d_out) return fail(DEDISP_ERR_INVALID_ARG, "NULL argument");
     if (!p->has_dms) return fail(DEDISP_ERR_NO_DM_LIST, "no DM list");
-    if (p->tree_nsub) return execute_tree(p, d_in, nsamps, d_out, stride, stream);
-    if (p->sb_step1) return execute_subband(p, d_in, nsamps, d_out, stride, stream);
-    if (!p->groups.empty()) return execute_groups(p, d_in, nsamps, d_out, stride, stream);
+    if (p->tree_nsub || p->sb_step1 || !p->groups.empty()) {
+        const dedisp_status st = p->tree_nsub  ? execute_tree(p, d_in, nsamps, d_out, stride, stream)
+                                 : p->sb_step1 ? execute_subband(p, d_in, nsamps, d_out, stride, stream)
+                                               : execute_groups(p, d_in, nsamps, d_out, stride, stream);
+        if (st == DEDISP_OK) p->inflight.record(static_cast<hipStream_t>(stream));
+        return st;
+    }
     // (an internal scrunch-group plan, run on its own while tuning, sums
     // p->scrunch input rows per sample)
     if (nsamps / p->scrunch <= static_cast<size_t>(p->max_delay))
@@ -1230,6 +1297,7 @@ dedisp_status dedisp_execute(dedisp_plan p, const void* d_in, size_t nsamps, uin
               static_cast<long long>(nsamps), d_out, static_cast<long long>(stride), p->xc.ptr, d);
     hipError_t e = launch_desc(d, lp, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    p->inflight.record(static_cast<hipStream_t>(stream));
     return DEDISP_OK;
 }
 
@@ -1524,7 +1592,7 @@ dedisp_status dedisp_set_scrunching(dedisp_plan p, const int32_t* factors)
         sub->df = p->df;
         sub->row_bytes = p->row_bytes;
         sub->scrunch = s;
-        sub->fmt = scrunch_format(p->nbits, s);
+        sub->fmt = scrunch_format(p->nbits, p->nchans, s);
         sub->cfg = default_config(sub->fmt);
         sub->killmask = p->killmask;
         sub->active = p->active;
@@ -1583,7 +1651,7 @@ dedisp_status dedisp_set_subband(dedisp_plan p, int nsub, int ngroup)
     // step 1: group n = sub-band n, rows = nominal DMs, delays relative to
     // the sub-band's first channel
     s1->nchans = nsub;
-    s1->fmt = p->fmt;
+    s1->fmt = p->nbits == 2 ? kFmtNib : dedisp::kFmtByte;   // grouped passes: one row per channel
     s1->ngroups = nsb;
     s1->dms = nom;
     s1->ndm_last = nnom;

@@ -75,6 +75,7 @@ hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st)
 }  // namespace dedisp
 
 struct dedisp_batch_s {
+    InFlight inflight;                // this batch's launches
     std::vector<dedisp_beam> beams;
     std::vector<Item> items;
     std::vector<Scratch> xcs;         // channel-major scratch per beam
@@ -172,6 +173,14 @@ dedisp_status tune_beam(const dedisp_beam& bm, std::map<std::string, std::vector
     return DEDISP_OK;
 }
 
+// A batch launch reads every beam's plan tables: track it on the batch and
+// on those plans.
+void record_batch(dedisp_batch b, hipStream_t st)
+{
+    b->inflight.record(st);
+    for (const auto& bm : b->beams) bm.plan->inflight.record(st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -201,6 +210,7 @@ dedisp_status dedisp_batch_create(const dedisp_beam* beams, int nbeams, const ch
     bt->beams.assign(beams, beams + nbeams);
     bt->items.resize(static_cast<size_t>(nbeams));
     bt->xcs.resize(static_cast<size_t>(nbeams));
+    for (auto& x : bt->xcs) x.owner = &bt->inflight;
     auto cache = read_cache(cache_path);
     bool dirty = false;
     dedisp_status rc = DEDISP_OK;
@@ -254,6 +264,7 @@ dedisp_status dedisp_batch_execute(dedisp_batch b, void* stream)
 {
     if (!b || !b->exec) return fail(DEDISP_ERR_INVALID_ARG, "NULL batch");
     HIP_TRY(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+    record_batch(b, static_cast<hipStream_t>(stream));
     return DEDISP_OK;
 }
 
@@ -262,13 +273,14 @@ dedisp_status dedisp_batch_execute_direct(dedisp_batch b, void* stream)
     if (!b) return fail(DEDISP_ERR_INVALID_ARG, "NULL batch");
     hipError_t e = enqueue_items(b->items, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "batched launch");
+    record_batch(b, static_cast<hipStream_t>(stream));
     return DEDISP_OK;
 }
 
 void dedisp_batch_destroy(dedisp_batch b)
 {
     if (!b) return;
-    (void)hipDeviceSynchronize();
+    b->inflight.wait();
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->capture) (void)hipStreamDestroy(b->capture);

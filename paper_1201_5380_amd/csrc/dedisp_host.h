@@ -34,10 +34,28 @@ struct BlockTables {
     int32_t* d_base = nullptr;
 };
 
-// A device buffer that only grows.
+// Work enqueued on behalf of one object (a plan, stream or batch): one event
+// per HIP stream the object was used on, recorded after each enqueue (not
+// while that stream is capturing a graph).  wait() blocks the calling host
+// thread until that work is done -- other work on the device goes on -- so
+// the object's device memory can be freed or rewritten.
+struct InFlight {
+    std::vector<std::pair<hipStream_t, hipEvent_t>> ev;
+    hipStream_t last = nullptr;    // most recent stream recorded on
+    bool any = false;
+    InFlight() = default;
+    InFlight(const InFlight&) = delete;
+    InFlight& operator=(const InFlight&) = delete;
+    ~InFlight();
+    void record(hipStream_t s);
+    void wait();
+};
+
+// A device buffer that only grows; freeing it waits for its owner's work.
 struct Scratch {
     uint8_t* ptr = nullptr;
     size_t bytes = 0;
+    InFlight* owner = nullptr;     // NULL: freeing waits for the whole device
 };
 
 // A resolved launch for one beam: shape, LDS size and window length.
@@ -108,6 +126,16 @@ struct ScrunchGroup {
 
 // The object behind dedisp_plan.
 struct dedisp_plan_s {
+    dedisp_plan_s()
+    {
+        xc.owner = &inflight;
+        sb_xc2.owner = &inflight;
+    }
+    dedisp_plan_s(const dedisp_plan_s&) = delete;
+    dedisp_plan_s& operator=(const dedisp_plan_s&) = delete;
+    // work enqueued with this plan's tables and scratch (its own executes,
+    // and the pushes and batch launches that read its tables)
+    dedisp::host::InFlight inflight;
     int nchans = 0;
     int nbits = 0;
     int fmt = 0;                    // scratch sample format (dedisp::Fmt)
@@ -174,8 +202,12 @@ struct dedisp_plan_s {
     int value_bound() const { return vbound ? vbound : (nbits == 2 ? 3 : 255) * scrunch; }
 
     int nact() const { return killmask.empty() ? nchans : static_cast<int>(active.size()); }
-    // scratch rows the tiled kernel sums: live channels padded with zero rows
-    // to a multiple of 8 (the kernel sums whole groups of 8 channels)
-    int nact_padded() const { return (nact() + 7) & ~7; }
+    // channel rows the tiled kernel sums: live channels padded with zero rows
+    // to a whole number of its channel units (8, or 32 for bit planes)
+    int nact_padded() const
+    {
+        const int u = dedisp::fmt_chan_unit(fmt);
+        return (nact() + u - 1) / u * u;
+    }
     int source_channel(int row) const { return killmask.empty() ? row : active[row]; }
 };

@@ -13,10 +13,23 @@ enum Fmt : int {
     kFmtByte = 1,    // 8-bit codes, one per byte
     kFmtByteS = 2,   // byte values at most 127 (time-scrunched 2-bit codes)
     kFmtHalf = 3,    // 16-bit values at most 32767 (time-scrunched 8-bit, or heavily scrunched 2-bit, codes)
+    kFmtPlane = 4,   // 2-bit codes as two bit planes: scratch row 2k + p holds bit p of row k's
+                     // codes, 32 samples per 32-bit word (sample 32w + i at bit i of word w)
 };
-constexpr int fmt_bytes_num(int fmt) { return fmt == kFmtHalf ? 2 : 1; }    // bytes per sample =
-constexpr int fmt_bytes_den(int fmt) { return fmt == kFmtNib ? 2 : 1; }     //   num / den
+// bytes per sample of one scratch row = num / den
+constexpr int fmt_bytes_num(int fmt) { return fmt == kFmtHalf ? 2 : 1; }
+constexpr int fmt_bytes_den(int fmt) { return fmt == kFmtNib ? 2 : fmt == kFmtPlane ? 8 : 1; }
 constexpr int fmt_samples_per_word(int fmt) { return 4 * fmt_bytes_den(fmt) / fmt_bytes_num(fmt); }
+// scratch rows per channel row and channel rows per unit of the summation
+constexpr int fmt_rows(int fmt) { return fmt == kFmtPlane ? 2 : 1; }
+constexpr int fmt_chan_unit(int fmt) { return fmt == kFmtPlane ? 32 : 8; }
+
+// Bit-plane sums: bit levels kept per sample (sums of up to 3 * 1365 two-bit
+// codes) and the LDS row length of one staged plane (32-bit words; plane 1
+// of a channel sits this many words after plane 0).
+constexpr int kPlaneLevels = 12;
+constexpr int kPlaneMaxChans = ((1 << kPlaneLevels) - 1) / 3;
+constexpr int kPlaneRowWords = 224;
 
 // One beam (or one stream push) as the kernels see it.  The input is a
 // virtual concatenation of two row segments so that a stream's resident
@@ -60,6 +73,7 @@ struct BeamDesc {
     int out_shift;            // outputs are min(sum >> out_shift, largest value of out_bytes)
     int dbuf;                 // tiled kernel: two LDS chunk buffers (one barrier per chunk)
     int in_nbits;             // input bit depth (multi-beam corner turn)
+    int xc_fmt;               // scratch format the corner turn writes (Fmt)
     long long g_xc;           // bytes
     long long g_rel;          // elements of rel
     long long g_base;         // elements of base

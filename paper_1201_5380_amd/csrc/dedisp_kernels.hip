@@ -155,6 +155,82 @@ __device__ __forceinline__ void unpack_tile(const BeamDesc& b, long long bx, int
     }
 }
 
+// Corner turn into bit planes (2-bit codes, format kFmtPlane).  A workgroup
+// covers 128 samples of up to 1024 channels: lane l of wave w takes input
+// word column g = 64*by + l (channels 16g .. 16g+15) over the 32 samples
+// 128*bx + 32w .. +31.  Its 32 row words form a 32 x 32 bit matrix (row i =
+// sample i, bit 2q + p = bit p of channel 16g + q); transposed, word 2q + p
+// is plane p of channel 16g + q over the 32 samples.  The words go through
+// LDS so that each scratch row receives one 16-byte store of its 128 samples.
+constexpr int kPlaneTileT = 128;               // samples per plane corner-turn tile
+constexpr int kPlaneTileW = 64;                // input words (16 channels each) per tile
+constexpr int kPlaneLdsPitch = kPlaneTileW * 4 + 4;   // LDS words per bit row (+4: fewer conflicts)
+
+// In-place transpose of a 32 x 32 bit matrix (a[r] bit c -> a[c] bit r) by
+// block swaps of 16, 8, 4, 2 and 1 bits (two shifts and two bit-field
+// selects per row pair and step).
+__device__ __forceinline__ void transpose32(uint32_t (&a)[32])
+{
+#pragma unroll
+    for (int st = 0; st < 5; ++st) {
+        const int j = 16 >> st;
+        const uint32_t m = st == 0 ? 0x0000FFFFu : st == 1 ? 0x00FF00FFu : st == 2 ? 0x0F0F0F0Fu
+                           : st == 3 ? 0x33333333u : 0x55555555u;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            if (k & j) continue;
+            const uint32_t top = a[k], bot = a[k + j];
+            a[k] = (top & m) | ((bot << j) & ~m);
+            a[k + j] = ((top >> j) & m) | (bot & ~m);
+        }
+    }
+}
+
+__device__ __forceinline__ void unpack_planes_tile(const BeamDesc& b, long long bx, int by, uint32_t* lds)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int ndw = b.nchans >> 4;                  // input words per row
+    const int g = by * kPlaneTileW + lane;
+    const long long t0 = bx * kPlaneTileT;
+    uint32_t a[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const long long t = t0 + 32 * wave + i;
+        a[i] = (t < b.nsamps && g < ndw) ? *reinterpret_cast<const uint32_t*>(row_ptr(b, t) + 4LL * g) : 0u;
+    }
+    transpose32(a);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) lds[k * kPlaneLdsPitch + 4 * lane + wave] = a[k];
+    __syncthreads();
+    // one 16-byte store per (channel, plane) row: item i -> word column
+    // i / 32, bit row k = i % 32 (channel 16g + k/2, plane k%2)
+    const long long byte0 = t0 >> 3;
+    if (t0 < b.nsamps) {
+        for (int i = threadIdx.x; i < kPlaneTileW * 32; i += 256) {
+            const int l = i >> 5, k = i & 31;
+            const int c = 16 * (by * kPlaneTileW + l) + (k >> 1);
+            if (c >= b.nchans) continue;
+            const int row = b.chanmap ? b.chanmap[c] : c;
+            if (row < 0) continue;
+            const bool killed = b.mask && b.mask[c] == 0;
+            const u32x4 v = killed ? u32x4{0u, 0u, 0u, 0u}
+                                   : *reinterpret_cast<const u32x4*>(lds + k * kPlaneLdsPitch + 4 * l);
+            *reinterpret_cast<u32x4*>(b.xc + (long long)(2 * row + (k & 1)) * b.pitch + byte0) = v;
+        }
+        // the padding rows (live channels up to a multiple of 32) read as zeros
+        if (b.pad_row >= 0 && by == 0 && threadIdx.x < 2 * (b.nact - b.pad_row))
+            *reinterpret_cast<u32x4*>(b.xc + (long long)(2 * b.pad_row + threadIdx.x) * b.pitch + byte0) =
+                u32x4{0u, 0u, 0u, 0u};
+    }
+}
+
+__global__ __launch_bounds__(256) void k_unpack_planes(BeamDesc b)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t lds[32 * kPlaneLdsPitch];
+    unpack_planes_tile(b, blockIdx.x, blockIdx.y, lds);
+}
+
 template <int NBITS>
 __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
 {
@@ -165,18 +241,31 @@ __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
 // Corner turns of up to kMaxBatchDescs beams in one launch: workgroup i
 // takes unit i of the beams' (time tile, channel tile) units, numbered beam
 // by beam; the beam's input bit depth (b.in_nbits) picks the unpack.
+__host__ __device__ inline long long unpack_grid_x(const BeamDesc& b)
+{
+    const int t = b.xc_fmt == kFmtPlane ? kPlaneTileT : kUT;
+    return (b.nsamps + t - 1) / t;
+}
+__host__ __device__ inline long long unpack_grid_y(const BeamDesc& b)
+{
+    return b.xc_fmt == kFmtPlane ? ((b.nchans >> 4) + kPlaneTileW - 1) / kPlaneTileW : (b.nchans + kUC - 1) / kUC;
+}
+
 __global__ __launch_bounds__(256) void k_unpack_multi(DescBlock blk, int nbeams)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t tile[kUC * Store<8>::kPitch];
+    constexpr int kBytes = kUC * Store<8>::kPitch > 128 * kPlaneLdsPitch ? kUC * Store<8>::kPitch
+                                                                         : 128 * kPlaneLdsPitch;
+    __shared__ __attribute__((aligned(16))) uint8_t tile[kBytes];
     long long id = blockIdx.x;
     for (int i = 0; i < nbeams; ++i) {
         const BeamDesc& b = blk.d[i];
-        const long long gx = (b.nsamps + kUT - 1) / kUT;
-        const long long units = gx * ((b.nchans + kUC - 1) / kUC);
+        const long long gx = unpack_grid_x(b);
+        const long long units = gx * unpack_grid_y(b);
         if (id < units) {
             const long long bx = id % gx;
             const int by = (int)(id / gx);
-            if (b.in_nbits == 2) unpack_tile<2>(b, bx, by, tile);
+            if (b.xc_fmt == kFmtPlane) unpack_planes_tile(b, bx, by, reinterpret_cast<uint32_t*>(tile));
+            else if (b.in_nbits == 2) unpack_tile<2>(b, bx, by, tile);
             else unpack_tile<8>(b, bx, by, tile);
             return;
         }
@@ -611,14 +700,353 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     }
 }
 
+// ------------------------------------------------------------ bit-plane sum
+//
+// 2-bit codes as two bit planes (format kFmtPlane): a 32-bit word of plane p
+// holds bit p of 32 consecutive samples.  For one (DM, channel) a lane
+// realigns M words of each plane with v_alignbit (any shift 0..31), giving
+// a = bit 0 and b = bit 1 of the channel's 32M shifted samples; the channel
+// adds a + 2b to every sample.  The sums are kept bit-sliced: acc[L][j] is
+// bit L of the running sum of the 32 samples of word j, and words are added
+// by full adders over 32 bit positions at once (Section 2.3's bit-level
+// parallelism with one-bit lanes; a full adder is one three-way xor and one
+// majority, each a single v_bitop3).  Carries are handed up the levels in a
+// fixed schedule over 32 channels (64 full adders, 5 half adders), so no
+// lane ever overflows and no flush is needed; at the end a bit transpose
+// turns the kPlaneLevels planes of each word into 32 integer sums.
+
+// Full adder over 32 bit positions: s <- s ^ x ^ y; returns the carry
+// majority(s, x, y), of twice the weight of s.
+__device__ __forceinline__ uint32_t fa(uint32_t& s, uint32_t x, uint32_t y)
+{
+    const uint32_t c = __builtin_amdgcn_bitop3_b32(s, x, y, 0xE8);
+    s = __builtin_amdgcn_bitop3_b32(s, x, y, 0x96);
+    return c;
+}
+
+__device__ __forceinline__ uint32_t ha(uint32_t& s, uint32_t x)
+{
+    const uint32_t c = s & x;
+    s ^= x;
+    return c;
+}
+
+// Realigned planes of one channel: bits r .. r + 32M - 1 of the staged rows
+// starting `row0` words after the lane's base (plane 1 RWS words after plane
+// 0).  The word offset is formed in a scalar register, so one vector add
+// gives the address and every read takes an immediate offset.
+template <int M, int RWS>
+__device__ __forceinline__ void plane_words(const uint32_t* lrow, int row0, uint32_t r, uint32_t (&a)[M],
+                                            uint32_t (&b)[M])
+{
+    int off = row0 + (int)(r >> 5);
+    asm volatile("" : "+s"(off));       // keep the constant row part out of the address fold
+    const uint32_t* src = lrow + off;
+    uint32_t w0[M + 1], w1[M + 1];
+#pragma unroll
+    for (int j = 0; j <= M; ++j) {
+        w0[j] = src[j];
+        w1[j] = src[RWS + j];
+    }
+    const uint32_t sh = r & 31u;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        a[j] = __builtin_amdgcn_alignbit(w0[j + 1], w0[j], sh);
+        b[j] = __builtin_amdgcn_alignbit(w1[j + 1], w1[j], sh);
+    }
+}
+
+// Four channels (LDS rows of channel j at row + 2*j*RWS; offset pairs in
+// lanes pair0, pair0 + 1 of voff) into the accumulators; returns their three
+// carries of weight 4 in k4.
+template <int M, int RWS>
+__device__ __forceinline__ void plane_quad(uint32_t (&acc)[kPlaneLevels][M], const uint32_t* lrow, int row,
+                                           uint32_t voff, int pair0, uint32_t (&k4)[3][M])
+{
+    uint32_t a0[M], b0[M], a1[M], b1[M];
+    uint32_t k2[2][M];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t rr = (uint32_t)lane_value((int)voff, pair0 + h);
+        plane_words<M, RWS>(lrow, row + (4 * h) * RWS, rr & 0xFFFFu, a0, b0);
+        plane_words<M, RWS>(lrow, row + (4 * h + 2) * RWS, rr >> 16, a1, b1);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            k2[h][j] = fa(acc[0][j], a0[j], a1[j]);
+            k4[h][j] = fa(acc[1][j], b0[j], b1[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) k4[2][j] = fa(acc[1][j], k2[0][j], k2[1][j]);
+}
+
+// Fold six carries of level L into three of level L + 1.
+template <int M>
+__device__ __forceinline__ void plane_fold(uint32_t (&accl)[M], const uint32_t (&x)[3][M], const uint32_t (&y)[3][M],
+                                           uint32_t (&out)[3][M])
+{
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        out[0][j] = fa(accl[j], x[0][j], x[1][j]);
+        out[1][j] = fa(accl[j], x[2][j], y[0][j]);
+        out[2][j] = fa(accl[j], y[1][j], y[2][j]);
+    }
+}
+
+template <int M, int RWS>
+__device__ __forceinline__ void plane_octet(uint32_t (&acc)[kPlaneLevels][M], const uint32_t* lrow, int row,
+                                            uint32_t voff, int pair0, uint32_t (&k8)[3][M])
+{
+    uint32_t p[3][M], q[3][M];
+    plane_quad<M, RWS>(acc, lrow, row, voff, pair0, p);
+    plane_quad<M, RWS>(acc, lrow, row + 8 * RWS, voff, pair0 + 2, q);
+    plane_fold<M>(acc[2], p, q, k8);
+}
+
+template <int M, int RWS>
+__device__ __forceinline__ void plane_sixteen(uint32_t (&acc)[kPlaneLevels][M], const uint32_t* lrow, int row,
+                                              uint32_t voff, int pair0, uint32_t (&k16)[3][M])
+{
+    uint32_t p[3][M], q[3][M];
+    plane_octet<M, RWS>(acc, lrow, row, voff, pair0, p);
+    plane_octet<M, RWS>(acc, lrow, row + 16 * RWS, voff, pair0 + 4, q);
+    plane_fold<M>(acc[3], p, q, k16);
+}
+
+// 32 channels (LDS rows from word `row` of the lane's base on): the full
+// schedule down to the top level (the sum of at most kPlaneMaxChans codes of
+// 3 never carries out of it).
+template <int M, int RWS>
+__device__ __forceinline__ void plane_unit(uint32_t (&acc)[kPlaneLevels][M], const uint32_t* lrow, int row,
+                                           uint32_t voff, int pair0)
+{
+    uint32_t p[3][M], q[3][M], k32[3][M];
+    plane_sixteen<M, RWS>(acc, lrow, row, voff, pair0, p);
+    plane_sixteen<M, RWS>(acc, lrow, row + 32 * RWS, voff, pair0 + 8, q);
+    plane_fold<M>(acc[4], p, q, k32);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const uint32_t k64a = fa(acc[5][j], k32[0][j], k32[1][j]);
+        const uint32_t k64b = ha(acc[5][j], k32[2][j]);
+        uint32_t c = fa(acc[6][j], k64a, k64b);
+#pragma unroll
+        for (int L = 7; L < kPlaneLevels - 1; ++L) c = ha(acc[L][j], c);
+        acc[kPlaneLevels - 1][j] ^= c;
+    }
+}
+
+// 16 x 16 bit transposes in both 16-bit halves at once: afterwards the low
+// half of r[s] holds bits s of the low halves of the input rows, the high
+// half bits 16 + s of their high halves.
+__device__ __forceinline__ void transpose16x2(uint32_t (&r)[16])
+{
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        const int j = 8 >> st;
+        const uint32_t m = st == 0 ? 0x00FF00FFu : st == 1 ? 0x0F0F0F0Fu : st == 2 ? 0x33333333u : 0x55555555u;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k & j) continue;
+            const uint32_t top = r[k], bot = r[k + j];
+            r[k] = (top & m) | ((bot << j) & ~m);
+            r[k + j] = ((top >> j) & m) | (bot & ~m);
+        }
+    }
+}
+
+// One (time tile, DM block) work item of the bit-plane format: NW waves,
+// one DM per wave, M plane words (32M samples) per lane, CC channels per
+// staged chunk (a multiple of 32).  LDS: CC channels x 2 planes x RWS words
+// (plane p of chunk channel c at row 2c + p); the staged window of a plane is
+// b.rw <= RWS words long.  Window tables as for tile_body (offsets in
+// samples, window starts multiples of 128 samples).
+template <int NW, int M, int CC, int PM>
+__device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int block, uint32_t* lds)
+{
+    constexpr int RWS = kPlaneRowWords;
+    constexpr int T = 64 * M * 32;               // tile length in samples
+    constexpr int DB = NW;                       // one DM per wave
+    constexpr int RPW = 2 * CC / NW;             // plane rows staged per wave per chunk
+    constexpr int CP = CC / 2;                   // channel pairs per chunk
+    constexpr int NL = kPlaneLevels;
+    static_assert(M % 2 == 1, "lanes must be an odd number of LDS words apart");
+    static_assert(CC % 32 == 0 && (2 * CC) % NW == 0 && CP <= 64, "bad chunk");
+    static_assert(RWS + M < 256, "plane 1 is read at an 8-bit dword offset from plane 0");
+    static_assert(RWS % 4 == 0 && RWS >= 64 * M + 8, "staged rows too short for the tile");
+
+    const int lane = threadIdx.x & 63;
+    const int wave = wave_uniform(threadIdx.x >> 6);
+    tile = wave_uniform(tile);
+    block = wave_uniform(block);
+    const long long t0 = (long long)tile * T;
+    const int nchans = wave_uniform(b.nact);     // a multiple of 32
+    const int rw = wave_uniform(b.rw);
+    const int rq = rw >> 2;
+    const long long pitch = wave_uniform64(b.pitch);
+    const long long nout = wave_uniform64(b.nout);
+    const long long out_stride = wave_uniform64(b.out_stride);
+    const int ndm = wave_uniform(b.ndm);
+    const uint8_t* xc = wave_uniform_ptr(b.xc);
+    uint32_t* out = wave_uniform_ptr(b.out);
+    const int32_t* base_row = wave_uniform_ptr(b.base) + (size_t)block * nchans;
+    const int npairs = nchans >> 1;
+    const uint32_t* rel_row = wave_uniform_ptr(b.rel) + (size_t)(block * DB + wave) * npairs;
+
+    uint32_t acc[NL][M];
+#pragma unroll
+    for (int L = 0; L < NL; ++L)
+#pragma unroll
+        for (int j = 0; j < M; ++j) acc[L][j] = 0u;
+
+    u32x4 pf[RPW][PM];
+    int vbase_nxt = 0;            // lane i < CC: window start of channel c0 + i (next chunk)
+    uint32_t vrel_cur = 0, vrel_nxt = 0;
+    const int last_c = nchans - 1;
+    const int last_p = rq - 1;
+
+#define DEDISP_PLOAD_BASE(C0) vbase_nxt = base_row[min((C0) + (lane < CC ? lane : 0), last_c)];
+#define DEDISP_PLOAD_REL(C0) vrel_nxt = rel_row[min(((C0) >> 1) + (lane < CP ? lane : 0), npairs - 1)];
+#define DEDISP_PLOAD_DATA(C0)                                                                         \
+    _Pragma("unroll") for (int i = 0; i < RPW; ++i) {                                                  \
+        const int cl = wave + NW * i;                                                                   \
+        const int bs = lane_value(vbase_nxt, cl >> 1);                                                  \
+        const uint8_t* src = xc + (long long)(2 * min((C0) + (cl >> 1), last_c) + (cl & 1)) * pitch + \
+                             ((t0 + bs) >> 3);                                                          \
+        _Pragma("unroll") for (int q = 0; q < PM; ++q)                                                  \
+            pf[i][q] = *reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p));          \
+    }
+
+    DEDISP_PLOAD_BASE(0)
+    DEDISP_PLOAD_DATA(0)
+    DEDISP_PLOAD_REL(0)
+    if (CC < nchans) {
+        DEDISP_PLOAD_BASE(CC)
+    }
+
+    const bool dbuf = wave_uniform(b.dbuf) != 0;
+    bool chunk_odd = false;
+    for (int c0 = 0; c0 < nchans; c0 += CC) {
+        const int ncur = min(CC, nchans - c0);   // a multiple of 32
+        uint32_t* lbuf = lds;
+        if (dbuf) {
+            if (chunk_odd) lbuf += (size_t)CC * 2 * RWS;
+            chunk_odd = !chunk_odd;
+        } else {
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int cl = wave + NW * i;
+            uint32_t* dst = lbuf + (size_t)cl * RWS;
+#pragma unroll
+            for (int q = 0; q < PM; ++q) {
+                const int pc = lane + 64 * q;
+                if ((cl >> 1) < ncur && pc < rq) *reinterpret_cast<u32x4*>(dst + 4 * pc) = pf[i][q];
+            }
+        }
+        vrel_cur = vrel_nxt;
+        __syncthreads();
+        if (c0 + CC < nchans) {
+            DEDISP_PLOAD_DATA(c0 + CC)
+            DEDISP_PLOAD_REL(c0 + CC)
+            if (c0 + 2 * CC < nchans) {
+                DEDISP_PLOAD_BASE(c0 + 2 * CC)
+            }
+        }
+        const uint32_t* lrow = lbuf + lane * M;
+        for (int u = 0; u < ncur; u += 32)
+            plane_unit<M, RWS>(acc, lrow, u * 2 * RWS, vrel_cur, u >> 1);
+    }
+#undef DEDISP_PLOAD_BASE
+#undef DEDISP_PLOAD_REL
+#undef DEDISP_PLOAD_DATA
+
+    const int d = block * DB + wave;
+    if (d >= ndm) return;
+    const int32_t* rowmap = wave_uniform_ptr(b.rowmap);
+    const int orow_idx = rowmap ? wave_uniform(rowmap[d]) : d;
+    const int out_bytes = wave_uniform(b.out_bytes);
+    const int out_shift = wave_uniform(b.out_shift);
+    const bool vec = ((out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
+    const bool nvec = ((reinterpret_cast<uintptr_t>(out) & 3) == 0) && ((out_stride & 3) == 0);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        uint32_t r[16];
+#pragma unroll
+        for (int L = 0; L < 16; ++L) r[L] = L < NL ? acc[L][j] : 0u;
+        transpose16x2(r);
+        const long long t = t0 + 32LL * (lane * M + j);
+        if (out_bytes == 4) {
+            uint32_t* orow = out + (size_t)orow_idx * (size_t)out_stride;
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const int h = g >> 2;            // 0: samples 0..15 (low halves), 1: 16..31 (high)
+                uint32_t o[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t v = r[4 * (g & 3) + e];
+                    o[e] = (h ? (v >> 16) : (v & 0xFFFFu)) >> out_shift;
+                }
+                const long long tg = t + 4 * g;
+                if (vec && tg + 3 < nout) {
+                    *reinterpret_cast<u32x4*>(orow + tg) = u32x4{o[0], o[1], o[2], o[3]};
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (tg + e < nout) orow[tg + e] = o[e];
+                }
+            }
+        } else {
+            uint8_t* nrow = reinterpret_cast<uint8_t*>(out) + (long long)orow_idx * out_stride;
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const int h = g >> 2;
+                uint32_t o[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t v = r[4 * (g & 3) + e];
+                    o[e] = out_value(h ? (v >> 16) : (v & 0xFFFFu), out_shift, out_bytes);
+                }
+                const long long tg = t + 4 * g;
+                if (nvec && tg + 3 < nout) {
+                    if (out_bytes == 1) {
+                        *reinterpret_cast<uint32_t*>(nrow + tg) = o[0] | (o[1] << 8) | (o[2] << 16) | (o[3] << 24);
+                    } else {
+                        *reinterpret_cast<uint32_t*>(nrow + 2 * tg) = o[0] | (o[1] << 16);
+                        *reinterpret_cast<uint32_t*>(nrow + 2 * tg + 4) = o[2] | (o[3] << 16);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (tg + e < nout) {
+                            if (out_bytes == 1) nrow[tg + e] = (uint8_t)o[e];
+                            else reinterpret_cast<uint16_t*>(nrow)[tg + e] = (uint16_t)o[e];
+                        }
+                }
+            }
+        }
+    }
+}
+
+template <int FMT, int NW, int DPW, int M, int CC, int PM>
+__device__ __forceinline__ void tiled_item(const BeamDesc& b, int tile, int block, int group, uint32_t* lds)
+{
+    if constexpr (FMT == kFmtPlane) {
+        static_assert(DPW == 1, "bit-plane shapes take one DM per wave");
+        plane_body<NW, M, CC, PM>(b, tile, block, lds);
+    } else {
+        tile_body<FMT, NW, DPW, M, CC, PM>(b, tile, block, group, lds);
+    }
+}
+
 template <int FMT, int NW, int DPW, int M, int CC, int PM>
 __global__ __launch_bounds__(NW * 64) void k_tiled(BeamDesc b)
 {
     extern __shared__ uint32_t lds_dyn[];
     const int n = b.ntiles * b.nblocks;
     const int logical = xcd_remap((int)blockIdx.x, n);
-    tile_body<FMT, NW, DPW, M, CC, PM>(b, logical / b.nblocks, logical % b.nblocks, (int)blockIdx.y,
-                                       lds_dyn);
+    tiled_item<FMT, NW, DPW, M, CC, PM>(b, logical / b.nblocks, logical % b.nblocks, (int)blockIdx.y,
+                                        lds_dyn);
 }
 
 // ------------------------------------------------------------ untiled
@@ -742,6 +1170,11 @@ __global__ __launch_bounds__(256) void k_zero(uint8_t* base, long long group_str
 // the multi-beam kernels (which allocate registers for the largest of them).
 // The first shape of each format is its default.
 #define DEDISP_SHAPES(X)                   \
+    X(kFmtPlane, 16, 1, 3, 32, 1, 2)       \
+    X(kFmtPlane, 8, 1, 3, 32, 1, 1)        \
+    X(kFmtPlane, 16, 1, 1, 32, 1, 0)       \
+    X(kFmtPlane, 8, 1, 1, 32, 1, 0)        \
+    X(kFmtPlane, 16, 1, 3, 64, 1, 0)       \
     X(kFmtNib, 8, 2, 3, 32, 2, 1)          \
     X(kFmtNib, 8, 2, 3, 16, 4, 1)          \
     X(kFmtNib, 8, 2, 1, 32, 2, 1)          \
@@ -795,7 +1228,7 @@ __device__ __forceinline__ bool run_if(int shape_id, int want, const BeamDesc& b
     if constexpr (MULTI == CLASS) {
         static_assert(NW == multi_waves(CLASS), "multi-beam shapes of a class share one workgroup size");
         if (shape_id == want) {
-            tile_body<FMT, NW, DPW, M, CC, PM>(b, tile, block, 0, lds);
+            tiled_item<FMT, NW, DPW, M, CC, PM>(b, tile, block, 0, lds);
             return true;
         }
     }
@@ -859,15 +1292,18 @@ const Shape& shape_at(int i) { return kShapes[i].s; }
 
 hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st)
 {
-    BeamDesc arg = d;
-    void* args[] = {&arg};
     if (d.scrunch > 1) return launch_scrunch(d, nbits, fmt, st);
-    const long long gx = (d.nsamps + kUT - 1) / kUT;
-    const long long gy = (d.nchans + kUC - 1) / kUC;
+    BeamDesc arg = d;
+    arg.xc_fmt = fmt;
+    void* args[] = {&arg};
+    const long long gx = unpack_grid_x(arg);
+    const long long gy = unpack_grid_y(arg);
     if (gx <= 0 || gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidValue;
-    if ((nbits == 2) != (fmt == kFmtNib)) return hipErrorInvalidValue;
-    const void* fn = nbits == 2 ? reinterpret_cast<const void*>(&k_unpack<2>)
-                                : reinterpret_cast<const void*>(&k_unpack<8>);
+    if ((nbits == 2) != (fmt == kFmtNib || fmt == kFmtPlane)) return hipErrorInvalidValue;
+    if (fmt == kFmtPlane && (d.nchans % 16 || d.row_bytes % 4)) return hipErrorInvalidValue;
+    const void* fn = fmt == kFmtPlane ? reinterpret_cast<const void*>(&k_unpack_planes)
+                     : nbits == 2     ? reinterpret_cast<const void*>(&k_unpack<2>)
+                                      : reinterpret_cast<const void*>(&k_unpack<8>);
     return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, 0, st);
 }
 
@@ -879,7 +1315,9 @@ hipError_t launch_unpack_multi(const DescBlock& blk, int nbeams, hipStream_t st)
         const BeamDesc& b = blk.d[i];
         if (b.scrunch != 1 || (b.in_nbits != 2 && b.in_nbits != 8) || b.nsamps <= 0 || b.nchans <= 0)
             return hipErrorInvalidValue;
-        units += ((b.nsamps + kUT - 1) / kUT) * ((b.nchans + kUC - 1) / kUC);
+        if ((b.in_nbits == 2) != (b.xc_fmt == kFmtNib || b.xc_fmt == kFmtPlane)) return hipErrorInvalidValue;
+        if (b.xc_fmt == kFmtPlane && (b.nchans % 16 || b.row_bytes % 4)) return hipErrorInvalidValue;
+        units += unpack_grid_x(b) * unpack_grid_y(b);
     }
     if (units > 0x7fffffffLL) return hipErrorInvalidValue;
     DescBlock a0 = blk;

@@ -23,6 +23,8 @@ using dedisp::BeamDesc;
 using namespace dedisp::host;
 
 struct dedisp_stream_s {
+    dedisp_stream_s() { xc.owner = &inflight; }
+    InFlight inflight;                        // this stream's pushes
     dedisp_plan plan = nullptr;
     int row_bytes = 0;
     int max_delay = 0;
@@ -155,7 +157,7 @@ dedisp_status dedisp_stream_create(dedisp_plan plan, dedisp_stream* out)
 void dedisp_stream_destroy(dedisp_stream s)
 {
     if (!s) return;
-    if (s->hist[0] || s->hist[1] || s->xc.ptr) (void)hipDeviceSynchronize();
+    s->inflight.wait();
     for (int i = 0; i < 2; ++i)
         if (s->hist[i]) (void)hipFree(s->hist[i]);
     free_scratch(s->xc);
@@ -195,6 +197,8 @@ dedisp_status dedisp_stream_push(dedisp_stream s, const void* chunk, size_t nsam
     }
     st = update_history(s, chunk, pp, hs);
     if (st != DEDISP_OK) return st;
+    s->inflight.record(hs);
+    s->plan->inflight.record(hs);
     *n_out = pp.nout;
     return DEDISP_OK;
 }
@@ -227,6 +231,8 @@ dedisp_status dedisp_stream_push_many(dedisp_stream* streams, const void* const*
     for (int i = 0; i < n; ++i) {
         dedisp_status st = update_history(streams[i], chunks[i], pps[i], hs);
         if (st != DEDISP_OK) return st;
+        streams[i]->inflight.record(hs);
+        streams[i]->plan->inflight.record(hs);
         n_outs[i] = pps[i].nout;
     }
     return DEDISP_OK;
@@ -254,9 +260,11 @@ dedisp_status dedisp_stream_get_history(dedisp_stream s, void* host_buf, size_t*
     *nsamps = s->hist_rows;
     if (s->hist_rows == 0) return DEDISP_OK;
     if (!host_buf) return fail(DEDISP_ERR_INVALID_ARG, "host_buf is NULL");
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(host_buf, s->hist[s->cur], s->hist_rows * s->row_bytes,
-                      hipMemcpyDeviceToHost));
+    // after this stream's pushes only, on the stream they last ran on
+    s->inflight.wait();
+    HIP_TRY(hipMemcpyAsync(host_buf, s->hist[s->cur], s->hist_rows * s->row_bytes, hipMemcpyDeviceToHost,
+                           s->inflight.last));
+    HIP_TRY(hipStreamSynchronize(s->inflight.last));
     return DEDISP_OK;
 }
 
@@ -270,9 +278,12 @@ dedisp_status dedisp_stream_set_history(dedisp_stream s, const void* host_buf, s
     if (total_rows > md ? nsamps != md : nsamps != total_rows)
         return fail(DEDISP_ERR_INVALID_ARG, "history rows inconsistent with total_rows");
     if (nsamps > 0 && !host_buf) return fail(DEDISP_ERR_INVALID_ARG, "host_buf is NULL");
-    HIP_TRY(hipDeviceSynchronize());
-    if (nsamps > 0)
-        HIP_TRY(hipMemcpy(s->hist[s->cur], host_buf, nsamps * s->row_bytes, hipMemcpyHostToDevice));
+    s->inflight.wait();
+    if (nsamps > 0) {
+        HIP_TRY(hipMemcpyAsync(s->hist[s->cur], host_buf, nsamps * s->row_bytes, hipMemcpyHostToDevice,
+                               s->inflight.last));
+        HIP_TRY(hipStreamSynchronize(s->inflight.last));
+    }
     s->hist_rows = nsamps;
     s->total = total_rows;
     return DEDISP_OK;

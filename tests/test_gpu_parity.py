@@ -3,8 +3,7 @@
 Every test dedisperses seeded synthetic input on the GPU through the C ABI and
 compares with the oracle on the same bytes: whole outputs at sizes the
 oracle finishes in seconds (several time tiles, several DM blocks, ragged
-tails), and sampled outputs plus size-independent properties at the full
-survey-beam size the benchmark times.
+tails).  The benchmark's full sizes are compared in test_gpu_full_size.py.
 """
 import numpy as np
 import pytest
@@ -196,72 +195,6 @@ def test_determinism(native, cuda):
     assert np.array_equal(a, c)
 
 
-def test_survey_beam_full_size_sampled(native, cuda):
-    """The 2-bit, 1024-channel, 1024-DM, 2^19-sample beam, in the benchmark's launch.
-
-    Sampled outputs against the oracle point by point; the DM 0 row against
-    numpy's channel sum over the whole output; every injected pulse at its
-    trial and time.
-    """
-    import torch
-    b = synth.survey_beam()
-    plan = _plan_for(b)
-    table = plan.delay_table()
-    otab, omx = oracle.delay_table(b.nchans, b.dt, b.f_top, b.df, b.dms)
-    assert np.array_equal(table, otab) and omx == 20456
-    b.inject(lambda i: otab[i])
-    packed = b.packed()
-    inp = _to_gpu(packed.reshape(-1), cuda)
-    out = plan.execute(inp, b.nsamps)
-    torch.cuda.synchronize()
-    got = _out_np(out)
-    nout = b.nsamps - omx
-    assert got.shape == (1024, nout)
-    rng = np.random.default_rng(99)
-    d = rng.integers(0, 1024, size=20000)
-    t = rng.integers(0, nout, size=20000)
-    # always include the corners and the last tile
-    d = np.concatenate([d, [0, 1023, 0, 1023, 511]])
-    t = np.concatenate([t, [0, 0, nout - 1, nout - 1, nout - 2]])
-    want = oracle.dedisperse_points(packed, b.nsamps, b.nchans, b.nbits, otab, d, t)
-    assert np.array_equal(got[d, t], want)
-    assert np.array_equal(got[0], b.codes.sum(axis=1, dtype=np.uint32)[:nout])
-    for p in b.pulses:
-        lo, hi = max(0, p.t0 - 100), min(nout, p.t0 + 101)
-        win = got[:, lo:hi].astype(np.int64)
-        dd, tt = np.unravel_index(int(win.argmax()), win.shape)
-        assert (dd, tt + lo) == (p.dm_index, p.t0), p
-
-
-def test_large_beam_full_size_sampled(native, cuda):
-    """8-bit, 4096 channels, 2^20 samples of 54.6 us, 2048 DMs in [0, 2000).
-
-    The input is made on the device (seeded) and copied back for the oracle;
-    sampled outputs are compared point by point, the DM 0 row against the
-    channel sum over the whole output.
-    """
-    import torch
-    nsamps, nchans, ndm = 1 << 20, 4096, 2048
-    dms = synth.dm_list_linear(ndm, 2000.0)
-    plan = Plan(nchans, 54.6e-6, 1500.0, -0.09765625, 8).set_dm_list(dms)
-    table, mx = oracle.delay_table(nchans, 54.6e-6, 1500.0, -0.09765625, dms)
-    assert mx == 58003 and np.array_equal(plan.delay_table(), table)
-    inp = synth.device_codes(nsamps, nchans, 8, seed=2, device=cuda, sd=20.0)
-    out = plan.execute(inp.view(-1), nsamps)
-    torch.cuda.synchronize()
-    nout = nsamps - mx
-    assert tuple(out.shape) == (ndm, nout)
-    chansum = inp[:nout].sum(dim=1, dtype=torch.int32)
-    assert torch.equal(out[0], chansum)
-    host = inp.cpu().numpy()
-    rng = np.random.default_rng(7)
-    d = np.concatenate([rng.integers(0, ndm, 4000), [0, ndm - 1, ndm - 1]])
-    t = np.concatenate([rng.integers(0, nout, 4000), [nout - 1, 0, nout - 1]])
-    want = oracle.dedisperse_points(host, nsamps, nchans, 8, table, d, t)
-    got = out[torch.from_numpy(d).to(cuda), torch.from_numpy(t).to(cuda)]
-    assert np.array_equal(_out_np(got), want)
-
-
 @pytest.mark.parametrize("nbits,nchans", [(2, 256), (8, 192)])
 def test_kill_mask_every_shape(native, cuda, nbits, nchans):
     """Killed channels are left out of the sum (oracle: each term times mask[c])."""
@@ -295,3 +228,43 @@ def test_kill_mask_every_shape(native, cuda, nbits, nchans):
     plan.set_killmask(None)
     assert np.array_equal(_run(plan, packed, nsamps, cuda),
                           oracle.dedisperse(packed, nsamps, nchans, nbits, table))
+
+
+@pytest.mark.parametrize("nchans,fmt", [(16, 4), (1344, 4), (1360, 0)])
+def test_two_bit_scratch_format_by_channel_count(native, cuda, nchans, fmt):
+    """2-bit codes are summed as bit planes while 3 x (channels rounded up to
+    32) fits the planes' 12 bit levels (up to 1344 channels) and as nibbles
+    beyond; both bit-exact on every shape, including all-maximum codes whose
+    sums reach the top level (3 x 1344 = 4032)."""
+    rng = np.random.default_rng(nchans)
+    dms = synth.dm_list_linear(40, 200.0)
+    df = -400.0 / nchans
+    plan = Plan(nchans, 64e-6, 1581.8, df, 2).set_dm_list(dms)
+    assert plan.tile_config()["sample_format"] == fmt
+    table = plan.delay_table()
+    nsamps = plan.max_delay + 7000
+    for codes in (synth.two_bit_codes(rng, nsamps, nchans), np.full((nsamps, nchans), 3, np.uint8)):
+        packed = synth.pack(codes, 2)
+        want = oracle.dedisperse(packed, nsamps, nchans, 2, table)
+        for cfg in _configs_for(plan):
+            if cfg["kind"] == 1 and nchans > 64:
+                continue
+            got = _run(plan, packed, nsamps, cuda, cfg)
+            assert np.array_equal(got, want), cfg
+
+
+def test_two_bit_wide_dm_steps_fall_back_within_planes(native, cuda):
+    """A DM list whose blocks spread too far for the 3-word plane windows runs
+    on the 1-word plane shapes (or the untiled kernel), still bit-exact."""
+    nchans, nsamps = 256, 60000
+    dms = np.arange(48) * 10.0
+    plan = Plan(nchans, 64e-6, 1581.8, -400.0 / nchans, 2).set_dm_list(dms)
+    table = plan.delay_table()
+    assert nsamps > plan.max_delay + 1000
+    codes = synth.two_bit_codes(np.random.default_rng(77), nsamps, nchans)
+    packed = synth.pack(codes, 2)
+    want = oracle.dedisperse(packed, nsamps, nchans, 2, table)
+    cfg = plan.tile_config()
+    assert cfg["kind"] == 0 and cfg["sample_format"] == 4 and cfg["words_per_lane"] == 1
+    got = _run(plan, packed, nsamps, cuda)
+    assert np.array_equal(got, want), cfg

@@ -112,7 +112,7 @@ def test_stream_reset_and_invalid_history(native, cuda):
 
 
 # 16-wave shapes, compiled into the second multi-beam kernel class
-_WIDE = {2: dict(kind=0, waves=16, dms_per_wave=1, words_per_lane=5, chunk_chans=64),
+_WIDE = {2: dict(kind=0, waves=16, dms_per_wave=1, words_per_lane=3, chunk_chans=32),
          8: dict(kind=0, waves=16, dms_per_wave=2, words_per_lane=5, chunk_chans=64)}
 
 
