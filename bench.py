@@ -90,6 +90,76 @@ def roofline_block(nbits, adds, kernel_ms, ctr):
     return blk
 
 
+def _counter_rows(d):
+    """(kernel name, dispatch id, counter, value) rows of every rocprofv3
+    counter-collection CSV under directory d."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((r.get("Kernel_Name", ""), (f, r.get("Dispatch_Id")), r["Counter_Name"],
+                             float(r["Counter_Value"])))
+    return rows
+
+
+def _per_dispatch_means(d, pick):
+    """Mean per dispatch of every counter over the dispatches of the kernel
+    `pick` selects (summed over the rows of one dispatch, e.g. per XCD)."""
+    per = {}
+    names = {}
+    for name, disp, ctr, val in _counter_rows(d):
+        if not pick(name):
+            continue
+        names[disp] = name
+        per.setdefault(ctr, {}).setdefault(disp, 0.0)
+        per[ctr][disp] += val
+    means = {c: sum(v.values()) / len(v) for c, v in per.items()}
+    kernels = sorted(set(names.values()))
+    return means, kernels, len(names)
+
+
+def summarize_counters(args):
+    """Fold rocprofv3 --pmc passes of the dominant kernel into the counters
+    file the roofline reads (one entry per workload, tile and kernel source
+    digest), with HBM bytes scaled by what the same counters read for a
+    plain 1 GiB device copy."""
+    w, dpw, m, cc, fmt = (int(x) for x in args.tile_key.split(","))
+    tile = dict(kind=0, waves=w, dms_per_wave=dpw, words_per_lane=m, chunk_chans=cc, sample_format=fmt)
+    sub = args.kernel_filter
+    means, kernels = {}, set()
+    for d in args.summarize_counters:
+        mm, ks, nd = _per_dispatch_means(d, lambda n: sub in n)
+        means.update(mm)
+        kernels.update(ks)
+    def copy_pick(n):
+        return "copy" in n.lower()
+    cf, _, _ = _per_dispatch_means(args.calibration_dirs[0], copy_pick)
+    cw, _, _ = _per_dispatch_means(args.calibration_dirs[1], copy_pick)
+    gib = float(1 << 30)
+    fs = gib / (cf["FETCH_SIZE"] * 1024.0)
+    ws = gib / (cw["WRITE_SIZE"] * 1024.0)
+    entry = {"workload": args.workload, "tile": tile, "kernel": sorted(kernels),
+             "kernel_source_sha256": kernel_source_sha(), "counters_per_dispatch": means,
+             "fetch_scale_from_copy": fs, "write_scale_from_copy": ws}
+    if "FETCH_SIZE" in means and "WRITE_SIZE" in means:
+        entry["hbm_bytes_per_launch"] = (means["FETCH_SIZE"] * fs + means["WRITE_SIZE"] * ws) * 1024.0
+    for key, ctr in (("grbm_gui_active", "GRBM_GUI_ACTIVE"), ("sq_insts_valu", "SQ_INSTS_VALU"),
+                     ("sq_lds_idx_active", "SQ_LDS_IDX_ACTIVE")):
+        if ctr in means:
+            entry[key] = means[ctr]
+    try:
+        doc = json.load(open(args.counters_json))
+    except (OSError, ValueError):
+        doc = {"entries": []}
+    doc["entries"] = [e for e in doc.get("entries", [])
+                      if not (e.get("workload") == args.workload and e.get("tile") == tile)] + [entry]
+    with open(args.counters_json, "w") as fh:
+        json.dump(doc, fh, indent=1, sort_keys=True)
+    print(json.dumps(entry, indent=1, sort_keys=True))
+
+
 def host_info():
     model = None
     try:
@@ -138,6 +208,14 @@ def parse():
                     help="approximate CPU time budget for the oracle baseline")
     ap.add_argument("--counters-json", default=os.path.join(ROOT, "profiles", "counters.json"),
                     help="rocprofv3 counters per launch (HBM bytes, VALU instructions), if present")
+    ap.add_argument("--summarize-counters", nargs="+", default=None, metavar="DIR",
+                    help="fold rocprofv3 --pmc output directories of one kernel into --counters-json "
+                         "and exit (needs --workload, --tile-key, --calibration-dirs)")
+    ap.add_argument("--workload", default=None)
+    ap.add_argument("--tile-key", default=None, help="waves,dms_per_wave,words_per_lane,chunk_chans,format")
+    ap.add_argument("--kernel-filter", default="k_tiled")
+    ap.add_argument("--calibration-dirs", nargs=2, default=None, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="rocprofv3 FETCH_SIZE and WRITE_SIZE passes over --calibrate-copy")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-systems", action="store_true",
@@ -381,7 +459,7 @@ def bench_tiny(torch, dev, reps=200):
             "outputs_per_s": plan.ndm * nout / (float(np.median(ms)) * 1e-3), "tile": plan.tile_config()}
 
 
-def bench_large(torch, dev, steps, counters_json, tile=None):
+def bench_large(torch, dev, steps, counters_json, tile=None, cache_path=None):
     """The large 8-bit beam: 2^20 samples x 4096 channels of 54.6 us,
     f_top 1500 MHz, df -0.09765625 MHz, 2048 DMs in [0, 2000); seeded
     rint(N(128, 20)) noise clipped to [0, 255] made on the host."""
@@ -401,7 +479,7 @@ def bench_large(torch, dev, steps, counters_json, tile=None):
         w, dpw, m, cc = (int(x) for x in tile.split(","))
         plan.set_tile_config(dict(kind=0, waves=w, dms_per_wave=dpw, words_per_lane=m, chunk_chans=cc))
     else:
-        plan.tune(inp, out, nsamps)
+        plan.tune(inp, out, nsamps, cache_path=cache_path)
     plan.execute(inp, nsamps, out=out)
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
@@ -550,6 +628,10 @@ def main():
               "beyond a max_delay halo).", file=sys.stderr)
         sys.exit(2)
 
+    if args.summarize_counters:
+        summarize_counters(args)
+        return
+
     import torch
     from paper_1201_5380_amd import Plan, synth
 
@@ -666,7 +748,8 @@ def main():
             "scrunched": lambda: bench_scrunched(torch, dev, plan, inp, nsamps, leg_steps, mean_ms),
             "subband": lambda: bench_subband(torch, dev, plan, inp, nsamps, leg_steps, mean_ms),
             "tree": lambda: bench_tree(torch, dev, beam, inp, nsamps, leg_steps),
-            "large_beam": lambda: bench_large(torch, dev, 11, args.counters_json, args.large_tile),
+            "large_beam": lambda: bench_large(torch, dev, 11, args.counters_json, args.large_tile,
+                                              args.tune_cache),
             "tiny": lambda: bench_tiny(torch, dev),
             "batched": lambda: bench_batch(torch, dev, max(3, leg_steps // 2)),
             "serving": lambda: bench_serve(torch, dev, args.serve_seconds),

@@ -122,7 +122,7 @@ def test_push_many_equals_each_stream_alone(native, cuda, wide):
     transform of each stream; with `wide`, every other stream uses a 16-wave
     shape, so one tick launches both multi-beam kernel classes."""
     import torch
-    specs = [(2, 1024, 32, 1000.0), (8, 512, 20, 300.0), (2, 256, 48, 200.0), (8, 1024, 8, 50.0),
+    specs = [(2, 1024, 32, 1000.0), (8, 512, 20, 300.0), (2, 256, 48, 100.0), (8, 1024, 8, 50.0),
              (2, 1024, 32, 1000.0), (8, 512, 24, 60.0), (8, 256, 16, 40.0)]
     plans, rngs, streams, packs, pos = [], [], [], [], []
     for i, (nb, nc, nd, dmx) in enumerate(specs):
