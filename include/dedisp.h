@@ -132,6 +132,33 @@ dedisp_status dedisp_get_delay_table(dedisp_plan plan, int32_t* host_out);
 dedisp_status dedisp_execute(dedisp_plan plan, const void* d_in, size_t nsamps,
                              uint32_t* d_out, size_t out_row_stride, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the plain
+ * direct transform of dedisp_execute, same arguments and results, with its
+ * channel-major scratch taken from one fixed device array of
+ * DEDISP_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  The call makes no hipMalloc, hipFree or other
+ * allocating call.  When one transform's scratch would not fit the array the
+ * input is processed in consecutive time slices (each a whole number of time
+ * tiles of outputs plus max_delay rows of input), which gives the same
+ * outputs.
+ * Preconditions: the plan's device tables for its current DM list, kill mask
+ * and tile shape are already built on the current device, i.e. dedisp_execute
+ * or dedisp_tune ran on the plan after the last change to any of them;
+ * time-scrunching, sub-band and tree modes are off.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (no output depends on what an earlier call left there): calls
+ * that overlap on one GPU (on different HIP streams, or from several host
+ * threads) race and must be serialised by the caller, e.g. by issuing them
+ * on one HIP stream.
+ * Errors: INVALID_ARG (null pointer, stride too small), NO_DM_LIST,
+ * TOO_FEW_SAMPLES, UNSUPPORTED (a mode other than the direct transform,
+ * device tables not built, or one time tile plus max_delay rows of scratch
+ * larger than the array), HIP. */
+#define DEDISP_NOALLOC_SCRATCH_BYTES (128u << 20)
+dedisp_status dedisp_execute_noalloc(dedisp_plan plan, const void* d_in, size_t nsamps,
+                                     uint32_t* d_out, size_t out_row_stride, void* stream);
+
 /* ----------------------------------------------------- time-scrunching */
 
 /* Section 2.1: once a trial's dispersion trail crosses more than one sample

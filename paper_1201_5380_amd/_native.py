@@ -60,6 +60,7 @@ SIGNATURES = {
     "dedisp_get_max_delay": (_i, [_vp, _pi]),
     "dedisp_get_delay_table": (_i, [_vp, _pi32]),
     "dedisp_execute": (_i, [_vp, _vp, _sz, _vp, _sz, _vp]),
+    "dedisp_execute_noalloc": (_i, [_vp, _vp, _sz, _vp, _sz, _vp]),
     "dedisp_get_diagonal_dm": (_i, [_vp, ctypes.POINTER(_d)]),
     "dedisp_default_scrunch_factors": (_i, [_vp, _i, _pi32]),
     "dedisp_set_scrunching": (_i, [_vp, _pi32]),

@@ -203,6 +203,16 @@ class Plan:
                                    _stream_handle(stream)), "dedisp_execute")
         return out
 
+    def execute_noalloc(self, inp, out, nsamps: int | None = None, out_row_stride: int = 0,
+                        stream=None):
+        """The direct transform into caller-given ``out`` with no device
+        allocation (``dedisp_execute_noalloc``): the plan's device tables must
+        already be built (``execute`` or ``tune`` ran after the last change)."""
+        nsamps = self._check_input(inp, nsamps)
+        check(lib().dedisp_execute_noalloc(self._h, _ptr(inp), nsamps, _ptr(out), int(out_row_stride),
+                                           _stream_handle(stream)), "dedisp_execute_noalloc")
+        return out
+
     def tune(self, inp, out, nsamps: int | None = None, out_row_stride: int = 0,
              cache_path: str | None = None, stream=None) -> float:
         nsamps = self._check_input(inp, nsamps)

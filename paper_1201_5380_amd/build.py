@@ -19,8 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdedisp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["dedisp_kernels.hip", "dedisp_tree.hip", "dedisp_scrunch.hip", "dedisp_api.cpp",
-           "dedisp_stream.cpp", "dedisp_batch.cpp"]
+SOURCES = ["dedisp_kernels.hip", "dedisp_tree.hip", "dedisp_scrunch.hip", "dedisp_noalloc.hip",
+           "dedisp_api.cpp", "dedisp_stream.cpp", "dedisp_batch.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -75,13 +75,26 @@ void InFlight::record(hipStream_t s)
     any = true;
 }
 
+void InFlight::record_existing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    hipEvent_t e = nullptr;
+    for (auto& x : ev)
+        if (x.first == s) e = x.second;
+    if (!e || hipEventRecord(e, s) != hipSuccess) untracked = true;
+    last = s;
+    any = true;
+}
+
 void InFlight::wait()
 {
     if (!any) return;
-    bool ok = !ev.empty();
+    bool ok = !ev.empty() && !untracked;
     for (auto& x : ev)
         if (hipEventSynchronize(x.second) != hipSuccess) ok = false;
     if (!ok) (void)hipDeviceSynchronize();
+    untracked = false;
 }
 
 void free_device(dedisp_plan p)

@@ -43,11 +43,15 @@ struct InFlight {
     std::vector<std::pair<hipStream_t, hipEvent_t>> ev;
     hipStream_t last = nullptr;    // most recent stream recorded on
     bool any = false;
+    bool untracked = false;        // work on a stream without an event: wait() waits for the device
     InFlight() = default;
     InFlight(const InFlight&) = delete;
     InFlight& operator=(const InFlight&) = delete;
     ~InFlight();
     void record(hipStream_t s);
+    // record() without creating an event: a stream seen before reuses its
+    // event, work on a new one is marked untracked.
+    void record_existing(hipStream_t s);
     void wait();
 };
 

@@ -385,3 +385,18 @@ def test_tree_validation_precedes_hip(native):
     assert L.dedisp_stream_create(plan.handle, ctypes.byref(h)) == -6
     plan.set_tree(0)
     assert np.all(plan.output_lengths(5000) == 5000 - plan.max_delay)
+
+
+def test_noalloc_execute_validation_precedes_hip(native):
+    L = lib()
+    plan = Plan(64, 64e-6, 1500.0, -1.0, 8)
+    p16 = ctypes.c_void_p(1 << 20)
+    assert L.dedisp_execute_noalloc(plan.handle, p16, 5000, p16, 0, None) == -2   # no DM list
+    plan.set_dm_list(synth.dm_list_linear(32, 100.0))
+    assert L.dedisp_execute_noalloc(None, p16, 5000, p16, 0, None) == -1
+    assert L.dedisp_execute_noalloc(plan.handle, None, 5000, p16, 0, None) == -1
+    assert L.dedisp_execute_noalloc(plan.handle, p16, 5000, None, 0, None) == -1
+    assert L.dedisp_execute_noalloc(plan.handle, p16, 250, p16, 0, None) == -3   # nsamps <= max_delay
+    assert L.dedisp_execute_noalloc(plan.handle, p16, 5000, p16, 10, None) == -1  # stride < nout
+    plan.set_tree(8)
+    assert L.dedisp_execute_noalloc(plan.handle, p16, 5000, p16, 0, None) == -6
