@@ -26,6 +26,17 @@ __device__ __forceinline__ T* wave_uniform_ptr(T* p)
     return reinterpret_cast<T*>(wave_uniform64(reinterpret_cast<long long>(p)));
 }
 
+// A load through the global address space (global_load, counted by the
+// vector-memory counter only).  Pointers taken from a descriptor are
+// generic, and a generic (flat) load also counts against the counter LDS
+// reads share, so every LDS wait issued while it is in flight would wait for
+// it too -- a prefetch of the next chunk would stall the current one.
+template <typename T>
+__device__ __forceinline__ T gload(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ int lane_value(int v, int lane)
 {
     return __builtin_amdgcn_readlane(v, lane);

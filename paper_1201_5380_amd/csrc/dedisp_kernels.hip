@@ -375,12 +375,12 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
     const int last_p = rq - 1;
 
 #define DEDISP_LOAD_BASE(C0)                                                        \
-    vbase_nxt = base_row[min((C0) + (lane < CC ? lane : 0), last_c)];
+    vbase_nxt = gload(base_row + min((C0) + (lane < CC ? lane : 0), last_c));
 #define DEDISP_LOAD_REL(C0, DST)                                                    \
     _Pragma("unroll") for (int r = 0; r < RV; ++r) {                                \
         const int idx = 64 * r + lane;                                              \
-        DST[r] = rel_rows[(size_t)min(idx / CP, DPW - 1) * npairs +                 \
-                          min(((C0) >> 1) + idx % CP, npairs - 1)];                 \
+        DST[r] = gload(rel_rows + (size_t)min(idx / CP, DPW - 1) * npairs +         \
+                       min(((C0) >> 1) + idx % CP, npairs - 1));                    \
     }
 #define DEDISP_LOAD_DATA(C0)                                                        \
     _Pragma("unroll") for (int i = 0; i < CPW; ++i) {                               \
@@ -388,7 +388,7 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
         const int bs = lane_value(vbase_nxt, cl);                                   \
         const uint8_t* src = xc + (long long)min((C0) + cl, last_c) * pitch + (t0 + bs) * BNUM / BDEN; \
         _Pragma("unroll") for (int q = 0; q < PM; ++q)                              \
-            pf[i][q] = *reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p)); \
+            pf[i][q] = gload(reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p))); \
     }
 
     DEDISP_LOAD_BASE(0)
@@ -487,10 +487,12 @@ __device__ __forceinline__ void tile_body(const BeamDesc& b, int tile, int block
                         w0[j] = src0[j];
                         w1[j] = src1[j];
                     }
-                    const uint32_t s0 = r0 & 3u, s1 = r1 & 3u;
                     // bytes s, s+1 -> 16-bit lanes of sw[0]; s+2, s+3 -> sw[1]
-                    const uint32_t lo0 = s0 | 0x0C00u | ((s0 + 1u) << 16) | 0x0C000000u;
-                    const uint32_t lo1 = s1 | 0x0C00u | ((s1 + 1u) << 16) | 0x0C000000u;
+                    // (selectors formed in scalar registers: they are
+                    // wave-uniform, and vector ALU slots are the bottleneck)
+                    uint32_t lo0 = (r0 & 3u) * 0x00010001u + 0x0C010C00u;
+                    uint32_t lo1 = (r1 & 3u) * 0x00010001u + 0x0C010C00u;
+                    asm volatile("" : "+s"(lo0), "+s"(lo1));
                     const uint32_t hi0 = lo0 + 0x00020002u, hi1 = lo1 + 0x00020002u;
 #pragma unroll
                     for (int j = 0; j < M; ++j) {
@@ -891,6 +893,13 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
     const int32_t* base_row = wave_uniform_ptr(b.base) + (size_t)block * nchans;
     const int npairs = nchans >> 1;
     const uint32_t* rel_row = wave_uniform_ptr(b.rel) + (size_t)(block * DB + wave) * npairs;
+    // Fields the stores need, read now: a scalar load left in flight across
+    // the channel loop would make every LDS wait in it a wait for all
+    // outstanding reads (scalar and LDS loads share one counter).
+    const int32_t* rowmap = wave_uniform_ptr(b.rowmap);
+    const int out_bytes = wave_uniform(b.out_bytes);
+    const int out_shift = wave_uniform(b.out_shift);
+    asm volatile("" ::"s"(rowmap), "s"(out_bytes), "s"(out_shift));
 
     uint32_t acc[NL][M];
 #pragma unroll
@@ -904,8 +913,8 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
     const int last_c = nchans - 1;
     const int last_p = rq - 1;
 
-#define DEDISP_PLOAD_BASE(C0) vbase_nxt = base_row[min((C0) + (lane < CC ? lane : 0), last_c)];
-#define DEDISP_PLOAD_REL(C0) vrel_nxt = rel_row[min(((C0) >> 1) + (lane < CP ? lane : 0), npairs - 1)];
+#define DEDISP_PLOAD_BASE(C0) vbase_nxt = gload(base_row + min((C0) + (lane < CC ? lane : 0), last_c));
+#define DEDISP_PLOAD_REL(C0) vrel_nxt = gload(rel_row + min(((C0) >> 1) + (lane < CP ? lane : 0), npairs - 1));
 #define DEDISP_PLOAD_DATA(C0)                                                                         \
     _Pragma("unroll") for (int i = 0; i < RPW; ++i) {                                                  \
         const int cl = wave + NW * i;                                                                   \
@@ -913,7 +922,7 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
         const uint8_t* src = xc + (long long)(2 * min((C0) + (cl >> 1), last_c) + (cl & 1)) * pitch + \
                              ((t0 + bs) >> 3);                                                          \
         _Pragma("unroll") for (int q = 0; q < PM; ++q)                                                  \
-            pf[i][q] = *reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p));          \
+            pf[i][q] = gload(reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p)));   \
     }
 
     DEDISP_PLOAD_BASE(0)
@@ -963,10 +972,7 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
 
     const int d = block * DB + wave;
     if (d >= ndm) return;
-    const int32_t* rowmap = wave_uniform_ptr(b.rowmap);
     const int orow_idx = rowmap ? wave_uniform(rowmap[d]) : d;
-    const int out_bytes = wave_uniform(b.out_bytes);
-    const int out_shift = wave_uniform(b.out_shift);
     const bool vec = ((out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
     const bool nvec = ((reinterpret_cast<uintptr_t>(out) & 3) == 0) && ((out_stride & 3) == 0);
 #pragma unroll
