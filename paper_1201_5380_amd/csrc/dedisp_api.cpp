@@ -1489,8 +1489,10 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
             LaunchPlan probe;
             if (resolve_launch(p, c, false, probe) != DEDISP_OK || probe.shape_index != i) continue;
             p->cfg = c;
-            // skip the untiled kernel on big problems: it is never the fastest
-            if (s.kind == 1 && static_cast<double>(nsamps) * p->nchans * p->dms.size() > 1e11)
+            // the untiled kernel is timed only on small problems or when no
+            // tiled shape fits: elsewhere it is never the fastest, and one
+            // launch over a survey-sized input takes hundreds of milliseconds
+            if (s.kind == 1 && best < 1e29f && static_cast<double>(nsamps) * p->nchans * p->dms.size() > 1e9)
                 continue;
             dedisp_status rc = dedisp_execute(p, d_in, nsamps, d_out, stride, stream);
             if (rc != DEDISP_OK) {
