@@ -225,17 +225,20 @@ __device__ __forceinline__ void unpack_planes_tile(const BeamDesc& b, long long 
     }
 }
 
+// Consecutive time tiles write consecutive 16-byte pieces of the same plane
+// rows' 128-byte lines, so they go to one XCD (whose L2 merges the pieces)
+// rather than round-robin over the eight.
 __global__ __launch_bounds__(256) void k_unpack_planes(BeamDesc b)
 {
     __shared__ __attribute__((aligned(16))) uint32_t lds[32 * kPlaneLdsPitch];
-    unpack_planes_tile(b, blockIdx.x, blockIdx.y, lds);
+    unpack_planes_tile(b, xcd_remap((int)blockIdx.x, (int)gridDim.x), blockIdx.y, lds);
 }
 
 template <int NBITS>
 __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
 {
     __shared__ __attribute__((aligned(16))) uint8_t tile[kUC * Store<NBITS>::kPitch];
-    unpack_tile<NBITS>(b, blockIdx.x, blockIdx.y, tile);
+    unpack_tile<NBITS>(b, xcd_remap((int)blockIdx.x, (int)gridDim.x), blockIdx.y, tile);
 }
 
 // Corner turns of up to kMaxBatchDescs beams in one launch: workgroup i

@@ -22,7 +22,9 @@ __global__ __launch_bounds__(256) void k_scrunch(BeamDesc b)
     static_assert(NBITS == 2 || OB == 2, "8-bit sums need 16 bits");
     const int s = b.scrunch;
     const long long ns = b.nsamps / s;             // whole scrunched samples
-    const long long tp0 = (long long)blockIdx.x * ST;
+    // consecutive time tiles write consecutive pieces of the same scratch
+    // lines: one XCD takes a contiguous range of them (its L2 merges the pieces)
+    const long long tp0 = (long long)xcd_remap((int)blockIdx.x, (int)gridDim.x) * ST;
     const int c0 = blockIdx.y * SC;
     const int w = threadIdx.x & 31;                // input word within the row segment
     const int cw = c0 + w * (32 / NBITS);          // first channel of that word
