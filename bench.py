@@ -55,6 +55,15 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
+def tile_arg(text):
+    """A tile shape from "waves,dms_per_wave,words_per_lane,chunk_chans[,sample_format]"."""
+    v = [int(x) for x in text.split(",")]
+    if len(v) not in (4, 5):
+        raise ValueError(f"tile shape {text!r}: four or five integers")
+    return dict(kind=0, waves=v[0], dms_per_wave=v[1], words_per_lane=v[2], chunk_chans=v[3],
+                sample_format=v[4] if len(v) == 5 else -1)
+
+
 def counters_for(path, workload, tile):
     """The committed rocprofv3 counter entry for this workload and tile shape,
     if it was taken on the current kernel sources (else None)."""
@@ -199,10 +208,12 @@ def parse():
     ap.add_argument("--nsamps", type=int, default=1 << 19)
     ap.add_argument("--no-tune", action="store_true", help="use the default tile shape")
     ap.add_argument("--tile", default=None,
-                    help="waves,dms_per_wave,words_per_lane,chunk_chans: use this shape, no tuning")
+                    help="waves,dms_per_wave,words_per_lane,chunk_chans[,sample_format]: use this shape, "
+                         "no tuning")
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--large-tile", default=None,
-                    help="waves,dms_per_wave,words_per_lane,chunk_chans for the large beam: no tuning")
+                    help="waves,dms_per_wave,words_per_lane,chunk_chans[,sample_format] for the large beam: "
+                         "no tuning")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget for the oracle baseline")
@@ -476,8 +487,7 @@ def bench_large(torch, dev, steps, counters_json, tile=None, cache_path=None):
     nout = nsamps - plan.max_delay
     out = torch.empty((ndm, nout), dtype=torch.int32, device=dev)
     if tile:
-        w, dpw, m, cc = (int(x) for x in tile.split(","))
-        plan.set_tile_config(dict(kind=0, waves=w, dms_per_wave=dpw, words_per_lane=m, chunk_chans=cc))
+        plan.set_tile_config(tile_arg(tile))
     else:
         plan.tune(inp, out, nsamps, cache_path=cache_path)
     plan.execute(inp, nsamps, out=out)
@@ -662,9 +672,7 @@ def main():
 
     tune_ms = None
     if args.tile:
-        w, dpw, m, cc = (int(x) for x in args.tile.split(","))
-        plan.set_tile_config(dict(kind=0, waves=w, dms_per_wave=dpw, words_per_lane=m,
-                                  chunk_chans=cc))
+        plan.set_tile_config(tile_arg(args.tile))
     elif not args.no_tune:
         tune_ms = plan.tune(inp, out, nsamps, cache_path=args.tune_cache)
     cfg = plan.tile_config()

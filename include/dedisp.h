@@ -276,13 +276,16 @@ dedisp_status dedisp_set_subband(dedisp_plan plan, int nsub, int ngroup);
  * channel-major scratch, i.e. words_per_lane times the samples a word holds
  * (`sample_format`: 0 = 2-bit codes as nibbles, 8 per word; 1 = bytes, 4;
  * 2 = small byte sums, 4; 3 = 16-bit sums, 2; 4 = 2-bit codes as two bit
- * planes, 32 per word of each plane), so a tile is 64 lanes times that;
+ * planes, 32 per word of each plane; 5 = the same bit planes with the output
+ * cut into 32 time segments, bit i of a word holding segment i, so that a
+ * delay moves whole words), so a tile is 64 lanes times that;
  * `chunk_chans` channels are staged in LDS at a time.  kind = 0 is the
  * LDS-tiled kernel, kind = 1 the untiled fallback (no LDS; used
  * automatically when a tile would not fit).  The plan's bit depth and
  * channel count fix the scratch format (2-bit codes are bit planes up to
- * 1365 channels, nibbles beyond); `sample_format` is reported by the getters
- * and ignored by dedisp_set_tile_config. */
+ * 1365 channels, nibbles beyond); `sample_format` is reported by the getters;
+ * dedisp_set_tile_config reads it only on a bit-plane plan, where 5 selects
+ * the segmented planes and any other value the plain ones. */
 typedef struct {
     int kind;
     int waves;

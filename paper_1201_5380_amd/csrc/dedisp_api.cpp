@@ -160,12 +160,19 @@ bool build_delay_table(const dedisp_plan_s& p, const double* dms, int ndm,
 // rows (the live channels in order, then zero rows up to a multiple of 8):
 // base[b][k] is the smallest delay of row k's channel over the block,
 // rounded down to 16 bytes of scratch (32 two-bit or 16 eight-bit samples,
-// so staged windows start on 16-byte boundaries); the window offset of DM row d, scratch row k is
+// 128 samples of a bit plane, 4 words of the interleaved bit planes, whose
+// words advance one sample each, so staged windows start on 16-byte
+// boundaries); the window offset of DM row d, scratch row k is
 // delay[d][c(k)] - base[b][k] (0 for padding DM rows past ndm and for the
 // zero rows), stored for row pairs: rel[d][p] = off(2p) | off(2p+1) << 16.
-// relmax is the largest offset (always < 2^16 for a shape that fits).
-void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
+// relmax is the largest offset (always < 2^16 for a shape that fits).  For
+// the interleaved bit planes base holds (start, span) pairs, span = the
+// largest offset of the row over the block, so a row's window is staged only
+// as far as its own DMs read.
+void build_block_tables(const dedisp_plan_s& p, int db, int fmt, BlockTables& bt)
 {
+    const int bstride = fmt == dedisp::kFmtSeg ? 2 : 1;
+    const int align = fmt == dedisp::kFmtSeg ? 4 : 16 * dedisp::fmt_bytes_den(fmt) / dedisp::fmt_bytes_num(fmt);
     const int ndm = static_cast<int>(p.dms.size());
     const int nch = p.nchans;
     const int nrow = p.nact_padded();     // scratch rows: live channels, then zero rows
@@ -174,7 +181,7 @@ void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
     bt.db = db;
     bt.nblocks = (ndm + db - 1) / db;
     const size_t rel_per_group = static_cast<size_t>(bt.nblocks) * db * np;
-    const size_t base_per_group = static_cast<size_t>(bt.nblocks) * nrow;
+    const size_t base_per_group = static_cast<size_t>(bt.nblocks) * nrow * bstride;
     bt.rel.assign(rel_per_group * p.ngroups, 0u);
     bt.base.assign(base_per_group * p.ngroups, 0);
     bt.relmax = 0;
@@ -189,29 +196,38 @@ void build_block_tables(const dedisp_plan_s& p, int db, BlockTables& bt)
             int mn = 0x7fffffff;
             for (int d = d0; d < d1; ++d)
                 mn = std::min(mn, table[static_cast<size_t>(d) * nch + c]);
-            mn &= ~(16 * dedisp::fmt_bytes_den(p.fmt) / dedisp::fmt_bytes_num(p.fmt) - 1);
-            base[static_cast<size_t>(b) * nrow + k] = mn;
+            mn &= ~(align - 1);
+            int span = 0;
             for (int d = d0; d < d1; ++d) {
                 const int r = table[static_cast<size_t>(d) * nch + c] - mn;
                 bt.relmax = std::max(bt.relmax, r);
+                span = std::max(span, r);
                 const uint32_t v = static_cast<uint32_t>(std::min(r, 0xFFFF));
                 rel[static_cast<size_t>(d) * np + k / 2] |= (k & 1) ? (v << 16) : v;
             }
+            const size_t at = (static_cast<size_t>(b) * nrow + k) * bstride;
+            base[at] = mn;
+            if (bstride == 2) base[at + 1] = span;
         }
         }
     }
 }
 
+// A bit-plane plan also runs the interleaved bit-plane shapes.
 bool shape_matches(const Shape& s, const dedisp_plan_s& p)
 {
-    return s.kind == 0 ? s.fmt == p.fmt : s.fmt == p.nbits;
+    if (s.kind != 0) return s.fmt == p.nbits;
+    return s.fmt == p.fmt || (s.fmt == dedisp::kFmtSeg && p.fmt == dedisp::kFmtPlane);
 }
 
+// The shape of config c: for a bit-plane plan, sample_format kFmtSeg picks
+// the interleaved layout and any other value the plain one.
 const Shape* find_shape(const dedisp_tile_config& c, const dedisp_plan_s& p, int* index)
 {
     for (int i = 0; i < dedisp::shape_count(); ++i) {
         const Shape& s = dedisp::shape_at(i);
         if (!shape_matches(s, p) || s.kind != c.kind) continue;
+        if (s.kind == 0 && (s.fmt == dedisp::kFmtSeg) != (c.sample_format == dedisp::kFmtSeg)) continue;
         if (s.kind == 1 || (s.waves == c.waves && s.dpw == c.dms_per_wave &&
                             s.m == c.words_per_lane && s.cc == c.chunk_chans)) {
             if (index) *index = i;
@@ -274,13 +290,13 @@ dedisp_status ensure_device_table(dedisp_plan p)
     return DEDISP_OK;
 }
 
-dedisp_status ensure_block_tables(dedisp_plan p, int db, BlockTables** out)
+dedisp_status ensure_block_tables(dedisp_plan p, int db, int fmt, BlockTables** out)
 {
-    auto it = p->blocks.find(db);
+    auto it = p->blocks.find(block_key(db, fmt));
     if (it == p->blocks.end()) {
         BlockTables bt;
-        build_block_tables(*p, db, bt);
-        it = p->blocks.emplace(db, std::move(bt)).first;
+        build_block_tables(*p, db, fmt, bt);
+        it = p->blocks.emplace(block_key(db, fmt), std::move(bt)).first;
     }
     BlockTables& bt = it->second;
     if (!bt.d_rel) {
@@ -306,8 +322,11 @@ dedisp_status ensure_block_tables(dedisp_plan p, int db, BlockTables** out)
 
 // Window length (32-bit words per channel row in LDS, a multiple of 4) of
 // shape s: a lane reads words up to rel / (samples per word) + 64*m.
+// (Interleaved bit planes: offsets are in words, and a lane reads no word
+// past its last.)
 int window_words(const BlockTables& bt, const Shape& s)
 {
+    if (s.fmt == dedisp::kFmtSeg) return (bt.relmax + 64 * s.m + 3) & ~3;
     return ((bt.relmax / dedisp::fmt_samples_per_word(s.fmt) + 64 * s.m + 1) + 3) & ~3;
 }
 
@@ -316,6 +335,7 @@ int window_words(const BlockTables& bt, const Shape& s)
 int chunk_lds_bytes(const Shape& s, int rw)
 {
     if (s.fmt == dedisp::kFmtPlane) return s.cc * 2 * dedisp::kPlaneRowWords * 4;
+    if (s.fmt == dedisp::kFmtSeg) return s.cc * 2 * dedisp::kSegRowWords * 4;
     return s.cc * rw * 4;
 }
 
@@ -323,6 +343,7 @@ bool shape_fits(const BlockTables& bt, const Shape& s)
 {
     const int rw = window_words(bt, s);
     if (s.fmt == dedisp::kFmtPlane && rw > dedisp::kPlaneRowWords) return false;
+    if (s.fmt == dedisp::kFmtSeg && rw > dedisp::kSegRowWords) return false;
     return bt.relmax < 0x10000 && (rw >> 2) <= 64 * s.pi &&
            static_cast<long long>(chunk_lds_bytes(s, rw)) <= dedisp::kMaxLdsBytes;
 }
@@ -366,17 +387,18 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
     if (want.kind == 1 && !multi_only) order.clear();
     for (int i : order) {
         const Shape& s = dedisp::shape_at(i);
-        if (s.fmt != p->fmt || s.kind != 0 || !tiled_supported(*p)) continue;
+        if (s.kind != 0 || !shape_matches(s, *p) || !tiled_supported(*p)) continue;
         const int db = s.waves * s.dpw;
+        const int key = block_key(db, s.fmt);
         const BlockTables* bt = nullptr;
-        auto it = p->blocks.find(db);
+        auto it = p->blocks.find(key);
         if (it != p->blocks.end()) {
             bt = &it->second;
         } else {
-            auto h = host_tables.find(db);
+            auto h = host_tables.find(key);
             if (h == host_tables.end()) {
-                h = host_tables.emplace(db, BlockTables{}).first;
-                build_block_tables(*p, db, h->second);
+                h = host_tables.emplace(key, BlockTables{}).first;
+                build_block_tables(*p, db, s.fmt, h->second);
             }
             bt = &h->second;
         }
@@ -402,7 +424,7 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
         lp.bt = nullptr;
         if (upload) {
             BlockTables* dbt = nullptr;
-            dedisp_status st = ensure_block_tables(p, db, &dbt);
+            dedisp_status st = ensure_block_tables(p, db, s.fmt, &dbt);
             if (st != DEDISP_OK) return st;
             lp.bt = dbt;
         }
@@ -435,9 +457,12 @@ long long tile_len(const Shape& s) { return 64LL * dedisp::fmt_samples_per_word(
 
 // Row pitch in bytes of the channel-major scratch holding nsamps samples of
 // format fmt: a staged window starts before the last sample and spans 4*rw
-// bytes.
-long long xc_pitch(long long nsamps, int fmt, int rw)
+// bytes.  The interleaved bit planes hold seg_row_words words (a window
+// starts before word seg_len + max_delay).
+long long xc_pitch(long long nsamps, int fmt, int rw, long long max_delay)
 {
+    if (fmt == dedisp::kFmtSeg)
+        return ((4 * dedisp::seg_row_words(nsamps - max_delay, max_delay, rw) + 63) / 64) * 64;
     const long long num = dedisp::fmt_bytes_num(fmt), den = dedisp::fmt_bytes_den(fmt);
     const long long bytes = (nsamps * num + den - 1) / den;
     return ((bytes + 4LL * rw + 63) / 64) * 64;
@@ -470,7 +495,7 @@ dedisp_status ensure_xc(const dedisp_plan_s& p, Scratch& x, long long nsamps, co
 {
     if (lp.shape.kind != 0) return DEDISP_OK;
     const long long ns = nsamps / p.scrunch;
-    return ensure_scratch(x, static_cast<size_t>(xc_pitch(ns, lp.shape.fmt, lp.rw)) * p.nact_padded() *
+    return ensure_scratch(x, static_cast<size_t>(xc_pitch(ns, lp.shape.fmt, lp.rw, p.max_delay)) * p.nact_padded() *
                                  dedisp::fmt_rows(lp.shape.fmt));
 }
 
@@ -505,7 +530,7 @@ void fill_desc(dedisp_plan p, const LaunchPlan& lp, const void* in0, long long n
     if (lp.shape.kind == 0) {
         d.xc = xc;
         d.xc_fmt = lp.shape.fmt;
-        d.pitch = xc_pitch(nsamps / p->scrunch, lp.shape.fmt, lp.rw);
+        d.pitch = xc_pitch(nsamps / p->scrunch, lp.shape.fmt, lp.rw, p->max_delay);
         d.rel = lp.bt->d_rel;
         d.base = lp.bt->d_base;
         d.nblocks = lp.bt->nblocks;
@@ -920,7 +945,7 @@ static dedisp_status execute_groups(dedisp_plan p, const void* d_in, size_t nsam
         }
         if (lps[i].shape.kind == 0) {
             const long long ns = static_cast<long long>(nsamps) / sub->scrunch;
-            need = std::max(need, static_cast<size_t>(xc_pitch(ns, lps[i].shape.fmt, lps[i].rw)) *
+            need = std::max(need, static_cast<size_t>(xc_pitch(ns, lps[i].shape.fmt, lps[i].rw, sub->max_delay)) *
                                       sub->nact_padded() * dedisp::fmt_rows(lps[i].shape.fmt));
         }
         ScrunchGroup& g = p->groups[i];
@@ -977,8 +1002,8 @@ static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsa
     if (st != DEDISP_OK) return st;
     const int nsub = p->sb_nsub, ngroup = p->sb_ngroup;
     const int nsb = p->nchans / nsub, nsb_p = s2->nchans, nnom = s1->ndm_last;
-    const long long pitch1 = xc_pitch(static_cast<long long>(nsamps), s1->fmt, lp1.rw);
-    const long long pitch2 = xc_pitch(len1, s2->fmt, lp2.rw);
+    const long long pitch1 = xc_pitch(static_cast<long long>(nsamps), s1->fmt, lp1.rw, 0);
+    const long long pitch2 = xc_pitch(len1, s2->fmt, lp2.rw, 0);
     st = ensure_scratch(p->xc, static_cast<size_t>(pitch1) * p->nchans);
     if (st != DEDISP_OK) return st;
     st = ensure_scratch(p->sb_xc2, static_cast<size_t>(pitch2) * nsb_p * nnom);
@@ -1166,7 +1191,7 @@ static dedisp_status run_tree(dedisp_plan p, const void* d_in, size_t nsamps, ui
     const int tfmt = p->fmt == dedisp::kFmtPlane ? kFmtNib : p->fmt;
     const long long pitch1 = xc_pitch(ns + dedisp::tree_tile(nsub) + nsub +
                                           static_cast<long long>(p->tree_npass - 1) * (nsub - 1) + 8,
-                                      tfmt, 0);
+                                      tfmt, 0, 0);
     const int ob = tree_row_bytes(*p);
     const long long pitch2 = ((ob * len1 + 64) + 63) / 64 * 64;
     dedisp_status st = ensure_scratch(p->xc, static_cast<size_t>(pitch1) * p->nchans);
@@ -1463,6 +1488,7 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
         c.dms_per_wave = static_cast<int>(hit->second[2]);
         c.words_per_lane = static_cast<int>(hit->second[3]);
         c.chunk_chans = static_cast<int>(hit->second[4]);
+        c.sample_format = hit->second.size() > 6 ? static_cast<int>(hit->second[6]) : -1;
         if (find_shape(c, *p)) {
             p->cfg = c;
             if (best_ms) *best_ms = hit->second.size() > 5 ? static_cast<float>(hit->second[5]) : 0.f;
@@ -1485,6 +1511,7 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
             c.dms_per_wave = s.dpw;
             c.words_per_lane = s.m;
             c.chunk_chans = s.cc;
+            c.sample_format = s.kind == 0 ? s.fmt : -1;
             // a shape whose window does not fit would silently time another one
             LaunchPlan probe;
             if (resolve_launch(p, c, false, probe) != DEDISP_OK || probe.shape_index != i) continue;
@@ -1532,7 +1559,8 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
         cache[key] = {static_cast<double>(best_cfg.kind), static_cast<double>(best_cfg.waves),
                       static_cast<double>(best_cfg.dms_per_wave),
                       static_cast<double>(best_cfg.words_per_lane),
-                      static_cast<double>(best_cfg.chunk_chans), static_cast<double>(best)};
+                      static_cast<double>(best_cfg.chunk_chans), static_cast<double>(best),
+                      static_cast<double>(best_cfg.sample_format)};
         write_cache(cache_path, cache);
     }
     return DEDISP_OK;

@@ -94,6 +94,7 @@ dedisp_tile_config config_of(const Shape& s)
     c.dms_per_wave = s.dpw;
     c.words_per_lane = s.m;
     c.chunk_chans = s.cc;
+    c.sample_format = s.kind == 0 ? s.fmt : -1;
     return c;
 }
 

@@ -29,7 +29,7 @@ struct BlockTables {
     int nblocks = 0;
     int relmax = 0;
     std::vector<uint32_t> rel;   // [nblocks*db][nchans/2], channel pairs packed 16+16 bits
-    std::vector<int32_t> base;   // [nblocks][nchans]
+    std::vector<int32_t> base;   // [nblocks][nchans] ([nblocks][nchans][2] start, span: kFmtSeg)
     uint32_t* d_rel = nullptr;
     int32_t* d_base = nullptr;
 };
@@ -88,7 +88,13 @@ dedisp_status resolve_launch(::dedisp_plan p, const dedisp_tile_config& want, bo
                              LaunchPlan& lp, bool multi_only = false);
 
 long long tile_len(const Shape& s);
-long long xc_pitch(long long nsamps, int fmt, int rw);
+// Row pitch (bytes) of the channel-major scratch for nsamps input samples
+// (max_delay: the plan's, which fixes the interleaved format's segments).
+long long xc_pitch(long long nsamps, int fmt, int rw, long long max_delay);
+// Key of a plan's window tables: DM-block size and window granularity (the
+// interleaved bit-plane format aligns windows to 4 words, the others to 16
+// bytes of scratch).
+inline int block_key(int db, int fmt) { return 2 * db + (fmt == dedisp::kFmtSeg ? 1 : 0); }
 void free_scratch(Scratch& x);
 dedisp_status ensure_scratch(Scratch& x, size_t need);
 dedisp_status ensure_xc(const struct ::dedisp_plan_s& p, Scratch& x, long long nsamps,
@@ -155,7 +161,7 @@ struct dedisp_plan_s {
     dedisp_tile_config cfg{};
     int device = -1;
     int32_t* d_table = nullptr;
-    std::map<int, dedisp::host::BlockTables> blocks;  // keyed by DM-block size
+    std::map<int, dedisp::host::BlockTables> blocks;  // keyed by block_key(DM-block size, format)
     dedisp::host::Scratch xc;                          // channel-major scratch for execute
     // Channel kill mask (empty = every channel on): live channels in order,
     // and the device copies the kernels read.

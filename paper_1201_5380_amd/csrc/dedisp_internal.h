@@ -15,14 +15,28 @@ enum Fmt : int {
     kFmtHalf = 3,    // 16-bit values at most 32767 (time-scrunched 8-bit, or heavily scrunched 2-bit, codes)
     kFmtPlane = 4,   // 2-bit codes as two bit planes: scratch row 2k + p holds bit p of row k's
                      // codes, 32 samples per 32-bit word (sample 32w + i at bit i of word w)
+    kFmtSeg = 5,     // two bit planes of 32 interleaved time segments: the outputs are cut
+                     // into 32 segments of S = seg_len(nout) samples and bit i of word j of
+                     // row 2k + p holds bit p of sample j + S*i, so a delay of n samples is
+                     // a shift of n whole words
 };
 // bytes per sample of one scratch row = num / den
 constexpr int fmt_bytes_num(int fmt) { return fmt == kFmtHalf ? 2 : 1; }
-constexpr int fmt_bytes_den(int fmt) { return fmt == kFmtNib ? 2 : fmt == kFmtPlane ? 8 : 1; }
+constexpr int fmt_bytes_den(int fmt) { return fmt == kFmtNib ? 2 : fmt == kFmtPlane || fmt == kFmtSeg ? 8 : 1; }
 constexpr int fmt_samples_per_word(int fmt) { return 4 * fmt_bytes_den(fmt) / fmt_bytes_num(fmt); }
+constexpr bool fmt_planes(int fmt) { return fmt == kFmtPlane || fmt == kFmtSeg; }
 // scratch rows per channel row and channel rows per unit of the summation
-constexpr int fmt_rows(int fmt) { return fmt == kFmtPlane ? 2 : 1; }
-constexpr int fmt_chan_unit(int fmt) { return fmt == kFmtPlane ? 32 : 8; }
+constexpr int fmt_rows(int fmt) { return fmt_planes(fmt) ? 2 : 1; }
+constexpr int fmt_chan_unit(int fmt) { return fmt_planes(fmt) ? 32 : 8; }
+// Segment length of the interleaved bit-plane format for nout outputs, and
+// the number of words of its scratch rows (every segment's outputs and the
+// max_delay samples after the last, plus a staged window of rw words past a
+// whole number of 512-word tiles).
+__host__ __device__ constexpr long long seg_len(long long nout) { return (nout + 31) / 32; }
+constexpr long long seg_row_words(long long nout, long long max_delay, int rw)
+{
+    return (seg_len(nout) + 511) / 512 * 512 + max_delay + rw + 64;
+}
 
 // Bit-plane sums: bit levels kept per sample (sums of up to 3 * 1365 two-bit
 // codes) and the LDS row length of one staged plane (32-bit words; plane 1
@@ -30,6 +44,9 @@ constexpr int fmt_chan_unit(int fmt) { return fmt == kFmtPlane ? 32 : 8; }
 constexpr int kPlaneLevels = 12;
 constexpr int kPlaneMaxChans = ((1 << kPlaneLevels) - 1) / 3;
 constexpr int kPlaneRowWords = 224;
+// LDS row length of one staged plane of the interleaved format: a tile's 64M
+// words plus the spread of the DM block's delays, in whole words.
+constexpr int kSegRowWords = 512;
 
 // One beam (or one stream push) as the kernels see it.  The input is a
 // virtual concatenation of two row segments so that a stream's resident
@@ -46,7 +63,8 @@ struct BeamDesc {
     uint8_t* xc;              // channel-major scratch written by the unpack or scrunch kernel
     long long pitch;          // bytes between channel rows of xc (multiple of 16)
     const uint32_t* rel;      // [nblocks*DB][nchans/2] window offsets of channel pairs (16+16 bits)
-    const int32_t* base;      // [nblocks][nchans] window start (multiple of 16 bytes of scratch)
+    const int32_t* base;      // [nblocks][nchans] window start (multiple of 16 bytes of scratch);
+                              // kFmtSeg: [nblocks][nchans][2] (start, span)
     const int32_t* table;     // [ndm][nchans] full delay table (untiled kernel)
     const int32_t* chanmap;   // [nchans] scratch row of each channel, -1 = killed (NULL = identity)
     const int32_t* mask;      // [nchans] 0/1 kill mask for the untiled kernel (NULL = all on)

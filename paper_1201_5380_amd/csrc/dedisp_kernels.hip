@@ -186,17 +186,24 @@ __device__ __forceinline__ void transpose32(uint32_t (&a)[32])
     }
 }
 
+//
+// The interleaved format (SEG, kFmtSeg) uses the same transpose with other
+// rows: workgroup bx covers the four scratch words 4bx .. 4bx+3, wave w word
+// j = 4bx + w, whose row i is input sample j + S*i (S = seg_len(nout)); every
+// word of the scratch rows is written, zeros past the last sample.
+template <bool SEG>
 __device__ __forceinline__ void unpack_planes_tile(const BeamDesc& b, long long bx, int by, uint32_t* lds)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int ndw = b.nchans >> 4;                  // input words per row
     const int g = by * kPlaneTileW + lane;
-    const long long t0 = bx * kPlaneTileT;
+    const long long t0 = SEG ? 4 * bx + wave : bx * kPlaneTileT + 32 * wave;
+    const long long step = SEG ? seg_len(b.nout) : 1;
     uint32_t a[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) {
-        const long long t = t0 + 32 * wave + i;
+        const long long t = t0 + step * i;
         a[i] = (t < b.nsamps && g < ndw) ? *reinterpret_cast<const uint32_t*>(row_ptr(b, t) + 4LL * g) : 0u;
     }
     transpose32(a);
@@ -205,8 +212,8 @@ __device__ __forceinline__ void unpack_planes_tile(const BeamDesc& b, long long 
     __syncthreads();
     // one 16-byte store per (channel, plane) row: item i -> word column
     // i / 32, bit row k = i % 32 (channel 16g + k/2, plane k%2)
-    const long long byte0 = t0 >> 3;
-    if (t0 < b.nsamps) {
+    const long long byte0 = SEG ? 16 * bx : bx * (kPlaneTileT / 8);
+    if (SEG || bx * kPlaneTileT < b.nsamps) {
         for (int i = threadIdx.x; i < kPlaneTileW * 32; i += 256) {
             const int l = i >> 5, k = i & 31;
             const int c = 16 * (by * kPlaneTileW + l) + (k >> 1);
@@ -231,7 +238,13 @@ __device__ __forceinline__ void unpack_planes_tile(const BeamDesc& b, long long 
 __global__ __launch_bounds__(256) void k_unpack_planes(BeamDesc b)
 {
     __shared__ __attribute__((aligned(16))) uint32_t lds[32 * kPlaneLdsPitch];
-    unpack_planes_tile(b, xcd_remap((int)blockIdx.x, (int)gridDim.x), blockIdx.y, lds);
+    unpack_planes_tile<false>(b, xcd_remap((int)blockIdx.x, (int)gridDim.x), blockIdx.y, lds);
+}
+
+__global__ __launch_bounds__(256) void k_unpack_seg(BeamDesc b)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t lds[32 * kPlaneLdsPitch];
+    unpack_planes_tile<true>(b, xcd_remap((int)blockIdx.x, (int)gridDim.x), blockIdx.y, lds);
 }
 
 template <int NBITS>
@@ -246,12 +259,13 @@ __global__ __launch_bounds__(256) void k_unpack(BeamDesc b)
 // by beam; the beam's input bit depth (b.in_nbits) picks the unpack.
 __host__ __device__ inline long long unpack_grid_x(const BeamDesc& b)
 {
+    if (b.xc_fmt == kFmtSeg) return b.pitch / 16;      // four words of every row per workgroup
     const int t = b.xc_fmt == kFmtPlane ? kPlaneTileT : kUT;
     return (b.nsamps + t - 1) / t;
 }
 __host__ __device__ inline long long unpack_grid_y(const BeamDesc& b)
 {
-    return b.xc_fmt == kFmtPlane ? ((b.nchans >> 4) + kPlaneTileW - 1) / kPlaneTileW : (b.nchans + kUC - 1) / kUC;
+    return fmt_planes(b.xc_fmt) ? ((b.nchans >> 4) + kPlaneTileW - 1) / kPlaneTileW : (b.nchans + kUC - 1) / kUC;
 }
 
 __global__ __launch_bounds__(256) void k_unpack_multi(DescBlock blk, int nbeams)
@@ -267,7 +281,7 @@ __global__ __launch_bounds__(256) void k_unpack_multi(DescBlock blk, int nbeams)
         if (id < units) {
             const long long bx = id % gx;
             const int by = (int)(id / gx);
-            if (b.xc_fmt == kFmtPlane) unpack_planes_tile(b, bx, by, reinterpret_cast<uint32_t*>(tile));
+            if (b.xc_fmt == kFmtPlane) unpack_planes_tile<false>(b, bx, by, reinterpret_cast<uint32_t*>(tile));
             else if (b.in_nbits == 2) unpack_tile<2>(b, bx, by, tile);
             else unpack_tile<8>(b, bx, by, tile);
             return;
@@ -740,31 +754,43 @@ __device__ __forceinline__ uint32_t ha(uint32_t& s, uint32_t x)
 // starting `row0` words after the lane's base (plane 1 RWS words after plane
 // 0).  The word offset is formed in a scalar register, so one vector add
 // gives the address and every read takes an immediate offset.
-template <int M, int RWS>
+//
+// Interleaved format (SEG): r is the offset in whole words and lane l owns
+// words l, l + 64, ..., l + 64(M-1) of the tile, so the words need no
+// realignment and the 64 lanes of a read hit 64 consecutive words.
+template <int M, int RWS, bool SEG>
 __device__ __forceinline__ void plane_words(const uint32_t* lrow, int row0, uint32_t r, uint32_t (&a)[M],
                                             uint32_t (&b)[M])
 {
-    int off = row0 + (int)(r >> 5);
+    int off = row0 + (int)(SEG ? r : r >> 5);
     asm volatile("" : "+s"(off));       // keep the constant row part out of the address fold
     const uint32_t* src = lrow + off;
-    uint32_t w0[M + 1], w1[M + 1];
+    if constexpr (SEG) {
 #pragma unroll
-    for (int j = 0; j <= M; ++j) {
-        w0[j] = src[j];
-        w1[j] = src[RWS + j];
-    }
-    const uint32_t sh = r & 31u;
+        for (int j = 0; j < M; ++j) {
+            a[j] = src[64 * j];
+            b[j] = src[RWS + 64 * j];
+        }
+    } else {
+        uint32_t w0[M + 1], w1[M + 1];
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-        a[j] = __builtin_amdgcn_alignbit(w0[j + 1], w0[j], sh);
-        b[j] = __builtin_amdgcn_alignbit(w1[j + 1], w1[j], sh);
+        for (int j = 0; j <= M; ++j) {
+            w0[j] = src[j];
+            w1[j] = src[RWS + j];
+        }
+        const uint32_t sh = r & 31u;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            a[j] = __builtin_amdgcn_alignbit(w0[j + 1], w0[j], sh);
+            b[j] = __builtin_amdgcn_alignbit(w1[j + 1], w1[j], sh);
+        }
     }
 }
 
 // Four channels (LDS rows of channel j at row + 2*j*RWS; offset pairs in
 // lanes pair0, pair0 + 1 of voff) into the accumulators; returns their three
 // carries of weight 4 in k4.
-template <int M, int RWS>
+template <int M, int RWS, bool SEG>
 __device__ __forceinline__ void plane_quad(uint32_t (&acc)[kPlaneLevels][M], const uint32_t* lrow, int row,
                                            uint32_t voff, int pair0, uint32_t (&k4)[3][M])
 {
@@ -773,8 +799,8 @@ __device__ __forceinline__ void plane_quad(uint32_t (&acc)[kPlaneLevels][M], con
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const uint32_t rr = (uint32_t)lane_value((int)voff, pair0 + h);
-        plane_words<M, RWS>(lrow, row + (4 * h) * RWS, rr & 0xFFFFu, a0, b0);
-        plane_words<M, RWS>(lrow, row + (4 * h + 2) * RWS, rr >> 16, a1, b1);
+        plane_words<M, RWS, SEG>(lrow, row + (4 * h) * RWS, rr & 0xFFFFu, a0, b0);
+        plane_words<M, RWS, SEG>(lrow, row + (4 * h + 2) * RWS, rr >> 16, a1, b1);
 #pragma unroll
         for (int j = 0; j < M; ++j) {
             k2[h][j] = fa(acc[0][j], a0[j], a1[j]);
@@ -798,36 +824,36 @@ __device__ __forceinline__ void plane_fold(uint32_t (&accl)[M], const uint32_t (
     }
 }
 
-template <int M, int RWS>
+template <int M, int RWS, bool SEG>
 __device__ __forceinline__ void plane_octet(uint32_t (&acc)[kPlaneLevels][M], const uint32_t* lrow, int row,
                                             uint32_t voff, int pair0, uint32_t (&k8)[3][M])
 {
     uint32_t p[3][M], q[3][M];
-    plane_quad<M, RWS>(acc, lrow, row, voff, pair0, p);
-    plane_quad<M, RWS>(acc, lrow, row + 8 * RWS, voff, pair0 + 2, q);
+    plane_quad<M, RWS, SEG>(acc, lrow, row, voff, pair0, p);
+    plane_quad<M, RWS, SEG>(acc, lrow, row + 8 * RWS, voff, pair0 + 2, q);
     plane_fold<M>(acc[2], p, q, k8);
 }
 
-template <int M, int RWS>
+template <int M, int RWS, bool SEG>
 __device__ __forceinline__ void plane_sixteen(uint32_t (&acc)[kPlaneLevels][M], const uint32_t* lrow, int row,
                                               uint32_t voff, int pair0, uint32_t (&k16)[3][M])
 {
     uint32_t p[3][M], q[3][M];
-    plane_octet<M, RWS>(acc, lrow, row, voff, pair0, p);
-    plane_octet<M, RWS>(acc, lrow, row + 16 * RWS, voff, pair0 + 4, q);
+    plane_octet<M, RWS, SEG>(acc, lrow, row, voff, pair0, p);
+    plane_octet<M, RWS, SEG>(acc, lrow, row + 16 * RWS, voff, pair0 + 4, q);
     plane_fold<M>(acc[3], p, q, k16);
 }
 
 // 32 channels (LDS rows from word `row` of the lane's base on): the full
 // schedule down to the top level (the sum of at most kPlaneMaxChans codes of
 // 3 never carries out of it).
-template <int M, int RWS>
+template <int M, int RWS, bool SEG>
 __device__ __forceinline__ void plane_unit(uint32_t (&acc)[kPlaneLevels][M], const uint32_t* lrow, int row,
                                            uint32_t voff, int pair0)
 {
     uint32_t p[3][M], q[3][M], k32[3][M];
-    plane_sixteen<M, RWS>(acc, lrow, row, voff, pair0, p);
-    plane_sixteen<M, RWS>(acc, lrow, row + 32 * RWS, voff, pair0 + 8, q);
+    plane_sixteen<M, RWS, SEG>(acc, lrow, row, voff, pair0, p);
+    plane_sixteen<M, RWS, SEG>(acc, lrow, row + 32 * RWS, voff, pair0 + 8, q);
     plane_fold<M>(acc[4], p, q, k32);
 #pragma unroll
     for (int j = 0; j < M; ++j) {
@@ -859,31 +885,35 @@ __device__ __forceinline__ void transpose16x2(uint32_t (&r)[16])
     }
 }
 
-// One (time tile, DM block) work item of the bit-plane format: NW waves,
+// One (time tile, DM block) work item of the bit-plane formats: NW waves,
 // one DM per wave, M plane words (32M samples) per lane, CC channels per
 // staged chunk (a multiple of 32).  LDS: CC channels x 2 planes x RWS words
 // (plane p of chunk channel c at row 2c + p); the staged window of a plane is
-// b.rw <= RWS words long.  Window tables as for tile_body (offsets in
-// samples, window starts multiples of 128 samples).
-template <int NW, int M, int CC, int PM>
+// b.rw <= RWS words long.  Window tables as for tile_body: offsets in
+// samples, window starts multiples of 128 samples (kFmtPlane), or offsets
+// and starts in words, the starts multiples of 4 (SEG: kFmtSeg, where a
+// tile is the words 64M*tile .. +64M-1 of every row, i.e. 64M outputs of
+// each of the 32 segments).
+template <int NW, int M, int CC, int PM, bool SEG>
 __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int block, uint32_t* lds)
 {
-    constexpr int RWS = kPlaneRowWords;
-    constexpr int T = 64 * M * 32;               // tile length in samples
+    constexpr int RWS = SEG ? kSegRowWords : kPlaneRowWords;
+    constexpr int T = 64 * M * 32;               // tile length in samples (kFmtPlane)
     constexpr int DB = NW;                       // one DM per wave
     constexpr int RPW = 2 * CC / NW;             // plane rows staged per wave per chunk
     constexpr int CP = CC / 2;                   // channel pairs per chunk
     constexpr int NL = kPlaneLevels;
-    static_assert(M % 2 == 1, "lanes must be an odd number of LDS words apart");
+    static_assert(SEG || M % 2 == 1, "lanes must be an odd number of LDS words apart");
     static_assert(CC % 32 == 0 && (2 * CC) % NW == 0 && CP <= 64, "bad chunk");
-    static_assert(RWS + M < 256, "plane 1 is read at an 8-bit dword offset from plane 0");
-    static_assert(RWS % 4 == 0 && RWS >= 64 * M + 8, "staged rows too short for the tile");
+    static_assert(SEG || RWS + M < 256, "plane 1 is read at an 8-bit dword offset from plane 0");
+    static_assert(RWS % 4 == 0 && RWS >= 64 * M + 8 && RWS <= 256 * PM, "staged rows too short for the tile");
 
     const int lane = threadIdx.x & 63;
     const int wave = wave_uniform(threadIdx.x >> 6);
     tile = wave_uniform(tile);
     block = wave_uniform(block);
-    const long long t0 = (long long)tile * T;
+    // first sample (kFmtPlane) or word (SEG) of the tile
+    const long long t0 = (long long)tile * (SEG ? 64 * M : T);
     const int nchans = wave_uniform(b.nact);     // a multiple of 32
     const int rw = wave_uniform(b.rw);
     const int rq = rw >> 2;
@@ -893,7 +923,8 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
     const int ndm = wave_uniform(b.ndm);
     const uint8_t* xc = wave_uniform_ptr(b.xc);
     uint32_t* out = wave_uniform_ptr(b.out);
-    const int32_t* base_row = wave_uniform_ptr(b.base) + (size_t)block * nchans;
+    // SEG: (start, span) pairs, span = the block's largest window offset of the row
+    const int32_t* base_row = wave_uniform_ptr(b.base) + (size_t)block * nchans * (SEG ? 2 : 1);
     const int npairs = nchans >> 1;
     const uint32_t* rel_row = wave_uniform_ptr(b.rel) + (size_t)(block * DB + wave) * npairs;
     // Fields the stores need, read now: a scalar load left in flight across
@@ -910,22 +941,33 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
 #pragma unroll
         for (int j = 0; j < M; ++j) acc[L][j] = 0u;
 
-    u32x4 pf[RPW][PM];
+    u32x4 pf[RPW][PM] = {};
     int vbase_nxt = 0;            // lane i < CC: window start of channel c0 + i (next chunk)
+    int vspan_nxt = 0;            // SEG, lane i < CC: its span
     uint32_t vrel_cur = 0, vrel_nxt = 0;
     const int last_c = nchans - 1;
     const int last_p = rq - 1;
 
-#define DEDISP_PLOAD_BASE(C0) vbase_nxt = gload(base_row + min((C0) + (lane < CC ? lane : 0), last_c));
+#define DEDISP_PLOAD_BASE(C0)                                                                         \
+    if constexpr (SEG) {                                                                                \
+        const int32_t* bp = base_row + 2 * min((C0) + (lane < CC ? lane : 0), last_c);                   \
+        vbase_nxt = gload(bp);                                                                          \
+        vspan_nxt = gload(bp + 1);                                                                      \
+    } else {                                                                                            \
+        vbase_nxt = gload(base_row + min((C0) + (lane < CC ? lane : 0), last_c));                        \
+    }
 #define DEDISP_PLOAD_REL(C0) vrel_nxt = gload(rel_row + min(((C0) >> 1) + (lane < CP ? lane : 0), npairs - 1));
 #define DEDISP_PLOAD_DATA(C0)                                                                         \
     _Pragma("unroll") for (int i = 0; i < RPW; ++i) {                                                  \
         const int cl = wave + NW * i;                                                                   \
         const int bs = lane_value(vbase_nxt, cl >> 1);                                                  \
         const uint8_t* src = xc + (long long)(2 * min((C0) + (cl >> 1), last_c) + (cl & 1)) * pitch + \
-                             ((t0 + bs) >> 3);                                                          \
+                             (SEG ? 4 * (t0 + bs) : (t0 + bs) >> 3);                                    \
+        /* SEG: only the pieces the row's own span needs (the rest of its LDS row is never read) */     \
+        const int np = SEG ? (lane_value(vspan_nxt, cl >> 1) + 64 * M + 3) >> 2 : rq;                  \
         _Pragma("unroll") for (int q = 0; q < PM; ++q)                                                  \
-            pf[i][q] = gload(reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p)));   \
+            if (!SEG || lane + 64 * q < np)                                                             \
+                pf[i][q] = gload(reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p))); \
     }
 
     DEDISP_PLOAD_BASE(0)
@@ -965,9 +1007,9 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
                 DEDISP_PLOAD_BASE(c0 + 2 * CC)
             }
         }
-        const uint32_t* lrow = lbuf + lane * M;
+        const uint32_t* lrow = lbuf + (SEG ? lane : lane * M);
         for (int u = 0; u < ncur; u += 32)
-            plane_unit<M, RWS>(acc, lrow, u * 2 * RWS, vrel_cur, u >> 1);
+            plane_unit<M, RWS, SEG>(acc, lrow, u * 2 * RWS, vrel_cur, u >> 1);
     }
 #undef DEDISP_PLOAD_BASE
 #undef DEDISP_PLOAD_REL
@@ -976,6 +1018,42 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
     const int d = block * DB + wave;
     if (d >= ndm) return;
     const int orow_idx = rowmap ? wave_uniform(rowmap[d]) : d;
+    if constexpr (SEG) {
+        // word w of the tile holds outputs w + S*i of segments i = 0..31;
+        // for each (word, segment) the 64 lanes store 64 consecutive outputs
+        const long long S = seg_len(nout);
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            uint32_t r[16];
+#pragma unroll
+            for (int L = 0; L < 16; ++L) r[L] = L < NL ? acc[L][j] : 0u;
+            transpose16x2(r);
+            const long long w = t0 + lane + 64 * j;
+            if (w >= S) continue;
+            if (out_bytes == 4) {
+                uint32_t* orow = out + (size_t)orow_idx * (size_t)out_stride;
+#pragma unroll
+                for (int i = 0; i < 32; ++i) {
+                    const long long t = w + S * i;
+                    const uint32_t v = i < 16 ? (r[i] & 0xFFFFu) : (r[i - 16] >> 16);
+                    if (t < nout) orow[t] = v >> out_shift;
+                }
+            } else {
+                uint8_t* nrow = reinterpret_cast<uint8_t*>(out) + (long long)orow_idx * out_stride;
+#pragma unroll
+                for (int i = 0; i < 32; ++i) {
+                    const long long t = w + S * i;
+                    const uint32_t v = out_value(i < 16 ? (r[i] & 0xFFFFu) : (r[i - 16] >> 16), out_shift,
+                                                 out_bytes);
+                    if (t < nout) {
+                        if (out_bytes == 1) nrow[t] = (uint8_t)v;
+                        else reinterpret_cast<uint16_t*>(nrow)[t] = (uint16_t)v;
+                    }
+                }
+            }
+        }
+        return;
+    }
     const bool vec = ((out_stride & 3) == 0) && ((reinterpret_cast<uintptr_t>(out) & 15) == 0);
     const bool nvec = ((reinterpret_cast<uintptr_t>(out) & 3) == 0) && ((out_stride & 3) == 0);
 #pragma unroll
@@ -1040,9 +1118,9 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
 template <int FMT, int NW, int DPW, int M, int CC, int PM>
 __device__ __forceinline__ void tiled_item(const BeamDesc& b, int tile, int block, int group, uint32_t* lds)
 {
-    if constexpr (FMT == kFmtPlane) {
+    if constexpr (fmt_planes(FMT)) {
         static_assert(DPW == 1, "bit-plane shapes take one DM per wave");
-        plane_body<NW, M, CC, PM>(b, tile, block, lds);
+        plane_body<NW, M, CC, PM, FMT == kFmtSeg>(b, tile, block, lds);
     } else {
         tile_body<FMT, NW, DPW, M, CC, PM>(b, tile, block, group, lds);
     }
@@ -1054,8 +1132,19 @@ __global__ __launch_bounds__(NW * 64) void k_tiled(BeamDesc b)
     extern __shared__ uint32_t lds_dyn[];
     const int n = b.ntiles * b.nblocks;
     const int logical = xcd_remap((int)blockIdx.x, n);
-    tiled_item<FMT, NW, DPW, M, CC, PM>(b, logical / b.nblocks, logical % b.nblocks, (int)blockIdx.y,
-                                        lds_dyn);
+    int tile, block;
+    if constexpr (FMT == kFmtSeg) {
+        // DM-block-major: an XCD sweeps the tiles of its blocks in time
+        // order, so the workgroups in flight on it read overlapping windows
+        // (a block's window spans its delay spread in words, more than a
+        // tile), and the eight XCDs sweep the scratch side by side.
+        block = logical / b.ntiles;
+        tile = logical - block * b.ntiles;
+    } else {
+        tile = logical / b.nblocks;
+        block = logical % b.nblocks;
+    }
+    tiled_item<FMT, NW, DPW, M, CC, PM>(b, tile, block, (int)blockIdx.y, lds_dyn);
 }
 
 // ------------------------------------------------------------ untiled
@@ -1184,6 +1273,8 @@ __global__ __launch_bounds__(256) void k_zero(uint8_t* base, long long group_str
     X(kFmtPlane, 16, 1, 1, 32, 1, 0)       \
     X(kFmtPlane, 8, 1, 1, 32, 1, 0)        \
     X(kFmtPlane, 16, 1, 3, 64, 1, 0)       \
+    X(kFmtSeg, 16, 1, 3, 32, 2, 0)         \
+    X(kFmtSeg, 16, 1, 1, 32, 2, 0)         \
     X(kFmtNib, 8, 2, 3, 32, 2, 1)          \
     X(kFmtNib, 8, 2, 3, 16, 4, 1)          \
     X(kFmtNib, 8, 2, 1, 32, 2, 1)          \
@@ -1308,9 +1399,11 @@ hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st)
     const long long gx = unpack_grid_x(arg);
     const long long gy = unpack_grid_y(arg);
     if (gx <= 0 || gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidValue;
-    if ((nbits == 2) != (fmt == kFmtNib || fmt == kFmtPlane)) return hipErrorInvalidValue;
-    if (fmt == kFmtPlane && (d.nchans % 16 || d.row_bytes % 4)) return hipErrorInvalidValue;
+    if ((nbits == 2) != (fmt == kFmtNib || fmt_planes(fmt))) return hipErrorInvalidValue;
+    if (fmt_planes(fmt) && (d.nchans % 16 || d.row_bytes % 4)) return hipErrorInvalidValue;
+    if (fmt == kFmtSeg && (d.pitch % 16 || d.nout <= 0)) return hipErrorInvalidValue;
     const void* fn = fmt == kFmtPlane ? reinterpret_cast<const void*>(&k_unpack_planes)
+                     : fmt == kFmtSeg ? reinterpret_cast<const void*>(&k_unpack_seg)
                      : nbits == 2     ? reinterpret_cast<const void*>(&k_unpack<2>)
                                       : reinterpret_cast<const void*>(&k_unpack<8>);
     return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, 0, st);
@@ -1324,6 +1417,7 @@ hipError_t launch_unpack_multi(const DescBlock& blk, int nbeams, hipStream_t st)
         const BeamDesc& b = blk.d[i];
         if (b.scrunch != 1 || (b.in_nbits != 2 && b.in_nbits != 8) || b.nsamps <= 0 || b.nchans <= 0)
             return hipErrorInvalidValue;
+        if (b.xc_fmt == kFmtSeg) return hipErrorInvalidValue;   // single-beam launches only
         if ((b.in_nbits == 2) != (b.xc_fmt == kFmtNib || b.xc_fmt == kFmtPlane)) return hipErrorInvalidValue;
         if (b.xc_fmt == kFmtPlane && (b.nchans % 16 || b.row_bytes % 4)) return hipErrorInvalidValue;
         units += unpack_grid_x(b) * unpack_grid_y(b);

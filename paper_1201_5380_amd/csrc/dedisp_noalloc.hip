@@ -76,7 +76,7 @@ extern "C" dedisp_status dedisp_execute_noalloc(dedisp_plan p, const void* d_in,
     if (p->device != dev || !p->d_table) return fail(DEDISP_ERR_UNSUPPORTED, not_built);
     if (!p->killmask.empty() && (!p->d_chanmap || !p->d_mask)) return fail(DEDISP_ERR_UNSUPPORTED, not_built);
     if (lp.shape.kind == 0) {
-        auto it = p->blocks.find(lp.shape.waves * lp.shape.dpw);
+        auto it = p->blocks.find(block_key(lp.shape.waves * lp.shape.dpw, lp.shape.fmt));
         if (it == p->blocks.end() || !it->second.d_rel || !it->second.d_base)
             return fail(DEDISP_ERR_UNSUPPORTED, not_built);
         lp.bt = &it->second;
@@ -99,17 +99,18 @@ extern "C" dedisp_status dedisp_execute_noalloc(dedisp_plan p, const void* d_in,
     // (overlap-save), T a whole number of time tiles.
     const long long rows = static_cast<long long>(p->nact_padded()) * dedisp::fmt_rows(lp.shape.fmt);
     const long long cap = static_cast<long long>(DEDISP_NOALLOC_SCRATCH_BYTES);
-    auto need = [&](long long ns) { return xc_pitch(ns, lp.shape.fmt, lp.rw) * rows; };
+    auto need = [&](long long ns) { return xc_pitch(ns, lp.shape.fmt, lp.rw, p->max_delay) * rows; };
     const long long tl = tile_len(lp.shape);
     long long T = nout;
     if (need(static_cast<long long>(nsamps)) > cap) {
-        const long long pitch_max = (cap / rows) / 64 * 64;
-        const long long room = pitch_max - 4LL * lp.rw;       // data bytes per row
-        const long long ns_max = room > 0 ? room * dedisp::fmt_bytes_den(lp.shape.fmt) /
-                                                dedisp::fmt_bytes_num(lp.shape.fmt)
-                                          : 0;
-        T = (ns_max - p->max_delay) / tl * tl;
-        while (T > 0 && need(T + p->max_delay) > cap) T -= tl;
+        // the most whole tiles per slice whose scratch fits (need grows with ns)
+        long long lo = 0, hi = (nout + tl - 1) / tl;
+        while (lo < hi) {
+            const long long mid = (lo + hi + 1) / 2;
+            if (need(mid * tl + p->max_delay) <= cap) lo = mid;
+            else hi = mid - 1;
+        }
+        T = lo * tl;
         if (T <= 0)
             return fail(DEDISP_ERR_UNSUPPORTED,
                         "one time tile plus max_delay rows of this plan's channel-major scratch (" +

@@ -1,0 +1,174 @@
+"""GPU parity of the segmented bit-plane layout (sample_format 5) against the
+oracle, bit for bit.
+
+In this layout the outputs of a transform are cut into 32 segments of
+S = ceil(nout / 32) samples and bit i of a scratch word holds segment i, so
+every edge of the segment arithmetic is exercised here: outputs shorter than
+one segment row (nout < 32), lengths one either side of a multiple of 32 and
+of a whole tile, DM counts that leave a ragged last block, killed channels,
+narrow outputs with a row stride, stream pushes (each push is its own
+segmented transform over [history | chunk]) and the allocation-free entry
+point's time slices.  The layout stages a DM block's whole delay spread in
+words, so it runs only on fine DM grids like the survey's (steps of about
+one unit of DM over a 400 MHz band at 1.4 GHz); the cases below use steps of
+0.9.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1201_5380_amd import Plan, Stream, synth, tile_configs
+
+pytestmark = pytest.mark.gpu
+
+
+def _seg_configs():
+    cfgs = [c for c in tile_configs() if c["kind"] == 0 and c["sample_format"] == 5]
+    assert cfgs, "no segmented bit-plane shape compiled"
+    return cfgs
+
+
+def _use(plan, cfg):
+    plan.set_tile_config(cfg)
+    got = plan.tile_config()
+    assert got["sample_format"] == 5 and got["words_per_lane"] == cfg["words_per_lane"], got
+
+
+def _gpu(arr, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(arr).reshape(-1)).to(dev)
+
+
+def _np(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("extra", [1, 5, 31, 32, 33, 6143, 6145, 40000])
+def test_segmented_lengths_bit_exact(native, cuda, extra):
+    """Every segmented shape, nout = extra outputs per DM (1 .. several tiles)."""
+    import torch
+    nchans, ndm = 96, 37                      # 96 channels: three 32-channel units; 37 DMs: ragged block
+    rng = np.random.default_rng(500 + extra)
+    plan = Plan(nchans, 64e-6, 1581.8, -400.0 / nchans, 2).set_dm_list(synth.dm_list_linear(ndm, 0.9 * ndm))
+    table = plan.delay_table()
+    nsamps = plan.max_delay + extra
+    print(f"segmented lengths: nout {extra}, nsamps {nsamps}", flush=True)
+    packed = synth.pack(synth.two_bit_codes(rng, nsamps, nchans), 2)
+    want = oracle.dedisperse(packed, nsamps, nchans, 2, table)
+    inp = _gpu(packed, cuda)
+    for cfg in _seg_configs():
+        _use(plan, cfg)
+        stride = extra + 5
+        out = torch.full((ndm, stride), -1, dtype=torch.int32, device=cuda)
+        plan.execute(inp, nsamps, out=out, out_row_stride=stride)
+        torch.cuda.synchronize()
+        o = _np(out)
+        assert np.all(o[:, extra:] == 0xFFFFFFFF), ("wrote past nout", cfg)
+        assert np.array_equal(o[:, :extra], want), cfg
+
+
+def test_segmented_survey_band_all_max_codes_and_killmask(native, cuda):
+    """1344 channels of code 3 reach the top bit level (3 x 1344 = 4032); then
+    a kill mask compacts the live channels (padding rows up to a multiple of 32)."""
+    nchans, ndm = 1344, 20
+    plan = Plan(nchans, 64e-6, 1581.8, -400.0 / nchans, 2).set_dm_list(synth.dm_list_linear(ndm, 0.9 * ndm))
+    table = plan.delay_table()
+    nsamps = plan.max_delay + 9000
+    codes = np.full((nsamps, nchans), 3, np.uint8)
+    packed = synth.pack(codes, 2)
+    inp = _gpu(packed, cuda)
+    want = oracle.dedisperse(packed, nsamps, nchans, 2, table)
+    assert want.max() == 3 * nchans
+    for cfg in _seg_configs():
+        _use(plan, cfg)
+        got = _np(plan.execute(inp, nsamps))
+        assert np.array_equal(got, want), cfg
+    rng = np.random.default_rng(9)
+    codes = synth.two_bit_codes(rng, nsamps, nchans)
+    packed = synth.pack(codes, 2)
+    inp = _gpu(packed, cuda)
+    mask = (rng.random(nchans) > 0.3).astype(np.int32)
+    plan.set_killmask(mask)
+    want = oracle.dedisperse(packed, nsamps, nchans, 2, table, mask=mask)
+    for cfg in _seg_configs():
+        _use(plan, cfg)
+        got = _np(plan.execute(inp, nsamps))
+        assert np.array_equal(got, want), cfg
+
+
+@pytest.mark.parametrize("nbits_out,shift", [(8, 3), (16, 0)])
+def test_segmented_narrow_outputs(native, cuda, nbits_out, shift):
+    import torch
+    nchans, ndm = 256, 18
+    rng = np.random.default_rng(nbits_out)
+    plan = Plan(nchans, 64e-6, 1581.8, -400.0 / nchans, 2).set_dm_list(synth.dm_list_linear(ndm, 0.9 * ndm))
+    plan.set_output_format(nbits_out, shift)
+    table = plan.delay_table()
+    nsamps = plan.max_delay + 7001
+    packed = synth.pack(synth.two_bit_codes(rng, nsamps, nchans), 2)
+    want = oracle.reduce_output(oracle.dedisperse(packed, nsamps, nchans, 2, table), nbits_out, shift)
+    inp = _gpu(packed, cuda)
+    nout = nsamps - plan.max_delay
+    npdt = np.uint8 if nbits_out == 8 else np.uint16
+    for cfg in _seg_configs():
+        _use(plan, cfg)
+        stride = nout + 7
+        fill = 255 if nbits_out == 8 else -1
+        out = torch.full((ndm, stride), fill, dtype=plan.output_dtype(), device=cuda)
+        plan.execute(inp, nsamps, out=out, out_row_stride=stride)
+        torch.cuda.synchronize()
+        o = out.cpu().numpy().view(npdt)
+        assert np.all(o[:, nout:] == npdt((1 << nbits_out) - 1)), ("wrote past nout", cfg)
+        assert np.array_equal(o[:, :nout], want), cfg
+
+
+def test_segmented_stream_pushes_equal_one_shot(native, cuda):
+    import torch
+    nchans = 512
+    rng = np.random.default_rng(31)
+    plan = Plan(nchans, 64e-6, 1581.8, -400.0 / nchans, 2).set_dm_list(synth.dm_list_linear(24, 0.9 * 24))
+    _use(plan, _seg_configs()[0])
+    mx = plan.max_delay
+    lengths = [mx // 3, 7, mx + 5, 1, 3 * mx, 1300, 2 * mx + 1]
+    total = sum(lengths)
+    packed = synth.pack(synth.two_bit_codes(rng, total, nchans), 2).reshape(total, -1)
+    s = Stream(plan)
+    outs, pos = [], 0
+    for L in lengths:
+        t = _gpu(packed[pos:pos + L], cuda)
+        pos += L
+        out = torch.full((plan.ndm, L + mx), -1, dtype=torch.int32, device=cuda)
+        n, _ = s.push(t, out=out, out_row_stride=out.shape[1], nsamps=L)
+        torch.cuda.synchronize()
+        o = _np(out)
+        assert np.all(o[:, n:] == 0xFFFFFFFF)
+        outs.append(o[:, :n])
+    got = np.concatenate(outs, axis=1)
+    want = oracle.dedisperse(packed.reshape(-1), total, nchans, 2, plan.delay_table())
+    assert np.array_equal(got, want)
+
+
+def test_segmented_noalloc_slices_equal_execute(native, cuda):
+    """The allocation-free entry point on a segmented shape: an input whose
+    scratch exceeds the fixed array is cut into time slices, each its own
+    segmented transform; then a smaller input in one slice."""
+    import torch
+    rng = np.random.default_rng(8)
+    plan = Plan(1024, 64e-6, 1581.8, -0.390625, 2).set_dm_list(synth.dm_list_linear(256, 0.9 * 256))
+    _use(plan, _seg_configs()[0])
+    for n in (1 << 19, 40000):
+        raw = torch.from_numpy(rng.integers(0, 256, size=n * plan.row_bytes, dtype=np.uint8)).to(cuda)
+        nout = n - plan.max_delay
+        want = torch.full((plan.ndm, nout), -1, dtype=torch.int32, device=cuda)
+        got = torch.full((plan.ndm, nout), -1, dtype=torch.int32, device=cuda)
+        print(f"segmented no-alloc: {n} samples", flush=True)
+        plan.execute(raw, n, out=want)
+        plan.execute_noalloc(raw, got, n)
+        torch.cuda.synchronize()
+        assert torch.equal(got, want)
+        # and the segmented transform against the oracle on sampled DM rows
+        rows = [0, 1, 127, 255]
+        table = plan.delay_table()
+        packed = raw.cpu().numpy()
+        exp = oracle.dedisperse(packed, n, 1024, 2, table[rows], max_delay=plan.max_delay)
+        assert np.array_equal(_np(want)[rows], exp)
