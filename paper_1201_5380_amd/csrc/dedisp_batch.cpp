@@ -39,11 +39,11 @@ hipError_t enqueue_items(std::vector<Item>& items, hipStream_t st)
         }
     }
     // multi-beam launches per class, up to kMaxBatchDescs beams each
-    for (int cls = 1; cls <= 2; ++cls) {
+    for (int cls = 1; cls <= dedisp::kMultiClasses; ++cls) {
         std::vector<Item*> tiled;
         for (Item& it : items) {
             if (it.lp.shape.kind != 0) continue;
-            if (it.lp.shape.multi != 1 && it.lp.shape.multi != 2) return hipErrorInvalidValue;
+            if (it.lp.shape.multi < 1 || it.lp.shape.multi > dedisp::kMultiClasses) return hipErrorInvalidValue;
             if (it.lp.shape.multi == cls) tiled.push_back(&it);
         }
         for (size_t g0 = 0; g0 < tiled.size(); g0 += kMaxBatchDescs) {
@@ -114,6 +114,7 @@ dedisp_status tune_beam(const dedisp_beam& bm, std::map<std::string, std::vector
         c.dms_per_wave = static_cast<int>(hit->second[2]);
         c.words_per_lane = static_cast<int>(hit->second[3]);
         c.chunk_chans = static_cast<int>(hit->second[4]);
+        c.sample_format = hit->second.size() > 6 ? static_cast<int>(hit->second[6]) : -1;
         int idx = -1;
         if (find_shape(c, *p, &idx) && dedisp::shape_at(idx).multi) {
             best = c;
@@ -169,7 +170,8 @@ dedisp_status tune_beam(const dedisp_beam& bm, std::map<std::string, std::vector
     if (rc != DEDISP_OK) return rc;
     cache[key] = {static_cast<double>(best.kind), static_cast<double>(best.waves),
                   static_cast<double>(best.dms_per_wave), static_cast<double>(best.words_per_lane),
-                  static_cast<double>(best.chunk_chans), static_cast<double>(best_ms / 3)};
+                  static_cast<double>(best.chunk_chans), static_cast<double>(best_ms / 3),
+                  static_cast<double>(best.sample_format)};
     cache_dirty = true;
     return DEDISP_OK;
 }

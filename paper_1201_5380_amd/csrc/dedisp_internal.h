@@ -184,10 +184,13 @@ hipError_t launch_untiled_xc(const BeamDesc& d, int fmt, hipStream_t st);
 // travel in the kernel arguments (work_begin = prefix sum of ntiles*nblocks,
 // each rounded up to a multiple of 8).  Every beam of a launch must use a
 // shape of the launch's multi-beam class (shape.multi): class 1 holds 8-wave
-// shapes, class 2 the 16-wave ones; the LDS size is the largest any beam
+// shapes, class 2 the 16-wave ones, class 3 the 16-wave segmented bit-plane
+// shape (in a kernel of its own, so its registers do not add to the others');
+// the LDS size is the largest any beam
 // needs.
 constexpr int kMultiWaves = 8;
-__host__ __device__ constexpr int multi_waves(int cls) { return cls == 2 ? 16 : 8; }
+constexpr int kMultiClasses = 3;
+__host__ __device__ constexpr int multi_waves(int cls) { return cls == 1 ? 8 : 16; }
 constexpr int kMaxBatchDescs = 16;
 struct DescBlock {
     BeamDesc d[kMaxBatchDescs];

@@ -282,6 +282,7 @@ __global__ __launch_bounds__(256) void k_unpack_multi(DescBlock blk, int nbeams)
             const long long bx = id % gx;
             const int by = (int)(id / gx);
             if (b.xc_fmt == kFmtPlane) unpack_planes_tile<false>(b, bx, by, reinterpret_cast<uint32_t*>(tile));
+            else if (b.xc_fmt == kFmtSeg) unpack_planes_tile<true>(b, bx, by, reinterpret_cast<uint32_t*>(tile));
             else if (b.in_nbits == 2) unpack_tile<2>(b, bx, by, tile);
             else unpack_tile<8>(b, bx, by, tile);
             return;
@@ -1273,7 +1274,7 @@ __global__ __launch_bounds__(256) void k_zero(uint8_t* base, long long group_str
     X(kFmtPlane, 16, 1, 1, 32, 1, 0)       \
     X(kFmtPlane, 8, 1, 1, 32, 1, 0)        \
     X(kFmtPlane, 16, 1, 3, 64, 1, 0)       \
-    X(kFmtSeg, 16, 1, 3, 32, 2, 0)         \
+    X(kFmtSeg, 16, 1, 3, 32, 2, 3)         \
     X(kFmtSeg, 16, 1, 1, 32, 2, 0)         \
     X(kFmtNib, 8, 2, 3, 32, 2, 1)          \
     X(kFmtNib, 8, 2, 3, 16, 4, 1)          \
@@ -1352,8 +1353,10 @@ __device__ __forceinline__ void run_item(const DescBlock& blk, int nbeams, int i
     const int span = (nreal + 7) & ~7;
     const int local = xcd_remap(item - (int)b.work_begin, span);
     if (local >= nreal) return;
-    const int tile = local / b.nblocks;
-    const int block = local - tile * b.nblocks;
+    // the segmented bit planes run DM-block-major, as in k_tiled
+    const bool bmajor = wave_uniform(b.xc_fmt) == kFmtSeg;
+    const int tile = bmajor ? local % b.ntiles : local / b.nblocks;
+    const int block = bmajor ? local / b.ntiles : local - tile * b.nblocks;
     int id = 0;
     bool done = false;
 #define DEDISP_RUN(FMT, NW, DPW, M, CC, PM, MULTI) \
@@ -1417,9 +1420,9 @@ hipError_t launch_unpack_multi(const DescBlock& blk, int nbeams, hipStream_t st)
         const BeamDesc& b = blk.d[i];
         if (b.scrunch != 1 || (b.in_nbits != 2 && b.in_nbits != 8) || b.nsamps <= 0 || b.nchans <= 0)
             return hipErrorInvalidValue;
-        if (b.xc_fmt == kFmtSeg) return hipErrorInvalidValue;   // single-beam launches only
-        if ((b.in_nbits == 2) != (b.xc_fmt == kFmtNib || b.xc_fmt == kFmtPlane)) return hipErrorInvalidValue;
-        if (b.xc_fmt == kFmtPlane && (b.nchans % 16 || b.row_bytes % 4)) return hipErrorInvalidValue;
+        if ((b.in_nbits == 2) != (b.xc_fmt == kFmtNib || fmt_planes(b.xc_fmt))) return hipErrorInvalidValue;
+        if (fmt_planes(b.xc_fmt) && (b.nchans % 16 || b.row_bytes % 4)) return hipErrorInvalidValue;
+        if (b.xc_fmt == kFmtSeg && (b.pitch % 16 || b.nout <= 0)) return hipErrorInvalidValue;
         units += unpack_grid_x(b) * unpack_grid_y(b);
     }
     if (units > 0x7fffffffLL) return hipErrorInvalidValue;
@@ -1497,10 +1500,11 @@ hipError_t launch_untiled(const BeamDesc& d, int nbits, hipStream_t st)
 hipError_t launch_multi(const DescBlock& blk, int nbeams, int total_work, int lds_bytes, int cls,
                         hipStream_t st)
 {
-    if (nbeams <= 0 || nbeams > kMaxBatchDescs || total_work <= 0 || (cls != 1 && cls != 2))
+    if (nbeams <= 0 || nbeams > kMaxBatchDescs || total_work <= 0 || cls < 1 || cls > kMultiClasses)
         return hipErrorInvalidValue;
-    const void* fn = cls == 1 ? reinterpret_cast<const void*>(&k_multi<1>)
-                              : reinterpret_cast<const void*>(&k_multi<2>);
+    const void* fn = cls == 1   ? reinterpret_cast<const void*>(&k_multi<1>)
+                     : cls == 2 ? reinterpret_cast<const void*>(&k_multi<2>)
+                                : reinterpret_cast<const void*>(&k_multi<3>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
     if (e != hipSuccess) return e;
     DescBlock a0 = blk;

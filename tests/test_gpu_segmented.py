@@ -172,3 +172,100 @@ def test_segmented_noalloc_slices_equal_execute(native, cuda):
         packed = raw.cpu().numpy()
         exp = oracle.dedisperse(packed, n, 1024, 2, table[rows], max_delay=plan.max_delay)
         assert np.array_equal(_np(want)[rows], exp)
+
+
+def _fine_plan(nbits, nchans, ndm):
+    return Plan(nchans, 64e-6, 1581.8, -400.0 / nchans, nbits).set_dm_list(synth.dm_list_linear(ndm, 0.9 * ndm))
+
+
+def _codes(rng, n, nchans, nbits):
+    if nbits == 2:
+        return synth.two_bit_codes(rng, n, nchans)
+    return synth.eight_bit_noise(rng, n, nchans, 128.0, 16.0)
+
+
+def test_segmented_multi_beam_push_many(native, cuda):
+    """Streams on the segmented shape beside plain bit-plane (16-wave) and
+    8-bit (8-wave) streams: every tick launches the three multi-beam kernel
+    classes, and each stream's concatenated outputs equal its one-shot
+    oracle transform."""
+    import torch
+    from paper_1201_5380_amd import push_many
+    seg = _seg_configs()[0]
+    specs = [(2, 1024, 24, "seg"), (2, 512, 20, "plane"), (8, 256, 16, None), (2, 256, 30, "seg")]
+    plans, streams, packs, pos = [], [], [], []
+    for i, (nb, nc, nd, kind) in enumerate(specs):
+        p = _fine_plan(nb, nc, nd)
+        if kind == "seg":
+            _use(p, seg)
+        elif kind == "plane":
+            p.set_tile_config(dict(seg, sample_format=4))
+            assert p.tile_config()["sample_format"] == 4 and p.tile_config()["waves"] == 16
+        plans.append(p)
+        streams.append(Stream(p))
+        n = 3 * p.max_delay + 7000
+        packs.append(synth.pack(_codes(np.random.default_rng(60 + i), n, nc, nb), nb).reshape(n, -1))
+        pos.append(0)
+    outs = [[] for _ in specs]
+    rng = np.random.default_rng(5)
+    for step in range(5):
+        chunks, bufs, active = [], [], []
+        for i, p in enumerate(plans):
+            L = min(int(rng.integers(1, p.max_delay + 2500)), packs[i].shape[0] - pos[i])
+            if L <= 0:
+                continue
+            chunks.append(_gpu(packs[i][pos[i]:pos[i] + L], cuda))
+            bufs.append(torch.full((p.ndm, L + p.max_delay), -1, dtype=torch.int32, device=cuda))
+            active.append(i)
+            pos[i] += L
+        print(f"push_many step {step}: streams {active}", flush=True)
+        n_outs = push_many([streams[i] for i in active], chunks, bufs,
+                           out_row_strides=[b.shape[1] for b in bufs])
+        torch.cuda.synchronize()
+        for i, b, n in zip(active, bufs, n_outs):
+            o = _np(b)
+            assert np.all(o[:, n:] == 0xFFFFFFFF)
+            outs[i].append(o[:, :n])
+    for i, p in enumerate(plans):
+        got = np.concatenate(outs[i], axis=1)
+        want = oracle.dedisperse(packs[i][:pos[i]].reshape(-1), pos[i], p.nchans, p.nbits, p.delay_table())
+        assert np.array_equal(got, want), specs[i]
+
+
+def test_segmented_batch_from_tune_cache(native, cuda, tmp_path):
+    """A batch whose bit-plane beams are pinned to the segmented shape through
+    the tune cache (the library's own entries, rewritten), on every replay of
+    the captured graph."""
+    import json
+    import torch
+    from paper_1201_5380_amd import Batch
+    seg = _seg_configs()[0]
+    beams, refs = [], []
+    for i, (nb, nc, nd) in enumerate([(2, 1024, 24), (8, 256, 16), (2, 512, 33), (2, 256, 17)]):
+        p = _fine_plan(nb, nc, nd)
+        n = p.max_delay + 5000 + 1111 * i
+        packed = synth.pack(_codes(np.random.default_rng(80 + i), n, nc, nb), nb)
+        out = torch.full((p.ndm, n - p.max_delay), -1, dtype=torch.int32, device=cuda)
+        beams.append((p, _gpu(packed, cuda), n, out, 0))
+        refs.append(oracle.dedisperse(packed, n, nc, nb, p.delay_table()))
+    cache = tmp_path / "tune.json"
+    Batch(beams, tune_cache_path=str(cache)).execute()
+    torch.cuda.synchronize()
+    entries = json.load(open(cache))
+    pinned = 0
+    for k, v in entries.items():
+        if k.startswith("multi:") and "nbits=2,fmt=4," in k:
+            entries[k] = [0, seg["waves"], seg["dms_per_wave"], seg["words_per_lane"], seg["chunk_chans"],
+                          v[5] if len(v) > 5 else 0.0, 5]
+            pinned += 1
+    assert pinned == 3, entries
+    json.dump(entries, open(cache, "w"))
+    batch = Batch(beams, tune_cache_path=str(cache))
+    for rep in range(3):
+        for _, _, _, out, _ in beams:
+            out.fill_(-1)
+        torch.cuda.synchronize()
+        batch.execute(graph=(rep != 1))
+        torch.cuda.synchronize()
+        for (p, _, n, out, _), want in zip(beams, refs):
+            assert np.array_equal(_np(out), want), (rep, p.nchans, p.nbits)
