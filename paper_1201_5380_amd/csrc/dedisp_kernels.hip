@@ -131,19 +131,29 @@ __device__ __forceinline__ void unpack_tile(const BeamDesc& b, long long bx, int
     // have none); pieces past the last sample hold zeros
     constexpr int PPR = S::kRowBytes / 16;          // pieces per channel row
     const long long byte0 = t0 / S::kSamplesPerByte;
-    for (int it = threadIdx.x; it < kUC * PPR; it += 256) {
+    // rows and kill flags first (a load inside the store loop would make
+    // every store wait for the one before it); without a channel map
+    // (sub-band passes keep every channel's row) killed channels are
+    // written as zeros
+    constexpr int NIT = kUC * PPR / 256;
+    static_assert(kUC * PPR % 256 == 0, "whole items per thread");
+    int rows[NIT];
+    bool killed[NIT];
+#pragma unroll
+    for (int n = 0; n < NIT; ++n) {
+        const int c = c0 + (threadIdx.x + 256 * n) / PPR;
+        rows[n] = c < b.nchans ? (b.chanmap ? b.chanmap[c] : c) : -1;
+        killed[n] = c < b.nchans && b.mask && b.mask[c] == 0;
+    }
+#pragma unroll
+    for (int n = 0; n < NIT; ++n) {
+        const int it = threadIdx.x + 256 * n;
         const int c = it / PPR;
         const int p = it % PPR;
-        if (c0 + c >= b.nchans) continue;
-        if (t0 + 16LL * S::kSamplesPerByte * p >= b.nsamps) continue;
-        const int row = b.chanmap ? b.chanmap[c0 + c] : c0 + c;
-        if (row < 0) continue;
-        // without a channel map (sub-band passes keep every channel's row),
-        // killed channels are written as zeros
-        const bool killed = b.mask && b.mask[c0 + c] == 0;
-        const u32x4 val = killed ? u32x4{0u, 0u, 0u, 0u}
-                                 : *reinterpret_cast<const u32x4*>(tile + (size_t)c * S::kPitch + 16 * p);
-        *reinterpret_cast<u32x4*>(b.xc + (long long)row * b.pitch + byte0 + 16 * p) = val;
+        if (rows[n] < 0 || t0 + 16LL * S::kSamplesPerByte * p >= b.nsamps) continue;
+        const u32x4 val = killed[n] ? u32x4{0u, 0u, 0u, 0u}
+                                    : *reinterpret_cast<const u32x4*>(tile + (size_t)c * S::kPitch + 16 * p);
+        *reinterpret_cast<u32x4*>(b.xc + (long long)rows[n] * b.pitch + byte0 + 16 * p) = val;
     }
     // the padding rows (live channels up to a multiple of 8) read as zeros
     if (b.pad_row >= 0 && by == 0 && threadIdx.x < PPR * (b.nact - b.pad_row)) {
@@ -214,16 +224,28 @@ __device__ __forceinline__ void unpack_planes_tile(const BeamDesc& b, long long 
     // i / 32, bit row k = i % 32 (channel 16g + k/2, plane k%2)
     const long long byte0 = SEG ? 16 * bx : bx * (kPlaneTileT / 8);
     if (SEG || bx * kPlaneTileT < b.nsamps) {
-        for (int i = threadIdx.x; i < kPlaneTileW * 32; i += 256) {
+        // rows and kill flags of all the thread's items first: a load inside
+        // the store loop would make every store wait for the one before it
+        // (vector loads and stores share one counter)
+        constexpr int NIT = kPlaneTileW * 32 / 256;
+        static_assert(kPlaneTileW * 32 % 256 == 0, "whole items per thread");
+        int rows[NIT];
+        bool killed[NIT];
+#pragma unroll
+        for (int n = 0; n < NIT; ++n) {
+            const int i = threadIdx.x + 256 * n;
+            const int c = 16 * (by * kPlaneTileW + (i >> 5)) + ((i & 31) >> 1);
+            rows[n] = c < b.nchans ? (b.chanmap ? b.chanmap[c] : c) : -1;
+            killed[n] = c < b.nchans && b.mask && b.mask[c] == 0;
+        }
+#pragma unroll
+        for (int n = 0; n < NIT; ++n) {
+            if (rows[n] < 0) continue;
+            const int i = threadIdx.x + 256 * n;
             const int l = i >> 5, k = i & 31;
-            const int c = 16 * (by * kPlaneTileW + l) + (k >> 1);
-            if (c >= b.nchans) continue;
-            const int row = b.chanmap ? b.chanmap[c] : c;
-            if (row < 0) continue;
-            const bool killed = b.mask && b.mask[c] == 0;
-            const u32x4 v = killed ? u32x4{0u, 0u, 0u, 0u}
-                                   : *reinterpret_cast<const u32x4*>(lds + k * kPlaneLdsPitch + 4 * l);
-            *reinterpret_cast<u32x4*>(b.xc + (long long)(2 * row + (k & 1)) * b.pitch + byte0) = v;
+            const u32x4 v = killed[n] ? u32x4{0u, 0u, 0u, 0u}
+                                      : *reinterpret_cast<const u32x4*>(lds + k * kPlaneLdsPitch + 4 * l);
+            *reinterpret_cast<u32x4*>(b.xc + (long long)(2 * rows[n] + (k & 1)) * b.pitch + byte0) = v;
         }
         // the padding rows (live channels up to a multiple of 32) read as zeros
         if (b.pad_row >= 0 && by == 0 && threadIdx.x < 2 * (b.nact - b.pad_row))

@@ -84,11 +84,22 @@ __global__ __launch_bounds__(256) void k_scrunch(BeamDesc b)
         __syncthreads();
         // 16-byte pieces to each live channel's scratch row; samples past
         // the last whole scrunched sample hold zeros
-        for (int it = threadIdx.x; it < SC * PPR; it += 256) {
+        // scratch rows first: a load inside the store loop would make every
+        // store wait for the one before it
+        constexpr int NIT = SC * PPR / 256;
+        static_assert(SC * PPR % 256 == 0, "whole items per thread");
+        int rows[NIT];
+#pragma unroll
+        for (int n = 0; n < NIT; ++n) {
+            const int c = c0 + (threadIdx.x + 256 * n) / PPR;
+            rows[n] = c < b.nchans ? (b.chanmap ? b.chanmap[c] : c) : -1;
+        }
+#pragma unroll
+        for (int n = 0; n < NIT; ++n) {
+            const int it = threadIdx.x + 256 * n;
             const int c = it / PPR;
             const int p = it % PPR;
-            if (c0 + c >= b.nchans) continue;
-            const int row = b.chanmap ? b.chanmap[c0 + c] : c0 + c;
+            const int row = rows[n];
             if (row < 0) continue;
             const uint32_t* src = tile + c * LPW;
             const int csw = (c >> 4) & (NCOL - 1);
@@ -121,13 +132,21 @@ __global__ __launch_bounds__(256) void k_scrunch(BeamDesc b)
             t16[(4 * w + 3) * (LP / 2) + q] = (uint16_t)(hi >> 16);
         }
         __syncthreads();
-        for (int it = threadIdx.x; it < SC * PPR; it += 256) {
+        constexpr int NIT = SC * PPR / 256;
+        static_assert(SC * PPR % 256 == 0, "whole items per thread");
+        int rows[NIT];
+#pragma unroll
+        for (int n = 0; n < NIT; ++n) {
+            const int c = c0 + (threadIdx.x + 256 * n) / PPR;
+            rows[n] = c < b.nchans ? (b.chanmap ? b.chanmap[c] : c) : -1;
+        }
+#pragma unroll
+        for (int n = 0; n < NIT; ++n) {
+            const int it = threadIdx.x + 256 * n;
             const int c = it / PPR;
             const int p = it % PPR;
-            if (c0 + c >= b.nchans) continue;
-            const int row = b.chanmap ? b.chanmap[c0 + c] : c0 + c;
-            if (row < 0) continue;
-            *reinterpret_cast<u32x4*>(b.xc + (long long)row * b.pitch + byte0 + 16 * p) =
+            if (rows[n] < 0) continue;
+            *reinterpret_cast<u32x4*>(b.xc + (long long)rows[n] * b.pitch + byte0 + 16 * p) =
                 *reinterpret_cast<const u32x4*>(tile + (size_t)c * LP + 16 * p);
         }
     }
