@@ -370,8 +370,9 @@ int flush_channels(const dedisp_plan_s& p)
 // fits, else the first compiled tiled shape of the same bit depth that fits,
 // else the untiled kernel.  Host-only (no HIP call) when `upload` is false.
 dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool upload,
-                             LaunchPlan& lp, bool multi_only)
+                             LaunchPlan& lp, bool multi_only, long long nout)
 {
+    const bool seg_ok = nout < 0 || nout >= dedisp::kSegMinOutPerDelay * p->max_delay;
     int idx = -1;
     if (!find_shape(want, *p, &idx)) return fail(DEDISP_ERR_INVALID_ARG, "unknown tile shape");
     std::vector<int> order{idx};
@@ -388,6 +389,7 @@ dedisp_status resolve_launch(dedisp_plan p, const dedisp_tile_config& want, bool
     for (int i : order) {
         const Shape& s = dedisp::shape_at(i);
         if (s.kind != 0 || !shape_matches(s, *p) || !tiled_supported(*p)) continue;
+        if (s.fmt == dedisp::kFmtSeg && !seg_ok) continue;
         const int db = s.waves * s.dpw;
         const int key = block_key(db, s.fmt);
         const BlockTables* bt = nullptr;
@@ -935,7 +937,8 @@ static dedisp_status execute_groups(dedisp_plan p, const void* d_in, size_t nsam
     size_t need = 0;
     for (size_t i = 0; i < p->groups.size(); ++i) {
         dedisp_plan sub = p->groups[i].sub;
-        dedisp_status st = resolve_launch(sub, sub->cfg, true, lps[i]);
+        const long long gout = static_cast<long long>(nsamps) / sub->scrunch - sub->max_delay;
+        dedisp_status st = resolve_launch(sub, sub->cfg, true, lps[i], false, gout);
         if (st != DEDISP_OK) return st;
         if (lps[i].shape.kind == 0 && (reinterpret_cast<uintptr_t>(d_in) & 3)) {
             dedisp_tile_config u{};
@@ -1319,7 +1322,7 @@ dedisp_status dedisp_execute(dedisp_plan p, const void* d_in, size_t nsamps, uin
     if (stride == 0) stride = nout;
     if (stride < nout) return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < nsamps - max_delay");
     LaunchPlan lp;
-    dedisp_status st = resolve_launch(p, p->cfg, true, lp);
+    dedisp_status st = resolve_launch(p, p->cfg, true, lp, false, static_cast<long long>(nout));
     if (st != DEDISP_OK) return st;
     if (lp.shape.kind == 0 && (reinterpret_cast<uintptr_t>(d_in) & 3)) {
         // the corner turn reads 32-bit words
@@ -1514,7 +1517,8 @@ dedisp_status dedisp_tune(dedisp_plan p, const void* d_in, size_t nsamps, uint32
             c.sample_format = s.kind == 0 ? s.fmt : -1;
             // a shape whose window does not fit would silently time another one
             LaunchPlan probe;
-            if (resolve_launch(p, c, false, probe) != DEDISP_OK || probe.shape_index != i) continue;
+            const long long tout = static_cast<long long>(nsamps) / p->scrunch - p->max_delay;
+            if (resolve_launch(p, c, false, probe, false, tout) != DEDISP_OK || probe.shape_index != i) continue;
             p->cfg = c;
             // the untiled kernel is timed only on small problems or when no
             // tiled shape fits: elsewhere it is never the fastest, and one

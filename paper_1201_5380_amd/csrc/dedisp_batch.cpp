@@ -126,7 +126,9 @@ dedisp_status tune_beam(const dedisp_beam& bm, std::map<std::string, std::vector
         const Shape& s = dedisp::shape_at(i);
         if (!shape_matches(s, *p) || s.kind != 0 || !s.multi) continue;
         LaunchPlan probe;
-        if (resolve_launch(p, config_of(s), false, probe, true) != DEDISP_OK || probe.shape_index != i)
+        if (resolve_launch(p, config_of(s), false, probe, true,
+                           static_cast<long long>(bm.nsamps) - p->max_delay) != DEDISP_OK ||
+            probe.shape_index != i)
             continue;
         cands.push_back(i);
     }
@@ -223,7 +225,8 @@ dedisp_status dedisp_batch_create(const dedisp_beam* beams, int nbeams, const ch
         rc = tune_beam(b, cache, dirty, st, cfg);
         if (rc != DEDISP_OK) break;
         LaunchPlan lp;
-        rc = resolve_launch(b.plan, cfg, true, lp, cfg.kind == 0);
+        rc = resolve_launch(b.plan, cfg, true, lp, cfg.kind == 0,
+                            static_cast<long long>(b.nsamps) - b.plan->max_delay);
         if (rc != DEDISP_OK) break;
         if (lp.shape.kind == 0 && (reinterpret_cast<uintptr_t>(b.d_in) & 3)) {
             dedisp_tile_config u{};

@@ -83,9 +83,11 @@ bool tiled_supported(const struct ::dedisp_plan_s& p);
 // Resolve the shape used for plan p (requested one if it fits, else another
 // tiled shape, else the untiled kernel).  `upload` makes the device tables.
 // With multi_only, only shapes compiled into the multi-beam kernels are
-// considered before the untiled fallback.
+// considered before the untiled fallback.  nout (outputs per DM row of the
+// launch, -1 if not known) excludes the segmented bit planes from launches
+// shorter than kSegMinOutPerDelay * max_delay.
 dedisp_status resolve_launch(::dedisp_plan p, const dedisp_tile_config& want, bool upload,
-                             LaunchPlan& lp, bool multi_only = false);
+                             LaunchPlan& lp, bool multi_only = false, long long nout = -1);
 
 long long tile_len(const Shape& s);
 // Row pitch (bytes) of the channel-major scratch for nsamps input samples

@@ -47,6 +47,12 @@ constexpr int kPlaneRowWords = 224;
 // LDS row length of one staged plane of the interleaved format: a tile's 64M
 // words plus the spread of the DM block's delays, in whole words.
 constexpr int kSegRowWords = 512;
+// The segmented layout writes seg_len(nout) + max_delay words per plane row
+// where the plain planes write (nout + max_delay) / 32, so its corner turn
+// costs more than its sum saves unless nout is several times max_delay
+// (break-even near 6 on the survey band): below this many max_delays of
+// outputs a launch takes the plain bit planes.
+constexpr long long kSegMinOutPerDelay = 8;
 
 // One beam (or one stream push) as the kernels see it.  The input is a
 // virtual concatenation of two row segments so that a stream's resident

@@ -59,7 +59,7 @@ extern "C" dedisp_status dedisp_execute_noalloc(dedisp_plan p, const void* d_in,
 
     // the shape dedisp_execute would use, resolved without touching the device
     LaunchPlan lp;
-    dedisp_status st = resolve_launch(p, p->cfg, false, lp);
+    dedisp_status st = resolve_launch(p, p->cfg, false, lp, false, nout);
     if (st != DEDISP_OK) return st;
     if (lp.shape.kind == 0 && (reinterpret_cast<uintptr_t>(d_in) & 3)) {
         dedisp_tile_config u{};

@@ -73,7 +73,7 @@ dedisp_status prepare_push(dedisp_stream s, const void* chunk, size_t L, uint32_
     if (stride < pp.nout) return fail(DEDISP_ERR_INVALID_ARG, "out_row_stride < new outputs");
     dedisp_plan p = s->plan;
     LaunchPlan lp;
-    st = resolve_launch(p, p->cfg, true, lp, multi);
+    st = resolve_launch(p, p->cfg, true, lp, multi, static_cast<long long>(pp.nout));
     if (st != DEDISP_OK) return st;
     if (lp.shape.kind == 0 && (reinterpret_cast<uintptr_t>(chunk) & 3)) {
         dedisp_tile_config u{};
@@ -174,7 +174,7 @@ dedisp_status dedisp_stream_reserve(dedisp_stream s, size_t max_chunk)
     const long long n = static_cast<long long>(s->max_delay + max_chunk);
     for (bool multi : {true, false}) {
         LaunchPlan lp;
-        st = resolve_launch(s->plan, s->plan->cfg, false, lp, multi);
+        st = resolve_launch(s->plan, s->plan->cfg, false, lp, multi, static_cast<long long>(max_chunk));
         if (st != DEDISP_OK) return st;
         st = ensure_xc(*s->plan, s->xc, n, lp);
         if (st != DEDISP_OK) return st;

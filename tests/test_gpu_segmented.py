@@ -10,8 +10,9 @@ narrow outputs with a row stride, stream pushes (each push is its own
 segmented transform over [history | chunk]) and the allocation-free entry
 point's time slices.  The layout stages a DM block's whole delay spread in
 words, so it runs only on fine DM grids like the survey's (steps of about
-one unit of DM over a 400 MHz band at 1.4 GHz); the cases below use steps of
-0.9.
+one unit of DM over a 400 MHz band at 1.4 GHz; the cases below use steps of
+0.9), and only on launches of at least 8 max_delays of outputs (shorter
+ones take the plain planes; the zero-DM cases have no delays at all).
 """
 import numpy as np
 import pytest
@@ -44,12 +45,17 @@ def _np(t):
 
 
 @pytest.mark.parametrize("extra", [1, 5, 31, 32, 33, 6143, 6145, 40000])
-def test_segmented_lengths_bit_exact(native, cuda, extra):
-    """Every segmented shape, nout = extra outputs per DM (1 .. several tiles)."""
+@pytest.mark.parametrize("zero_dms", [True, False])
+def test_segmented_lengths_bit_exact(native, cuda, extra, zero_dms):
+    """Every segmented shape, nout = extra outputs per DM (1 .. several tiles).
+    A launch shorter than 8 max_delays takes the plain planes, so the short
+    lengths run the segmented layout only with an all-zero DM list (no
+    delays); with the fine grid they check the fallback."""
     import torch
     nchans, ndm = 96, 37                      # 96 channels: three 32-channel units; 37 DMs: ragged block
     rng = np.random.default_rng(500 + extra)
-    plan = Plan(nchans, 64e-6, 1581.8, -400.0 / nchans, 2).set_dm_list(synth.dm_list_linear(ndm, 0.9 * ndm))
+    dms = np.zeros(ndm) if zero_dms else synth.dm_list_linear(ndm, 0.9 * ndm)
+    plan = Plan(nchans, 64e-6, 1581.8, -400.0 / nchans, 2).set_dm_list(dms)
     table = plan.delay_table()
     nsamps = plan.max_delay + extra
     print(f"segmented lengths: nout {extra}, nsamps {nsamps}", flush=True)
@@ -129,7 +135,8 @@ def test_segmented_stream_pushes_equal_one_shot(native, cuda):
     plan = Plan(nchans, 64e-6, 1581.8, -400.0 / nchans, 2).set_dm_list(synth.dm_list_linear(24, 0.9 * 24))
     _use(plan, _seg_configs()[0])
     mx = plan.max_delay
-    lengths = [mx // 3, 7, mx + 5, 1, 3 * mx, 1300, 2 * mx + 1]
+    # pushes of at least 8 max_delays of outputs run segmented, the rest plain
+    lengths = [mx // 3, 7, 9 * mx, 1, 12 * mx + 5, 1300, 20 * mx + 1, mx + 3]
     total = sum(lengths)
     packed = synth.pack(synth.two_bit_codes(rng, total, nchans), 2).reshape(total, -1)
     s = Stream(plan)
@@ -151,7 +158,8 @@ def test_segmented_stream_pushes_equal_one_shot(native, cuda):
 def test_segmented_noalloc_slices_equal_execute(native, cuda):
     """The allocation-free entry point on a segmented shape: an input whose
     scratch exceeds the fixed array is cut into time slices, each its own
-    segmented transform; then a smaller input in one slice."""
+    segmented transform; then a smaller input in one slice (short enough to
+    take the plain planes)."""
     import torch
     rng = np.random.default_rng(8)
     plan = Plan(1024, 64e-6, 1581.8, -0.390625, 2).set_dm_list(synth.dm_list_linear(256, 0.9 * 256))
@@ -203,15 +211,15 @@ def test_segmented_multi_beam_push_many(native, cuda):
             assert p.tile_config()["sample_format"] == 4 and p.tile_config()["waves"] == 16
         plans.append(p)
         streams.append(Stream(p))
-        n = 3 * p.max_delay + 7000
+        n = 40 * p.max_delay + 7000
         packs.append(synth.pack(_codes(np.random.default_rng(60 + i), n, nc, nb), nb).reshape(n, -1))
         pos.append(0)
     outs = [[] for _ in specs]
     rng = np.random.default_rng(5)
-    for step in range(5):
+    for step in range(6):
         chunks, bufs, active = [], [], []
         for i, p in enumerate(plans):
-            L = min(int(rng.integers(1, p.max_delay + 2500)), packs[i].shape[0] - pos[i])
+            L = min(int(rng.integers(1, 12 * p.max_delay)), packs[i].shape[0] - pos[i])
             if L <= 0:
                 continue
             chunks.append(_gpu(packs[i][pos[i]:pos[i] + L], cuda))
