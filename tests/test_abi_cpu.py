@@ -400,3 +400,46 @@ def test_noalloc_execute_validation_precedes_hip(native):
     assert L.dedisp_execute_noalloc(plan.handle, p16, 5000, p16, 10, None) == -1  # stride < nout
     plan.set_tree(8)
     assert L.dedisp_execute_noalloc(plan.handle, p16, 5000, p16, 0, None) == -6
+
+
+def _shape(cfg):
+    return tuple(cfg[k] for k in ("waves", "dms_per_wave", "words_per_lane", "chunk_chans", "sample_format"))
+
+
+def test_segmented_plane_shapes_selected_by_sample_format(native):
+    """On a bit-plane plan the tile config's sample_format picks the segmented
+    layout (5) or the plain planes (anything else) for the same wave shape;
+    host-only (the shape is resolved without the device)."""
+    segs = [c for c in tile_configs() if c["kind"] == 0 and c["sample_format"] == 5]
+    assert segs
+    plan = Plan(1024, 64e-6, 1581.8, -0.390625, 2).set_dm_list(synth.dm_list_linear(1024, 1000.0))
+    for c in segs:
+        plan.set_tile_config(c)
+        assert _shape(plan.tile_config()) == _shape(c)
+        plain = dict(c, sample_format=4)
+        if any(_shape(p) == _shape(plain) for p in tile_configs()):
+            plan.set_tile_config(plain)
+            assert plan.tile_config()["sample_format"] == 4
+        plan.set_tile_config(dict(c, sample_format=-1))
+        assert plan.tile_config()["sample_format"] != 5
+
+
+def test_segmented_shape_falls_back_when_the_spread_does_not_fit(native):
+    """A DM block's delay spread is staged in words on the segmented planes:
+    with DM steps of 15 (survey band) it exceeds the 512-word LDS rows, and
+    the plan resolves to another tiled shape (host-only)."""
+    seg = [c for c in tile_configs() if c["kind"] == 0 and c["sample_format"] == 5][0]
+    plan = Plan(1024, 64e-6, 1581.8, -0.390625, 2).set_dm_list(synth.dm_list_linear(64, 1000.0))
+    plan.set_tile_config(seg)
+    got = plan.tile_config()
+    assert got["kind"] == 0 and got["sample_format"] == 4
+
+
+def test_segmented_shape_not_offered_to_other_formats(native):
+    """8-bit and nibble plans have no segmented shapes: such a config is
+    rejected as an unknown shape."""
+    seg = [c for c in tile_configs() if c["kind"] == 0 and c["sample_format"] == 5][0]
+    for nchans, nbits in ((256, 8), (2048, 2)):
+        plan = Plan(nchans, 64e-6, 1581.8, -400.0 / nchans, nbits).set_dm_list(synth.dm_list_linear(16, 16.0))
+        with pytest.raises(DedispError):
+            plan.set_tile_config(seg)
