@@ -965,6 +965,7 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
         for (int j = 0; j < M; ++j) acc[L][j] = 0u;
 
     u32x4 pf[RPW][PM] = {};
+    int npr[RPW];                 // pieces of each staged row that are loaded (and written to LDS)
     int vbase_nxt = 0;            // lane i < CC: window start of channel c0 + i (next chunk)
     int vspan_nxt = 0;            // SEG, lane i < CC: its span
     uint32_t vrel_cur = 0, vrel_nxt = 0;
@@ -988,6 +989,7 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
                              (SEG ? 4 * (t0 + bs) : (t0 + bs) >> 3);                                    \
         /* SEG: only the pieces the row's own span needs (the rest of its LDS row is never read) */     \
         const int np = SEG ? (lane_value(vspan_nxt, cl >> 1) + 64 * M + 3) >> 2 : rq;                  \
+        npr[i] = np;                                                                                    \
         _Pragma("unroll") for (int q = 0; q < PM; ++q)                                                  \
             if (!SEG || lane + 64 * q < np)                                                             \
                 pf[i][q] = gload(reinterpret_cast<const u32x4*>(src + 16 * min(lane + 64 * q, last_p))); \
@@ -1018,7 +1020,7 @@ __device__ __forceinline__ void plane_body(const BeamDesc& b, int tile, int bloc
 #pragma unroll
             for (int q = 0; q < PM; ++q) {
                 const int pc = lane + 64 * q;
-                if ((cl >> 1) < ncur && pc < rq) *reinterpret_cast<u32x4*>(dst + 4 * pc) = pf[i][q];
+                if ((cl >> 1) < ncur && pc < npr[i]) *reinterpret_cast<u32x4*>(dst + 4 * pc) = pf[i][q];
             }
         }
         vrel_cur = vrel_nxt;
