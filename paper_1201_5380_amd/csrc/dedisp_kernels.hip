@@ -5,14 +5,16 @@
 //
 // Two kernels per beam.
 //
-// 1. Corner turn + unpack (k_unpack).  Reads the packed time-major input
-//    with coalesced loads (two row segments, so a stream's history and a new
-//    chunk need not be contiguous) and writes it channel-major, one scratch
-//    row per live channel: 2-bit codes as nibbles (two samples per byte,
-//    eight per 32-bit word), 8-bit codes as bytes.  This is the "corner turn"
-//    the paper times separately (Table 2); it costs about 1% of the main
-//    kernel's time and turns every later access into aligned contiguous
-//    16-byte loads.
+// 1. Corner turn + unpack (k_unpack, k_unpack_planes, k_unpack_seg).  Reads
+//    the packed time-major input with coalesced loads (two row segments, so
+//    a stream's history and a new chunk need not be contiguous) and writes
+//    it channel-major, one scratch row per live channel: 2-bit codes as
+//    nibbles (two samples per byte, eight per 32-bit word) or as two bit
+//    planes (32 consecutive samples per word, or 32 time segments per word
+//    in the segmented layout), 8-bit codes as bytes.  This is the "corner
+//    turn" the paper times separately (Table 2); it costs a few percent of
+//    the main kernel's time and turns every later access into aligned
+//    contiguous 16-byte loads.
 //
 // 2. LDS-tiled shifted sum (k_tiled).  A workgroup owns one time tile of
 //    64*M scratch words per lane-row (512*M samples of 2-bit or 256*M of
@@ -37,12 +39,15 @@
 //    offsets arrive through vector loads and v_readlane, never through
 //    scalar memory, so waits on LDS are never held up by scalar loads.
 //
-//    The sums use bit-level parallelism (Section 2.3).  2-bit codes are
-//    added eight at a time in the 4-bit lanes of a register (exact for up to
-//    (2^4-1)/(2^2-1) = 5 codes, so flushed every 4 channels), then in 8-bit
-//    lanes (85 codes) and finally in 16-bit lanes (21845 codes).  8-bit
-//    codes are added two at a time in 16-bit lanes (257 codes), then in
-//    32-bit accumulators.
+//    The sums use bit-level parallelism (Section 2.3).  2-bit codes held as
+//    bit planes are added 32 samples at a time by bit-sliced full adders
+//    (plane_body); on the segmented planes a delay is a whole number of
+//    words, so a lane reads M words and realigns nothing.  2-bit codes held
+//    as nibbles are added eight at a time in the 4-bit lanes of a register
+//    (exact for up to (2^4-1)/(2^2-1) = 5 codes, so flushed every 4
+//    channels), then in 8-bit lanes (85 codes) and finally in 16-bit lanes
+//    (21845 codes).  8-bit codes are added two at a time in 16-bit lanes
+//    (257 codes), then in 32-bit accumulators.
 //
 // Untiled kernel (k_untiled): one thread per 4 outputs of one DM reading the
 // packed input directly.  Used when a DM block's delay spread is too large
@@ -1287,11 +1292,13 @@ __global__ __launch_bounds__(256) void k_zero(uint8_t* base, long long group_str
 // ---------------------------------------------------------------- shapes
 
 // (scratch format, waves, DMs per wave, words per lane, channels per chunk,
-// pieces, multi): a tile is 64*words scratch words long (512*words 2-bit,
-// 256*words byte or 128*words 16-bit samples); a staged channel row holds at
-// most 64*pieces 16-byte pieces; shapes marked multi are also compiled into
-// the multi-beam kernels (which allocate registers for the largest of them).
-// The first shape of each format is its default.
+// pieces, multi): a tile is 64*words scratch words long (2048*words outputs
+// of bit planes, 512*words 2-bit nibble, 256*words byte or 128*words 16-bit
+// samples); a staged channel row holds at most 64*pieces 16-byte pieces;
+// shapes marked multi are also compiled into multi-beam kernel `multi` (which
+// allocates registers for the largest of its shapes).  The first shape of
+// each format is its default; the segmented bit planes are chosen by tile
+// config (sample format 5) or by the tuner.
 #define DEDISP_SHAPES(X)                   \
     X(kFmtPlane, 16, 1, 3, 32, 1, 2)       \
     X(kFmtPlane, 8, 1, 3, 32, 1, 1)        \
