@@ -306,8 +306,11 @@ dedisp_status dedisp_set_tile_config(dedisp_plan plan, const dedisp_tile_config*
 /* (Under time-scrunching the shape also applies to every scrunch group
  * whose scratch format has it; dedisp_tune picks one per group.) */
 
-/* The tile shape the next compute call on `nsamps` samples will use
- * (after falling back if the chosen one does not fit in LDS). */
+/* The tile shape the next compute call will use (after falling back if the
+ * chosen one does not fit in LDS).  A segmented bit-plane shape (sample
+ * format 5) is reported as chosen; a call producing fewer than 8 max_delays
+ * of outputs per DM runs the plain bit planes instead (for short inputs the
+ * segmented layout's corner turn costs more than its sum saves). */
 dedisp_status dedisp_get_tile_config(dedisp_plan plan, dedisp_tile_config* cfg);
 
 /* Autotune: time every compiled shape on the given input/output buffers
