@@ -268,10 +268,60 @@ __global__ __launch_bounds__(256) void k_unpack_planes(BeamDesc b)
     unpack_planes_tile<false>(b, xcd_remap((int)blockIdx.x, (int)gridDim.x), blockIdx.y, lds);
 }
 
-__global__ __launch_bounds__(256) void k_unpack_seg(BeamDesc b)
+// The single-beam segmented corner turn: eight waves, words 8x .. 8x+7 of
+// every plane row per workgroup, so each row receives one 32-byte piece
+// (a quarter of a 128-byte line) per workgroup.
+constexpr int kSegTurnWaves = 8;
+constexpr int kSegLdsPitch = kPlaneTileW * kSegTurnWaves + 4;   // LDS words per bit row
+__global__ __launch_bounds__(64 * kSegTurnWaves) void k_unpack_seg(BeamDesc b)
 {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[32 * kPlaneLdsPitch];
-    unpack_planes_tile<true>(b, xcd_remap((int)blockIdx.x, (int)gridDim.x), blockIdx.y, lds);
+    __shared__ __attribute__((aligned(16))) uint32_t lds[32 * kSegLdsPitch];
+    const long long bx = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int by = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int ndw = b.nchans >> 4;
+    const int g = by * kPlaneTileW + lane;
+    const long long S = seg_len(b.nout);
+    const long long j = kSegTurnWaves * bx + wave;
+    uint32_t a[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+        const long long t = j + S * i;
+        a[i] = (t < b.nsamps && g < ndw) ? *reinterpret_cast<const uint32_t*>(row_ptr(b, t) + 4LL * g) : 0u;
+    }
+    transpose32(a);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) lds[k * kSegLdsPitch + kSegTurnWaves * lane + wave] = a[k];
+    // rows and kill flags first: a load inside the store loop would make
+    // every store wait for the one before it
+    constexpr int NIT = kPlaneTileW * 32 * (kSegTurnWaves / 4) / (64 * kSegTurnWaves);
+    static_assert(NIT * 64 * kSegTurnWaves == kPlaneTileW * 32 * (kSegTurnWaves / 4), "whole items per thread");
+    int rows[NIT];
+    bool killed[NIT];
+#pragma unroll
+    for (int n = 0; n < NIT; ++n) {
+        const int i = threadIdx.x + 64 * kSegTurnWaves * n;
+        const int c = 16 * (by * kPlaneTileW + (i >> 6)) + (((i >> 1) & 31) >> 1);
+        rows[n] = c < b.nchans ? (b.chanmap ? b.chanmap[c] : c) : -1;
+        killed[n] = c < b.nchans && b.mask && b.mask[c] == 0;
+    }
+    __syncthreads();
+    // item i: lane column l = i / 64, bit row k = (i / 2) % 32, 16-byte half h = i % 2
+    const long long byte0 = 4 * kSegTurnWaves * bx;
+#pragma unroll
+    for (int n = 0; n < NIT; ++n) {
+        if (rows[n] < 0) continue;
+        const int i = threadIdx.x + 64 * kSegTurnWaves * n;
+        const int l = i >> 6, k = (i >> 1) & 31, h = i & 1;
+        const u32x4 v = killed[n] ? u32x4{0u, 0u, 0u, 0u}
+                                  : *reinterpret_cast<const u32x4*>(lds + k * kSegLdsPitch + kSegTurnWaves * l + 4 * h);
+        *reinterpret_cast<u32x4*>(b.xc + (long long)(2 * rows[n] + (k & 1)) * b.pitch + byte0 + 16 * h) = v;
+    }
+    // the padding rows (live channels up to a multiple of 32) read as zeros
+    if (b.pad_row >= 0 && by == 0 && threadIdx.x < 4 * (b.nact - b.pad_row))
+        *reinterpret_cast<u32x4*>(b.xc + (long long)(2 * b.pad_row + (threadIdx.x >> 1)) * b.pitch + byte0 +
+                                  16 * (threadIdx.x & 1)) = u32x4{0u, 0u, 0u, 0u};
 }
 
 template <int NBITS>
@@ -1435,9 +1485,13 @@ hipError_t launch_unpack(const BeamDesc& d, int nbits, int fmt, hipStream_t st)
     if (gx <= 0 || gx > 0x7fffffffLL || gy > 65535) return hipErrorInvalidValue;
     if ((nbits == 2) != (fmt == kFmtNib || fmt_planes(fmt))) return hipErrorInvalidValue;
     if (fmt_planes(fmt) && (d.nchans % 16 || d.row_bytes % 4)) return hipErrorInvalidValue;
-    if (fmt == kFmtSeg && (d.pitch % 16 || d.nout <= 0)) return hipErrorInvalidValue;
+    if (fmt == kFmtSeg) {
+        if (d.pitch % (4 * kSegTurnWaves) || d.nout <= 0) return hipErrorInvalidValue;
+        return hipLaunchKernel(reinterpret_cast<const void*>(&k_unpack_seg),
+                               dim3((unsigned)(d.pitch / (4 * kSegTurnWaves)), (unsigned)gy),
+                               dim3(64 * kSegTurnWaves), args, 0, st);
+    }
     const void* fn = fmt == kFmtPlane ? reinterpret_cast<const void*>(&k_unpack_planes)
-                     : fmt == kFmtSeg ? reinterpret_cast<const void*>(&k_unpack_seg)
                      : nbits == 2     ? reinterpret_cast<const void*>(&k_unpack<2>)
                                       : reinterpret_cast<const void*>(&k_unpack<8>);
     return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)gy), dim3(256), args, 0, st);
