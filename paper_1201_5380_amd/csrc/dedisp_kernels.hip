@@ -268,10 +268,10 @@ __global__ __launch_bounds__(256) void k_unpack_planes(BeamDesc b)
     unpack_planes_tile<false>(b, xcd_remap((int)blockIdx.x, (int)gridDim.x), blockIdx.y, lds);
 }
 
-// The single-beam segmented corner turn: eight waves, words 8x .. 8x+7 of
-// every plane row per workgroup, so each row receives one 32-byte piece
-// (a quarter of a 128-byte line) per workgroup.
-constexpr int kSegTurnWaves = 8;
+// The single-beam segmented corner turn: kSegTurnWaves waves, words
+// W x .. W x + W-1 (W = kSegTurnWaves) of every plane row per workgroup, so
+// each row receives 4W bytes of a 128-byte line from one workgroup.
+constexpr int kSegTurnWaves = 16;
 constexpr int kSegLdsPitch = kPlaneTileW * kSegTurnWaves + 4;   // LDS words per bit row
 __global__ __launch_bounds__(64 * kSegTurnWaves) void k_unpack_seg(BeamDesc b)
 {
@@ -295,33 +295,34 @@ __global__ __launch_bounds__(64 * kSegTurnWaves) void k_unpack_seg(BeamDesc b)
     for (int k = 0; k < 32; ++k) lds[k * kSegLdsPitch + kSegTurnWaves * lane + wave] = a[k];
     // rows and kill flags first: a load inside the store loop would make
     // every store wait for the one before it
-    constexpr int NIT = kPlaneTileW * 32 * (kSegTurnWaves / 4) / (64 * kSegTurnWaves);
-    static_assert(NIT * 64 * kSegTurnWaves == kPlaneTileW * 32 * (kSegTurnWaves / 4), "whole items per thread");
+    constexpr int PPR = kSegTurnWaves / 4;           // 16-byte pieces per row and workgroup
+    constexpr int NIT = kPlaneTileW * 32 * PPR / (64 * kSegTurnWaves);
+    static_assert(NIT * 64 * kSegTurnWaves == kPlaneTileW * 32 * PPR, "whole items per thread");
     int rows[NIT];
     bool killed[NIT];
 #pragma unroll
     for (int n = 0; n < NIT; ++n) {
         const int i = threadIdx.x + 64 * kSegTurnWaves * n;
-        const int c = 16 * (by * kPlaneTileW + (i >> 6)) + (((i >> 1) & 31) >> 1);
+        const int c = 16 * (by * kPlaneTileW + i / (32 * PPR)) + ((i / PPR) % 32 >> 1);
         rows[n] = c < b.nchans ? (b.chanmap ? b.chanmap[c] : c) : -1;
         killed[n] = c < b.nchans && b.mask && b.mask[c] == 0;
     }
     __syncthreads();
-    // item i: lane column l = i / 64, bit row k = (i / 2) % 32, 16-byte half h = i % 2
+    // item i: lane column l = i / (32 PPR), bit row k = (i / PPR) % 32, piece h = i % PPR
     const long long byte0 = 4 * kSegTurnWaves * bx;
 #pragma unroll
     for (int n = 0; n < NIT; ++n) {
         if (rows[n] < 0) continue;
         const int i = threadIdx.x + 64 * kSegTurnWaves * n;
-        const int l = i >> 6, k = (i >> 1) & 31, h = i & 1;
+        const int l = i / (32 * PPR), k = (i / PPR) % 32, h = i % PPR;
         const u32x4 v = killed[n] ? u32x4{0u, 0u, 0u, 0u}
                                   : *reinterpret_cast<const u32x4*>(lds + k * kSegLdsPitch + kSegTurnWaves * l + 4 * h);
         *reinterpret_cast<u32x4*>(b.xc + (long long)(2 * rows[n] + (k & 1)) * b.pitch + byte0 + 16 * h) = v;
     }
     // the padding rows (live channels up to a multiple of 32) read as zeros
-    if (b.pad_row >= 0 && by == 0 && threadIdx.x < 4 * (b.nact - b.pad_row))
-        *reinterpret_cast<u32x4*>(b.xc + (long long)(2 * b.pad_row + (threadIdx.x >> 1)) * b.pitch + byte0 +
-                                  16 * (threadIdx.x & 1)) = u32x4{0u, 0u, 0u, 0u};
+    if (b.pad_row >= 0 && by == 0 && threadIdx.x < 2 * PPR * (b.nact - b.pad_row))
+        *reinterpret_cast<u32x4*>(b.xc + (long long)(2 * b.pad_row + threadIdx.x / PPR) * b.pitch + byte0 +
+                                  16 * (threadIdx.x % PPR)) = u32x4{0u, 0u, 0u, 0u};
 }
 
 template <int NBITS>
