@@ -635,6 +635,7 @@ void destroy_tree(dedisp_plan p)
     p->tree_off.clear();
     p->tree_gtrials.clear();
     p->tree_lds = 0;
+    p->tree_span = 0;
     p->tree_rows.clear();
     p->tree_delay.clear();
     p->tree_pairs.clear();
@@ -1241,10 +1242,13 @@ static dedisp_status run_tree(dedisp_plan p, const void* d_in, size_t nsamps, ui
     // 16-bit partial sums of at most 65535 / (largest row value) terms
     const int row_max = p->value_bound() * nsub;
     const int flush = 65535 / row_max;
-    if (!p->tree_sblocks.empty()) {
+    // the staged kernel addresses a sub-band's rows with 32-bit offsets
+    if (!p->tree_sblocks.empty() &&
+        (std::max<long long>(p->tree_span, 4) + 1) * dg.pitch + 4LL * dedisp::kTreeTile < (1LL << 31)) {
         // the staged trial blocks through LDS, the rest gathered
+        // rows below 128 let two terms be added as bytes first
         e = dedisp::launch_tree_combine_lds(dg, p->d_tree_sblocks, static_cast<int>(p->tree_sblocks.size()),
-                                            p->d_tree_stage, p->d_tree_off, p->tree_lds, hs);
+                                            p->d_tree_stage, p->d_tree_off, p->tree_lds, 2 * row_max <= 255, hs);
         if (e != hipSuccess) return hip_fail(e, "kernel launch");
         if (!p->tree_gtrials.empty())
             e = dedisp::launch_tree_combine(dg, ob, flush, p->d_tree_gtrials,
@@ -1815,7 +1819,7 @@ static dedisp_status build_tree(dedisp_plan q, int nsub)
     constexpr long long kTreeLdsDwords = 16 * 1024;          // 64 KB: two workgroups per CU
     std::vector<dedisp::TreeStage> stage;
     std::vector<int32_t> sblocks, off, gtrials;
-    int lds_max = 0;
+    int lds_max = 0, span_max = 0;
     // (the kernel keeps a trial's offsets in two registers: up to 128 sub-bands)
     if (static_cast<long long>(q->value_bound()) * nsub <= 255 && nsb <= 128) {
         off.assign(static_cast<size_t>(ndm) * nsb, 0);
@@ -1837,10 +1841,12 @@ static dedisp_status build_tree(dedisp_plan q, int nsub)
                 g.lo = lo;
                 g.span = hi - lo + 1;
                 g.dmin4 = dmin & ~3;
-                // the window covers the tile, the block's delay spread and the
-                // second dword each lane reads past its four outputs
-                g.wdw = (TT + (dmax - g.dmin4) + 8 + 3) / 4;
-                g.rcp = static_cast<uint32_t>(((1ull << 32) + g.wdw - 1) / g.wdw);
+                // staged rows are segmented within the tile (four segments of
+                // TT/4 outputs, one byte of each per dword): the window covers
+                // a segment and the block's delay spread, in whole groups of
+                // four dwords
+                g.wdw = ((dmax - g.dmin4) + TT / 4 + 3) / 4 * 4;
+                g.rcp = static_cast<uint32_t>(((1ull << 32) + g.wdw / 4 - 1) / (g.wdw / 4));
                 g.lds = static_cast<int>(std::min<long long>(lds, 0x7fffffff));
                 lds += static_cast<long long>(g.span) * g.wdw;
             }
@@ -1852,11 +1858,12 @@ static dedisp_status build_tree(dedisp_plan q, int nsub)
                 for (int d = d0; d < d1; ++d) {
                     const size_t i = static_cast<size_t>(d) * nsb + n;
                     const dedisp::TreeStage& g = st[n];
-                    off[i] = 4 * (g.lds + (rows[i] - g.lo) * g.wdw) + (delay[i] - g.dmin4);
+                    off[i] = 4 * (g.lds + (rows[i] - g.lo) * g.wdw + (delay[i] - g.dmin4));
                 }
             sblocks.push_back(b);
             stage.insert(stage.end(), st.begin(), st.end());
             lds_max = std::max(lds_max, static_cast<int>(lds));
+            for (const auto& g : st) span_max = std::max(span_max, g.span);
         }
     }
     destroy_tree(q);
@@ -1872,6 +1879,7 @@ static dedisp_status build_tree(dedisp_plan q, int nsub)
         q->tree_off.swap(off);
         q->tree_gtrials.swap(gtrials);
         q->tree_lds = lds_max;
+        q->tree_span = span_max;
     }
     return DEDISP_OK;
 }

@@ -201,6 +201,7 @@ struct dedisp_plan_s {
     std::vector<dedisp::TreeStage> tree_stage;
     std::vector<int32_t> tree_sblocks, tree_off, tree_gtrials;
     int tree_lds = 0;                       // dwords per workgroup
+    int tree_span = 0;                      // most rows a staged block reads of one sub-band
     dedisp::TreeStage* d_tree_stage = nullptr;
     int32_t* d_tree_sblocks = nullptr;
     int32_t* d_tree_off = nullptr;

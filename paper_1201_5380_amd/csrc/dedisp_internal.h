@@ -158,21 +158,24 @@ hipError_t launch_tree_combine(const BeamDesc& d, int ob, int flush, const int32
 
 // Stage 2 with LDS staging, byte rows only: for the nblocks trial blocks
 // blocks[] (block k = trials k*kTreeBlock .. +kTreeBlock-1), a workgroup
-// stages, per sub-band n, rows stage[.][n].lo .. + span over a window of wdw
-// dwords starting at sample t0 + dmin4 (a multiple of 4) at LDS dword lds,
-// then every trial d of the block sums, over n, the bytes at LDS byte
-// off[d][n] + (t - t0) for its outputs t of the time tile [t0, t0 +
-// kTreeTile).  lds_dwords = LDS per workgroup; at most 128 sub-bands.  d as
-// for launch_tree_combine (32-bit sums: no flush interval).
+// stages, per sub-band n, rows stage[.][n].lo .. + span, each as wdw (a
+// multiple of 4) dwords at LDS dword lds + (row - lo) wdw, segmented within
+// the time tile [t0, t0 + kTreeTile): with P = kTreeTile / 4, byte i of
+// staged dword k is sample t0 + dmin4 + k + i P (dmin4 a multiple of 4).
+// Every trial d of the block then sums, over n, byte i of the LDS dword at
+// byte offset off[d][n] + 4 u for its output t0 + u + i P (u < P).  rcp =
+// ceil(2^32 / (wdw / 4)).  lds_dwords = LDS per workgroup; at most 128
+// sub-bands.  pair: every row value is below 128.  d as for
+// launch_tree_combine (32-bit sums: no flush interval).
 constexpr int kTreeBlock = 32;
 constexpr int kTreeTile = 512;
 struct TreeStage {
     int lo, span, dmin4, wdw, lds;
-    uint32_t rcp;          // ceil(2^32 / wdw): i / wdw = umulhi(i, rcp) for i < 2^16
+    uint32_t rcp;          // ceil(2^32 / (wdw / 4)): i / (wdw / 4) = umulhi(i, rcp) for i < 2^16
     int pad_[2];
 };
 hipError_t launch_tree_combine_lds(const BeamDesc& d, const int32_t* blocks, int nblocks, const TreeStage* stage,
-                                   const int32_t* off, int lds_dwords, hipStream_t st);
+                                   const int32_t* off, int lds_dwords, bool pair, hipStream_t st);
 
 // Zero `bytes` (a multiple of 16) at base + g*group_stride for g < ngroups.
 hipError_t launch_zero(uint8_t* base, long long group_stride, long long bytes, int ngroups,

@@ -466,127 +466,239 @@ __global__ __launch_bounds__(256) void k_tree_combine(BeamDesc b, int flush, lon
 // dense DM list use nearly the same tree rows (d'_n changes slowly with DM)
 // at nearly the same delays, so a workgroup stages, for its time tile and
 // block of kTreeBlock trials, each sub-band's rows the block uses over the
-// block's delay window once, and every trial then reads its terms from LDS:
-// lane l takes outputs t0 + 256 j + 4 l .. +3 (j < kTreeTile / 256), one realigned dword
-// (two consecutive LDS dwords, consecutive lanes on consecutive dwords) per
-// four outputs, added as byte pairs in 16-bit lanes.
-__global__ __launch_bounds__(256) void k_tree_combine_lds(BeamDesc b, const int32_t* blocks, const TreeStage* stage,
-                                                          const int32_t* off)
+// block's delay window once, and every trial then reads its terms from LDS.
+//
+// The staged rows are segmented within the tile: with P = kTreeTile / 4 and
+// B = t0 + dmin4 the window's first sample, byte i of staged dword k is
+// sample B + k + i P.  A trial whose delay is o samples past dmin4 finds
+// the samples of outputs t0 + u + i P (i = 0 .. 3) in dword o + u, so every
+// delay is a whole-dword offset: no realignment, one LDS dword per four
+// outputs and term.  Lane l takes u = l + 64 j (j < P / 64).  Bytes 0 and 2
+// are added in 16-bit lanes (a mask), bytes 1 and 3 through an unmasked
+// shift whose byte-2 part is taken out at the end; with PAIR (row values
+// below 128) two terms are first added as bytes.
+// Staging turns four aligned dwords of the row (samples B + 4c .. + 3 of
+// each of the four segments) into four staged dwords with eight v_perm.
+__device__ __forceinline__ void tree_store_at(const BeamDesc& b, int drow, long long t, uint32_t v)
 {
-    extern __shared__ uint32_t sl[];
-    constexpr int TT = kTreeTile, TB = kTreeBlock;
-    constexpr int J = TT / 256;                    // groups of four outputs per lane
-    static_assert(TT % 256 == 0, "whole groups per lane");
-    const long long t0 = (long long)blockIdx.x * TT;
-    const int blk = blocks[blockIdx.y];
-    const int nsb = b.nact;
-    const TreeStage* st = stage + (size_t)blockIdx.y * nsb;
-    const long long pitch_dw = b.pitch / 4;
-    // staged dword i of a sub-band is row r = i / wdw, column c; i stays
-    // below 2^14 (the LDS budget), where the rounded-up reciprocal gives the
-    // exact quotient
-    auto fetch = [&](const TreeStage& g, int i) -> uint32_t {
-        const int r = (int)__umulhi((uint32_t)i, g.rcp), c = i - r * g.wdw;
-        const long long col = (t0 + g.dmin4) / 4 + c;   // dword column in the row
-        const uint32_t* row = reinterpret_cast<const uint32_t*>(b.xc + (long long)(g.lo + r) * b.pitch);
-        return col < pitch_dw ? row[col] : 0u;
-    };
-    // staging: sixteen sub-bands at a time, up to two dwords of each per
-    // thread, all of a batch's loads in flight before its LDS stores
-    constexpr int SB = 16;
-    for (int n0 = 0; n0 < nsb; n0 += SB) {
-        uint32_t v[SB][2];
-#pragma unroll
-        for (int u = 0; u < SB; ++u)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                v[u][k] = 0u;
-                if (n0 + u < nsb) {
-                    const TreeStage g = st[n0 + u];
-                    const int i = threadIdx.x + 256 * k;
-                    if (i < g.span * g.wdw) v[u][k] = fetch(g, i);
-                }
-            }
-#pragma unroll
-        for (int u = 0; u < SB; ++u)
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-                if (n0 + u < nsb) {
-                    const TreeStage g = st[n0 + u];
-                    const int i = threadIdx.x + 256 * k;
-                    if (i < g.span * g.wdw) sl[g.lds + i] = v[u][k];
-                }
+    if (t >= b.nout) return;
+    if (b.out_bytes == 4) {
+        b.out[(size_t)drow * (size_t)b.out_stride + t] = v >> b.out_shift;
+    } else {
+        uint8_t* nrow = reinterpret_cast<uint8_t*>(b.out) + (long long)drow * b.out_stride;
+        const uint32_t w = out_value(v, b.out_shift, b.out_bytes);
+        if (b.out_bytes == 1) nrow[t] = (uint8_t)w;
+        else reinterpret_cast<uint16_t*>(nrow)[t] = (uint16_t)w;
     }
-    // wider rows (more than 512 dwords of a sub-band)
-    for (int n = 0; n < nsb; ++n) {
+}
+
+// eight waves per workgroup: a workgroup's LDS (the staged rows) then
+// carries twice the waves of four, for latency hiding
+constexpr int kTreeWaves = 8;
+template <bool PAIR>
+__global__ __launch_bounds__(64 * kTreeWaves) void k_tree_combine_lds(BeamDesc b, const int32_t* blocks, const TreeStage* stage,
+                                                          const int32_t* off, int nblocks)
+{
+    extern __shared__ __attribute__((aligned(16))) uint32_t sl[];
+    constexpr int TT = kTreeTile, TB = kTreeBlock;
+    constexpr int P = TT / 4;                      // outputs per segment of the tile
+    constexpr int J = P / 64;                      // staged dwords per lane and term
+    static_assert(P % 64 == 0, "whole dwords per lane");
+    // workgroup i: trial block i mod nblocks of time tile i / nblocks, so the
+    // workgroups in flight write long runs of each output row (a tile-fastest
+    // order spreads them over every tile of few rows, which writes HBM at
+    // about two thirds the rate)
+    const int bi = (int)(blockIdx.x % (unsigned)nblocks);
+    const long long t0 = (long long)(blockIdx.x / (unsigned)nblocks) * TT;
+    const int blk = blocks[bi];
+    const int nsb = b.nact;
+    const TreeStage* st = stage + (size_t)bi * nsb;
+    // staging: item i of sub-band n (i < span * wdw/4: row i / (wdw/4),
+    // dword group c = i mod (wdw/4)) fills LDS dwords lds + 4 i .. + 3.
+    // Wave w stages sub-bands w, w + kTreeWaves, ...: items lane and lane +
+    // 64 of SB sub-bands at a time, all of their loads in flight before the
+    // first transpose; items from 128 on in a loop of their own.
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // the wave's trials (wave, wave + kTreeWaves, ...) and their rows of the
+    // whole output, read before the first store (a vector load issued after
+    // the stores would wait for them)
+    constexpr int KT = TB / kTreeWaves;
+    int drow[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+        const int d = blk * TB + wave + kTreeWaves * k;
+        const int dd = d < b.ndm ? d : 0;
+        drow[k] = b.rowmap ? b.rowmap[dd] : dd;
+    }
+    // The sub-band's rows lo .. lo + span - 1 are read as one buffer (32-bit
+    // offsets: (max(span, 4) + 1) * pitch stays below 2^31, which the host
+    // checks): loads past its end read zeros, and loads past the end of an
+    // earlier row read the next row's bytes, which only outputs at or past
+    // nout see (output t reads sample t + delay < nout + the largest delay
+    // <= the row length).
+    auto stage_item = [&](const TreeStage& g, int i, uint32_t (&a)[4]) {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void*)(b.xc + (long long)g.lo * b.pitch), (short)0, (int)(g.span * b.pitch), 0x00020000);
+        // i < 2^14: the rounded-up reciprocal gives the exact quotient
+        const int row = (int)__umulhi((uint32_t)i, g.rcp), c = i - row * (g.wdw / 4);
+        const int voff = row * (int)b.pitch + (int)(t0 + g.dmin4) + 4 * c;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[s] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff + s * P, 0, 0);
+    };
+    auto put_item = [&](const TreeStage& g, int i, bool live, const uint32_t (&a)[4]) {
+        // 4x4 byte transpose: staged dword e = byte e of a[0 .. 3]
+        const uint32_t x01l = __builtin_amdgcn_perm(a[1], a[0], 0x05010400u);
+        const uint32_t x01h = __builtin_amdgcn_perm(a[1], a[0], 0x07030602u);
+        const uint32_t x23l = __builtin_amdgcn_perm(a[3], a[2], 0x05010400u);
+        const uint32_t x23h = __builtin_amdgcn_perm(a[3], a[2], 0x07030602u);
+        const u32x4 v = {__builtin_amdgcn_perm(x23l, x01l, 0x05040100u),
+                         __builtin_amdgcn_perm(x23l, x01l, 0x07060302u),
+                         __builtin_amdgcn_perm(x23h, x01h, 0x05040100u),
+                         __builtin_amdgcn_perm(x23h, x01h, 0x07060302u)};
+        if (live) *reinterpret_cast<u32x4*>(sl + g.lds + 4 * i) = v;
+    };
+    // Items past a sub-band's end read zeros (rows past its span lie outside
+    // its buffer) and are transposed but not written, so every load's value
+    // is consumed on every path and loads of later items never wait for
+    // earlier ones.
+    // At most 128 sub-bands: four passes of kTreeWaves * SB, unrolled (a
+    // loop would make the first loads of a pass wait for the last pass's).
+    constexpr int SB = 4, H = 2;
+    static_assert(4 * kTreeWaves * SB >= 128, "every sub-band staged");
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+        const int n0 = wave + kTreeWaves * SB * it;
+        if (n0 >= nsb) break;                      // uniform
+        uint32_t a[SB][H][4];
+        int items[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int n = n0 + kTreeWaves * u;
+            items[u] = n < nsb ? st[n].span * (st[n].wdw / 4) : 0;
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                if (items[u] > 64 * h) stage_item(st[n], lane + 64 * h, a[u][h]);   // uniform
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int n = n0 + kTreeWaves * u;
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                if (items[u] > 64 * h) put_item(st[n], lane + 64 * h, lane + 64 * h < items[u], a[u][h]);
+            }
+        }
+    }
+    for (int n = wave; n < nsb; n += kTreeWaves) {
         const TreeStage g = st[n];
-        for (int i = 512 + threadIdx.x; i < g.span * g.wdw; i += 256) sl[g.lds + i] = fetch(g, i);
+        for (int i = 64 * H + lane; i < g.span * (g.wdw / 4); i += 64) {
+            uint32_t a[4];
+            stage_item(g, i, a);
+            put_item(g, i, true, a);
+        }
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int k = wave; k < TB; k += 4) {
-        const int d = blk * TB + k;
+    constexpr uint32_t M = 0x00FF00FFu;
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+        const int d = blk * TB + wave + kTreeWaves * kt;
         if (d >= b.ndm) break;                     // no barriers below
-        // the trial's LDS offsets, lane n holding sub-band n's (and n + 64's),
-        // broadcast per term with v_readlane
-        const int32_t* od = off + (size_t)d * nsb;
-        const int o_lo = lane < nsb ? od[lane] : 0;
-        const int o_hi = lane + 64 < nsb ? od[lane + 64] : 0;
-        // the four bytes at LDS byte offset o + 4 (64 j + lane) are outputs
-        // 256 j + 4 lane .. +3; one v_perm of the aligned dword pair picks
-        // bytes s, s+2 (s = o mod 4) into the 16-bit lanes of p[j], another
-        // bytes s+1, s+3 into q[j].  At most 128 terms of byte values: the
-        // 16-bit lanes never carry (128 * 255 < 2^16).
+        // p[j]: outputs u, u + 2P in its 16-bit lanes (bytes 0 and 2 of each
+        // term); q[j]: the terms shifted right by 8 bits, unmasked, so that
+        // q = S1 + 2^8 S2 + 2^16 S3 (S_i the sum of bytes i, each below 2^15:
+        // no wrap), and q - 2^8 S2 holds outputs u + P, u + 3P.
         uint32_t p[J], q[J];
 #pragma unroll
         for (int j = 0; j < J; ++j) p[j] = q[j] = 0u;
-        // C terms at a time (offsets o[0 .. C-1]): every LDS read of the
-        // group is issued before the first add
+        // the trial's LDS byte offsets through scalar loads (the table is
+        // constant during the launch)
+        typedef const __attribute__((address_space(4))) int32_t* coff_t;
+        const coff_t od = (coff_t)(off + (size_t)d * nsb);
+        // C terms at a time: every LDS read of the group before the first add
         auto terms = [&](auto cnt, const int* o) {
             constexpr int C = decltype(cnt)::value;
-            uint32_t w[C][J][2];
+            uint32_t w[C][J];
 #pragma unroll
-            for (int u = 0; u < C; ++u) {
-                const uint32_t* src = sl + (o[u] >> 2) + lane;
+            for (int u = 0; u < C; ++u)
 #pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    w[u][j][0] = src[64 * j];
-                    w[u][j][1] = src[64 * j + 1];
-                }
-            }
+                for (int j = 0; j < J; ++j)
+                    w[u][j] = *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(sl) + o[u] + 4 * lane +
+                                                                 256 * j);
 #pragma unroll
-            for (int u = 0; u < C; ++u) {
-                // selectors: bytes (s, zero, s+2, zero) and (s+1, zero, s+3, zero)
-                const uint32_t sa = 0x0C020C00u + (uint32_t)(o[u] & 3) * 0x00010001u;
-                const uint32_t sb = sa + 0x00010001u;
+            for (int j = 0; j < J; ++j) {
+                if constexpr (PAIR && C % 2 == 0) {
 #pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    p[j] += __builtin_amdgcn_perm(w[u][j][1], w[u][j][0], sa);
-                    q[j] += __builtin_amdgcn_perm(w[u][j][1], w[u][j][0], sb);
+                    for (int u = 0; u < C; u += 2) {
+                        const uint32_t s = w[u][j] + w[u + 1][j];   // bytes below 128: no carry
+                        p[j] += s & M;
+                        q[j] += s >> 8;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < C; ++u) {
+                        p[j] += w[u][j] & M;
+                        q[j] += w[u][j] >> 8;
+                    }
                 }
             }
         };
-        // sub-bands n0 .. n1-1, offsets in lanes n - base of reg
-        auto range = [&](int reg, int base, int n0, int n1) {
-            constexpr int U = 4;
-            int n = n0;
-            for (; n + U <= n1; n += U) {
-                int o[U];
+        // terms n .. n + C - 1
+        auto group = [&](auto cnt, int n) {
+            constexpr int C = decltype(cnt)::value;
+            int o[C];
 #pragma unroll
-                for (int u = 0; u < U; ++u) o[u] = __builtin_amdgcn_readlane(reg, n - base + u);
-                terms(std::integral_constant<int, U>(), o);
-            }
-            for (; n < n1; ++n) {
-                const int o[1] = {__builtin_amdgcn_readlane(reg, n - base)};
-                terms(std::integral_constant<int, 1>(), o);
-            }
+            for (int u = 0; u < C; ++u) o[u] = od[n + u];
+            terms(cnt, o);
         };
-        range(o_lo, 0, 0, nsb < 64 ? nsb : 64);
-        if (nsb > 64) range(o_hi, 64, 64, nsb);
+        // eight terms at a time, the next eight offsets loaded ahead
+        int n = 0;
+        int o8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (nsb >= 8) {
 #pragma unroll
-        for (int j = 0; j < J; ++j) {
-            const uint32_t a4[4] = {p[j] & 0xFFFFu, q[j] & 0xFFFFu, p[j] >> 16, q[j] >> 16};
-            tree_store<4>(b, d, t0 + 256 * j + 4 * lane, a4);
+            for (int u = 0; u < 8; ++u) o8[u] = od[u];
+        }
+        for (; n + 8 <= nsb; n += 8) {
+            int o[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) o[u] = o8[u];
+            if (n + 16 <= nsb) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) o8[u] = od[n + 8 + u];
+            }
+            terms(std::integral_constant<int, 8>(), o);
+        }
+        if (n + 4 <= nsb) {
+            group(std::integral_constant<int, 4>(), n);
+            n += 4;
+        }
+        if (n + 2 <= nsb) {
+            group(std::integral_constant<int, 2>(), n);
+            n += 2;
+        }
+        if (n < nsb) group(std::integral_constant<int, 1>(), n);
+#pragma unroll
+        for (int j = 0; j < J; ++j) q[j] -= (p[j] >> 16) << 8;
+        if (b.out_bytes == 4 && t0 + TT <= b.nout) {
+            // a whole tile of 32-bit outputs: one row address, no bounds checks
+            uint32_t* orow = b.out + (size_t)drow[kt] * (size_t)b.out_stride + t0 + lane;
+            const int sh = b.out_shift;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                orow[64 * j] = (p[j] & 0xFFFFu) >> sh;
+                orow[64 * j + P] = (q[j] & 0xFFFFu) >> sh;
+                orow[64 * j + 2 * P] = (p[j] >> 16) >> sh;
+                orow[64 * j + 3 * P] = (q[j] >> 16) >> sh;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const long long t = t0 + 64 * j + lane;
+                tree_store_at(b, drow[kt], t, p[j] & 0xFFFFu);
+                tree_store_at(b, drow[kt], t + P, q[j] & 0xFFFFu);
+                tree_store_at(b, drow[kt], t + 2 * P, p[j] >> 16);
+                tree_store_at(b, drow[kt], t + 3 * P, q[j] >> 16);
+            }
         }
     }
 }
@@ -596,16 +708,17 @@ __global__ __launch_bounds__(256) void k_tree_combine_lds(BeamDesc b, const int3
 int tree_tile(int nsub) { return tree_tile_len_b(nsub) > tree_tile_len(nsub) ? tree_tile_len_b(nsub) : tree_tile_len(nsub); }
 
 hipError_t launch_tree_combine_lds(const BeamDesc& d, const int32_t* blocks, int nblocks, const TreeStage* stage,
-                                   const int32_t* off, int lds_dwords, hipStream_t st)
+                                   const int32_t* off, int lds_dwords, bool pair, hipStream_t st)
 {
     if (d.nout <= 0 || d.ndm <= 0 || d.nact <= 0 || d.nact > 128 || nblocks <= 0 || nblocks > 65535 ||
         lds_dwords <= 0 || (size_t)lds_dwords * 4 > (size_t)kMaxLdsBytes || (d.pitch & 3) ||
         (reinterpret_cast<uintptr_t>(d.xc) & 3) ||
         (reinterpret_cast<uintptr_t>(d.out) & (d.out_bytes == 4 ? 3 : d.out_bytes - 1)))
         return hipErrorInvalidValue;
-    const long long gx = (d.nout + kTreeTile - 1) / kTreeTile;
+    const long long gx = (d.nout + kTreeTile - 1) / kTreeTile * nblocks;
     if (gx > 0x7fffffffLL) return hipErrorInvalidValue;
-    const void* fn = reinterpret_cast<const void*>(&k_tree_combine_lds);
+    const void* fn = pair ? reinterpret_cast<const void*>(&k_tree_combine_lds<true>)
+                          : reinterpret_cast<const void*>(&k_tree_combine_lds<false>);
     const size_t lds = (size_t)lds_dwords * 4;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -613,8 +726,9 @@ hipError_t launch_tree_combine_lds(const BeamDesc& d, const int32_t* blocks, int
     const int32_t* a1 = blocks;
     const TreeStage* a2 = stage;
     const int32_t* a3 = off;
-    void* args[] = {&a0, &a1, &a2, &a3};
-    return hipLaunchKernel(fn, dim3((unsigned)gx, (unsigned)nblocks), dim3(256), args, lds, st);
+    int a4 = nblocks;
+    void* args[] = {&a0, &a1, &a2, &a3, &a4};
+    return hipLaunchKernel(fn, dim3((unsigned)gx), dim3(64 * kTreeWaves), args, lds, st);
 }
 
 hipError_t launch_tree_combine(const BeamDesc& d, int ob, int flush, const int32_t* trials, int ntrials,
