@@ -182,3 +182,34 @@ def test_tree_more_than_64_sub_bands_staged_and_gathered(native, cuda):
     plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms).set_tree(nsub)
     assert np.all(plan.output_lengths(nsamps) == want.shape[1])
     assert np.array_equal(_run(plan, packed, nsamps, cuda), want)
+
+
+@pytest.mark.parametrize("nsub", [32, 64])
+def test_tree_staged_rows_at_their_largest_values(native, cuda, nsub):
+    """Staged stage 2 with every code at its largest value over long runs:
+    sub-band sums of 32 channels (at most 96: two terms added as bytes
+    before they are spread) and of 64 channels (at most 192: spread one at a
+    time), 16 sub-bands a trial, dense sorted trials in a whole and a ragged
+    block, and a ragged last time tile, bit for bit against the oracle.  The
+    trials sit in a narrow DM range so that each block's rows fit the LDS
+    budget of the staged kernel (checked from the oracle's tables)."""
+    nbits, nsamps = 2, 13001
+    nchans = 16 * nsub
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    diag = _diag(nchans, nsub, dt, f_top, df)
+    dms = np.linspace(0.30 * diag, 0.36 * diag, 45)
+    dp, dd = oracle.tree_combine_tables(nchans, dt, f_top, df, nsub, dms)
+    for b0 in (0, 32):                               # staged: rows x window well inside 16 K dwords
+        blk = slice(b0, b0 + 32)
+        span = dp[blk].max(axis=0) - dp[blk].min(axis=0) + 1
+        wdw = (dd[blk].max(axis=0) - (dd[blk].min(axis=0) & ~3)) + 128 + 3
+        assert int((span * wdw).sum()) < 12 * 1024
+    rng = np.random.default_rng(nsub)
+    codes = rng.integers(0, 4, size=(nsamps, nchans), dtype=np.uint8)
+    codes[1000:5000] = 3
+    codes[9000:] = 3
+    packed = synth.pack(codes, nbits)
+    want = oracle.dedisperse_piecewise_tree(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub)
+    assert want.max() == 3 * nchans                  # every channel at 3 on some output
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms).set_tree(nsub)
+    assert np.array_equal(_run(plan, packed, nsamps, cuda), want)
