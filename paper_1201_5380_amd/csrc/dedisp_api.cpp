@@ -985,6 +985,11 @@ static void subband_lengths(const dedisp_plan_s& p, size_t nsamps, long long& le
     nout = len1 - p.sb_step2->max_delay;
 }
 
+static dedisp_status tree_upload(dedisp_plan p);
+static dedisp_status combine_rows(dedisp_plan q, const dedisp_plan_s& outp, uint8_t* xc, long long pitch, int ob,
+                                  int nsb, int row_max, int ndm, long long nout, uint32_t* d_out, size_t stride,
+                                  const int32_t* rowmap, hipStream_t hs);
+
 static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsamps,
                                      uint32_t* d_out, size_t stride, void* stream)
 {
@@ -1071,6 +1076,13 @@ static dedisp_status execute_subband(dedisp_plan p, const void* d_in, size_t nsa
     e = lp1.shape.kind == 0 ? dedisp::launch_tiled(d1, lp1.shape, lp1.lds, hs)
                             : dedisp::launch_untiled_xc(d1, s1->fmt, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    if (!s2->tree_rows.empty() && s2->fmt != kFmtHalf) {
+        // step 2 as the combination of per-sub-band rows (byte sums)
+        st = tree_upload(s2);
+        if (st != DEDISP_OK) return st;
+        return combine_rows(s2, *p, p->sb_xc2.ptr, pitch2, 1, nsb, s2->vbound, static_cast<int>(p->dms.size()), nout,
+                            d_out, stride, nullptr, hs);
+    }
     // step 2: for every nominal DM, its trials over the miniature filterbank
     BeamDesc d2;
     std::memset(&d2, 0, sizeof(d2));
@@ -1140,7 +1152,7 @@ static dedisp_status tree_upload(dedisp_plan p)
         HIP_TRY(hipMemcpy(p->d_tree_rows, p->tree_rows.data(), bytes, hipMemcpyHostToDevice));
         HIP_TRY(hipMemcpy(p->d_tree_delay, p->tree_delay.data(), bytes, hipMemcpyHostToDevice));
     }
-    if (!p->d_tree_pairs) {
+    if (!p->d_tree_pairs && !p->tree_pairs.empty()) {
         const size_t bytes = p->tree_pairs.size() * sizeof(int32_t);
         if (hipMalloc(&p->d_tree_pairs, bytes) != hipSuccess) {
             p->d_tree_pairs = nullptr;
@@ -1175,6 +1187,54 @@ static dedisp_status tree_upload(dedisp_plan p)
 static int tree_row_bytes(const dedisp_plan_s& p)
 {
     return static_cast<long long>(p.value_bound()) * p.tree_nsub <= 255 ? 1 : 2;
+}
+
+// The combination of per-sub-band rows (tree stage 2; sub-band step 2 with
+// byte sums): out[d][t] = sum over the nsb sub-bands n of row q->tree_rows[d][n]
+// of xc (pitch bytes, ob bytes per sample, values at most row_max) at sample
+// t + q->tree_delay[d][n], for the ndm trials and t < nout, in outp's output
+// format.  Dense trial blocks whose rows fit go through LDS (q->tree_sblocks),
+// the rest are gathered.  Tables must be on the device (tree_upload).
+static dedisp_status combine_rows(dedisp_plan q, const dedisp_plan_s& outp, uint8_t* xc, long long pitch, int ob,
+                                  int nsb, int row_max, int ndm, long long nout, uint32_t* d_out, size_t stride,
+                                  const int32_t* rowmap, hipStream_t hs)
+{
+    BeamDesc dg;
+    std::memset(&dg, 0, sizeof(dg));
+    dg.xc = xc;
+    dg.pitch = pitch;
+    dg.table = q->d_tree_delay;
+    dg.rowsel = q->d_tree_rows;
+    dg.rowmap = rowmap;
+    dg.nact = nsb;
+    dg.nchans = nsb;
+    dg.ndm = dg.ndm_last = ndm;
+    dg.ngroups = 1;
+    dg.nout = nout;
+    dg.scrunch = 1;
+    dg.out = d_out;
+    dg.out_bytes = outp.out_nbits / 8;
+    dg.out_shift = outp.out_shift;
+    dg.out_stride = static_cast<long long>(stride) * (dg.out_bytes == 4 ? 1 : dg.out_bytes);
+    // 16-bit partial sums of at most 65535 / (largest row value) terms
+    const int flush = 65535 / row_max;
+    hipError_t e;
+    // the staged kernel addresses a sub-band's rows with 32-bit offsets
+    if (!q->tree_sblocks.empty() &&
+        (std::max<long long>(q->tree_span, 4) + 1) * dg.pitch + 4LL * dedisp::kTreeTile < (1LL << 31)) {
+        // the staged trial blocks through LDS, the rest gathered
+        // rows below 128 let two terms be added as bytes first
+        e = dedisp::launch_tree_combine_lds(dg, q->d_tree_sblocks, static_cast<int>(q->tree_sblocks.size()),
+                                            q->d_tree_stage, q->d_tree_off, q->tree_lds, 2 * row_max <= 255, hs);
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        if (!q->tree_gtrials.empty())
+            e = dedisp::launch_tree_combine(dg, ob, flush, q->d_tree_gtrials,
+                                            static_cast<int>(q->tree_gtrials.size()), hs);
+    } else {
+        e = dedisp::launch_tree_combine(dg, ob, flush, nullptr, 0, hs);
+    }
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return DEDISP_OK;
 }
 
 // Enqueue one plan's tree: corner turn (scrunching for a group's plan),
@@ -1222,42 +1282,8 @@ static dedisp_status run_tree(dedisp_plan p, const void* d_in, size_t nsamps, ui
     e = dedisp::launch_tree(d0, tfmt, nsub, ob, p->d_tree_pairs, npairs, p->sb_xc2.ptr, pitch2, len1, hs);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     // stage 2: every trial sums, over the sub-bands, its tree row at its delay
-    BeamDesc dg;
-    std::memset(&dg, 0, sizeof(dg));
-    dg.xc = p->sb_xc2.ptr;
-    dg.pitch = pitch2;
-    dg.table = p->d_tree_delay;
-    dg.rowsel = p->d_tree_rows;
-    dg.rowmap = rowmap;
-    dg.nact = nsb;
-    dg.nchans = nsb;
-    dg.ndm = dg.ndm_last = static_cast<int>(p->dms.size());
-    dg.ngroups = 1;
-    dg.nout = nout;
-    dg.scrunch = 1;
-    dg.out = d_out;
-    dg.out_bytes = p->out_nbits / 8;
-    dg.out_shift = p->out_shift;
-    dg.out_stride = static_cast<long long>(stride) * (dg.out_bytes == 4 ? 1 : dg.out_bytes);
-    // 16-bit partial sums of at most 65535 / (largest row value) terms
-    const int row_max = p->value_bound() * nsub;
-    const int flush = 65535 / row_max;
-    // the staged kernel addresses a sub-band's rows with 32-bit offsets
-    if (!p->tree_sblocks.empty() &&
-        (std::max<long long>(p->tree_span, 4) + 1) * dg.pitch + 4LL * dedisp::kTreeTile < (1LL << 31)) {
-        // the staged trial blocks through LDS, the rest gathered
-        // rows below 128 let two terms be added as bytes first
-        e = dedisp::launch_tree_combine_lds(dg, p->d_tree_sblocks, static_cast<int>(p->tree_sblocks.size()),
-                                            p->d_tree_stage, p->d_tree_off, p->tree_lds, 2 * row_max <= 255, hs);
-        if (e != hipSuccess) return hip_fail(e, "kernel launch");
-        if (!p->tree_gtrials.empty())
-            e = dedisp::launch_tree_combine(dg, ob, flush, p->d_tree_gtrials,
-                                            static_cast<int>(p->tree_gtrials.size()), hs);
-    } else {
-        e = dedisp::launch_tree_combine(dg, ob, flush, nullptr, 0, hs);
-    }
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
-    return DEDISP_OK;
+    return combine_rows(p, *p, p->sb_xc2.ptr, pitch2, ob, nsb, p->value_bound() * nsub,
+                        static_cast<int>(p->dms.size()), nout, d_out, stride, rowmap, hs);
 }
 
 static dedisp_status execute_tree(dedisp_plan p, const void* d_in, size_t nsamps, uint32_t* d_out,
@@ -1665,6 +1691,79 @@ dedisp_status dedisp_set_scrunching(dedisp_plan p, const int32_t* factors)
     return DEDISP_OK;
 }
 
+// Staging tables of the combination of per-sub-band rows (byte rows, at
+// most 128 sub-bands): per block of kTreeBlock consecutive trials and
+// sub-band, the rows the block uses and its delay window; a block whose rows
+// exceed the LDS budget is gathered instead.  rows and delay are
+// [ndm][nsb].
+struct Stage2Tables {
+    std::vector<dedisp::TreeStage> stage;
+    std::vector<int32_t> sblocks, off, gtrials;
+    int lds_max = 0, span_max = 0;
+    void assign_to(dedisp_plan q)
+    {
+        if (sblocks.empty()) return;
+        q->tree_stage.swap(stage);
+        q->tree_sblocks.swap(sblocks);
+        q->tree_off.swap(off);
+        q->tree_gtrials.swap(gtrials);
+        q->tree_lds = lds_max;
+        q->tree_span = span_max;
+    }
+};
+
+static Stage2Tables stage2_tables(int ndm, int nsb, const std::vector<int32_t>& rows,
+                                  const std::vector<int32_t>& delay)
+{
+    constexpr int TB = dedisp::kTreeBlock, TT = dedisp::kTreeTile;
+    constexpr long long kTreeLdsDwords = 16 * 1024;          // 64 KB: two workgroups per CU
+    Stage2Tables r;
+    r.off.assign(static_cast<size_t>(ndm) * nsb, 0);
+    std::vector<dedisp::TreeStage> st(nsb);
+    for (int b = 0; b * TB < ndm; ++b) {
+        const int d0 = b * TB, d1 = std::min(ndm, d0 + TB);
+        long long lds = 0;
+        for (int n = 0; n < nsb; ++n) {
+            int lo = 0x7fffffff, hi = -1, dmin = 0x7fffffff, dmax = -1;
+            for (int d = d0; d < d1; ++d) {
+                const size_t i = static_cast<size_t>(d) * nsb + n;
+                lo = std::min(lo, rows[i]);
+                hi = std::max(hi, rows[i]);
+                dmin = std::min(dmin, delay[i]);
+                dmax = std::max(dmax, delay[i]);
+            }
+            dedisp::TreeStage& g = st[n];
+            g = dedisp::TreeStage{};
+            g.lo = lo;
+            g.span = hi - lo + 1;
+            g.dmin4 = dmin & ~3;
+            // staged rows are segmented within the tile (four segments of
+            // TT/4 outputs, one byte of each per dword): the window covers
+            // a segment and the block's delay spread, in whole groups of
+            // four dwords
+            g.wdw = ((dmax - g.dmin4) + TT / 4 + 3) / 4 * 4;
+            g.rcp = static_cast<uint32_t>(((1ull << 32) + g.wdw / 4 - 1) / (g.wdw / 4));
+            g.lds = static_cast<int>(std::min<long long>(lds, 0x7fffffff));
+            lds += static_cast<long long>(g.span) * g.wdw;
+        }
+        if (lds > kTreeLdsDwords) {
+            for (int d = d0; d < d1; ++d) r.gtrials.push_back(d);
+            continue;
+        }
+        for (int n = 0; n < nsb; ++n)
+            for (int d = d0; d < d1; ++d) {
+                const size_t i = static_cast<size_t>(d) * nsb + n;
+                const dedisp::TreeStage& g = st[n];
+                r.off[i] = 4 * (g.lds + (rows[i] - g.lo) * g.wdw + (delay[i] - g.dmin4));
+            }
+        r.sblocks.push_back(b);
+        r.stage.insert(r.stage.end(), st.begin(), st.end());
+        r.lds_max = std::max(r.lds_max, static_cast<int>(lds));
+        for (const auto& g : st) r.span_max = std::max(r.span_max, g.span);
+    }
+    return r;
+}
+
 dedisp_status dedisp_set_subband(dedisp_plan p, int nsub, int ngroup)
 {
     if (!p) return fail(DEDISP_ERR_INVALID_ARG, "NULL plan");
@@ -1747,6 +1846,25 @@ dedisp_status dedisp_set_subband(dedisp_plan p, int nsub, int ngroup)
             }
         }
     s2->cfg = default_config(s2->fmt);
+    // byte sums: step 2 is the combination of per-sub-band rows, trial d
+    // summing row (d / ngroup) * nsb_p + n at the delay of sub-band n's first
+    // channel -- the tree's stage-2 kernels, used while the sums are bytes
+    // and every block of trials stages in LDS (ngroup a multiple of the
+    // block size); else the grouped tiled launch
+    if (vsum <= 255 && nsb <= 128) {
+        std::vector<int32_t> rows(static_cast<size_t>(ndm) * nsb), delay(rows.size());
+        for (int d = 0; d < ndm; ++d)
+            for (int n = 0; n < nsb; ++n) {
+                rows[static_cast<size_t>(d) * nsb + n] = (d / ngroup) * nsb_p + n;
+                delay[static_cast<size_t>(d) * nsb + n] = p->table[static_cast<size_t>(d) * p->nchans + n * nsub];
+            }
+        Stage2Tables t = stage2_tables(ndm, nsb, rows, delay);
+        if (!t.sblocks.empty() && t.gtrials.empty()) {
+            s2->tree_rows.swap(rows);
+            s2->tree_delay.swap(delay);
+            t.assign_to(s2);
+        }
+    }
     destroy_subband(p);
     p->sb_nsub = nsub;
     p->sb_ngroup = ngroup;
@@ -1754,6 +1872,7 @@ dedisp_status dedisp_set_subband(dedisp_plan p, int nsub, int ngroup)
     p->sb_step2 = s2;
     return DEDISP_OK;
 }
+
 
 // Tables of the piecewise tree with sub-bands of nsub channels for plan q's
 // trials, at q's resolution (dt, or s*dt for a scrunch group's plan).
@@ -1812,60 +1931,10 @@ static dedisp_status build_tree(dedisp_plan q, int nsub)
         const int n = static_cast<int>(i % nsb), ps = dprime[i] / nsub;
         rows[i] = pair_of[static_cast<size_t>(n) * (maxpass + 1) + ps] * nsub + dprime[i] % nsub;
     }
-    // LDS staging of stage 2 (byte rows only): per block of kTreeBlock
-    // consecutive trials and sub-band, the rows the block uses and its delay
-    // window; a block whose rows exceed kTreeLdsDwords is gathered instead
-    constexpr int TB = dedisp::kTreeBlock, TT = dedisp::kTreeTile;
-    constexpr long long kTreeLdsDwords = 16 * 1024;          // 64 KB: two workgroups per CU
-    std::vector<dedisp::TreeStage> stage;
-    std::vector<int32_t> sblocks, off, gtrials;
-    int lds_max = 0, span_max = 0;
-    // (the kernel keeps a trial's offsets in two registers: up to 128 sub-bands)
-    if (static_cast<long long>(q->value_bound()) * nsub <= 255 && nsb <= 128) {
-        off.assign(static_cast<size_t>(ndm) * nsb, 0);
-        std::vector<dedisp::TreeStage> st(nsb);
-        for (int b = 0; b * TB < ndm; ++b) {
-            const int d0 = b * TB, d1 = std::min(ndm, d0 + TB);
-            long long lds = 0;
-            for (int n = 0; n < nsb; ++n) {
-                int lo = 0x7fffffff, hi = -1, dmin = 0x7fffffff, dmax = -1;
-                for (int d = d0; d < d1; ++d) {
-                    const size_t i = static_cast<size_t>(d) * nsb + n;
-                    lo = std::min(lo, rows[i]);
-                    hi = std::max(hi, rows[i]);
-                    dmin = std::min(dmin, delay[i]);
-                    dmax = std::max(dmax, delay[i]);
-                }
-                dedisp::TreeStage& g = st[n];
-                g = dedisp::TreeStage{};
-                g.lo = lo;
-                g.span = hi - lo + 1;
-                g.dmin4 = dmin & ~3;
-                // staged rows are segmented within the tile (four segments of
-                // TT/4 outputs, one byte of each per dword): the window covers
-                // a segment and the block's delay spread, in whole groups of
-                // four dwords
-                g.wdw = ((dmax - g.dmin4) + TT / 4 + 3) / 4 * 4;
-                g.rcp = static_cast<uint32_t>(((1ull << 32) + g.wdw / 4 - 1) / (g.wdw / 4));
-                g.lds = static_cast<int>(std::min<long long>(lds, 0x7fffffff));
-                lds += static_cast<long long>(g.span) * g.wdw;
-            }
-            if (lds > kTreeLdsDwords) {
-                for (int d = d0; d < d1; ++d) gtrials.push_back(d);
-                continue;
-            }
-            for (int n = 0; n < nsb; ++n)
-                for (int d = d0; d < d1; ++d) {
-                    const size_t i = static_cast<size_t>(d) * nsb + n;
-                    const dedisp::TreeStage& g = st[n];
-                    off[i] = 4 * (g.lds + (rows[i] - g.lo) * g.wdw + (delay[i] - g.dmin4));
-                }
-            sblocks.push_back(b);
-            stage.insert(stage.end(), st.begin(), st.end());
-            lds_max = std::max(lds_max, static_cast<int>(lds));
-            for (const auto& g : st) span_max = std::max(span_max, g.span);
-        }
-    }
+    // LDS staging of stage 2 (byte rows only; the kernel keeps a trial's
+    // offsets in two registers: up to 128 sub-bands)
+    Stage2Tables s2t;
+    if (static_cast<long long>(q->value_bound()) * nsub <= 255 && nsb <= 128) s2t = stage2_tables(ndm, nsb, rows, delay);
     destroy_tree(q);
     q->tree_nsub = nsub;
     q->tree_maxdelay = mx;
@@ -1873,14 +1942,7 @@ static dedisp_status build_tree(dedisp_plan q, int nsub)
     q->tree_pairs.swap(pairs);
     q->tree_rows.swap(rows);
     q->tree_delay.swap(delay);
-    if (!sblocks.empty()) {
-        q->tree_stage.swap(stage);
-        q->tree_sblocks.swap(sblocks);
-        q->tree_off.swap(off);
-        q->tree_gtrials.swap(gtrials);
-        q->tree_lds = lds_max;
-        q->tree_span = span_max;
-    }
+    s2t.assign_to(q);
     return DEDISP_OK;
 }
 

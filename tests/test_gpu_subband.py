@@ -144,3 +144,38 @@ def test_subband_tuned_intermediate_width_bit_exact(native, cuda, nchans, nsub, 
     got = _run(plan, packed, nsamps, cuda, width)
     assert np.array_equal(got[:, :nout], want)
     assert np.all(got[:, nout:] == SENTINEL)
+
+
+@pytest.mark.parametrize("nchans,nsub,ngroup,ndm", [(1024, 32, 32, 80), (1024, 64, 64, 100), (512, 16, 32, 70)])
+def test_subband_step2_as_row_combination_bit_exact(native, cuda, nchans, nsub, ngroup, ndm):
+    """Byte sub-band sums with whole blocks of 32 trials per nominal DM
+    (ngroup a multiple of 32) over a narrow DM range: step 2 runs as the
+    combination of per-sub-band rows staged in LDS (sums up to 96 added two
+    terms at a time as bytes, up to 192 one at a time, up to 48 two at a
+    time), with a ragged last nominal DM, a kill mask, and 16-bit outputs in
+    a wider row stride, bit for bit against the oracle."""
+    import torch
+    nbits, nsamps = 2, 30011
+    dt, f_top, df = 64e-6, 1581.8, -400.0 / nchans
+    dms = np.linspace(0.0, 40.0, ndm)
+    rng = np.random.default_rng(nchans + nsub + ngroup)
+    codes = _codes(rng, nsamps, nchans, nbits)
+    codes[5000:9000] = 3
+    packed = synth.pack(codes, nbits)
+    mask = (rng.random(nchans) < 0.93).astype(np.int32)
+    want = oracle.dedisperse_subband(packed, nsamps, nchans, nbits, dt, f_top, df, dms, nsub, ngroup, mask=mask)
+    plan = Plan(nchans, dt, f_top, df, nbits).set_dm_list(dms).set_killmask(mask)
+    plan.set_subband(nsub, ngroup)
+    nout = want.shape[1]
+    width = nout + 5
+    got = _run(plan, packed, nsamps, cuda, width)
+    assert np.array_equal(got[:, :nout], want)
+    assert np.all(got[:, nout:] == SENTINEL)
+    plan.set_output_format(16, 1)
+    inp = torch.from_numpy(np.ascontiguousarray(packed.reshape(-1))).to(cuda)
+    out = torch.full((plan.ndm, width), 0x7777, dtype=plan.output_dtype(), device=cuda)
+    plan.execute(inp, nsamps, out=out, out_row_stride=width)
+    torch.cuda.synchronize()
+    got16 = out.cpu().numpy().view(np.uint16)
+    assert np.array_equal(got16[:, :nout], oracle.reduce_output(want, 16, 1))
+    assert np.all(got16[:, nout:] == 0x7777)
